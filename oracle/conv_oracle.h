@@ -1,0 +1,109 @@
+/*
+ * conv_oracle.h -- C entry points of the CPU oracle for the deep (Zhang-McFarlane-style) and
+ * shallow (UW bulk-plume-style) cumulus convection schemes.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is a plain, slow, single-threaded FP64 reference used by the
+ * tests, by the smoke check and by the benchmark's CPU baseline to judge the HIP path.  Nothing in
+ * the product library links, includes or calls it, and it shares no code with the HIP kernels.
+ *
+ * The paper (Ramesh et al., "Deep and Shallow convections in Atmosphere Models on Intel Xeon Phi
+ * Coprocessor Systems", arXiv:1711.00289) names the two schemes (Background, "Deep Convection" /
+ * "Shallow Convection") and gives their loop skeletons (Algorithms 2 and 3) but no physics; the
+ * scheme computed here is the written reading frozen in DESIGN.md ("Scheme"), steps D1-D10 and
+ * S1-S9.  All arrays are host arrays, level-major: element (k, col) at [k*ld + col], level 0 at
+ * the model top; interface arrays have nlev+1 rows.
+ */
+#ifndef CONV_ORACLE_H
+#define CONV_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    double cape_threshold, tau, eps_deep, alpha_dd, evap_max_frac, p_launch_min, p_top_min;
+    double eps_sh, delta_sh, qlcrit_sh, cin_max, a_buoy, b_drag, c_tke, p_lcl_min, p_sh_top_min;
+} oracle_params_t;
+
+typedef struct {
+    const double *T, *q, *p_mid, *z; /* [nlev][ld] */
+    const double *p_int;             /* [nlev+1][ld] */
+    const double *phis, *pblh, *tke; /* [ld] */
+    int64_t ld;
+    double dt;
+} oracle_state_t;
+
+typedef struct {
+    double *dTdt, *dqdt;   /* [nlev][ld]   K/s, kg/kg/s */
+    double *mu, *md;       /* [nlev+1][ld] kg m^-2 s^-1 (md <= 0) */
+    double *prec, *cape;   /* [ld] */
+    int32_t *klaunch, *ktop, *trig, *status;
+} oracle_deep_out_t;
+
+typedef struct {
+    double *dTdt, *dqdt;   /* [nlev][ld] */
+    double *mu;            /* [nlev+1][ld] */
+    double *prec, *cin;    /* [ld] */
+    int32_t *kbase, *ktop, *status;
+} oracle_shallow_out_t;
+
+/* Per-column diagnostics of the deep scheme (for the pins). */
+typedef struct {
+    int32_t kb, kt, kd, klim, status;
+    double cape, F, Mc, Mlim, Mb, alpha, C1, E1, P1;
+} oracle_deep_diag_t;
+
+/* Per-column diagnostics of the shallow scheme. */
+typedef struct {
+    int32_t ks, klcl, klfc, kt, status;
+    double hs, qs, cin, rho_s, sigw2, Mclos, Mlim, Mb, P1;
+} oracle_shallow_diag_t;
+
+/* Full column runs over ncol columns (0 on success, -1 on bad arguments). */
+int oracle_deep(int64_t ncol, int nlev, const oracle_params_t *p, const oracle_state_t *s,
+                oracle_deep_out_t *o);
+int oracle_shallow(int64_t ncol, int nlev, const oracle_params_t *p, const oracle_state_t *s,
+                   oracle_shallow_out_t *o);
+/* Deep, then T' = T + dt*dTdt, q' = q + dt*dqdt, then shallow on (T', q') (Algorithm 1 order). */
+int oracle_step(int64_t ncol, int nlev, const oracle_params_t *p, const oracle_state_t *s,
+                oracle_deep_out_t *od, oracle_shallow_out_t *os);
+
+/* Same as oracle_step with OpenMP dynamic scheduling over columns (CPU baseline only). */
+int oracle_step_omp(int64_t ncol, int nlev, const oracle_params_t *p, const oracle_state_t *s,
+                    oracle_deep_out_t *od, oracle_shallow_out_t *os, int chunk, int nthreads);
+
+/* One column (contiguous arrays of length nlev / nlev+1) with diagnostics and the plume profiles
+ * (eta, eta_d at interfaces; may be NULL). */
+int oracle_deep_column(int nlev, const oracle_params_t *p, const double *T, const double *q,
+                       const double *p_mid, const double *p_int, const double *z, double phis,
+                       double dt, double *dTdt, double *dqdt, double *mu, double *md, double *prec,
+                       oracle_deep_diag_t *diag, double *eta, double *eta_d);
+int oracle_shallow_column(int nlev, const oracle_params_t *p, const double *T, const double *q,
+                          const double *p_mid, const double *p_int, const double *z, double phis,
+                          double pblh, double tke, double dt, double *dTdt, double *dqdt,
+                          double *mu, double *prec, oracle_shallow_diag_t *diag);
+
+/* Undilute parcel diagnostics of the deep trigger for one column: B[k], saturation flag, Tp, qp. */
+int oracle_deep_parcel(int nlev, const oracle_params_t *p, const double *T, const double *q,
+                       const double *p_mid, const double *p_int, const double *z, double phis,
+                       double *B, int32_t *sat, double *Tp, double *qp);
+
+/* Forward-mode directional derivative (dual numbers) of the deep scheme of one column along
+ * (dT, dq, dtau, deps) with every branch held where the primal run takes it.  Outputs are the
+ * tangents of dTdt, dqdt [nlev] and prec. */
+int oracle_deep_column_jvp(int nlev, const oracle_params_t *p, const double *T, const double *q,
+                           const double *p_mid, const double *p_int, const double *z, double phis,
+                           double dt, const double *dT, const double *dq, double dtau, double deps,
+                           double *t_dTdt, double *t_dqdt, double *t_prec);
+
+/* Thermodynamics (C1 of the scheme). */
+double oracle_es(double T);
+double oracle_qs(double T, double p);
+double oracle_dqsdT(double T, double p);
+double oracle_tsat(double H, double p, double T_guess, int *iterations);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
