@@ -409,17 +409,21 @@ template <class R> struct ShallowRes {
     int ks, klcl, klfc, kt, status;
 };
 
+// `state_checked`: the column's validity (C0) was already decided on the input state of the step;
+// the deep-updated state of a valid column is not re-validated (its humidity can sit a rounding
+// error below zero where the deep limiter binds).
 template <class R>
 void shallow_column(int L, const oracle_params_t &P, const R *T, const R *q, const double *pm,
                     const double *pi, const double *z, double phis, double pblh, double tke,
-                    double dt, ShallowRes<R> &o) {
+                    double dt, ShallowRes<R> &o, bool state_checked = false) {
     o.dTdt.assign(L, R(0.0));
     o.dqdt.assign(L, R(0.0));
     o.mu.assign(L + 1, R(0.0));
     o.prec = o.cin = o.hs = o.qsrc = o.rho_s = o.sigw2 = o.Mclos = o.Mb = o.P1 = R(0.0);
     o.Mlim = R(std::numeric_limits<double>::infinity());
     o.ks = o.klcl = o.klfc = o.kt = -1;
-    if (!column_valid(L, T, q, pm, pi, z, phis) || !std::isfinite(pblh) || !std::isfinite(tke)) {
+    if ((!state_checked && !column_valid(L, T, q, pm, pi, z, phis)) || !std::isfinite(pblh) ||
+        !std::isfinite(tke)) {
         o.status = 6;
         return;
     }
@@ -651,11 +655,15 @@ void step_one(int L, const oracle_params_t *p, const oracle_state_t *s, int64_t 
         T2[k] = col.T[k] + s->dt * d.dTdt[k];
         q2[k] = col.q[k] + s->dt * d.dqdt[k];
     }
-    // An invalid input column has all-zero deep outputs, so (T', q') = (T, q) and the shallow
-    // scheme reports it invalid too.
+    // Validity is a property of the input column: an invalid one (deep status 3) is invalid for
+    // the shallow scheme too; a valid one stays valid after the deep update.
     ShallowRes<double> sh;
-    shallow_column<double>(L, *p, T2.data(), q2.data(), col.pm.data(), col.pi.data(), col.z.data(),
-                           col.phis, col.pblh, col.tke, s->dt, sh);
+    if (d.status == 3)
+        shallow_column<double>(L, *p, col.T.data(), col.q.data(), col.pm.data(), col.pi.data(),
+                               col.z.data(), col.phis, col.pblh, col.tke, s->dt, sh);
+    else
+        shallow_column<double>(L, *p, T2.data(), q2.data(), col.pm.data(), col.pi.data(),
+                               col.z.data(), col.phis, col.pblh, col.tke, s->dt, sh, true);
     scatter_shallow(sh, L, s->ld, c, os);
 }
 

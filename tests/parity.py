@@ -1,0 +1,59 @@
+"""Element-by-element comparison of HIP outputs with the oracle (host-side test helpers).
+
+Bar: integer and index outputs bit-exact; FP64 arrays within 1e-9 normwise per column
+(max_k |g - o| <= 1e-9 * max_k |o| + 1e-300); FP64 per-column scalars within 1e-9 relative (same
+floor).  Any index mismatch is reported with the column and values so its decision margin can be
+inspected."""
+import numpy as np
+
+RTOL = 1e-9
+FLOOR = 1e-300
+
+DEEP_INT = ("klaunch", "ktop", "trig", "status")
+DEEP_ARR = ("dTdt", "dqdt", "mu", "md")
+DEEP_SCAL = ("prec", "cape")
+SH_INT = ("kbase", "ktop", "status")
+SH_ARR = ("dTdt", "dqdt", "mu")
+SH_SCAL = ("prec", "cin")
+
+
+def to_np(d):
+    return {k: v.detach().cpu().numpy() for k, v in d.items()}
+
+
+def compare(gpu: dict, ora: dict, ints, arrs, scals, ncol, cols=None, label=""):
+    """Raise AssertionError with details on the first failing output."""
+    idx = np.arange(ncol) if cols is None else np.asarray(cols)
+    for f in ints:
+        g, o = gpu[f][..., :ncol][..., idx], ora[f]
+        bad = np.nonzero(g != o)[0]
+        assert bad.size == 0, (f"{label} {f}: {bad.size} mismatches, first cols "
+                               f"{idx[bad[:5]].tolist()} gpu={g[bad[:5]].tolist()} "
+                               f"oracle={o[bad[:5]].tolist()}")
+    for f in arrs:
+        g, o = gpu[f][:, :ncol][:, idx], ora[f]
+        err = np.abs(g - o).max(axis=0)
+        scale = np.abs(o).max(axis=0)
+        bad = np.nonzero(~(err <= RTOL * scale + FLOOR))[0]
+        assert bad.size == 0, (f"{label} {f}: {bad.size} columns beyond tolerance, first "
+                               f"{idx[bad[:5]].tolist()} rel={(err[bad[:5]] / (scale[bad[:5]] + FLOOR)).tolist()}")
+    for f in scals:
+        g, o = gpu[f][:ncol][idx], ora[f]
+        bad = np.nonzero(~(np.abs(g - o) <= RTOL * np.abs(o) + FLOOR))[0]
+        assert bad.size == 0, (f"{label} {f}: {bad.size} mismatches, first cols "
+                               f"{idx[bad[:5]].tolist()} gpu={g[bad[:5]].tolist()} "
+                               f"oracle={o[bad[:5]].tolist()}")
+
+
+def compare_deep(gpu, ora, ncol, cols=None, label="deep"):
+    compare(gpu, ora, DEEP_INT, DEEP_ARR, DEEP_SCAL, ncol, cols, label)
+
+
+def compare_shallow(gpu, ora, ncol, cols=None, label="shallow"):
+    compare(gpu, ora, SH_INT, SH_ARR, SH_SCAL, ncol, cols, label)
+
+
+def exact_positive_zero(d: dict, fields, cols):
+    for f in fields:
+        a = d[f][..., cols]
+        assert (a == 0).all() and not np.signbit(a).any(), f
