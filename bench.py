@@ -1,0 +1,173 @@
+#!/usr/bin/env python3
+"""Benchmark: one physics step of FP64 deep + shallow convection (the paper's Algorithm 1 order)
+over the 1152 x 768 = 884,736-column x 30-level latitude-clustered synthetic grid on one MI355X.
+
+Prints ONE JSON line.  `value` is columns per second of the whole step with inputs resident in HBM.
+`roofline` is for the kernel that takes the most time in the step, its duration measured live with
+HIP events recorded by the library on the stream it launches on.  `cpu_baseline` is the CPU oracle
+(OpenMP dynamic schedule over the host cores, the paper's own load-balancing technique) timed on
+the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("convection columns/s (FP64, 1 GPU) at 884,736×30; adjoint/forward cost; "
+          "surrogate error")
+HBM_PEAK_GBS = 8000.0
+NLEV = 30
+NLON, NLAT = 1152, 768
+
+
+def bytes_per_column(L: int):
+    """Algorithmic HBM bytes per column of the fused step: every input read once, every output
+    written once."""
+    inputs = (4 * L + (L + 1) + 3) * 8
+    deep_scalars = 8 + 4 * 4                         # cape, klaunch, ktop, trig, status
+    deep_arrays = (2 * L + 2 * (L + 1) + 1) * 8      # dTdt, dqdt, mu, md, prec
+    shallow = (2 * L + (L + 1) + 2) * 8 + 3 * 4     # dTdt, dqdt, mu, prec, cin, kbase, ktop, status
+    return dict(inputs=inputs, deep_scalars=deep_scalars, deep_arrays=deep_arrays,
+                shallow=shallow, total=inputs + deep_scalars + deep_arrays + shallow)
+
+
+def kernel_bytes(L, n, trig, sh_status):
+    """Algorithmic bytes attributed to each kernel of the step (each input read and each output
+    written once, charged to the kernel that does it)."""
+    b = bytes_per_column(L)
+    quiet = trig == 0
+    sh_in_trigger = quiet & ~np.isin(sh_status, (0, 5))
+    sh_in_deep = (~quiet) & ~np.isin(sh_status, (0, 5))
+    sh_in_plume = np.isin(sh_status, (0, 5))
+    return dict(
+        trigger=n * (b["inputs"] + b["deep_scalars"]) + quiet.sum() * b["deep_arrays"] +
+        sh_in_trigger.sum() * b["shallow"],
+        deep_plume=(~quiet).sum() * b["deep_arrays"] + sh_in_deep.sum() * b["shallow"],
+        shallow_plume=sh_in_plume.sum() * b["shallow"],
+        reset=0,
+    )
+
+
+def cpu_baseline(st, threads):
+    import oracle
+
+    t0 = time.perf_counter()
+    oracle.step(st, threads=threads, chunk=16)
+    dt = time.perf_counter() - t0
+    return st["ncol"] / dt, dt
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--ncol", type=int, default=NLON * NLAT)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the column-sharded design "
+              "for more GPUs is described in DESIGN.md and not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1711_00289_amd import binding as B
+    from paper_1711_00289_amd import soundings as S
+
+    t0 = time.perf_counter()
+    if args.ncol == NLON * NLAT:
+        st = S.grid_quarter_deg(NLEV)
+    else:
+        st = S.make_state(args.ncol, NLEV, seed=103,
+                          warm=S.latlon_warm_mask(NLON, NLAT)[:args.ncol])
+    n = st["ncol"]
+    print(f"[bench] inputs generated ({n} columns) in {time.perf_counter() - t0:.1f} s",
+          file=sys.stderr, flush=True)
+    dev = B.to_device(st)
+    conv = B.Conv(n, NLEV)
+    deep = conv.alloc_deep(n)
+    shallow = conv.alloc_shallow(n)
+    torch.cuda.synchronize()
+
+    for _ in range(args.warmup):
+        conv.step(dev, deep, shallow)
+    torch.cuda.synchronize()
+    print("[bench] warmup done", file=sys.stderr, flush=True)
+
+    conv.timing_start(args.steps)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        conv.step(dev, deep, shallow)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms_step = e0.elapsed_time(e1) / args.steps
+    kms, ncalls = conv.timing_read()
+    conv.timing_start(0)
+    kavg = {k: v / max(ncalls, 1) for k, v in kms.items()}
+
+    trig = deep["trig"].cpu().numpy()
+    dst = deep["status"].cpu().numpy()
+    sst = shallow["status"].cpu().numpy()
+    kb = kernel_bytes(NLEV, n, trig, sst)
+    dom = max(("trigger", "deep_plume", "shallow_plume"), key=lambda k: kavg[k])
+    achieved = kb[dom] / (kavg[dom] * 1e-3) / 1e9
+    step_bytes = bytes_per_column(NLEV)["total"] * n
+    value = n / (ms_step * 1e-3)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "columns/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "conv_step (deep then shallow), 1152x768 = 884,736 columns x 30 "
+                               "levels, latitude-clustered synthetic soundings, dt=1800 s",
+                   "ncol": n, "nlev": NLEV},
+        "roofline": {"bound": "hbm", "kernel": f"k_{dom}", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None,
+                     "algorithmic_bytes_per_launch": int(kb[dom]),
+                     "avg_launch_ms": kavg[dom]},
+        "step_roofline": {"algorithmic_bytes": int(step_bytes),
+                          "bytes_per_column": bytes_per_column(NLEV)["total"],
+                          "achieved_GBs": step_bytes / (ms_step * 1e-3) / 1e9,
+                          "frac": step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "kernels_ms": kavg,
+        "active_fraction": {"deep": float((dst == 0).mean()), "deep_triggered": float(trig.mean()),
+                            "shallow": float((sst == 0).mean())},
+        "wall_s_timed": wall,
+    }
+
+    if not args.no_cpu:
+        threads = min(16, len(os.sched_getaffinity(0)))
+        rate, secs = cpu_baseline(st, threads)
+        out["cpu_baseline"] = {"value": rate, "unit": "columns/s", "cores": threads,
+                               "kind": "oracle",
+                               "sample": f"the full {n}-column grid, one oracle step "
+                                         f"(OpenMP dynamic schedule, chunk 16), {secs:.1f} s wall"}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,141 @@
+/*
+ * conv.h -- C ABI of libconv.so: FP64 deep (Zhang-McFarlane-style) and shallow (UW
+ * bulk-plume-style) cumulus convection over many independent columns on one MI355X (gfx950).
+ *
+ * The paper (Ramesh et al., arXiv:1711.00289) states the problem these calls follow: physics is
+ * computed per vertical column, independently across columns, once per time step, deep convection
+ * before shallow convection (Background, Algorithm 1); deep convection is an entrainment loop and a
+ * precipitation loop over columns x levels around an iterative thermodynamic inversion (Algorithm
+ * 2); shallow convection tests thermodynamic conditions at several points and zeroes the outputs of
+ * columns that exit early (Algorithm 3); inputs and outputs travel as one structure of arrays with
+ * resident parameters and static buffers (Methodology, "Proportional Partitioning": packing,
+ * offloading only the needed data, static in/out variables).  The scheme computed (steps D1-D10 and
+ * S1-S9) is the written reading in the design doc, section 2.
+ *
+ * Conventions for every call:
+ *  - All array pointers are DEVICE pointers owned by the caller.  The library never allocates or
+ *    frees device memory and never synchronises the host: calls only enqueue work on `stream`
+ *    (a hipStream_t; NULL = the default stream) and return.  Kernel faults surface at the caller's
+ *    next synchronisation.
+ *  - Arrays are FP64, level-major: element (k, col) is at [k*ld + col], level 0 is the model top,
+ *    the column index is fastest.  Layer arrays have nlev rows, interface arrays nlev+1 rows
+ *    (interface i is the top of layer i; interface nlev is the surface).  Per-column arrays have
+ *    ld entries.  Only columns 0 .. ncol-1 are read or written; ld >= ncol allows padding.
+ *  - Index outputs are 0-based with -1 meaning "undefined".
+ *  - Return value: CONV_OK (0) or a negative CONV_E* code.  CONV_EINVAL: a NULL pointer, a bad
+ *    size, ld < ncol, dt <= 0 or a workspace that is too small; nothing is enqueued.  CONV_EHIP: a
+ *    kernel launch failed (conv_last_hip_error() returns the hipError_t value).
+ *  - A context is not thread-safe and its workspace is shared by its calls: calls on one context
+ *    must be ordered on one stream.
+ *  - Per-column physics outcomes are not errors; they are reported in `status`:
+ *      deep:    0 convecting, 1 not triggered, 2 closure F <= 0, 3 invalid column
+ *      shallow: 0 convecting, 1 no LCL, 2 no LFC, 3 CIN > cin_max, 4 tke <= 0,
+ *               5 plume dies in the first layer, 6 invalid column
+ *    Every flux, tendency and precipitation output of a non-convecting column is exactly +0.0.
+ */
+#ifndef CONV_H
+#define CONV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CONV_OK 0
+#define CONV_EINVAL (-1)
+#define CONV_EUNSUPPORTED (-2)
+#define CONV_EHIP (-3)
+
+typedef struct conv_ctx conv_ctx_t; /* opaque host-side handle */
+
+/* Scheme parameters, SI units (defaults in parentheses). */
+typedef struct {
+    double cape_threshold; /* trigger: CAPE > threshold (70 J/kg) */
+    double tau;            /* deep closure time scale (3600 s) */
+    double eps_deep;       /* deep entrainment rate (1e-4 1/m) */
+    double alpha_dd;       /* downdraft strength (0.2) */
+    double evap_max_frac;  /* downdraft evaporation <= this fraction of condensate (0.9) */
+    double p_launch_min;   /* launch layer search: p_mid >= this (60000 Pa) */
+    double p_top_min;      /* cloud top: p_mid >= this (4000 Pa) */
+    double eps_sh;         /* shallow entrainment rate (1e-3 1/m) */
+    double delta_sh;       /* shallow detrainment rate (1e-3 1/m) */
+    double qlcrit_sh;      /* shallow rain-out threshold (1e-3 kg/kg) */
+    double cin_max;        /* shallow CIN limit (100 J/kg) */
+    double a_buoy;         /* buoyancy factor in w^2 (1) */
+    double b_drag;         /* drag factor in w^2 (1) */
+    double c_tke;          /* sigma_w^2 = c_tke * tke (1) */
+    double p_lcl_min;      /* LCL must lie at p_mid >= this (60000 Pa) */
+    double p_sh_top_min;   /* shallow LFC and plume top: p >= this (40000 Pa) */
+} conv_params_t;
+
+/* Input state (device pointers, read only). */
+typedef struct {
+    const double *T;     /* [nlev][ld]   temperature, K */
+    const double *q;     /* [nlev][ld]   specific humidity, kg/kg */
+    const double *p_mid; /* [nlev][ld]   mid-layer pressure, Pa */
+    const double *z;     /* [nlev][ld]   mid-layer height above the surface, m */
+    const double *p_int; /* [nlev+1][ld] interface pressure, Pa */
+    const double *phis;  /* [ld]         surface geopotential, m^2/s^2 */
+    const double *pblh;  /* [ld]         boundary-layer height, m (shallow only) */
+    const double *tke;   /* [ld]         boundary-layer TKE, m^2/s^2 (shallow only) */
+    int64_t ld;          /* leading dimension, >= ncol */
+    double dt;           /* physics time step, s (> 0) */
+} conv_state_t;
+
+/* Deep-scheme outputs (device pointers, written). */
+typedef struct {
+    double *dTdt, *dqdt;           /* [nlev][ld]   heating K/s, moistening 1/s */
+    double *mu, *md;               /* [nlev+1][ld] updraft / downdraft mass flux kg m^-2 s^-1 */
+    double *prec, *cape;           /* [ld]         kg m^-2 s^-1, J/kg */
+    int32_t *klaunch, *ktop, *trig, *status; /* [ld] */
+} conv_deep_out_t;
+
+/* Shallow-scheme outputs (device pointers, written). */
+typedef struct {
+    double *dTdt, *dqdt; /* [nlev][ld] */
+    double *mu;          /* [nlev+1][ld] */
+    double *prec, *cin;  /* [ld] */
+    int32_t *kbase, *ktop, *status; /* [ld] */
+} conv_shallow_out_t;
+
+/* Device workspace size (bytes) that a context over (ncol, nlev) needs on the current device. */
+size_t conv_workspace_bytes(int64_t ncol, int32_t nlev);
+
+/* Create a context for up to `ncol` columns of `nlev` levels (2 <= nlev <= 256) over a
+ * caller-owned device workspace of at least conv_workspace_bytes(ncol, nlev) bytes, 256-byte
+ * aligned.  `params` is a host pointer and is copied.  The handle is host memory. */
+int conv_create(int64_t ncol, int32_t nlev, const conv_params_t *params, void *workspace,
+                size_t ws_bytes, conv_ctx_t **out);
+/* Replace the parameters (host pointer, copied). */
+int conv_set_params(conv_ctx_t *ctx, const conv_params_t *params);
+/* Free the host handle (the workspace stays the caller's). */
+void conv_destroy(conv_ctx_t *ctx);
+
+/* Deep scheme (steps D1-D10) over columns 0 .. ncol-1. */
+int conv_deep_forward(conv_ctx_t *ctx, const conv_state_t *state, conv_deep_out_t *out,
+                      void *stream);
+/* Shallow scheme (steps S1-S9) on the given state. */
+int conv_shallow_forward(conv_ctx_t *ctx, const conv_state_t *state, conv_shallow_out_t *out,
+                         void *stream);
+/* One physics step of both schemes in the paper's Algorithm 1 order: deep, then the state update
+ * T' = T + dt*dTdt, q' = q + dt*dqdt, then shallow on (T', q'). */
+int conv_step(conv_ctx_t *ctx, const conv_state_t *state, conv_deep_out_t *deep,
+              conv_shallow_out_t *shallow, void *stream);
+
+/* Instrumentation: record HIP events on the call's stream around each kernel of the next
+ * `max_calls` calls (0 turns recording off).  conv_timing_read() waits for the recorded calls and
+ * returns, per stage, the summed milliseconds over those calls in ms[0..3] (list reset, trigger
+ * pass, deep plume pass, shallow plume pass) and the number of recorded calls in *ncalls.  Events
+ * are host-side handles created here; no device memory is allocated. */
+int conv_timing_start(conv_ctx_t *ctx, int max_calls);
+int conv_timing_read(conv_ctx_t *ctx, double *ms, int *ncalls);
+
+const char *conv_strerror(int code);
+int conv_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

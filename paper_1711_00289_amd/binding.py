@@ -1,0 +1,248 @@
+"""ctypes binding of libconv.so (include/conv.h).
+
+Argument marshalling only: torch tensors supply device memory and the stream; every step of the
+scheme runs in the library's HIP kernels.  There is no CPU path: if the library is missing or no
+GPU is present, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libconv.so")
+
+CONV_OK, CONV_EINVAL, CONV_EUNSUPPORTED, CONV_EHIP = 0, -1, -2, -3
+
+PARAM_FIELDS = (
+    "cape_threshold", "tau", "eps_deep", "alpha_dd", "evap_max_frac", "p_launch_min", "p_top_min",
+    "eps_sh", "delta_sh", "qlcrit_sh", "cin_max", "a_buoy", "b_drag", "c_tke", "p_lcl_min",
+    "p_sh_top_min",
+)
+DEFAULTS = dict(
+    cape_threshold=70.0, tau=3600.0, eps_deep=1.0e-4, alpha_dd=0.2, evap_max_frac=0.9,
+    p_launch_min=60000.0, p_top_min=4000.0, eps_sh=1.0e-3, delta_sh=1.0e-3, qlcrit_sh=1.0e-3,
+    cin_max=100.0, a_buoy=1.0, b_drag=1.0, c_tke=1.0, p_lcl_min=60000.0, p_sh_top_min=40000.0,
+)
+
+EXPORTS = ("conv_workspace_bytes", "conv_create", "conv_set_params", "conv_destroy",
+           "conv_deep_forward", "conv_shallow_forward", "conv_step", "conv_timing_start",
+           "conv_timing_read", "conv_strerror", "conv_last_hip_error")
+
+
+class Params(C.Structure):
+    _fields_ = [(n, C.c_double) for n in PARAM_FIELDS]
+
+
+class State(C.Structure):
+    _fields_ = [("T", C.c_void_p), ("q", C.c_void_p), ("p_mid", C.c_void_p), ("z", C.c_void_p),
+                ("p_int", C.c_void_p), ("phis", C.c_void_p), ("pblh", C.c_void_p),
+                ("tke", C.c_void_p), ("ld", C.c_int64), ("dt", C.c_double)]
+
+
+class DeepOut(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in ("dTdt", "dqdt", "mu", "md", "prec", "cape", "klaunch",
+                                          "ktop", "trig", "status")]
+
+
+class ShallowOut(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in ("dTdt", "dqdt", "mu", "prec", "cin", "kbase", "ktop",
+                                          "status")]
+
+
+_lib = None
+
+
+def lib():
+    """Load libconv.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_1711_00289_amd.build` (there is no CPU fallback)")
+        L = C.CDLL(LIB_PATH)
+        L.conv_workspace_bytes.restype = C.c_size_t
+        L.conv_workspace_bytes.argtypes = [C.c_int64, C.c_int32]
+        L.conv_create.restype = C.c_int
+        L.conv_create.argtypes = [C.c_int64, C.c_int32, C.POINTER(Params), C.c_void_p, C.c_size_t,
+                                  C.POINTER(C.c_void_p)]
+        L.conv_set_params.restype = C.c_int
+        L.conv_set_params.argtypes = [C.c_void_p, C.POINTER(Params)]
+        L.conv_destroy.restype = None
+        L.conv_destroy.argtypes = [C.c_void_p]
+        L.conv_deep_forward.restype = C.c_int
+        L.conv_deep_forward.argtypes = [C.c_void_p, C.POINTER(State), C.POINTER(DeepOut), C.c_void_p]
+        L.conv_shallow_forward.restype = C.c_int
+        L.conv_shallow_forward.argtypes = [C.c_void_p, C.POINTER(State), C.POINTER(ShallowOut),
+                                           C.c_void_p]
+        L.conv_step.restype = C.c_int
+        L.conv_step.argtypes = [C.c_void_p, C.POINTER(State), C.POINTER(DeepOut),
+                                C.POINTER(ShallowOut), C.c_void_p]
+        L.conv_timing_start.restype = C.c_int
+        L.conv_timing_start.argtypes = [C.c_void_p, C.c_int]
+        L.conv_timing_read.restype = C.c_int
+        L.conv_timing_read.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int)]
+        L.conv_strerror.restype = C.c_char_p
+        L.conv_strerror.argtypes = [C.c_int]
+        L.conv_last_hip_error.restype = C.c_int
+        L.conv_last_hip_error.argtypes = []
+        _lib = L
+    return _lib
+
+
+def make_params(**over) -> Params:
+    d = dict(DEFAULTS)
+    for k, v in over.items():
+        if k not in d:
+            raise KeyError(k)
+        d[k] = float(v)
+    return Params(*[d[n] for n in PARAM_FIELDS])
+
+
+def check(rc: int, what: str):
+    if rc != CONV_OK:
+        msg = lib().conv_strerror(rc).decode()
+        if rc == CONV_EHIP:
+            msg += f" (hipError {lib().conv_last_hip_error()})"
+        raise RuntimeError(f"{what}: {msg}")
+
+
+def _torch():
+    import torch
+
+    if not torch.cuda.is_available():
+        raise RuntimeError("libconv needs a ROCm GPU (torch.cuda is not available)")
+    return torch
+
+
+def _stream(torch):
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def to_device(st: dict, device="cuda", ld: int | None = None):
+    """Copy a level-major numpy state dict (from soundings.make_state) to device tensors."""
+    torch = _torch()
+    out = {}
+    for k in ("T", "q", "p_mid", "z", "p_int", "phis", "pblh", "tke"):
+        out[k] = torch.as_tensor(st[k], dtype=torch.float64).to(device).contiguous()
+    out["dt"] = float(st["dt"])
+    out["ncol"] = int(st.get("ncol", st["T"].shape[1]))
+    return out
+
+
+class Conv:
+    """A context over `ncol` columns of `nlev` levels with a torch-allocated workspace."""
+
+    def __init__(self, ncol: int, nlev: int, params: Params | None = None, device="cuda"):
+        torch = _torch()
+        self.torch = torch
+        self.ncol, self.nlev = int(ncol), int(nlev)
+        self.device = device
+        L = lib()
+        nbytes = L.conv_workspace_bytes(self.ncol, self.nlev)
+        if nbytes == 0:
+            raise ValueError("unsupported size")
+        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        base = self.ws.data_ptr()
+        self.ws_ptr = (base + 255) & ~255
+        self.params = params or make_params()
+        h = C.c_void_p()
+        check(L.conv_create(self.ncol, self.nlev, C.byref(self.params), C.c_void_p(self.ws_ptr),
+                            nbytes, C.byref(h)), "conv_create")
+        self.h = h
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                lib().conv_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+    def set_params(self, params: Params):
+        self.params = params
+        check(lib().conv_set_params(self.h, C.byref(params)), "conv_set_params")
+
+    # -- outputs -------------------------------------------------------------------------
+    def _f64(self, *shape):
+        return self.torch.empty(*shape, dtype=self.torch.float64, device=self.device)
+
+    def _i32(self, n):
+        return self.torch.empty(n, dtype=self.torch.int32, device=self.device)
+
+    def alloc_deep(self, ld: int):
+        L = self.nlev
+        return dict(dTdt=self._f64(L, ld), dqdt=self._f64(L, ld), mu=self._f64(L + 1, ld),
+                    md=self._f64(L + 1, ld), prec=self._f64(ld), cape=self._f64(ld),
+                    klaunch=self._i32(ld), ktop=self._i32(ld), trig=self._i32(ld),
+                    status=self._i32(ld))
+
+    def alloc_shallow(self, ld: int):
+        L = self.nlev
+        return dict(dTdt=self._f64(L, ld), dqdt=self._f64(L, ld), mu=self._f64(L + 1, ld),
+                    prec=self._f64(ld), cin=self._f64(ld), kbase=self._i32(ld),
+                    ktop=self._i32(ld), status=self._i32(ld))
+
+    # -- marshalling ---------------------------------------------------------------------
+    def _state(self, s: dict) -> State:
+        T = s["T"]
+        if T.dim() != 2 or T.shape[0] != self.nlev or T.shape[1] < self.ncol:
+            raise ValueError("state arrays must be [nlev][ld] with ld >= ncol")
+        ld = T.shape[1]
+        for k, rows in (("T", self.nlev), ("q", self.nlev), ("p_mid", self.nlev),
+                        ("z", self.nlev), ("p_int", self.nlev + 1)):
+            a = s[k]
+            if a.dtype != self.torch.float64 or not a.is_contiguous() or tuple(a.shape) != (rows, ld):
+                raise ValueError(f"{k}: expected contiguous float64 [{rows}][{ld}]")
+        for k in ("phis", "pblh", "tke"):
+            a = s[k]
+            if a.dtype != self.torch.float64 or a.numel() < ld:
+                raise ValueError(f"{k}: expected float64 [{ld}]")
+        return State(*[s[k].data_ptr() for k in ("T", "q", "p_mid", "z", "p_int", "phis", "pblh",
+                                                  "tke")], ld, float(s["dt"]))
+
+    @staticmethod
+    def _deep_struct(o):
+        return DeepOut(*[o[f].data_ptr() for f, _ in DeepOut._fields_])
+
+    @staticmethod
+    def _shallow_struct(o):
+        return ShallowOut(*[o[f].data_ptr() for f, _ in ShallowOut._fields_])
+
+    # -- calls ---------------------------------------------------------------------------
+    def deep_forward(self, s: dict, out: dict | None = None) -> dict:
+        st = self._state(s)
+        out = out or self.alloc_deep(st.ld)
+        o = self._deep_struct(out)
+        check(lib().conv_deep_forward(self.h, C.byref(st), C.byref(o), _stream(self.torch)),
+              "conv_deep_forward")
+        return out
+
+    def shallow_forward(self, s: dict, out: dict | None = None) -> dict:
+        st = self._state(s)
+        out = out or self.alloc_shallow(st.ld)
+        o = self._shallow_struct(out)
+        check(lib().conv_shallow_forward(self.h, C.byref(st), C.byref(o), _stream(self.torch)),
+              "conv_shallow_forward")
+        return out
+
+    def step(self, s: dict, deep: dict | None = None, shallow: dict | None = None):
+        st = self._state(s)
+        deep = deep or self.alloc_deep(st.ld)
+        shallow = shallow or self.alloc_shallow(st.ld)
+        d, h = self._deep_struct(deep), self._shallow_struct(shallow)
+        check(lib().conv_step(self.h, C.byref(st), C.byref(d), C.byref(h), _stream(self.torch)),
+              "conv_step")
+        return deep, shallow
+
+    # -- instrumentation -----------------------------------------------------------------
+    STAGES = ("reset", "trigger", "deep_plume", "shallow_plume")
+
+    def timing_start(self, max_calls: int):
+        check(lib().conv_timing_start(self.h, int(max_calls)), "conv_timing_start")
+
+    def timing_read(self):
+        ms = (C.c_double * 4)()
+        n = C.c_int(0)
+        check(lib().conv_timing_read(self.h, ms, C.byref(n)), "conv_timing_read")
+        return {s: ms[i] for i, s in enumerate(self.STAGES)}, n.value
