@@ -44,14 +44,12 @@ def kernel_bytes(L, n, trig, sh_status):
     written once, charged to the kernel that does it)."""
     b = bytes_per_column(L)
     quiet = trig == 0
-    sh_in_trigger = quiet & ~np.isin(sh_status, (0, 5))
-    sh_in_deep = (~quiet) & ~np.isin(sh_status, (0, 5))
-    sh_in_plume = np.isin(sh_status, (0, 5))
+    sh_done = ~np.isin(sh_status, (0, 5))
     return dict(
-        trigger=n * (b["inputs"] + b["deep_scalars"]) + quiet.sum() * b["deep_arrays"] +
-        sh_in_trigger.sum() * b["shallow"],
-        deep_plume=(~quiet).sum() * b["deep_arrays"] + sh_in_deep.sum() * b["shallow"],
-        shallow_plume=sh_in_plume.sum() * b["shallow"],
+        trigger=int(n * (b["inputs"] + b["deep_scalars"]) + quiet.sum() * b["deep_arrays"] +
+                    (quiet & sh_done).sum() * b["shallow"]),
+        deep_plume=int((~quiet).sum() * b["deep_arrays"] + ((~quiet) & sh_done).sum() * b["shallow"]),
+        shallow_plume=int((~sh_done).sum() * b["shallow"]),
         reset=0,
     )
 
@@ -72,6 +70,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--ncol", type=int, default=NLON * NLAT)
+    ap.add_argument("--launch", type=str, default="", help="deep,shallow plume blocks per CU")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="after timing, copy a MIB-MiB device buffer once (a plain copy kernel of "
+                         "known size for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the column-sharded design "
@@ -94,6 +96,8 @@ def main():
           file=sys.stderr, flush=True)
     dev = B.to_device(st)
     conv = B.Conv(n, NLEV)
+    if args.launch:
+        conv.set_launch(*[int(x) for x in args.launch.split(",")])
     deep = conv.alloc_deep(n)
     shallow = conv.alloc_shallow(n)
     torch.cuda.synchronize()
@@ -118,6 +122,15 @@ def main():
     kms, ncalls = conv.timing_read()
     conv.timing_start(0)
     kavg = {k: v / max(ncalls, 1) for k, v in kms.items()}
+
+    if args.calibrate_copy:
+        nb = args.calibrate_copy * (1 << 20)
+        src = torch.ones(nb // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     trig = deep["trig"].cpu().numpy()
     dst = deep["status"].cpu().numpy()
@@ -154,6 +167,7 @@ def main():
                           "achieved_GBs": step_bytes / (ms_step * 1e-3) / 1e9,
                           "frac": step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "kernels_ms": kavg,
+        "launch_blocks_per_cu": conv.get_launch(),
         "active_fraction": {"deep": float((dst == 0).mean()), "deep_triggered": float(trig.mean()),
                             "shallow": float((sst == 0).mean())},
         "wall_s_timed": wall,

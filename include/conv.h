@@ -124,11 +124,17 @@ int conv_shallow_forward(conv_ctx_t *ctx, const conv_state_t *state, conv_shallo
 int conv_step(conv_ctx_t *ctx, const conv_state_t *state, conv_deep_out_t *deep,
               conv_shallow_out_t *shallow, void *stream);
 
+/* Launch shape of the persistent kernels: blocks of 256 threads per compute unit for the
+ * deep-plume kernel and for the shallow-plume kernel (each 1..8; default 4 and 2).  The
+ * workspace size does not depend on it.  Results do not depend on it (bit-identical). */
+int conv_set_launch(conv_ctx_t *ctx, int fused_blocks_per_cu, int shallow_blocks_per_cu);
+int conv_get_launch(conv_ctx_t *ctx, int *fused_blocks_per_cu, int *shallow_blocks_per_cu);
+
 /* Instrumentation: record HIP events on the call's stream around each kernel of the next
  * `max_calls` calls (0 turns recording off).  conv_timing_read() waits for the recorded calls and
- * returns, per stage, the summed milliseconds over those calls in ms[0..3] (list reset, trigger
- * pass, deep plume pass, shallow plume pass) and the number of recorded calls in *ncalls.  Events
- * are host-side handles created here; no device memory is allocated. */
+ * returns, per stage, the summed milliseconds over those calls in ms[0..3] (counter reset, trigger
+ * pass, deep-plume pass, shallow-plume pass) and the number of recorded calls in *ncalls.
+ * Events are host-side handles created here; no device memory is allocated. */
 int conv_timing_start(conv_ctx_t *ctx, int max_calls);
 int conv_timing_read(conv_ctx_t *ctx, double *ms, int *ncalls);
 

@@ -26,7 +26,8 @@ DEFAULTS = dict(
 )
 
 EXPORTS = ("conv_workspace_bytes", "conv_create", "conv_set_params", "conv_destroy",
-           "conv_deep_forward", "conv_shallow_forward", "conv_step", "conv_timing_start",
+           "conv_deep_forward", "conv_shallow_forward", "conv_step", "conv_set_launch",
+           "conv_get_launch", "conv_timing_start",
            "conv_timing_read", "conv_strerror", "conv_last_hip_error")
 
 
@@ -78,6 +79,10 @@ def lib():
         L.conv_step.restype = C.c_int
         L.conv_step.argtypes = [C.c_void_p, C.POINTER(State), C.POINTER(DeepOut),
                                 C.POINTER(ShallowOut), C.c_void_p]
+        L.conv_set_launch.restype = C.c_int
+        L.conv_set_launch.argtypes = [C.c_void_p, C.c_int, C.c_int]
+        L.conv_get_launch.restype = C.c_int
+        L.conv_get_launch.argtypes = [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.conv_timing_start.restype = C.c_int
         L.conv_timing_start.argtypes = [C.c_void_p, C.c_int]
         L.conv_timing_read.restype = C.c_int
@@ -238,11 +243,20 @@ class Conv:
     # -- instrumentation -----------------------------------------------------------------
     STAGES = ("reset", "trigger", "deep_plume", "shallow_plume")
 
+    def set_launch(self, fused_blocks_per_cu: int, shallow_blocks_per_cu: int):
+        check(lib().conv_set_launch(self.h, int(fused_blocks_per_cu), int(shallow_blocks_per_cu)),
+              "conv_set_launch")
+
+    def get_launch(self):
+        a, b = C.c_int(0), C.c_int(0)
+        check(lib().conv_get_launch(self.h, C.byref(a), C.byref(b)), "conv_get_launch")
+        return a.value, b.value
+
     def timing_start(self, max_calls: int):
         check(lib().conv_timing_start(self.h, int(max_calls)), "conv_timing_start")
 
     def timing_read(self):
-        ms = (C.c_double * 4)()
+        ms = (C.c_double * len(self.STAGES))()
         n = C.c_int(0)
         check(lib().conv_timing_read(self.h, ms, C.byref(n)), "conv_timing_read")
         return {s: ms[i] for i, s in enumerate(self.STAGES)}, n.value

@@ -1,22 +1,25 @@
 // conv.hip -- gfx950 kernels and the C ABI (include/conv.h) of the FP64 deep + shallow convection
 // library.
 //
-// Pipeline of one step (the paper's Algorithm 1 order: deep, then shallow on the updated state):
-//   k_reset         zero the on-device list counters (a fill kernel, so the step stays capturable)
-//   k_trigger       one lane per column over all columns, one bottom-up sweep: validity, moist
-//                   static energy, launch layer (D1), the undilute parcel with CAPE and the closure's
-//                   parcel sensitivities (D2-D4), and the shallow source and parcel (S1-S6).  Columns
-//                   that do not convect get their exact-zero outputs here; columns that do are
-//                   compacted into on-device lists by wavefront ballot + popcount + one atomic per
-//                   wavefront, so the imbalance between convecting and quiet columns (the paper's
-//                   Methodology, "Load Balancing Convections") is removed by compaction rather than by
-//                   scheduling.
-//   k_deep_plume    persistent over the deep list: updraft (D5), downdraft (D6), flux-form unit
-//                   tendencies (D7), closure (D8), limiter (D9), outputs (D10); in a full step also the
-//                   shallow trigger on the deep-updated state.
-//   k_shallow_plume persistent over the shallow list: plume, tendencies, limiter (S7-S9).
+// One physics step (the paper's Algorithm 1 order: deep, then shallow on the updated state):
+//   k_reset          zero the on-device counters (a fill kernel, so a captured step replays).
+//   k_trigger        one lane per column, one bottom-up sweep over every level: validity, moist
+//                    static energy, the launch layer (D1), then the undilute parcel with CAPE and
+//                    the closure's parcel sensitivities (D2-D4) and the shallow source, parcel and
+//                    CIN (S1-S6).  Quiet columns get their exact-zero outputs at once; triggered
+//                    ones are compacted into an on-device list by wavefront ballot + popcount + one
+//                    atomic per wavefront, so the imbalance between convecting and quiet columns
+//                    (the paper's Methodology, "Load Balancing Convections") is removed by
+//                    compaction rather than by scheduling individual columns.
+//   k_deep_plume     persistent over the deep list, every lane busy: updraft (D5), downdraft (D6),
+//                    flux-form tendencies (D7), closure (D8), limiter (D9), outputs (D10), then the
+//                    shallow trigger on the deep-updated state.
+//   k_shallow_plume  persistent over the shallow list: plume, tendencies, limiter (S7-S9).
 // Per-level plume profiles live in a per-thread scratch region of the caller's workspace laid out
-// [array][level][thread], so a wavefront's accesses to one level are contiguous.
+// [array][level][thread], so a wavefront's accesses to one level are contiguous.  Level loops load
+// the next level's inputs before working on the current level.  Kernels are generic over a member
+// source: one grid (kernel argument) or an ensemble table of grids with their own level counts,
+// parameters and arrays (device memory) covered by the same launches.
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
@@ -31,34 +34,72 @@ namespace {
 
 constexpr int BLOCK = 256;
 constexpr int WAVE = 64;
-constexpr int PLUME_BLOCKS_PER_CU = 4;
+constexpr int NWAVES = BLOCK / WAVE;
 constexpr int NCOUNTERS = 64;
-constexpr int DEEP_SCR = 8;     // su, qu, c->dT1, sd, qd, e1->dq1, eta_d, eta
+constexpr int DEEP_SCR = 9;     // su, qu, c->dT1, sd, qd, e1->dq1, eta_d, eta, h
 constexpr int SHALLOW_SCR = 3;  // eta, dT1, dq1
+constexpr int CNT_DEEP = 0;
+constexpr int CNT_SHALLOW = 1;
 
-struct Work {
-    int *cnt;  // [0] deep list length, [1] shallow list length
-    int *dlist, *dkb, *dkt;
-    double *dcape, *dSA, *dSB;
-    int *slist, *sks, *sflag;
-    double *shs, *sqs, *scin, *sMc, *ssig2;
-    double *dscr, *sscr;
-    int64_t scr_stride;  // threads of the persistent grid
-};
-
-struct Args {
+// One grid of columns with its arrays and parameters.
+struct Member {
     const double *T, *q, *pm, *pi, *z, *phis, *pblh, *tke;
     int64_t ld;
     double dt;
     int64_t ncol;
-    int nlev;
+    int64_t tile0;  // first tile of this member in the launch's tile space
+    int nlev, pad_;
     conv_params_t P;
     conv_deep_out_t dout;
     conv_shallow_out_t sout;
-    Work w;
+};
+
+struct Work {
+    int *cnt;
+    int *dlist, *dmem, *dkb, *dkt;
+    double *dcape, *dSA, *dSB;
+    int *slist, *smem, *sks, *sflag;
+    double *shs, *sqs, *scin, *sMc, *ssig2;
+    double *dscr, *sscr;
+    int64_t dstride, sstride;  // threads of the fused / shallow-plume persistent grids
+    int lmax;                  // level capacity of the scratch
+};
+
+struct One {
+    Member m;
+    int64_t ntiles;
+    __device__ const Member &at(int) const { return m; }
+    __device__ int find(int64_t) const { return 0; }
+};
+
+struct Many {
+    const Member *ms;  // device table, ascending tile0
+    int nm;
+    int64_t ntiles;
+    __device__ const Member &at(int i) const { return ms[i]; }
+    __device__ int find(int64_t tile) const {
+        int i = 0;
+        while (i + 1 < nm && ms[i + 1].tile0 <= tile) ++i;
+        return i;
+    }
 };
 
 #define AT(arr, k) (arr)[(int64_t)(k) * ld + col]
+
+constexpr int SWEEP1_CHUNK = 6;
+
+// The inputs of one level of one column (pt = p_int at the level's top interface).
+struct Lev {
+    double T, q, pm, z, pt;
+};
+
+__device__ __forceinline__ void load_lev(Lev &v, const Member &M, int64_t ld, int64_t col, int k) {
+    v.T = AT(M.T, k);
+    v.q = AT(M.q, k);
+    v.pm = AT(M.pm, k);
+    v.z = AT(M.z, k);
+    v.pt = AT(M.pi, k);
+}
 
 // ------------------------------------------------------------------ wavefront compaction
 // Appends the lanes with `pred` set to the list counted by *counter: one ballot, one popcount and
@@ -79,6 +120,7 @@ struct ShallowTrigger {
     int ks, klcl, klfc;
     bool inpbl, act;
     double hsum, qsum, wsum, hs, qs, cin;
+    Hint hint;
 
     __device__ void init(int L) {
         ks = L - 1;
@@ -87,6 +129,7 @@ struct ShallowTrigger {
         klcl = klfc = -1;
         cin = 0.0;
         act = false;
+        hint.clear();
     }
     // S1, called bottom-up for k = L-1, L-2, ...: the contiguous run of layers with z <= pblh.
     __device__ void pbl(int k, int L, double z, double pblh, double h, double q, double dp) {
@@ -113,8 +156,9 @@ struct ShallowTrigger {
         }
         return true;
     }
-    __device__ void level(int k, const Lifted &r, double tve, double pm, double lam,
+    __device__ void level(int k, double z, double phis, double tve, double pm, double lam,
                           const conv_params_t &P) {
+        const Lifted r = lift(hs - GRAV * z - phis, qs, pm, hint);
         const double B = tv(r.T, r.qv) - tve;
         if (klcl < 0 && r.sat) klcl = k;
         if (klcl >= 0 && B > 0.0 && pm >= P.p_sh_top_min) {
@@ -134,48 +178,49 @@ struct ShallowTrigger {
     }
 };
 
-__device__ void write_shallow_zero(const Args &a, int64_t col, int st, double cin, int ks) {
-    const int L = a.nlev;
-    const int64_t ld = a.ld;
+__device__ void write_shallow_zero(const Member &M, int64_t col, int st, double cin, int ks) {
+    const int L = M.nlev;
+    const int64_t ld = M.ld;
     for (int k = 0; k < L; ++k) {
-        AT(a.sout.dTdt, k) = 0.0;
-        AT(a.sout.dqdt, k) = 0.0;
+        AT(M.sout.dTdt, k) = 0.0;
+        AT(M.sout.dqdt, k) = 0.0;
     }
-    for (int k = 0; k <= L; ++k) AT(a.sout.mu, k) = 0.0;
-    a.sout.prec[col] = 0.0;
-    a.sout.cin[col] = (st == 3 || st == 4) ? cin : 0.0;
-    a.sout.kbase[col] = (st == 6) ? -1 : ks;
-    a.sout.ktop[col] = -1;
-    a.sout.status[col] = st;
+    for (int k = 0; k <= L; ++k) AT(M.sout.mu, k) = 0.0;
+    M.sout.prec[col] = 0.0;
+    M.sout.cin[col] = (st == 3 || st == 4) ? cin : 0.0;
+    M.sout.kbase[col] = (st == 6) ? -1 : ks;
+    M.sout.ktop[col] = -1;
+    M.sout.status[col] = st;
 }
 
-__device__ void write_deep_zero(const Args &a, int64_t col) {
-    const int L = a.nlev;
-    const int64_t ld = a.ld;
+__device__ void write_deep_zero(const Member &M, int64_t col) {
+    const int L = M.nlev;
+    const int64_t ld = M.ld;
     for (int k = 0; k < L; ++k) {
-        AT(a.dout.dTdt, k) = 0.0;
-        AT(a.dout.dqdt, k) = 0.0;
+        AT(M.dout.dTdt, k) = 0.0;
+        AT(M.dout.dqdt, k) = 0.0;
     }
     for (int k = 0; k <= L; ++k) {
-        AT(a.dout.mu, k) = 0.0;
-        AT(a.dout.md, k) = 0.0;
+        AT(M.dout.mu, k) = 0.0;
+        AT(M.dout.md, k) = 0.0;
     }
-    a.dout.prec[col] = 0.0;
+    M.dout.prec[col] = 0.0;
 }
 
-// Stores the closure inputs of a shallow column that passed S1-S6 and appends it to the list.
-__device__ void shallow_enqueue(const Args &a, int slot, int64_t col, const ShallowTrigger &s,
-                                double rho_s, double tke, int updated) {
-    const double sigw2 = a.P.c_tke * tke;
+// Stores the closure inputs of a shallow column that passed S1-S6 in list slot `slot`.
+__device__ void shallow_enqueue(const Member &M, const Work &w, int slot, int mi, int64_t col,
+                                const ShallowTrigger &s, double rho_s, double tke, int updated) {
+    const double sigw2 = M.P.c_tke * tke;
     const double sigw = sqrt(sigw2);
-    a.w.slist[slot] = (int)col;
-    a.w.sks[slot] = s.ks;
-    a.w.sflag[slot] = updated;
-    a.w.shs[slot] = s.hs;
-    a.w.sqs[slot] = s.qs;
-    a.w.scin[slot] = s.cin;
-    a.w.ssig2[slot] = sigw2;
-    a.w.sMc[slot] = rho_s * sigw / SQRT_2PI * exp(-a.P.a_buoy * s.cin / sigw2);
+    w.slist[slot] = (int)col;
+    w.smem[slot] = mi;
+    w.sks[slot] = s.ks;
+    w.sflag[slot] = updated;
+    w.shs[slot] = s.hs;
+    w.sqs[slot] = s.qs;
+    w.scin[slot] = s.cin;
+    w.ssig2[slot] = sigw2;
+    w.sMc[slot] = rho_s * sigw / SQRT_2PI * exp(-M.P.a_buoy * s.cin / sigw2);
 }
 
 // ------------------------------------------------------------------ kernels
@@ -183,13 +228,19 @@ __global__ void k_reset(int *cnt) {
     if (threadIdx.x < NCOUNTERS) cnt[threadIdx.x] = 0;
 }
 
-template <bool DEEP, bool SHALLOW>
-__global__ __launch_bounds__(BLOCK) void k_trigger(Args a) {
-    const int64_t col = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    const bool live = col < a.ncol;
-    const int L = a.nlev;
-    const int64_t ld = a.ld;
-    const conv_params_t &P = a.P;
+// Trigger pass: one lane per column; block b covers tile b of the launch's tile space.  Every
+// level loop loads the next level's inputs before working on the current one, so the loads of a
+// level are in flight during the previous level's Newton solves.
+template <class Src, bool DEEP, bool SHALLOW>
+__global__ __launch_bounds__(BLOCK) void k_trigger(Src src, Work w) {
+    const int64_t tile = blockIdx.x;
+    const int mi = src.find(tile);
+    const Member &M = src.at(mi);
+    const int L = M.nlev;
+    const int64_t ld = M.ld;
+    const conv_params_t &P = M.P;
+    const int64_t col = (tile - M.tile0) * BLOCK + threadIdx.x;
+    const bool live = col < M.ncol;
 
     bool valid = live;
     double phis = 0.0, pblh = 0.0, tke = 0.0;
@@ -198,63 +249,73 @@ __global__ __launch_bounds__(BLOCK) void k_trigger(Args a) {
     ShallowTrigger sh;
     sh.init(L);
 
-    // Sweep 1 (bottom-up, every level): validity, h, launch layer, top limit, boundary layer.
+    // Sweep 1 (bottom-up, every level): validity, h, launch layer, top limit, PBL.  Levels are
+    // loaded SWEEP1_CHUNK at a time so a wavefront has that many levels of loads in flight.
     if (live) {
-        phis = a.phis[col];
+        phis = M.phis[col];
         if (SHALLOW) {
-            pblh = a.pblh[col];
-            tke = a.tke[col];
+            pblh = M.pblh[col];
+            tke = M.tke[col];
         }
         valid = isfinite(phis);
-        double pbot = AT(a.pi, L);
+        double pbot = AT(M.pi, L);
         double zbelow = 0.0;
-        for (int k = L - 1; k >= 0; --k) {
-            const double T = AT(a.T, k), q = AT(a.q, k), pm = AT(a.pm, k), z = AT(a.z, k);
-            const double pt = AT(a.pi, k);
-            valid = valid && isfinite(T) && isfinite(q) && isfinite(pm) && isfinite(z) &&
-                    isfinite(pbot) && T > 100.0 && T < 400.0 && q >= 0.0 && q < 1.0 && pt < pm &&
-                    pm < pbot && (k == L - 1 ? z > 0.0 : z > zbelow);
-            const double h = (CP * T + GRAV * z + phis) + LV * q;
-            if (DEEP && pm >= P.p_launch_min && (kb < 0 || h > hkb)) {
-                kb = k;
-                hkb = h;
-                qkb = q;
+        for (int k0 = L - 1; k0 >= 0; k0 -= SWEEP1_CHUNK) {
+            Lev v[SWEEP1_CHUNK];
+#pragma unroll
+            for (int j = 0; j < SWEEP1_CHUNK; ++j) load_lev(v[j], M, ld, col, max(k0 - j, 0));
+#pragma unroll
+            for (int j = 0; j < SWEEP1_CHUNK; ++j) {
+                const int k = k0 - j;
+                if (k < 0) break;
+                const double T = v[j].T, q = v[j].q, pm = v[j].pm, z = v[j].z, pt = v[j].pt;
+                valid = valid && isfinite(T) && isfinite(q) && isfinite(pm) && isfinite(z) &&
+                        isfinite(pbot) && T > 100.0 && T < 400.0 && q >= 0.0 && q < 1.0 &&
+                        pt < pm && pm < pbot && (k == L - 1 ? z > 0.0 : z > zbelow);
+                const double h = (CP * T + GRAV * z + phis) + LV * q;
+                if (DEEP && pm >= P.p_launch_min && (kb < 0 || h > hkb)) {
+                    kb = k;
+                    hkb = h;
+                    qkb = q;
+                }
+                if (pm >= P.p_top_min) klim = k;
+                if (SHALLOW) sh.pbl(k, L, z, pblh, h, q, pbot - pt);
+                zbelow = z;
+                pbot = pt;
             }
-            if (pm >= P.p_top_min) klim = k;
-            if (SHALLOW) sh.pbl(k, L, z, pblh, h, q, pbot - pt);
-            zbelow = z;
-            pbot = pt;
         }
         valid = valid && isfinite(pbot) && pbot > 0.0;
     }
     const bool svalid = valid && (!SHALLOW || (isfinite(pblh) && isfinite(tke)));
 
-    // Sweep 2 (bottom-up): deep parcel from kb (D2-D4) and shallow parcel from the source
-    // (S2-S5), both evaluated at each layer they need.
+    // Sweep 2 (bottom-up): deep parcel from kb (D2-D4), shallow parcel from the source (S2-S5),
+    // each at the layers it needs.
     const bool dscan = DEEP && valid && kb >= 0 && klim >= 0 && klim < kb;
     int kt = -1;
     double S = 0.0, SA = 0.0, SB = 0.0, Skt = 0.0, SAkt = 0.0, SBkt = 0.0;
+    Hint hd;
+    hd.clear();
     if (SHALLOW && svalid) sh.start();
     if (dscan || (SHALLOW && sh.act)) {
-        for (int k = L - 2; k >= 0; --k) {
+        const int k0 = L - 2;
+        double lpb = log(AT(M.pi, k0 + 1));  // ln p_int below the current layer
+        // One level of the combined scan; false once neither scan needs a higher level.
+        auto step = [&](const Lev &v, int k) -> bool {
+            const double lpt = log(v.pt);
+            const double lam = lpb - lpt;
+            lpb = lpt;
             const bool dd = dscan && k < kb && k >= klim;
-            const double pm = AT(a.pm, k);
-            const bool ss = SHALLOW && sh.wants(k, pm, P);
-            if (!dd && !ss) {
-                if ((!dscan || k < klim) && !(SHALLOW && sh.act)) break;
-                continue;
-            }
-            const double T = AT(a.T, k), q = AT(a.q, k), z = AT(a.z, k);
-            const double lam = log(AT(a.pi, k + 1) / AT(a.pi, k));
-            const double tve = tv(T, q);
+            const bool ss = SHALLOW && sh.wants(k, v.pm, P);
+            if (!dd && !ss) return !((!dscan || k < klim) && !(SHALLOW && sh.act));
+            const double tve = tv(v.T, v.q);
             if (dd) {
-                const Lifted r = lift(hkb - GRAV * z - phis, qkb, pm);
+                const Lifted r = lift(hkb - GRAV * v.z - phis, qkb, v.pm, hd);
                 const double B = tv(r.T, r.qv) - tve;
                 S += RD * B * lam;
                 double ca, cb;
                 if (r.sat) {
                     const double c = (1.0 + CVIR * r.qv) + CVIR * r.T * r.dqs;
-                    const double rden = 1.0 / (CP + LV * r.dqs);
+                    const double rden = frcp(CP + LV * r.dqs);
                     ca = c * CP * rden;
                     cb = c * LV * rden;
                 } else {
@@ -270,14 +331,23 @@ __global__ __launch_bounds__(BLOCK) void k_trigger(Args a) {
                     SBkt = SB;
                 }
             }
-            if (ss) {
-                const Lifted r = lift(sh.hs - GRAV * z - phis, sh.qs, pm);
-                sh.level(k, r, tve, pm, lam, P);
-            }
+            if (ss) sh.level(k, v.z, phis, tve, v.pm, lam, P);
+            return true;
+        };
+        // Two level buffers: level k-1 loads while level k is worked on.
+        // Loads are unconditional (level index clamped at 0) so the wait counts stay exact.
+        Lev A, B;
+        load_lev(A, M, ld, col, k0);
+        for (int k = k0; k >= 0; k -= 2) {
+            load_lev(B, M, ld, col, max(k - 1, 0));
+            if (!step(A, k) || k == 0) break;
+            load_lev(A, M, ld, col, max(k - 2, 0));
+            if (!step(B, k - 1)) break;
         }
     }
 
-    // Deep epilogue (D4): trigger; quiet columns get their zeros, triggered ones are compacted.
+    // Deep epilogue (D4): quiet columns get their zeros; triggered ones are compacted into the
+    // deep list with what the plume pass needs.
     bool trig = false;
     if (DEEP) {
         double cape = 0.0;
@@ -292,21 +362,22 @@ __global__ __launch_bounds__(BLOCK) void k_trigger(Args a) {
             st = trig ? 0 : 1;
         }
         if (live) {
-            a.dout.cape[col] = cape;
-            a.dout.klaunch[col] = kb;
-            a.dout.ktop[col] = dscan ? kt : -1;
-            a.dout.trig[col] = trig ? 1 : 0;
-            a.dout.status[col] = st;
-            if (!trig) write_deep_zero(a, col);
+            M.dout.cape[col] = cape;
+            M.dout.klaunch[col] = kb;
+            M.dout.ktop[col] = dscan ? kt : -1;
+            M.dout.trig[col] = trig ? 1 : 0;
+            M.dout.status[col] = st;
+            if (!trig) write_deep_zero(M, col);
         }
-        const int slot = wave_append(live && trig, &a.w.cnt[0]);
+        const int slot = wave_append(live && trig, &w.cnt[CNT_DEEP]);
         if (slot >= 0) {
-            a.w.dlist[slot] = (int)col;
-            a.w.dkb[slot] = kb;
-            a.w.dkt[slot] = kt;
-            a.w.dcape[slot] = cape;
-            a.w.dSA[slot] = SAkt;
-            a.w.dSB[slot] = SBkt;
+            w.dlist[slot] = (int)col;
+            w.dmem[slot] = mi;
+            w.dkb[slot] = kb;
+            w.dkt[slot] = kt;
+            w.dcape[slot] = cape;
+            w.dSA[slot] = SAkt;
+            w.dSB[slot] = SBkt;
         }
     }
 
@@ -317,114 +388,144 @@ __global__ __launch_bounds__(BLOCK) void k_trigger(Args a) {
         double rho_s = 0.0;
         if (mine) {
             st = svalid ? sh.status(tke, P) : 6;
-            if (st < 0) rho_s = AT(a.pi, sh.ks) / (RD * tv(AT(a.T, sh.ks), AT(a.q, sh.ks)));
-            else write_shallow_zero(a, col, st, sh.cin, sh.ks);
+            if (st < 0)
+                rho_s = AT(M.pi, sh.ks) / (RD * tv(AT(M.T, sh.ks), AT(M.q, sh.ks)));
+            else
+                write_shallow_zero(M, col, st, sh.cin, sh.ks);
         }
-        const int slot = wave_append(mine && st < 0, &a.w.cnt[1]);
-        if (slot >= 0) shallow_enqueue(a, slot, col, sh, rho_s, tke, 0);
+        const int slot = wave_append(mine && st < 0, &w.cnt[CNT_SHALLOW]);
+        if (slot >= 0) shallow_enqueue(M, w, slot, mi, col, sh, rho_s, tke, 0);
     }
 }
 
-template <bool SHALLOW>
-__global__ __launch_bounds__(BLOCK) void k_deep_plume(Args a) {
-    const int n = a.w.cnt[0];
-    const int L = a.nlev;
-    const int64_t ld = a.ld;
-    const conv_params_t &P = a.P;
-    const int64_t tid = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+// Deep plume pass, persistent over the deep list (wavefront-uniform loop: every lane of a
+// wavefront iterates together so the shallow list's ballot is convergent).
+template <class Src, bool SHALLOW>
+__global__ __launch_bounds__(BLOCK) void k_deep_plume(Src src, Work w) {
+    const int n = w.cnt[CNT_DEEP];
+    const int64_t gtid = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     const int64_t nthreads = (int64_t)gridDim.x * BLOCK;
-    const int64_t stride = a.w.scr_stride;
-    double *scr = a.w.dscr;
-#define SCR(arr, lev) scr[((int64_t)(arr) * (L + 1) + (lev)) * stride + tid]
+    double *scr = w.dscr;
+#define SCR(arr, lev) scr[((int64_t)(arr) * (w.lmax + 1) + (lev)) * w.dstride + gtid]
 
-    // Wavefront-uniform loop: every lane of a wavefront iterates together (for the ballot).
-    const int64_t wave0 = tid - (threadIdx.x % WAVE);
+    const int64_t wave0 = gtid - (threadIdx.x % WAVE);
     for (int64_t base = wave0; base < n; base += nthreads) {
         const int64_t slot = base + (threadIdx.x % WAVE);
         const bool act = slot < n;
+        const int mi = act ? w.dmem[slot] : 0;
+        const Member &M = src.at(mi);
+        const int L = M.nlev;
+        const int64_t ld = M.ld;
+        const conv_params_t &P = M.P;
         int64_t col = 0;
         int st = 0, kb = 0, kt = 0;
         double Mb = 0.0;
         if (act) {
-            col = a.w.dlist[slot];
-            kb = a.w.dkb[slot];
-            kt = a.w.dkt[slot];
-            const double cape = a.w.dcape[slot];
-            const double SA = a.w.dSA[slot], SB = a.w.dSB[slot];
-            const double phis = a.phis[col];
+            col = w.dlist[slot];
+            kb = w.dkb[slot];
+            kt = w.dkt[slot];
+            const double cape = w.dcape[slot];
+            const double SA = w.dSA[slot], SB = w.dSB[slot];
+            const double phis = M.phis[col];
             const double epsd = P.eps_deep;
-            auto zi = [&](int i) { return 0.5 * (AT(a.z, i - 1) + AT(a.z, i)); };
-            auto hk = [&](int k) {
-                return (CP * AT(a.T, k) + GRAV * AT(a.z, k) + phis) + LV * AT(a.q, k);
-            };
 
-            // D5: updraft, interfaces kb .. kt+1.
-            const double qkb = AT(a.q, kb);
-            double hu = hk(kb);
-            double eta = 1.0, C1;
+            // D5: updraft, interfaces kb .. kt+1.  At interface k the plume needs layer k's T, q, z
+            // (entrained air), z[k-1] (interface height) and p_int[k]; the next interface's values
+            // are loaded one step ahead.
+            Hint hu;
+            hu.clear();
+            const double qkb = AT(M.q, kb);
+            double zk1 = AT(M.z, kb);  // z of the layer below the current interface
+            double zup = AT(M.z, kb - 1);
+            double hu_m = (CP * AT(M.T, kb) + GRAV * zk1 + phis) + LV * qkb;
+            double zlo = 0.5 * (zup + zk1);
+            double C1, qup;
             {
-                const double zb = zi(kb);
-                const Lifted r = lift(hu - GRAV * zb - phis, qkb, AT(a.pi, kb));
-                SCR(0, kb) = CP * r.T + GRAV * zb + phis;
+                const Lifted r = lift(hu_m - GRAV * zlo - phis, qkb, AT(M.pi, kb), hu);
+                qup = r.qv;
+                SCR(0, kb) = CP * r.T + GRAV * zlo + phis;
                 SCR(1, kb) = r.qv;
                 C1 = qkb - r.qv;
                 SCR(2, kb) = C1;
                 SCR(7, kb) = 1.0;
+                SCR(8, kb) = hu_m;  // h of the launch layer
             }
-            double qup = SCR(1, kb);
-            double zlo = zi(kb);
-            for (int k = kb - 1; k >= kt + 1; --k) {
-                const double zk = zi(k);
-                const double E = epsd * eta * (zk - zlo);
-                const double etan = eta + E;
-                const double hm = (eta * hu + E * hk(k)) / etan;
-                const double qm = (eta * qup + E * AT(a.q, k)) / etan;
-                const Lifted r = lift(hm - GRAV * zk - phis, qm, AT(a.pi, k));
-                const double c = etan * (qm - r.qv);
-                SCR(0, k) = CP * r.T + GRAV * zk + phis;
-                SCR(1, k) = r.qv;
-                SCR(2, k) = c;
-                SCR(7, k) = etan;
-                C1 += c;
-                eta = etan;
-                hu = hm;
-                qup = r.qv;
-                zlo = zk;
+            double eta = 1.0;
+            {
+                // Loads are unconditional (level index clamped at 0) so the wait counts stay exact.
+                int k = kb - 1;
+                double Tn = AT(M.T, k), qn = AT(M.q, k), zn = zup, zn2 = AT(M.z, max(k - 1, 0)),
+                       pn = AT(M.pi, k);
+                for (; k >= kt + 1; --k) {
+                    const double Tk = Tn, qk = qn, zkk = zn, zabove = zn2, pik = pn;
+                    Tn = AT(M.T, k - 1);
+                    qn = AT(M.q, k - 1);
+                    zn = zabove;
+                    zn2 = AT(M.z, max(k - 2, 0));
+                    pn = AT(M.pi, k - 1);
+                    const double zk = 0.5 * (zabove + zkk);
+                    const double hkk = (CP * Tk + GRAV * zkk + phis) + LV * qk;
+                    const double E = epsd * eta * (zk - zlo);
+                    const double etan = eta + E;
+                    const double hm = (eta * hu_m + E * hkk) / etan;
+                    const double qm = (eta * qup + E * qk) / etan;
+                    const Lifted r = lift(hm - GRAV * zk - phis, qm, pik, hu);
+                    const double c = etan * (qm - r.qv);
+                    SCR(0, k) = CP * r.T + GRAV * zk + phis;
+                    SCR(1, k) = r.qv;
+                    SCR(2, k) = c;
+                    SCR(7, k) = etan;
+                    SCR(8, k) = hkk;
+                    C1 += c;
+                    eta = etan;
+                    hu_m = hm;
+                    qup = r.qv;
+                    zlo = zk;
+                }
             }
 
-            // D6: downdraft from the minimum-h layer between top and base.
+            // D6: saturated downdraft from the minimum-h layer between top and base (h of the
+            // layers kt+1 .. kb-1 was kept by the updraft pass).
             int kd = -1;
             double alpha = 0.0;
             if (kb - kt >= 2) {
                 kd = kt + 1;
-                double hkd = hk(kd);
+                double hkd = SCR(8, kd);
                 for (int k = kt + 2; k <= kb - 1; ++k) {
-                    const double h = hk(k);
+                    const double h = SCR(8, k);
                     if (h < hkd) {
                         kd = k;
                         hkd = h;
                     }
                 }
+                Hint hdn;
+                hdn.clear();
                 double ad = 1.0, hd = hkd;
-                int i = kd + 1;
-                double zii = zi(i);
+                double zii = 0.5 * (AT(M.z, kd) + AT(M.z, kd + 1));
                 Sat s;
                 double H = hd - GRAV * zii - phis;
-                double Td = tsat(H, AT(a.pi, i), (H - LV * AT(a.q, kd)) * (1.0 / CP), s);
+                double Td = tsat_h(H, AT(M.pi, kd + 1), (H - LV * AT(M.q, kd)) * RCP_CP, s, hdn);
                 double qd = s.qs;
-                SCR(3, i) = CP * Td + GRAV * zii + phis;
-                SCR(4, i) = qd;
-                SCR(6, i) = -ad;
-                double E1 = qd - AT(a.q, kd);
+                SCR(3, kd + 1) = CP * Td + GRAV * zii + phis;
+                SCR(4, kd + 1) = qd;
+                SCR(6, kd + 1) = -ad;
+                double E1 = qd - AT(M.q, kd);
                 SCR(5, kd) = E1;
-                for (int k = kd + 1; k <= kb - 1; ++k) {
-                    const double zlow = zi(k + 1);
+                int k = kd + 1;
+                double qn = AT(M.q, k), hn = SCR(8, k), zn = AT(M.z, min(k + 1, L - 1)),
+                       pn = AT(M.pi, k + 1);
+                for (; k <= kb - 1; ++k) {
+                    const double qk = qn, hkk = hn, zbelow = zn, pbel = pn;
+                    qn = AT(M.q, k + 1);
+                    hn = SCR(8, k + 1);
+                    zn = AT(M.z, min(k + 2, L - 1));
+                    pn = AT(M.pi, min(k + 2, L));
+                    const double zlow = 0.5 * (AT(M.z, k) + zbelow);
                     const double Ed = epsd * ad * (zii - zlow);
                     const double adn = ad + Ed;
-                    const double qk = AT(a.q, k);
-                    hd = (ad * hd + Ed * hk(k)) / adn;
+                    hd = (ad * hd + Ed * hkk) / adn;
                     H = hd - GRAV * zlow - phis;
-                    Td = tsat(H, AT(a.pi, k + 1), (H - LV * qk) * (1.0 / CP), s);
+                    Td = tsat_h(H, pbel, (H - LV * qk) * RCP_CP, s, hdn);
                     const double e1 = adn * s.qs - ad * qd - Ed * qk;
                     SCR(5, k) = e1;
                     SCR(3, k + 1) = CP * Td + GRAV * zlow + phis;
@@ -439,46 +540,77 @@ __global__ __launch_bounds__(BLOCK) void k_deep_plume(Args a) {
                 if (P.alpha_dd * E1 > P.evap_max_frac * C1) alpha = P.evap_max_frac * C1 / E1;
             }
 
-            // D7 + D8/D9 accumulations: top-down over layers kt .. kb.
+            // D7 with the D8/D9 accumulations: top-down over layers kt .. kb, two level buffers.
             double Fs_top = 0.0, Fq_top = 0.0, P1 = 0.0, Fenv = 0.0;
             double Mlim = __builtin_inf();
             double dT1 = 0.0, dq1 = 0.0;
-            for (int k = kt; k <= kb; ++k) {
+            double pi_top = AT(M.pi, kt);
+            struct TL {
+                double T, q, z, pib, et, ed, su, qu, sd, qd, c, e1;
+            };
+            auto load_tl = [&](TL &t, int k) {
+                const int kk = min(k, kb);
+                const int i = kk + 1;
+                t.T = AT(M.T, kk);
+                t.q = AT(M.q, kk);
+                t.z = AT(M.z, kk);
+                t.pib = AT(M.pi, i);
+                t.et = SCR(7, i);
+                t.ed = SCR(6, i);
+                t.su = SCR(0, i);
+                t.qu = SCR(1, i);
+                t.sd = SCR(3, i);
+                t.qd = SCR(4, i);
+                t.c = SCR(2, kk);
+                t.e1 = SCR(5, kk);
+            };
+            auto proc = [&](const TL &t, int k) {
                 double Fs = 0.0, Fq = 0.0;
                 const int i = k + 1;
                 if (i <= kb) {
-                    const double et = SCR(7, i);
                     const bool dn = kd >= 0 && i >= kd + 1;
-                    const double ed = dn ? SCR(6, i) : 0.0;
-                    const int up = (et + alpha * ed >= 0.0) ? i - 1 : i;
-                    const double s_up = CP * AT(a.T, up) + GRAV * AT(a.z, up) + phis;
-                    const double q_up = AT(a.q, up);
-                    Fs = et * (SCR(0, i) - s_up);
-                    Fq = et * (SCR(1, i) - q_up);
+                    const double ed = dn ? t.ed : 0.0;
+                    const bool upw = t.et + alpha * ed >= 0.0;
+                    const double s_up = upw ? CP * t.T + GRAV * t.z + phis
+                                            : CP * AT(M.T, i) + GRAV * AT(M.z, i) + phis;
+                    const double q_up = upw ? t.q : AT(M.q, i);
+                    Fs = t.et * (t.su - s_up);
+                    Fq = t.et * (t.qu - q_up);
                     if (dn) {
-                        Fs += alpha * ed * (SCR(3, i) - s_up);
-                        Fq += alpha * ed * (SCR(4, i) - q_up);
+                        Fs += alpha * ed * (t.sd - s_up);
+                        Fq += alpha * ed * (t.qd - q_up);
                     }
                 }
-                const double c = (k >= kt + 1) ? SCR(2, k) : 0.0;
-                const double e1 = (kd >= 0 && k >= kd && k <= kb - 1) ? SCR(5, k) : 0.0;
+                const double c = (k >= kt + 1) ? t.c : 0.0;
+                const double e1 = (kd >= 0 && k >= kd && k <= kb - 1) ? t.e1 : 0.0;
                 const double net = c - alpha * e1;
-                const double dp = AT(a.pi, k + 1) - AT(a.pi, k);
+                const double dp = t.pib - pi_top;
                 dT1 = (Fs - Fs_top + LV * net) * GRAV / (CP * dp);
                 dq1 = (Fq - Fq_top - net) * GRAV / dp;
                 SCR(2, k) = dT1;
                 SCR(5, k) = dq1;
                 P1 += net;
-                const double Tk = AT(a.T, k), qk = AT(a.q, k);
                 if (k <= kb - 1) {
-                    const double lam = log(AT(a.pi, k + 1) / AT(a.pi, k));
-                    Fenv += lam * ((1.0 + CVIR * qk) * dT1 + CVIR * Tk * dq1);
+                    const double lam = log(t.pib / pi_top);
+                    Fenv += lam * ((1.0 + CVIR * t.q) * dT1 + CVIR * t.T * dq1);
                 }
-                if (dq1 < 0.0) Mlim = fmin(Mlim, qk / (-a.dt * dq1));
+                if (dq1 < 0.0) Mlim = fmin(Mlim, t.q / (-M.dt * dq1));
                 Fs_top = Fs;
                 Fq_top = Fq;
+                pi_top = t.pib;
+            };
+            {
+                TL A, B;
+                load_tl(A, kt);
+                for (int k = kt; k <= kb; k += 2) {
+                    load_tl(B, k + 1);
+                    proc(A, k);
+                    if (k + 1 > kb) break;
+                    load_tl(A, k + 2);
+                    proc(B, k + 1);
+                }
             }
-            // D8: F from the launch-layer tendencies and the parcel sensitivities of the trigger.
+            // D8: F from the launch-layer tendencies and the trigger's parcel sensitivities.
             const double F = -RD * (dT1 * SA + dq1 * SB - Fenv);
             if (!(F > 0.0)) {
                 st = 2;
@@ -486,20 +618,20 @@ __global__ __launch_bounds__(BLOCK) void k_deep_plume(Args a) {
                 const double Mc = cape / (P.tau * F);
                 Mb = Mc <= Mlim ? Mc : Mlim;
             }
-            // D10: write every level of this column.
+            // D10: every level of the column.
             for (int k = 0; k < L; ++k) {
                 const bool in = st == 0 && k >= kt && k <= kb;
-                AT(a.dout.dTdt, k) = in ? Mb * SCR(2, k) : 0.0;
-                AT(a.dout.dqdt, k) = in ? Mb * SCR(5, k) : 0.0;
+                AT(M.dout.dTdt, k) = in ? Mb * SCR(2, k) : 0.0;
+                AT(M.dout.dqdt, k) = in ? Mb * SCR(5, k) : 0.0;
             }
             for (int i = 0; i <= L; ++i) {
                 const bool in = st == 0 && i >= kt + 1 && i <= kb;
                 const bool dn = in && kd >= 0 && i >= kd + 1;
-                AT(a.dout.mu, i) = in ? Mb * SCR(7, i) : 0.0;
-                AT(a.dout.md, i) = dn ? Mb * (alpha * SCR(6, i)) : 0.0;
+                AT(M.dout.mu, i) = in ? Mb * SCR(7, i) : 0.0;
+                AT(M.dout.md, i) = dn ? Mb * (alpha * SCR(6, i)) : 0.0;
             }
-            a.dout.prec[col] = st == 0 ? Mb * P1 : 0.0;
-            a.dout.status[col] = st;
+            M.dout.prec[col] = st == 0 ? Mb * P1 : 0.0;
+            M.dout.status[col] = st;
         }
 
         if (SHALLOW) {
@@ -509,101 +641,105 @@ __global__ __launch_bounds__(BLOCK) void k_deep_plume(Args a) {
             int sst = -1;
             double rho_s = 0.0, tke = 0.0;
             if (act) {
-                const double phis = a.phis[col];
-                const double pblh = a.pblh[col];
-                tke = a.tke[col];
+                const double phis = M.phis[col];
+                const double pblh = M.pblh[col];
+                tke = M.tke[col];
                 const bool conv = st == 0;
                 auto Tn = [&](int k) {
-                    return (conv && k >= kt && k <= kb) ? AT(a.T, k) + a.dt * (Mb * SCR(2, k))
-                                                        : AT(a.T, k);
+                    return (conv && k >= kt && k <= kb) ? AT(M.T, k) + M.dt * (Mb * SCR(2, k))
+                                                        : AT(M.T, k);
                 };
                 auto qn = [&](int k) {
-                    return (conv && k >= kt && k <= kb) ? AT(a.q, k) + a.dt * (Mb * SCR(5, k))
-                                                        : AT(a.q, k);
+                    return (conv && k >= kt && k <= kb) ? AT(M.q, k) + M.dt * (Mb * SCR(5, k))
+                                                        : AT(M.q, k);
                 };
-                const bool svalid = isfinite(pblh) && isfinite(tke);
-                if (svalid) {
-                    double pbot = AT(a.pi, L);
+                if (isfinite(pblh) && isfinite(tke)) {
+                    double pbot = AT(M.pi, L);
                     for (int k = L - 1; k >= 0 && (k == L - 1 || sh.inpbl); --k) {
-                        const double pt = AT(a.pi, k), z = AT(a.z, k), q = qn(k);
-                        sh.pbl(k, L, z, pblh, (CP * Tn(k) + GRAV * z + phis) + LV * q, q,
-                               pbot - pt);
+                        const double pt = AT(M.pi, k), z = AT(M.z, k), q = qn(k);
+                        sh.pbl(k, L, z, pblh, (CP * Tn(k) + GRAV * z + phis) + LV * q, q, pbot - pt);
                         pbot = pt;
                     }
                     sh.start();
-                    for (int k = sh.ks - 1; k >= 0; --k) {
-                        const double pm = AT(a.pm, k);
+                    int k = sh.ks - 1;
+                    const int k0 = max(k, 0);
+                    double pmn = AT(M.pm, k0), zn = AT(M.z, k0), Tnn = Tn(k0), qnn = qn(k0),
+                           ptn = AT(M.pi, k0), pbn = AT(M.pi, k0 + 1);
+                    for (; k >= 0; --k) {
+                        const double pm = pmn, z = zn, Tk = Tnn, qk = qnn, pt = ptn, pb = pbn;
                         if (!sh.wants(k, pm, P)) break;
-                        const double z = AT(a.z, k);
-                        const double lam = log(AT(a.pi, k + 1) / AT(a.pi, k));
-                        const Lifted r = lift(sh.hs - GRAV * z - phis, sh.qs, pm);
-                        sh.level(k, r, tv(Tn(k), qn(k)), pm, lam, P);
+                        const int kn = max(k - 1, 0);
+                        pmn = AT(M.pm, kn);
+                        zn = AT(M.z, kn);
+                        Tnn = Tn(kn);
+                        qnn = qn(kn);
+                        ptn = AT(M.pi, kn);
+                        pbn = pt;
+                        sh.level(k, z, phis, tv(Tk, qk), pm, log(pb / pt), P);
                     }
                     sst = sh.status(tke, P);
                 } else {
                     sst = 6;
                 }
                 if (sst < 0)
-                    rho_s = AT(a.pi, sh.ks) / (RD * tv(Tn(sh.ks), qn(sh.ks)));
+                    rho_s = AT(M.pi, sh.ks) / (RD * tv(Tn(sh.ks), qn(sh.ks)));
                 else
-                    write_shallow_zero(a, col, sst, sh.cin, sh.ks);
+                    write_shallow_zero(M, col, sst, sh.cin, sh.ks);
             }
-            const int sslot = wave_append(act && sst < 0, &a.w.cnt[1]);
-            if (sslot >= 0) shallow_enqueue(a, sslot, col, sh, rho_s, tke, 1);
+            const int sslot = wave_append(act && sst < 0, &w.cnt[CNT_SHALLOW]);
+            if (sslot >= 0) shallow_enqueue(M, w, sslot, mi, col, sh, rho_s, tke, 1);
         }
     }
 #undef SCR
 }
 
-__global__ __launch_bounds__(BLOCK) void k_shallow_plume(Args a) {
-    const int n = a.w.cnt[1];
-    const int L = a.nlev;
-    const int64_t ld = a.ld;
-    const conv_params_t &P = a.P;
-    const int64_t tid = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+template <class Src>
+__global__ __launch_bounds__(BLOCK) void k_shallow_plume(Src src, Work w) {
+    const int n = w.cnt[CNT_SHALLOW];
+    const int64_t gtid = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     const int64_t nthreads = (int64_t)gridDim.x * BLOCK;
-    const int64_t stride = a.w.scr_stride;
-    double *scr = a.w.sscr;
-#define SCR(arr, lev) scr[((int64_t)(arr) * (L + 1) + (lev)) * stride + tid]
+    double *scr = w.sscr;
+#define SCR(arr, lev) scr[((int64_t)(arr) * (w.lmax + 1) + (lev)) * w.sstride + gtid]
 
-    for (int64_t slot = tid; slot < n; slot += nthreads) {
-        const int64_t col = a.w.slist[slot];
-        const int ks = a.w.sks[slot];
-        const bool upd = a.w.sflag[slot] != 0;
-        const double hs = a.w.shs[slot], qsrc = a.w.sqs[slot], cin = a.w.scin[slot];
-        const double Mclos = a.w.sMc[slot], sigw2 = a.w.ssig2[slot];
-        const double phis = a.phis[col];
-        auto Tn = [&](int k) {
-            return upd ? AT(a.T, k) + a.dt * AT(a.dout.dTdt, k) : AT(a.T, k);
-        };
-        auto qn = [&](int k) {
-            return upd ? AT(a.q, k) + a.dt * AT(a.dout.dqdt, k) : AT(a.q, k);
-        };
-        auto zi = [&](int i) { return 0.5 * (AT(a.z, i - 1) + AT(a.z, i)); };
+    for (int64_t slot = gtid; slot < n; slot += nthreads) {
+        const Member &M = src.at(w.smem[slot]);
+        const int L = M.nlev;
+        const int64_t ld = M.ld;
+        const conv_params_t &P = M.P;
+        const int64_t col = w.slist[slot];
+        const int ks = w.sks[slot];
+        const bool upd = w.sflag[slot] != 0;
+        const double hs = w.shs[slot], qsrc = w.sqs[slot], cin = w.scin[slot];
+        const double Mclos = w.sMc[slot], sigw2 = w.ssig2[slot];
+        const double phis = M.phis[col];
+        auto Tn = [&](int k) { return upd ? AT(M.T, k) + M.dt * AT(M.dout.dTdt, k) : AT(M.T, k); };
+        auto qn = [&](int k) { return upd ? AT(M.q, k) + M.dt * AT(M.dout.dqdt, k) : AT(M.q, k); };
+        auto zi = [&](int i) { return 0.5 * (AT(M.z, i - 1) + AT(M.z, i)); };
 
+        Hint hp;
+        hp.clear();
         double Mlim = __builtin_inf();
         double P1;
-        // Source interface ks (S7 start).
         double Fs_lo, Fq_lo;  // fluxes at the interface below the current layer
         double eta = 1.0, hu = hs, qtu;
+        // S7 start: thermodynamics at the source interface ks.
         {
             const double zs = zi(ks);
-            const Lifted r = lift(hs - GRAV * zs - phis, qsrc, AT(a.pi, ks));
+            const Lifted r = lift(hs - GRAV * zs - phis, qsrc, AT(M.pi, ks), hp);
             const double ql = qsrc - r.qv;
             const double rr = ql - P.qlcrit_sh > 0.0 ? ql - P.qlcrit_sh : 0.0;
             qtu = qsrc - rr;
             const double slu = CP * r.T + GRAV * zs + phis - LV * (ql - rr);
-            const double Tup = Tn(ks - 1), qupk = qn(ks - 1);
-            const double s_up = CP * Tup + GRAV * AT(a.z, ks - 1) + phis;
-            const double Fs = slu - s_up, Fq = qtu - qupk;
-            const double dp = AT(a.pi, ks + 1) - AT(a.pi, ks);
+            const double s_up = CP * Tn(ks - 1) + GRAV * AT(M.z, ks - 1) + phis;
+            const double Fs = slu - s_up, Fq = qtu - qn(ks - 1);
+            const double dp = AT(M.pi, ks + 1) - AT(M.pi, ks);
             const double dT1 = (0.0 - Fs + LV * rr) * GRAV / (CP * dp);
             const double dq1 = (0.0 - Fq - rr) * GRAV / dp;
             SCR(0, ks) = 1.0;
             SCR(1, ks) = dT1;
             SCR(2, ks) = dq1;
             P1 = rr;
-            if (dq1 < 0.0) Mlim = fmin(Mlim, qn(ks) / (-a.dt * dq1));
+            if (dq1 < 0.0) Mlim = fmin(Mlim, qn(ks) / (-M.dt * dq1));
             Fs_lo = Fs;
             Fq_lo = Fq;
         }
@@ -611,7 +747,7 @@ __global__ __launch_bounds__(BLOCK) void k_shallow_plume(Args a) {
         int kt = -1;
         double zlo = zi(ks);
         for (int k = ks - 1; k >= 0; --k) {
-            bool stop = AT(a.pi, k) < P.p_sh_top_min || k == 0;
+            bool stop = AT(M.pi, k) < P.p_sh_top_min || k == 0;
             double zk = 0.0, E = 0.0, D = 0.0, en = 0.0;
             if (!stop) {
                 zk = zi(k);
@@ -624,9 +760,9 @@ __global__ __launch_bounds__(BLOCK) void k_shallow_plume(Args a) {
             double Fs = 0.0, Fq = 0.0, rr = 0.0, w2n = 0.0, hm = 0.0, qtn = 0.0;
             if (!stop) {
                 const double Tk = Tn(k), qk = qn(k);
-                hm = ((eta - D) * hu + E * ((CP * Tk + GRAV * AT(a.z, k) + phis) + LV * qk)) / en;
+                hm = ((eta - D) * hu + E * ((CP * Tk + GRAV * AT(M.z, k) + phis) + LV * qk)) / en;
                 const double qm = ((eta - D) * qtu + E * qk) / en;
-                const Lifted r = lift(hm - GRAV * zk - phis, qm, AT(a.pi, k));
+                const Lifted r = lift(hm - GRAV * zk - phis, qm, AT(M.pi, k), hp);
                 const double ql = qm - r.qv;
                 rr = ql - P.qlcrit_sh > 0.0 ? ql - P.qlcrit_sh : 0.0;
                 const double Trho = r.T * (1.0 + CVIR * r.qv - (ql - rr));
@@ -637,19 +773,19 @@ __global__ __launch_bounds__(BLOCK) void k_shallow_plume(Args a) {
                 if (!stop) {
                     qtn = qm - rr;
                     const double slu = CP * r.T + GRAV * zk + phis - LV * (ql - rr);
-                    const double s_up = CP * Tn(k - 1) + GRAV * AT(a.z, k - 1) + phis;
+                    const double s_up = CP * Tn(k - 1) + GRAV * AT(M.z, k - 1) + phis;
                     Fs = en * (slu - s_up);
                     Fq = en * (qtn - qn(k - 1));
                 }
             }
             const double pr = stop ? 0.0 : en * rr;
-            const double dp = AT(a.pi, k + 1) - AT(a.pi, k);
+            const double dp = AT(M.pi, k + 1) - AT(M.pi, k);
             const double dT1 = (Fs_lo - Fs + LV * pr) * GRAV / (CP * dp);
             const double dq1 = (Fq_lo - Fq - pr) * GRAV / dp;
             SCR(1, k) = dT1;
             SCR(2, k) = dq1;
             P1 += pr;
-            if (dq1 < 0.0) Mlim = fmin(Mlim, qn(k) / (-a.dt * dq1));
+            if (dq1 < 0.0) Mlim = fmin(Mlim, qn(k) / (-M.dt * dq1));
             if (stop) {
                 kt = k;
                 break;
@@ -667,18 +803,18 @@ __global__ __launch_bounds__(BLOCK) void k_shallow_plume(Args a) {
         const double Mb = Mclos <= Mlim ? Mclos : Mlim;
         for (int k = 0; k < L; ++k) {
             const bool in = st == 0 && k >= kt && k <= ks;
-            AT(a.sout.dTdt, k) = in ? Mb * SCR(1, k) : 0.0;
-            AT(a.sout.dqdt, k) = in ? Mb * SCR(2, k) : 0.0;
+            AT(M.sout.dTdt, k) = in ? Mb * SCR(1, k) : 0.0;
+            AT(M.sout.dqdt, k) = in ? Mb * SCR(2, k) : 0.0;
         }
         for (int i = 0; i <= L; ++i) {
             const bool in = st == 0 && i >= kt + 1 && i <= ks;
-            AT(a.sout.mu, i) = in ? Mb * SCR(0, i) : 0.0;
+            AT(M.sout.mu, i) = in ? Mb * SCR(0, i) : 0.0;
         }
-        a.sout.prec[col] = st == 0 ? Mb * P1 : 0.0;
-        a.sout.cin[col] = cin;
-        a.sout.kbase[col] = ks;
-        a.sout.ktop[col] = kt;
-        a.sout.status[col] = st;
+        M.sout.prec[col] = st == 0 ? Mb * P1 : 0.0;
+        M.sout.cin[col] = cin;
+        M.sout.kbase[col] = ks;
+        M.sout.ktop[col] = kt;
+        M.sout.status[col] = st;
     }
 #undef SCR
 }
@@ -687,12 +823,6 @@ __global__ __launch_bounds__(BLOCK) void k_shallow_plume(Args a) {
 
 // ------------------------------------------------------------------ host side
 thread_local int g_last_hip = 0;
-
-struct Layout {
-    size_t cnt, dlist, dkb, dkt, dcape, dSA, dSB, slist, sks, sflag, shs, sqs, scin, sMc, ssig2;
-    size_t dscr, sscr, total;
-    int64_t plume_threads;
-};
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -705,12 +835,29 @@ int device_cus() {
     return cus;
 }
 
-Layout make_layout(int64_t ncol, int nlev, int cus) {
+// Launch shape: persistent blocks per compute unit for the fused and the shallow-plume kernels.
+struct Launch {
+    int fused_bpc, shallow_bpc;
+};
+constexpr int MAX_BPC = 8;
+constexpr Launch DEFAULT_LAUNCH = {4, 2};
+
+struct Layout {
+    size_t cnt, dlist, dmem, dkb, dkt, dcape, dSA, dSB;
+    size_t slist, smem, sks, sflag, shs, sqs, scin, sMc, ssig2, members, dscr, sscr, total;
+    int64_t threads;  // largest persistent grid (threads) the launch shape allows
+    int lmax;
+};
+
+// Workspace layout for `ncol` columns (all members together) of at most `lmax` levels and `nmem`
+// ensemble members.
+Layout make_layout(int64_t ncol, int lmax, int nmem, int cus) {
     Layout l{};
     const int64_t n = ncol > 0 ? ncol : 1;
-    const int64_t rounded = (n + BLOCK - 1) / BLOCK * BLOCK;
-    const int64_t cap = (int64_t)cus * PLUME_BLOCKS_PER_CU * BLOCK;
-    l.plume_threads = rounded < cap ? rounded : cap;
+    const int64_t tiles = (n + BLOCK - 1) / BLOCK;
+    const int64_t cap = (int64_t)cus * MAX_BPC;
+    l.threads = (tiles < cap ? tiles : cap) * BLOCK;
+    l.lmax = lmax;
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t o = off;
@@ -719,12 +866,14 @@ Layout make_layout(int64_t ncol, int nlev, int cus) {
     };
     l.cnt = take(NCOUNTERS * sizeof(int));
     l.dlist = take(n * sizeof(int));
+    l.dmem = take(n * sizeof(int));
     l.dkb = take(n * sizeof(int));
     l.dkt = take(n * sizeof(int));
     l.dcape = take(n * sizeof(double));
     l.dSA = take(n * sizeof(double));
     l.dSB = take(n * sizeof(double));
     l.slist = take(n * sizeof(int));
+    l.smem = take(n * sizeof(int));
     l.sks = take(n * sizeof(int));
     l.sflag = take(n * sizeof(int));
     l.shs = take(n * sizeof(double));
@@ -732,8 +881,9 @@ Layout make_layout(int64_t ncol, int nlev, int cus) {
     l.scin = take(n * sizeof(double));
     l.sMc = take(n * sizeof(double));
     l.ssig2 = take(n * sizeof(double));
-    l.dscr = take((size_t)DEEP_SCR * (nlev + 1) * l.plume_threads * sizeof(double));
-    l.sscr = take((size_t)SHALLOW_SCR * (nlev + 1) * l.plume_threads * sizeof(double));
+    l.members = take((size_t)(nmem > 0 ? nmem : 1) * sizeof(Member));
+    l.dscr = take((size_t)DEEP_SCR * (lmax + 1) * l.threads * sizeof(double));
+    l.sscr = take((size_t)SHALLOW_SCR * (lmax + 1) * l.threads * sizeof(double));
     l.total = off;
     return l;
 }
@@ -749,6 +899,8 @@ struct conv_ctx {
     char *ws;
     size_t ws_bytes;
     Layout lay;
+    Launch launch;
+    int cus;
     // Optional per-kernel timing: NSTAGES+1 events per recorded call.
     hipEvent_t *ev;
     int ev_cap, ev_used;
@@ -756,18 +908,20 @@ struct conv_ctx {
 
 namespace {
 
-Work make_work(conv_ctx *c) {
+Work make_work(const conv_ctx *c) {
     Work w;
     char *b = c->ws;
     const Layout &l = c->lay;
     w.cnt = (int *)(b + l.cnt);
     w.dlist = (int *)(b + l.dlist);
+    w.dmem = (int *)(b + l.dmem);
     w.dkb = (int *)(b + l.dkb);
     w.dkt = (int *)(b + l.dkt);
     w.dcape = (double *)(b + l.dcape);
     w.dSA = (double *)(b + l.dSA);
     w.dSB = (double *)(b + l.dSB);
     w.slist = (int *)(b + l.slist);
+    w.smem = (int *)(b + l.smem);
     w.sks = (int *)(b + l.sks);
     w.sflag = (int *)(b + l.sflag);
     w.shs = (double *)(b + l.shs);
@@ -777,14 +931,18 @@ Work make_work(conv_ctx *c) {
     w.ssig2 = (double *)(b + l.ssig2);
     w.dscr = (double *)(b + l.dscr);
     w.sscr = (double *)(b + l.sscr);
-    w.scr_stride = l.plume_threads;
+    const int64_t fd = (int64_t)c->cus * c->launch.fused_bpc * BLOCK;
+    const int64_t sh = (int64_t)c->cus * c->launch.shallow_bpc * BLOCK;
+    w.dstride = fd < l.threads ? fd : l.threads;
+    w.sstride = sh < l.threads ? sh : l.threads;
+    w.lmax = l.lmax;
     return w;
 }
 
-bool state_ok(const conv_ctx *c, const conv_state_t *s, bool shallow) {
+bool state_ok(int64_t ncol, const conv_state_t *s, bool shallow) {
     if (!s || !s->T || !s->q || !s->p_mid || !s->z || !s->p_int || !s->phis) return false;
     if (shallow && (!s->pblh || !s->tke)) return false;
-    if (s->ld < c->ncol || !(s->dt > 0.0)) return false;
+    if (s->ld < ncol || !(s->dt > 0.0)) return false;
     return true;
 }
 
@@ -798,27 +956,27 @@ bool shallow_ok(const conv_shallow_out_t *o) {
            o->status;
 }
 
-Args make_args(conv_ctx *c, const conv_state_t *s, const conv_deep_out_t *d,
-               const conv_shallow_out_t *sh) {
-    Args a;
-    memset(&a, 0, sizeof(a));
-    a.T = s->T;
-    a.q = s->q;
-    a.pm = s->p_mid;
-    a.pi = s->p_int;
-    a.z = s->z;
-    a.phis = s->phis;
-    a.pblh = s->pblh;
-    a.tke = s->tke;
-    a.ld = s->ld;
-    a.dt = s->dt;
-    a.ncol = c->ncol;
-    a.nlev = c->nlev;
-    a.P = c->P;
-    if (d) a.dout = *d;
-    if (sh) a.sout = *sh;
-    a.w = make_work(c);
-    return a;
+Member make_member(int64_t ncol, int nlev, const conv_params_t &P, const conv_state_t *s,
+                   const conv_deep_out_t *d, const conv_shallow_out_t *sh, int64_t tile0) {
+    Member m;
+    memset(&m, 0, sizeof(m));
+    m.T = s->T;
+    m.q = s->q;
+    m.pm = s->p_mid;
+    m.pi = s->p_int;
+    m.z = s->z;
+    m.phis = s->phis;
+    m.pblh = s->pblh;
+    m.tke = s->tke;
+    m.ld = s->ld;
+    m.dt = s->dt;
+    m.ncol = ncol;
+    m.tile0 = tile0;
+    m.nlev = nlev;
+    m.P = P;
+    if (d) m.dout = *d;
+    if (sh) m.sout = *sh;
+    return m;
 }
 
 int finish() {
@@ -830,22 +988,33 @@ int finish() {
     return CONV_OK;
 }
 
-template <bool DEEP, bool SHALLOW>
-int run(conv_ctx *c, const Args &a, hipStream_t st) {
-    const unsigned grid_cols = (unsigned)((c->ncol + BLOCK - 1) / BLOCK);
-    const unsigned grid_plume = (unsigned)(c->lay.plume_threads / BLOCK);
+template <class Src, bool DEEP, bool SHALLOW>
+int launch_step(conv_ctx *c, const Src &src, const Work &w, hipStream_t st) {
+    const unsigned gt = (unsigned)src.ntiles;
+    const unsigned gd = (unsigned)(w.dstride / BLOCK);
+    const unsigned gs = (unsigned)(w.sstride / BLOCK);
     hipEvent_t *ev = nullptr;
     if (c->ev && c->ev_used < c->ev_cap) ev = c->ev + (size_t)(c->ev_used++) * (NSTAGES + 1);
     if (ev) (void)hipEventRecord(ev[0], st);
-    hipLaunchKernelGGL(k_reset, dim3(1), dim3(NCOUNTERS), 0, st, a.w.cnt);
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(NCOUNTERS), 0, st, w.cnt);
     if (ev) (void)hipEventRecord(ev[1], st);
-    hipLaunchKernelGGL((k_trigger<DEEP, SHALLOW>), dim3(grid_cols), dim3(BLOCK), 0, st, a);
+    hipLaunchKernelGGL((k_trigger<Src, DEEP, SHALLOW>), dim3(gt), dim3(BLOCK), 0, st, src, w);
     if (ev) (void)hipEventRecord(ev[2], st);
-    if (DEEP) hipLaunchKernelGGL((k_deep_plume<SHALLOW>), dim3(grid_plume), dim3(BLOCK), 0, st, a);
+    if (DEEP) hipLaunchKernelGGL((k_deep_plume<Src, SHALLOW>), dim3(gd), dim3(BLOCK), 0, st, src, w);
     if (ev) (void)hipEventRecord(ev[3], st);
-    if (SHALLOW) hipLaunchKernelGGL(k_shallow_plume, dim3(grid_plume), dim3(BLOCK), 0, st, a);
+    if (SHALLOW) hipLaunchKernelGGL((k_shallow_plume<Src>), dim3(gs), dim3(BLOCK), 0, st, src, w);
     if (ev) (void)hipEventRecord(ev[4], st);
     return finish();
+}
+
+template <bool DEEP, bool SHALLOW>
+int run_one(conv_ctx *c, const conv_state_t *s, const conv_deep_out_t *d,
+            const conv_shallow_out_t *sh, hipStream_t st) {
+    One src;
+    src.m = make_member(c->ncol, c->nlev, c->P, s, d, sh, 0);
+    src.ntiles = (c->ncol + BLOCK - 1) / BLOCK;
+    const Work w = make_work(c);
+    return launch_step<One, DEEP, SHALLOW>(c, src, w, st);
 }
 
 void free_events(conv_ctx *c) {
@@ -862,8 +1031,8 @@ void free_events(conv_ctx *c) {
 extern "C" {
 
 size_t conv_workspace_bytes(int64_t ncol, int32_t nlev) {
-    if (ncol < 0 || nlev < 2 || nlev > 256) return 0;
-    return make_layout(ncol, nlev, device_cus()).total;
+    if (ncol < 0 || ncol > INT32_MAX || nlev < 2 || nlev > 256) return 0;
+    return make_layout(ncol, nlev, 1, device_cus()).total;
 }
 
 int conv_create(int64_t ncol, int32_t nlev, const conv_params_t *params, void *workspace,
@@ -872,7 +1041,8 @@ int conv_create(int64_t ncol, int32_t nlev, const conv_params_t *params, void *w
     if (!out || !params || !workspace || ncol < 0 || ncol > INT32_MAX || nlev < 2 || nlev > 256)
         return CONV_EINVAL;
     if (((uintptr_t)workspace & 255u) != 0) return CONV_EINVAL;
-    const Layout l = make_layout(ncol, nlev, device_cus());
+    const int cus = device_cus();
+    const Layout l = make_layout(ncol, nlev, 1, cus);
     if (ws_bytes < l.total) return CONV_EINVAL;
     conv_ctx *c = new conv_ctx;
     c->ncol = ncol;
@@ -881,6 +1051,8 @@ int conv_create(int64_t ncol, int32_t nlev, const conv_params_t *params, void *w
     c->ws = (char *)workspace;
     c->ws_bytes = ws_bytes;
     c->lay = l;
+    c->launch = DEFAULT_LAUNCH;
+    c->cus = cus;
     c->ev = nullptr;
     c->ev_cap = c->ev_used = 0;
     *out = c;
@@ -893,10 +1065,47 @@ int conv_set_params(conv_ctx_t *ctx, const conv_params_t *params) {
     return CONV_OK;
 }
 
+int conv_set_launch(conv_ctx_t *ctx, int fused_blocks_per_cu, int shallow_blocks_per_cu) {
+    if (!ctx || fused_blocks_per_cu < 1 || fused_blocks_per_cu > MAX_BPC ||
+        shallow_blocks_per_cu < 1 || shallow_blocks_per_cu > MAX_BPC)
+        return CONV_EINVAL;
+    ctx->launch = Launch{fused_blocks_per_cu, shallow_blocks_per_cu};
+    return CONV_OK;
+}
+
+int conv_get_launch(conv_ctx_t *ctx, int *fused_blocks_per_cu, int *shallow_blocks_per_cu) {
+    if (!ctx || !fused_blocks_per_cu || !shallow_blocks_per_cu) return CONV_EINVAL;
+    *fused_blocks_per_cu = ctx->launch.fused_bpc;
+    *shallow_blocks_per_cu = ctx->launch.shallow_bpc;
+    return CONV_OK;
+}
+
 void conv_destroy(conv_ctx_t *ctx) {
     if (!ctx) return;
     free_events(ctx);
     delete ctx;
+}
+
+int conv_deep_forward(conv_ctx_t *ctx, const conv_state_t *state, conv_deep_out_t *out,
+                      void *stream) {
+    if (!ctx || !state_ok(ctx->ncol, state, false) || !deep_ok(out)) return CONV_EINVAL;
+    if (ctx->ncol == 0) return CONV_OK;
+    return run_one<true, false>(ctx, state, out, nullptr, (hipStream_t)stream);
+}
+
+int conv_shallow_forward(conv_ctx_t *ctx, const conv_state_t *state, conv_shallow_out_t *out,
+                         void *stream) {
+    if (!ctx || !state_ok(ctx->ncol, state, true) || !shallow_ok(out)) return CONV_EINVAL;
+    if (ctx->ncol == 0) return CONV_OK;
+    return run_one<false, true>(ctx, state, nullptr, out, (hipStream_t)stream);
+}
+
+int conv_step(conv_ctx_t *ctx, const conv_state_t *state, conv_deep_out_t *deep,
+              conv_shallow_out_t *shallow, void *stream) {
+    if (!ctx || !state_ok(ctx->ncol, state, true) || !deep_ok(deep) || !shallow_ok(shallow))
+        return CONV_EINVAL;
+    if (ctx->ncol == 0) return CONV_OK;
+    return run_one<true, true>(ctx, state, deep, shallow, (hipStream_t)stream);
 }
 
 int conv_timing_start(conv_ctx_t *ctx, int max_calls) {
@@ -906,8 +1115,9 @@ int conv_timing_start(conv_ctx_t *ctx, int max_calls) {
     ctx->ev = new hipEvent_t[(size_t)max_calls * (NSTAGES + 1)];
     for (int i = 0; i < max_calls * (NSTAGES + 1); ++i) {
         if (hipEventCreate(&ctx->ev[i]) != hipSuccess) {
-            ctx->ev_cap = i / (NSTAGES + 1);
-            free_events(ctx);
+            for (int j = 0; j < i; ++j) (void)hipEventDestroy(ctx->ev[j]);
+            delete[] ctx->ev;
+            ctx->ev = nullptr;
             return CONV_EHIP;
         }
     }
@@ -930,31 +1140,6 @@ int conv_timing_read(conv_ctx_t *ctx, double *ms, int *ncalls) {
         }
     }
     return CONV_OK;
-}
-
-int conv_deep_forward(conv_ctx_t *ctx, const conv_state_t *state, conv_deep_out_t *out,
-                      void *stream) {
-    if (!ctx || !state_ok(ctx, state, false) || !deep_ok(out)) return CONV_EINVAL;
-    if (ctx->ncol == 0) return CONV_OK;
-    const Args a = make_args(ctx, state, out, nullptr);
-    return run<true, false>(ctx, a, (hipStream_t)stream);
-}
-
-int conv_shallow_forward(conv_ctx_t *ctx, const conv_state_t *state, conv_shallow_out_t *out,
-                         void *stream) {
-    if (!ctx || !state_ok(ctx, state, true) || !shallow_ok(out)) return CONV_EINVAL;
-    if (ctx->ncol == 0) return CONV_OK;
-    const Args a = make_args(ctx, state, nullptr, out);
-    return run<false, true>(ctx, a, (hipStream_t)stream);
-}
-
-int conv_step(conv_ctx_t *ctx, const conv_state_t *state, conv_deep_out_t *deep,
-              conv_shallow_out_t *shallow, void *stream) {
-    if (!ctx || !state_ok(ctx, state, true) || !deep_ok(deep) || !shallow_ok(shallow))
-        return CONV_EINVAL;
-    if (ctx->ncol == 0) return CONV_OK;
-    const Args a = make_args(ctx, state, deep, shallow);
-    return run<true, true>(ctx, a, (hipStream_t)stream);
 }
 
 const char *conv_strerror(int code) {
