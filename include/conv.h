@@ -124,6 +124,36 @@ int conv_shallow_forward(conv_ctx_t *ctx, const conv_state_t *state, conv_shallo
 int conv_step(conv_ctx_t *ctx, const conv_state_t *state, conv_deep_out_t *deep,
               conv_shallow_out_t *shallow, void *stream);
 
+/* Cotangents of the deep outputs (device pointers; any may be NULL = zero). */
+typedef struct {
+    const double *g_dTdt, *g_dqdt; /* [nlev][ld] */
+    const double *g_prec;          /* [ld] */
+} conv_deep_cot_t;
+
+/* Gradients (device pointers, written). */
+typedef struct {
+    double *g_T, *g_q; /* [nlev][ld]  dL/dT, dL/dq */
+    double *g_params;  /* [2]         dL/dtau, dL/deps_deep summed over columns */
+} conv_deep_grad_t;
+
+/* Device workspace (bytes) conv_deep_backward needs for a context over (ncol, nlev) and state
+ * arrays of leading dimension ld. */
+size_t conv_backward_workspace_bytes(int64_t ncol, int32_t nlev, int64_t ld);
+
+/* Hand-written adjoint of the deep scheme (steps D1-D10): the gradient of
+ * L = sum(g_dTdt*dTdt) + sum(g_dqdt*dqdt) + sum(g_prec*prec) with respect to T, q and the
+ * parameters tau and eps_deep, through the branch the forward run took (launch and top levels,
+ * downdraft start, saturation flags, upwind choices, downdraft-strength and base-flux branches held
+ * fixed).  `fwd` must hold the status, klaunch and ktop outputs of conv_deep_forward (or conv_step)
+ * on the same state and parameters; everything else is recomputed per column (checkpointing).
+ * Columns whose deep status is not 0 get zero gradients.  The parameter gradients are summed in a
+ * fixed order (bit-reproducible).  `workspace`: caller-owned, 256-byte aligned, at least
+ * conv_backward_workspace_bytes(ncol, nlev, ld) bytes; it may not be the context's forward
+ * workspace.  The paper's deep convection (Algorithm 2) is the forward this differentiates. */
+int conv_deep_backward(conv_ctx_t *ctx, const conv_state_t *state, const conv_deep_out_t *fwd,
+                       const conv_deep_cot_t *cot, conv_deep_grad_t *grad, void *workspace,
+                       size_t ws_bytes, void *stream);
+
 /* Launch shape of the persistent kernels: blocks of 256 threads per compute unit for the
  * deep-plume kernel and for the shallow-plume kernel (each 1..8; default 4 and 2).  The
  * workspace size does not depend on it.  Results do not depend on it (bit-identical). */

@@ -28,7 +28,8 @@ DEFAULTS = dict(
 EXPORTS = ("conv_workspace_bytes", "conv_create", "conv_set_params", "conv_destroy",
            "conv_deep_forward", "conv_shallow_forward", "conv_step", "conv_set_launch",
            "conv_get_launch", "conv_timing_start",
-           "conv_timing_read", "conv_strerror", "conv_last_hip_error")
+           "conv_timing_read", "conv_strerror", "conv_last_hip_error",
+           "conv_backward_workspace_bytes", "conv_deep_backward")
 
 
 class Params(C.Structure):
@@ -49,6 +50,14 @@ class DeepOut(C.Structure):
 class ShallowOut(C.Structure):
     _fields_ = [(n, C.c_void_p) for n in ("dTdt", "dqdt", "mu", "prec", "cin", "kbase", "ktop",
                                           "status")]
+
+
+class DeepCot(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in ("g_dTdt", "g_dqdt", "g_prec")]
+
+
+class DeepGrad(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in ("g_T", "g_q", "g_params")]
 
 
 _lib = None
@@ -87,6 +96,12 @@ def lib():
         L.conv_timing_start.argtypes = [C.c_void_p, C.c_int]
         L.conv_timing_read.restype = C.c_int
         L.conv_timing_read.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int)]
+        L.conv_backward_workspace_bytes.restype = C.c_size_t
+        L.conv_backward_workspace_bytes.argtypes = [C.c_int64, C.c_int32, C.c_int64]
+        L.conv_deep_backward.restype = C.c_int
+        L.conv_deep_backward.argtypes = [C.c_void_p, C.POINTER(State), C.POINTER(DeepOut),
+                                         C.POINTER(DeepCot), C.POINTER(DeepGrad), C.c_void_p,
+                                         C.c_size_t, C.c_void_p]
         L.conv_strerror.restype = C.c_char_p
         L.conv_strerror.argtypes = [C.c_int]
         L.conv_last_hip_error.restype = C.c_int
@@ -240,6 +255,38 @@ class Conv:
               "conv_step")
         return deep, shallow
 
+    def deep_backward(self, s: dict, fwd: dict, g_dTdt=None, g_dqdt=None, g_prec=None):
+        """Adjoint of deep_forward at state `s` (with `fwd` its outputs): returns dict(g_T, g_q,
+        g_tau, g_eps) for the cotangents given (None = zero)."""
+        torch = self.torch
+        st = self._state(s)
+        ld = st.ld
+        L = lib()
+
+        def cot(a, shape):
+            if a is None:
+                return None
+            if a.dtype != torch.float64 or tuple(a.shape) != shape:
+                raise ValueError(f"cotangent: expected float64 {shape}")
+            return a.contiguous()
+
+        cT = cot(g_dTdt, (self.nlev, ld))
+        cq = cot(g_dqdt, (self.nlev, ld))
+        cP = cot(g_prec, (ld,))
+        nbytes = L.conv_backward_workspace_bytes(self.ncol, self.nlev, ld)
+        if nbytes == 0:
+            raise ValueError("unsupported size")
+        if getattr(self, "_bws", None) is None or self._bws.numel() < nbytes + 256:
+            self._bws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        wptr = (self._bws.data_ptr() + 255) & ~255
+        gT, gq, gp = self._f64(self.nlev, ld), self._f64(self.nlev, ld), self._f64(2)
+        c = DeepCot(*[a.data_ptr() if a is not None else None for a in (cT, cq, cP)])
+        g = DeepGrad(gT.data_ptr(), gq.data_ptr(), gp.data_ptr())
+        o = self._deep_struct(fwd)
+        check(L.conv_deep_backward(self.h, C.byref(st), C.byref(o), C.byref(c), C.byref(g),
+                                   C.c_void_p(wptr), nbytes, _stream(torch)), "conv_deep_backward")
+        return dict(g_T=gT, g_q=gq, g_tau=gp[0], g_eps=gp[1])
+
     # -- instrumentation -----------------------------------------------------------------
     STAGES = ("reset", "trigger", "deep_plume", "shallow_plume")
 
@@ -260,3 +307,49 @@ class Conv:
         n = C.c_int(0)
         check(lib().conv_timing_read(self.h, ms, C.byref(n)), "conv_timing_read")
         return {s: ms[i] for i, s in enumerate(self.STAGES)}, n.value
+
+
+def _autograd():
+    import torch
+
+    class DeepConv(torch.autograd.Function):
+        """(T, q, tau, eps_deep) -> (dTdt, dqdt, prec) of the deep scheme, differentiable through
+        the library's hand-written adjoint (branches of the forward run held fixed)."""
+
+        @staticmethod
+        def forward(ctx, T, q, tau, eps_deep, conv, state):
+            import copy
+
+            p = copy.copy(conv.params)
+            p.tau = float(tau)
+            p.eps_deep = float(eps_deep)
+            conv.set_params(p)
+            s = dict(state)
+            s["T"], s["q"] = T.detach().contiguous(), q.detach().contiguous()
+            out = conv.deep_forward(s)
+            ctx.conv, ctx.s, ctx.out = conv, s, out
+            ctx.params = p
+            ctx.shapes = (tau.shape, eps_deep.shape)
+            return out["dTdt"].clone(), out["dqdt"].clone(), out["prec"].clone()
+
+        @staticmethod
+        def backward(ctx, gT, gq, gP):
+            conv = ctx.conv
+            conv.set_params(ctx.params)
+            g = conv.deep_backward(ctx.s, ctx.out, gT, gq, gP)
+            return (g["g_T"], g["g_q"], g["g_tau"].reshape(ctx.shapes[0]),
+                    g["g_eps"].reshape(ctx.shapes[1]), None, None)
+
+    return DeepConv
+
+
+_DeepConv = None
+
+
+def deep_conv(conv: "Conv", state: dict, T, q, tau, eps_deep):
+    """Differentiable deep convection: returns (dTdt, dqdt, prec); gradients flow to T, q and the
+    0-d tensors tau, eps_deep through conv_deep_backward."""
+    global _DeepConv
+    if _DeepConv is None:
+        _DeepConv = _autograd()
+    return _DeepConv.apply(T, q, tau, eps_deep, conv, state)

@@ -8,8 +8,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libconv.so")
-SOURCES = ["conv.hip"]
-HEADERS = ["conv_physics.hpp"]
+SOURCES = ["conv.hip", "conv_adjoint.hip"]
+HEADERS = ["conv_physics.hpp", "conv_internal.hpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

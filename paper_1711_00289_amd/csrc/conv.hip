@@ -26,33 +26,40 @@
 #include <string.h>
 
 #include "conv.h"
-#include "conv_physics.hpp"
+#include "conv_internal.hpp"
 
 using namespace cvk;
 
+thread_local int g_last_hip = 0;
+
+namespace cvk {
+
+int device_cus() {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+        return 256;
+    return cus;
+}
+
+int check_launch() {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        g_last_hip = (int)e;
+        return CONV_EHIP;
+    }
+    return CONV_OK;
+}
+
+}  // namespace cvk
+
 namespace {
 
-constexpr int BLOCK = 256;
-constexpr int WAVE = 64;
-constexpr int NWAVES = BLOCK / WAVE;
-constexpr int NCOUNTERS = 64;
 constexpr int DEEP_SCR = 9;     // su, qu, c->dT1, sd, qd, e1->dq1, eta_d, eta, h
 constexpr int SHALLOW_SCR = 3;  // eta, dT1, dq1
 constexpr int CNT_DEEP = 0;
 constexpr int CNT_SHALLOW = 1;
-
-// One grid of columns with its arrays and parameters.
-struct Member {
-    const double *T, *q, *pm, *pi, *z, *phis, *pblh, *tke;
-    int64_t ld;
-    double dt;
-    int64_t ncol;
-    int64_t tile0;  // first tile of this member in the launch's tile space
-    int nlev, pad_;
-    conv_params_t P;
-    conv_deep_out_t dout;
-    conv_shallow_out_t sout;
-};
 
 struct Work {
     int *cnt;
@@ -64,27 +71,6 @@ struct Work {
     int64_t dstride, sstride;  // threads of the fused / shallow-plume persistent grids
     int lmax;                  // level capacity of the scratch
 };
-
-struct One {
-    Member m;
-    int64_t ntiles;
-    __device__ const Member &at(int) const { return m; }
-    __device__ int find(int64_t) const { return 0; }
-};
-
-struct Many {
-    const Member *ms;  // device table, ascending tile0
-    int nm;
-    int64_t ntiles;
-    __device__ const Member &at(int i) const { return ms[i]; }
-    __device__ int find(int64_t tile) const {
-        int i = 0;
-        while (i + 1 < nm && ms[i + 1].tile0 <= tile) ++i;
-        return i;
-    }
-};
-
-#define AT(arr, k) (arr)[(int64_t)(k) * ld + col]
 
 constexpr int SWEEP1_CHUNK = 6;
 
@@ -99,20 +85,6 @@ __device__ __forceinline__ void load_lev(Lev &v, const Member &M, int64_t ld, in
     v.pm = AT(M.pm, k);
     v.z = AT(M.z, k);
     v.pt = AT(M.pi, k);
-}
-
-// ------------------------------------------------------------------ wavefront compaction
-// Appends the lanes with `pred` set to the list counted by *counter: one ballot, one popcount and
-// one atomicAdd per wavefront.  Must be reached by every lane of the wavefront.
-__device__ __forceinline__ int wave_append(bool pred, int *counter) {
-    const unsigned long long m = __ballot(pred);
-    if (m == 0ull) return -1;
-    const int lane = __lane_id();
-    const int leader = __ffsll((long long)m) - 1;
-    int base = 0;
-    if (lane == leader) base = atomicAdd(counter, (int)__popcll(m));
-    base = __shfl(base, leader);
-    return pred ? base + (int)__popcll(m & ((1ull << lane) - 1ull)) : -1;
 }
 
 // ------------------------------------------------------------------ shallow trigger (S1-S6)
@@ -822,32 +794,7 @@ __global__ __launch_bounds__(BLOCK) void k_shallow_plume(Src src, Work w) {
 #undef AT
 
 // ------------------------------------------------------------------ host side
-thread_local int g_last_hip = 0;
-
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
-
-int device_cus() {
-    int dev = 0, cus = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return 256;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        cus <= 0)
-        return 256;
-    return cus;
-}
-
-// Launch shape: persistent blocks per compute unit for the fused and the shallow-plume kernels.
-struct Launch {
-    int fused_bpc, shallow_bpc;
-};
-constexpr int MAX_BPC = 8;
-constexpr Launch DEFAULT_LAUNCH = {4, 2};
-
-struct Layout {
-    size_t cnt, dlist, dmem, dkb, dkt, dcape, dSA, dSB;
-    size_t slist, smem, sks, sflag, shs, sqs, scin, sMc, ssig2, members, dscr, sscr, total;
-    int64_t threads;  // largest persistent grid (threads) the launch shape allows
-    int lmax;
-};
 
 // Workspace layout for `ncol` columns (all members together) of at most `lmax` levels and `nmem`
 // ensemble members.
@@ -889,22 +836,6 @@ Layout make_layout(int64_t ncol, int lmax, int nmem, int cus) {
 }
 
 }  // namespace
-
-constexpr int NSTAGES = 4;  // reset, trigger, deep plume, shallow plume
-
-struct conv_ctx {
-    int64_t ncol;
-    int nlev;
-    conv_params_t P;
-    char *ws;
-    size_t ws_bytes;
-    Layout lay;
-    Launch launch;
-    int cus;
-    // Optional per-kernel timing: NSTAGES+1 events per recorded call.
-    hipEvent_t *ev;
-    int ev_cap, ev_used;
-};
 
 namespace {
 
@@ -956,37 +887,7 @@ bool shallow_ok(const conv_shallow_out_t *o) {
            o->status;
 }
 
-Member make_member(int64_t ncol, int nlev, const conv_params_t &P, const conv_state_t *s,
-                   const conv_deep_out_t *d, const conv_shallow_out_t *sh, int64_t tile0) {
-    Member m;
-    memset(&m, 0, sizeof(m));
-    m.T = s->T;
-    m.q = s->q;
-    m.pm = s->p_mid;
-    m.pi = s->p_int;
-    m.z = s->z;
-    m.phis = s->phis;
-    m.pblh = s->pblh;
-    m.tke = s->tke;
-    m.ld = s->ld;
-    m.dt = s->dt;
-    m.ncol = ncol;
-    m.tile0 = tile0;
-    m.nlev = nlev;
-    m.P = P;
-    if (d) m.dout = *d;
-    if (sh) m.sout = *sh;
-    return m;
-}
-
-int finish() {
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) {
-        g_last_hip = (int)e;
-        return CONV_EHIP;
-    }
-    return CONV_OK;
-}
+int finish() { return check_launch(); }
 
 template <class Src, bool DEEP, bool SHALLOW>
 int launch_step(conv_ctx *c, const Src &src, const Work &w, hipStream_t st) {
@@ -994,7 +895,7 @@ int launch_step(conv_ctx *c, const Src &src, const Work &w, hipStream_t st) {
     const unsigned gd = (unsigned)(w.dstride / BLOCK);
     const unsigned gs = (unsigned)(w.sstride / BLOCK);
     hipEvent_t *ev = nullptr;
-    if (c->ev && c->ev_used < c->ev_cap) ev = c->ev + (size_t)(c->ev_used++) * (NSTAGES + 1);
+    if (c->ev && c->ev_used < c->ev_cap) ev = c->ev + (size_t)(c->ev_used++) * (CONV_NSTAGES + 1);
     if (ev) (void)hipEventRecord(ev[0], st);
     hipLaunchKernelGGL(k_reset, dim3(1), dim3(NCOUNTERS), 0, st, w.cnt);
     if (ev) (void)hipEventRecord(ev[1], st);
@@ -1019,7 +920,7 @@ int run_one(conv_ctx *c, const conv_state_t *s, const conv_deep_out_t *d,
 
 void free_events(conv_ctx *c) {
     if (c->ev) {
-        for (int i = 0; i < c->ev_cap * (NSTAGES + 1); ++i) (void)hipEventDestroy(c->ev[i]);
+        for (int i = 0; i < c->ev_cap * (CONV_NSTAGES + 1); ++i) (void)hipEventDestroy(c->ev[i]);
         delete[] c->ev;
     }
     c->ev = nullptr;
@@ -1112,8 +1013,8 @@ int conv_timing_start(conv_ctx_t *ctx, int max_calls) {
     if (!ctx || max_calls < 0) return CONV_EINVAL;
     free_events(ctx);
     if (max_calls == 0) return CONV_OK;
-    ctx->ev = new hipEvent_t[(size_t)max_calls * (NSTAGES + 1)];
-    for (int i = 0; i < max_calls * (NSTAGES + 1); ++i) {
+    ctx->ev = new hipEvent_t[(size_t)max_calls * (CONV_NSTAGES + 1)];
+    for (int i = 0; i < max_calls * (CONV_NSTAGES + 1); ++i) {
         if (hipEventCreate(&ctx->ev[i]) != hipSuccess) {
             for (int j = 0; j < i; ++j) (void)hipEventDestroy(ctx->ev[j]);
             delete[] ctx->ev;
@@ -1128,12 +1029,12 @@ int conv_timing_start(conv_ctx_t *ctx, int max_calls) {
 
 int conv_timing_read(conv_ctx_t *ctx, double *ms, int *ncalls) {
     if (!ctx || !ms || !ncalls) return CONV_EINVAL;
-    for (int s = 0; s < NSTAGES; ++s) ms[s] = 0.0;
+    for (int s = 0; s < CONV_NSTAGES; ++s) ms[s] = 0.0;
     *ncalls = ctx->ev_used;
     for (int i = 0; i < ctx->ev_used; ++i) {
-        hipEvent_t *ev = ctx->ev + (size_t)i * (NSTAGES + 1);
-        if (hipEventSynchronize(ev[NSTAGES]) != hipSuccess) return CONV_EHIP;
-        for (int s = 0; s < NSTAGES; ++s) {
+        hipEvent_t *ev = ctx->ev + (size_t)i * (CONV_NSTAGES + 1);
+        if (hipEventSynchronize(ev[CONV_NSTAGES]) != hipSuccess) return CONV_EHIP;
+        for (int s = 0; s < CONV_NSTAGES; ++s) {
             float t = 0.f;
             if (hipEventElapsedTime(&t, ev[s], ev[s + 1]) != hipSuccess) return CONV_EHIP;
             ms[s] += t;

@@ -1,0 +1,586 @@
+// conv_adjoint.hip -- hand-written adjoint (reverse mode) of the deep convection scheme, D1-D10 of
+// the written reading of the paper's deep convection (arXiv:1711.00289, Background and Algorithm
+// 2: an entrainment loop and a precipitation loop around an iterative inversion).
+//
+// The derivative is taken through the branch the forward run took: launch layer kb, cloud top kt,
+// downdraft start kd, every saturation flag, every upwind choice, the downdraft-strength branch
+// (alpha_dd or the evaporation cap) and the base-flux branch (closure M_c or the humidity limiter,
+// with its limiting layer) are held fixed.  It is checkpointed: from the inputs and the forward
+// run's status / launch / top outputs, each active column recomputes its parcel, updraft,
+// downdraft, tendencies and closure (storing the per-level values the reverse sweep needs in a
+// per-thread scratch region of the caller's workspace), then runs the reverse sweep:
+//   base flux -> closure F (with the parcel sensitivities, which need qs'') and CAPE -> parcel
+//   (implicit derivative of the saturated inversion, dT/dH = 1/(cp + Lv qs')) -> flux-form
+//   tendencies -> downdraft strength alpha -> downdraft recurrence -> updraft recurrence -> h.
+// Outputs: dL/dT, dL/dq per level and dL/dtau, dL/deps_deep summed over columns in a fixed order.
+#include "conv_internal.hpp"
+
+using namespace cvk;
+
+namespace {
+
+// Per-level scratch arrays (index = level or interface).
+enum : int {
+    P_TP = 0, P_QP, P_Q1, P_Q2, P_SAT,                      // parcel, layers kt..kb-1
+    U_ETA, U_HM, U_QM, U_TU, U_QU, U_Q1, U_SAT, U_E, U_C,   // updraft (U_E, U_C per layer)
+    D_AD, D_HD, D_TD, D_QD, D_Q1, D_ED, D_E1,               // downdraft (D_ED, D_E1 per layer)
+    X_DT1, X_DQ1, X_UPW,                                    // unit tendencies, upwind flags
+    G_T, G_Q, G_ETA, G_TU, G_QU, G_HU, G_AD, G_TD, G_QD, G_HD, G_C, G_E1, G_DT1, G_DQ1,
+    N_ADJ
+};
+
+struct AdjWork {
+    int *cnt;
+    int *list;
+    double *pgrad;  // [2][ld]: per-column dL/dtau, dL/deps
+    double *scr;
+    int64_t stride;
+    int lmax;
+    const double *cT, *cq, *cP;  // cotangents of dTdt, dqdt [nlev][ld] and prec [ld] (may be NULL)
+    double *gT, *gq;             // [nlev][ld]
+};
+
+// Active (status 0) columns into a list; every other column gets zero gradients.
+__global__ __launch_bounds__(BLOCK) void k_adj_compact(Member M, AdjWork w) {
+    const int64_t col = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    const bool live = col < M.ncol;
+    const int64_t ld = M.ld;
+    const bool act = live && M.dout.status[col] == 0;
+    if (live && !act) {
+        for (int k = 0; k < M.nlev; ++k) {
+            AT(w.gT, k) = 0.0;
+            AT(w.gq, k) = 0.0;
+        }
+        w.pgrad[col] = 0.0;
+        w.pgrad[ld + col] = 0.0;
+    }
+    const int slot = wave_append(act, &w.cnt[0]);
+    if (slot >= 0) w.list[slot] = (int)col;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_deep_adjoint(Member M, AdjWork w) {
+    const int n = w.cnt[0];
+    const int64_t gtid = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    const int64_t nthreads = (int64_t)gridDim.x * BLOCK;
+    const int L = M.nlev;
+    const int64_t ld = M.ld;
+    const conv_params_t &P = M.P;
+    const double tau = P.tau, epsd = P.eps_deep, beta = P.evap_max_frac, dt = M.dt;
+    double *scr = w.scr;
+#define S(arr, lev) scr[((int64_t)(arr) * (w.lmax + 1) + (lev)) * w.stride + gtid]
+
+    for (int64_t slot = gtid; slot < n; slot += nthreads) {
+        const int64_t col = w.list[slot];
+        const int kb = M.dout.klaunch[col], kt = M.dout.ktop[col];
+        const double phis = M.phis[col];
+        auto Tk = [&](int k) { return AT(M.T, k); };
+        auto qk = [&](int k) { return AT(M.q, k); };
+        auto hk = [&](int k) { return (CP * AT(M.T, k) + GRAV * AT(M.z, k) + phis) + LV * AT(M.q, k); };
+        auto zi = [&](int i) { return 0.5 * (AT(M.z, i - 1) + AT(M.z, i)); };
+        auto lamk = [&](int k) { return log(AT(M.pi, k + 1) / AT(M.pi, k)); };
+        auto dpk = [&](int k) { return AT(M.pi, k + 1) - AT(M.pi, k); };
+
+        // ============================================ forward recomputation
+        const double hkb = hk(kb), qkb = qk(kb);
+        // D2-D4: parcel over [kt, kb), CAPE and the closure's parcel sensitivities.
+        double cape = 0.0, SA = 0.0, SB = 0.0;
+        {
+            Hint hp;
+            hp.clear();
+            for (int k = kb - 1; k >= kt; --k) {
+                const Lifted r = lift(hkb - GRAV * AT(M.z, k) - phis, qkb, AT(M.pm, k), hp);
+                // The closure's parcel sensitivity needs qs' and qs'' at the root itself (the
+                // solver carries qs'' only to zeroth order), so they are evaluated there.
+                const Sat sr = r.sat ? sat_eval(r.T, AT(M.pm, k)) : Sat{0.0, 0.0, 0.0, 0.0};
+                S(P_TP, k) = r.T;
+                S(P_QP, k) = r.qv;
+                S(P_Q1, k) = sr.dqs;
+                S(P_Q2, k) = sr.d2qs;
+                S(P_SAT, k) = r.sat ? 1.0 : 0.0;
+                const double lam = lamk(k);
+                cape += RD * (tv(r.T, r.qv) - tv(Tk(k), qk(k))) * lam;
+                double ca, cb;
+                if (r.sat) {
+                    const double c = (1.0 + CVIR * r.qv) + CVIR * r.T * sr.dqs;
+                    const double rden = frcp(CP + LV * sr.dqs);
+                    ca = c * CP * rden;
+                    cb = c * LV * rden;
+                } else {
+                    ca = 1.0 + CVIR * r.qv;
+                    cb = CVIR * r.T;
+                }
+                SA += lam * ca;
+                SB += lam * cb;
+            }
+        }
+        // D5: updraft.
+        double C1;
+        {
+            Hint hu;
+            hu.clear();
+            double zlo = zi(kb);
+            const Lifted r0 = lift(hkb - GRAV * zlo - phis, qkb, AT(M.pi, kb), hu);
+            S(U_ETA, kb) = 1.0;
+            S(U_HM, kb) = hkb;
+            S(U_QM, kb) = qkb;
+            S(U_TU, kb) = r0.T;
+            S(U_QU, kb) = r0.qv;
+            S(U_Q1, kb) = r0.dqs;
+            S(U_SAT, kb) = r0.sat ? 1.0 : 0.0;
+            C1 = qkb - r0.qv;
+            S(U_C, kb) = C1;
+            double eta = 1.0, hum = hkb, qup = r0.qv;
+            for (int k = kb - 1; k >= kt + 1; --k) {
+                const double zk = zi(k);
+                const double E = epsd * eta * (zk - zlo);
+                const double etan = eta + E;
+                const double hm = (eta * hum + E * hk(k)) / etan;
+                const double qm = (eta * qup + E * qk(k)) / etan;
+                const Lifted r = lift(hm - GRAV * zk - phis, qm, AT(M.pi, k), hu);
+                const double c = etan * (qm - r.qv);
+                S(U_ETA, k) = etan;
+                S(U_HM, k) = hm;
+                S(U_QM, k) = qm;
+                S(U_TU, k) = r.T;
+                S(U_QU, k) = r.qv;
+                S(U_Q1, k) = r.dqs;
+                S(U_SAT, k) = r.sat ? 1.0 : 0.0;
+                S(U_E, k) = E;
+                S(U_C, k) = c;
+                C1 += c;
+                eta = etan;
+                hum = hm;
+                qup = r.qv;
+                zlo = zk;
+            }
+        }
+        // D6: downdraft.
+        int kd = -1;
+        double alpha = 0.0, E1 = 0.0;
+        bool capped = false;
+        if (kb - kt >= 2) {
+            kd = kt + 1;
+            double hkd = hk(kd);
+            for (int k = kt + 2; k <= kb - 1; ++k) {
+                const double h = hk(k);
+                if (h < hkd) {
+                    kd = k;
+                    hkd = h;
+                }
+            }
+            Hint hdn;
+            hdn.clear();
+            double ad = 1.0, hd = hkd, zii = zi(kd + 1);
+            Sat s;
+            double H = hd - GRAV * zii - phis;
+            double Td = tsat_h(H, AT(M.pi, kd + 1), (H - LV * qk(kd)) * RCP_CP, s, hdn);
+            double qd = s.qs;
+            S(D_AD, kd + 1) = 1.0;
+            S(D_HD, kd + 1) = hd;
+            S(D_TD, kd + 1) = Td;
+            S(D_QD, kd + 1) = qd;
+            S(D_Q1, kd + 1) = s.dqs;
+            E1 = qd - qk(kd);
+            S(D_E1, kd) = E1;
+            for (int k = kd + 1; k <= kb - 1; ++k) {
+                const double zlow = zi(k + 1);
+                const double Ed = epsd * ad * (zii - zlow);
+                const double adn = ad + Ed;
+                hd = (ad * hd + Ed * hk(k)) / adn;
+                H = hd - GRAV * zlow - phis;
+                Td = tsat_h(H, AT(M.pi, k + 1), (H - LV * qk(k)) * RCP_CP, s, hdn);
+                const double e1 = adn * s.qs - ad * qd - Ed * qk(k);
+                S(D_ED, k) = Ed;
+                S(D_E1, k) = e1;
+                S(D_AD, k + 1) = adn;
+                S(D_HD, k + 1) = hd;
+                S(D_TD, k + 1) = Td;
+                S(D_QD, k + 1) = s.qs;
+                S(D_Q1, k + 1) = s.dqs;
+                E1 += e1;
+                ad = adn;
+                qd = s.qs;
+                zii = zlow;
+            }
+            alpha = P.alpha_dd;
+            if (P.alpha_dd * E1 > beta * C1) {
+                alpha = beta * C1 / E1;
+                capped = true;
+            }
+        }
+        // D7-D9: unit tendencies, F, limiter.
+        double P1 = 0.0, Fenv = 0.0, Mlim = __builtin_inf();
+        int klim_at = -1;
+        {
+            double Fs_top = 0.0, Fq_top = 0.0;
+            for (int k = kt; k <= kb; ++k) {
+                double Fs = 0.0, Fq = 0.0;
+                const int i = k + 1;
+                if (i <= kb) {
+                    const double et = S(U_ETA, i);
+                    const bool dn = kd >= 0 && i >= kd + 1;
+                    const double ed = dn ? -S(D_AD, i) : 0.0;
+                    const bool upw = et + alpha * ed >= 0.0;
+                    const int up = upw ? i - 1 : i;
+                    const double s_up = CP * Tk(up) + GRAV * AT(M.z, up) + phis;
+                    const double q_up = qk(up);
+                    const double zii = zi(i);
+                    Fs = et * ((CP * S(U_TU, i) + GRAV * zii + phis) - s_up);
+                    Fq = et * (S(U_QU, i) - q_up);
+                    if (dn) {
+                        Fs += alpha * ed * ((CP * S(D_TD, i) + GRAV * zii + phis) - s_up);
+                        Fq += alpha * ed * (S(D_QD, i) - q_up);
+                    }
+                    S(X_UPW, i) = upw ? 1.0 : 0.0;
+                }
+                const double c = (k >= kt + 1) ? S(U_C, k) : 0.0;
+                const double e1 = (kd >= 0 && k >= kd && k <= kb - 1) ? S(D_E1, k) : 0.0;
+                const double net = c - alpha * e1;
+                const double dp = dpk(k);
+                const double dT1 = (Fs - Fs_top + LV * net) * GRAV / (CP * dp);
+                const double dq1 = (Fq - Fq_top - net) * GRAV / dp;
+                S(X_DT1, k) = dT1;
+                S(X_DQ1, k) = dq1;
+                P1 += net;
+                if (k <= kb - 1) Fenv += lamk(k) * ((1.0 + CVIR * qk(k)) * dT1 + CVIR * Tk(k) * dq1);
+                if (dq1 < 0.0) {
+                    const double m = qk(k) / (-dt * dq1);
+                    if (m < Mlim) {
+                        Mlim = m;
+                        klim_at = k;
+                    }
+                }
+                Fs_top = Fs;
+                Fq_top = Fq;
+            }
+        }
+        const double dT1b = S(X_DT1, kb), dq1b = S(X_DQ1, kb);
+        const double F = -RD * (dT1b * SA + dq1b * SB - Fenv);
+        double gtau = 0.0, geps = 0.0;
+        if (!(F > 0.0)) {
+            // Not reachable for a status-0 column; no derivative there.
+            for (int k = 0; k < L; ++k) {
+                AT(w.gT, k) = 0.0;
+                AT(w.gq, k) = 0.0;
+            }
+            w.pgrad[col] = 0.0;
+            w.pgrad[ld + col] = 0.0;
+            continue;
+        }
+        const double Mc = cape / (tau * F);
+        const bool closure = Mc <= Mlim;
+        const double Mb = closure ? Mc : Mlim;
+
+        // ============================================ reverse sweep
+        for (int lev = kt; lev <= kb + 1; ++lev)
+            for (int a = G_T; a < N_ADJ; ++a) S(a, lev) = 0.0;
+        // D10: outputs = M_b * unit profiles.
+        double gMb = 0.0;
+        for (int k = kt; k <= kb; ++k) {
+            const double cT = w.cT ? AT(w.cT, k) : 0.0;
+            const double cq = w.cq ? AT(w.cq, k) : 0.0;
+            gMb += cT * S(X_DT1, k) + cq * S(X_DQ1, k);
+            S(G_DT1, k) = cT * Mb;
+            S(G_DQ1, k) = cq * Mb;
+        }
+        const double cPc = w.cP ? w.cP[col] : 0.0;
+        gMb += cPc * P1;
+        const double gP1 = cPc * Mb;
+        // D9/D8: base-flux branch.
+        double gF = 0.0, gcape = 0.0;
+        if (closure) {
+            gcape = gMb / (tau * F);
+            gF = -gMb * Mc / F;
+            gtau = -gMb * Mc / tau;
+        } else {
+            const double dq1m = S(X_DQ1, klim_at);
+            S(G_Q, klim_at) += gMb / (-dt * dq1m);
+            S(G_DQ1, klim_at) += gMb * (-Mlim / dq1m);
+        }
+        // D8 closure F and D4 CAPE, through the parcel (D2).
+        double ghkb = 0.0, gqkb = 0.0;
+        S(G_DT1, kb) += -RD * gF * SA;
+        S(G_DQ1, kb) += -RD * gF * SB;
+        for (int k = kt; k <= kb - 1; ++k) {
+            const double lam = lamk(k), T = Tk(k), q = qk(k);
+            const double dT1 = S(X_DT1, k), dq1 = S(X_DQ1, k);
+            S(G_DT1, k) += RD * gF * lam * (1.0 + CVIR * q);
+            S(G_DQ1, k) += RD * gF * lam * CVIR * T;
+            double gTk = RD * gF * lam * CVIR * dq1;
+            double gqk = RD * gF * lam * CVIR * dT1;
+            const double ga = -RD * gF * lam * dT1b, gb = -RD * gF * lam * dq1b;
+            const double gB = RD * lam * gcape;
+            const double Tp = S(P_TP, k), qp = S(P_QP, k);
+            double gTp = gB * (1.0 + CVIR * qp), gqp = gB * CVIR * Tp;
+            gTk -= gB * (1.0 + CVIR * q);
+            gqk -= gB * CVIR * T;
+            S(G_T, k) += gTk;
+            S(G_Q, k) += gqk;
+            if (S(P_SAT, k) != 0.0) {
+                const double Q1 = S(P_Q1, k), Q2 = S(P_Q2, k);
+                const double c = (1.0 + CVIR * qp) + CVIR * Tp * Q1;
+                const double den = CP + LV * Q1;
+                const double dc = CVIR * (2.0 * Q1 + Tp * Q2), dden = LV * Q2;
+                const double dq = (dc * den - c * dden) / (den * den);
+                gTp += ga * CP * dq + gb * LV * dq;
+                ghkb += (gTp + gqp * Q1) / den;
+            } else {
+                gqp += ga * CVIR;
+                gTp += gb * CVIR;
+                ghkb += gTp / CP;
+                gqkb += -LV * gTp / CP + gqp;
+            }
+        }
+        // D7 tendencies: net sources per layer, fluxes per interface.
+        double galpha = 0.0;
+        for (int k = kt; k <= kb; ++k) {
+            const double dp = dpk(k);
+            const double gnet = LV * GRAV / (CP * dp) * S(G_DT1, k) - GRAV / dp * S(G_DQ1, k) + gP1;
+            if (k >= kt + 1) S(G_C, k) += gnet;
+            if (kd >= 0 && k >= kd && k <= kb - 1) {
+                S(G_E1, k) += -alpha * gnet;
+                galpha -= gnet * S(D_E1, k);
+            }
+        }
+        for (int i = kt + 1; i <= kb; ++i) {
+            const double dpa = dpk(i - 1), dpb = dpk(i);
+            const double gPs = GRAV / (CP * dpa) * S(G_DT1, i - 1) - GRAV / (CP * dpb) * S(G_DT1, i);
+            const double gPq = GRAV / dpa * S(G_DQ1, i - 1) - GRAV / dpb * S(G_DQ1, i);
+            const double et = S(U_ETA, i);
+            const int up = S(X_UPW, i) != 0.0 ? i - 1 : i;
+            const double s_up = CP * Tk(up) + GRAV * AT(M.z, up) + phis;
+            const double q_up = qk(up);
+            const double zii = zi(i);
+            const double su = CP * S(U_TU, i) + GRAV * zii + phis, qu = S(U_QU, i);
+            const bool dn = kd >= 0 && i >= kd + 1;
+            const double ed = dn ? -S(D_AD, i) : 0.0;
+            const double m = et + alpha * ed;
+            S(G_ETA, i) += gPs * (su - s_up) + gPq * (qu - q_up);
+            S(G_TU, i) += CP * gPs * et;
+            S(G_QU, i) += gPq * et;
+            S(G_T, up) += -CP * gPs * m;
+            S(G_Q, up) += -gPq * m;
+            if (dn) {
+                const double sd = CP * S(D_TD, i) + GRAV * zii + phis, qd = S(D_QD, i);
+                galpha += gPs * ed * (sd - s_up) + gPq * ed * (qd - q_up);
+                S(G_AD, i) += -alpha * (gPs * (sd - s_up) + gPq * (qd - q_up));
+                S(G_TD, i) += CP * alpha * ed * gPs;
+                S(G_QD, i) += alpha * ed * gPq;
+            }
+        }
+        // D6 downdraft strength when capped by the evaporation limit.
+        if (capped) {
+            const double gC1 = galpha * beta / E1, gE1 = -galpha * alpha / E1;
+            for (int k = kt + 1; k <= kb; ++k) S(G_C, k) += gC1;
+            for (int k = kd; k <= kb - 1; ++k) S(G_E1, k) += gE1;
+        }
+        // D6 downdraft recurrence, in reverse (bottom layer first).
+        if (kd >= 0) {
+            for (int k = kb - 1; k >= kd + 1; --k) {
+                const double adk = S(D_AD, k), adk1 = S(D_AD, k + 1);
+                const double hdk = S(D_HD, k), hdk1 = S(D_HD, k + 1);
+                const double Ed = S(D_ED, k), qdk = S(D_QD, k), qdk1 = S(D_QD, k + 1);
+                const double Q1 = S(D_Q1, k + 1), q = qk(k), h = hk(k);
+                const double ge1 = S(G_E1, k);
+                double gad1 = S(G_AD, k + 1) + ge1 * qdk1;
+                const double gqd1 = S(G_QD, k + 1) + ge1 * adk1;
+                double gad0 = -ge1 * qdk;
+                S(G_QD, k) += -ge1 * adk;
+                double gEd = -ge1 * q;
+                double gq = -ge1 * Ed;
+                const double gTd1 = S(G_TD, k + 1) + gqd1 * Q1;
+                const double ghd1 = S(G_HD, k + 1) + gTd1 / (CP + LV * Q1);
+                gad0 += ghd1 * hdk / adk1;
+                S(G_HD, k) += ghd1 * adk / adk1;
+                gEd += ghd1 * h / adk1;
+                const double gh = ghd1 * Ed / adk1;
+                gad1 += -ghd1 * hdk1 / adk1;
+                gad0 += gad1;
+                gEd += gad1;
+                const double dz = zi(k) - zi(k + 1);
+                geps += gEd * adk * dz;
+                gad0 += gEd * epsd * dz;
+                S(G_AD, k) += gad0;
+                S(G_T, k) += CP * gh;
+                S(G_Q, k) += LV * gh + gq;
+            }
+            // Start: h_d = h of layer kd at interface kd+1; e1_kd = q_d(kd+1) - q_kd.
+            const double ge1 = S(G_E1, kd);
+            const double gqd1 = S(G_QD, kd + 1) + ge1;
+            const double Q1 = S(D_Q1, kd + 1);
+            const double gTd1 = S(G_TD, kd + 1) + gqd1 * Q1;
+            const double ghd1 = S(G_HD, kd + 1) + gTd1 / (CP + LV * Q1);
+            S(G_T, kd) += CP * ghd1;
+            S(G_Q, kd) += LV * ghd1 - ge1;
+        }
+        // D5 updraft recurrence, in reverse (top interface first).
+        for (int k = kt + 1; k <= kb - 1; ++k) {
+            const double eta = S(U_ETA, k), etan1 = S(U_ETA, k + 1);
+            const double hm = S(U_HM, k), hu1 = S(U_HM, k + 1);
+            const double qm = S(U_QM, k), qu = S(U_QU, k), qu1 = S(U_QU, k + 1);
+            const double E = S(U_E, k), Q1 = S(U_Q1, k);
+            const double gc = S(G_C, k);
+            double geta = S(G_ETA, k) + gc * (qm - qu);
+            double gqm = gc * eta;
+            const double gqu = S(G_QU, k) - gc * eta;
+            double ghm = S(G_HU, k);
+            const double gTu = S(G_TU, k);
+            if (S(U_SAT, k) != 0.0) {
+                ghm += (gTu + gqu * Q1) / (CP + LV * Q1);
+            } else {
+                ghm += gTu / CP;
+                gqm += -LV * gTu / CP + gqu;
+            }
+            const double reta = 1.0 / eta;
+            S(G_ETA, k + 1) += (ghm * hu1 + gqm * qu1) * reta;
+            S(G_HU, k + 1) += ghm * etan1 * reta;
+            S(G_QU, k + 1) += gqm * etan1 * reta;
+            double gE = (ghm * hk(k) + gqm * qk(k)) * reta;
+            const double gh = ghm * E * reta;
+            S(G_T, k) += CP * gh;
+            S(G_Q, k) += LV * gh + gqm * E * reta;
+            geta += -(ghm * hm + gqm * qm) * reta;
+            S(G_ETA, k + 1) += geta;
+            gE += geta;
+            const double dz = zi(k) - zi(k + 1);
+            geps += gE * etan1 * dz;
+            S(G_ETA, k + 1) += gE * epsd * dz;
+        }
+        {
+            // Launch interface kb: h_u = h_kb, q_m = q_kb, c_kb = q_kb - q_u(kb).
+            const double gc = S(G_C, kb);
+            const double gqu = S(G_QU, kb) - gc;
+            double ghm = S(G_HU, kb);
+            const double gTu = S(G_TU, kb), Q1 = S(U_Q1, kb);
+            double gqm = 0.0;
+            if (S(U_SAT, kb) != 0.0) {
+                ghm += (gTu + gqu * Q1) / (CP + LV * Q1);
+            } else {
+                ghm += gTu / CP;
+                gqm = -LV * gTu / CP + gqu;
+            }
+            ghkb += ghm;
+            gqkb += gqm + gc;
+        }
+        S(G_T, kb) += CP * ghkb;
+        S(G_Q, kb) += LV * ghkb + gqkb;
+
+        for (int k = 0; k < L; ++k) {
+            const bool in = k >= kt && k <= kb;
+            AT(w.gT, k) = in ? S(G_T, k) : 0.0;
+            AT(w.gq, k) = in ? S(G_Q, k) : 0.0;
+        }
+        w.pgrad[col] = gtau;
+        w.pgrad[ld + col] = geps;
+    }
+#undef S
+}
+
+// dL/dtau and dL/deps: sums of the per-column values over columns 0..ncol-1 in a fixed order
+// (one block; each thread sums a strided subset in order, then a fixed-shape tree).
+__global__ __launch_bounds__(BLOCK) void k_adj_reduce(const double *pgrad, int64_t ld, int64_t ncol,
+                                                      double *out) {
+    __shared__ double s0[BLOCK], s1[BLOCK];
+    double a = 0.0, b = 0.0;
+    for (int64_t c = threadIdx.x; c < ncol; c += BLOCK) {
+        a += pgrad[c];
+        b += pgrad[ld + c];
+    }
+    s0[threadIdx.x] = a;
+    s1[threadIdx.x] = b;
+    __syncthreads();
+    for (int h = BLOCK / 2; h > 0; h /= 2) {
+        if ((int)threadIdx.x < h) {
+            s0[threadIdx.x] += s0[threadIdx.x + h];
+            s1[threadIdx.x] += s1[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = s0[0];
+        out[1] = s1[0];
+    }
+}
+
+struct AdjLayout {
+    size_t cnt, list, pgrad, scr, total;
+    int64_t threads;
+};
+
+AdjLayout adj_layout(int64_t ncol, int nlev, int cus) {
+    AdjLayout l{};
+    const int64_t n = ncol > 0 ? ncol : 1;
+    const int64_t tiles = (n + BLOCK - 1) / BLOCK;
+    const int64_t cap = (int64_t)cus;  // one persistent block per compute unit
+    l.threads = (tiles < cap ? tiles : cap) * BLOCK;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = (off + bytes + 255) & ~size_t(255);
+        return o;
+    };
+    l.cnt = take(NCOUNTERS * sizeof(int));
+    l.list = take(n * sizeof(int));
+    l.pgrad = 0;  // per-column values live in a [2][ld] region sized at call time
+    l.scr = take((size_t)N_ADJ * (nlev + 1) * l.threads * sizeof(double));
+    l.total = off;
+    return l;
+}
+
+__global__ void k_adj_reset(int *cnt) {
+    if (threadIdx.x < NCOUNTERS) cnt[threadIdx.x] = 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t conv_backward_workspace_bytes(int64_t ncol, int32_t nlev, int64_t ld) {
+    if (ncol < 0 || ncol > INT32_MAX || nlev < 2 || nlev > 256 || ld < ncol) return 0;
+    const AdjLayout l = adj_layout(ncol, nlev, device_cus());
+    return l.total + (size_t)2 * (ld > 0 ? ld : 1) * sizeof(double) + 256;
+}
+
+int conv_deep_backward(conv_ctx_t *ctx, const conv_state_t *state, const conv_deep_out_t *fwd,
+                       const conv_deep_cot_t *cot, conv_deep_grad_t *grad, void *workspace,
+                       size_t ws_bytes, void *stream) {
+    if (!ctx || !state || !fwd || !cot || !grad || !workspace) return CONV_EINVAL;
+    if (!state->T || !state->q || !state->p_mid || !state->z || !state->p_int || !state->phis ||
+        state->ld < ctx->ncol || !(state->dt > 0.0))
+        return CONV_EINVAL;
+    if (!fwd->status || !fwd->klaunch || !fwd->ktop || !grad->g_T || !grad->g_q || !grad->g_params)
+        return CONV_EINVAL;
+    if (((uintptr_t)workspace & 255u) != 0) return CONV_EINVAL;
+    const AdjLayout l = adj_layout(ctx->ncol, ctx->nlev, ctx->cus);
+    const int64_t ld = state->ld;
+    if (ws_bytes < l.total + (size_t)2 * ld * sizeof(double)) return CONV_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    if (ctx->ncol == 0) {
+        hipLaunchKernelGGL(k_adj_reduce, dim3(1), dim3(BLOCK), 0, st, (const double *)nullptr,
+                           (int64_t)0, (int64_t)0, grad->g_params);
+        return check_launch();
+    }
+    char *b = (char *)workspace;
+    Member M = make_member(ctx->ncol, ctx->nlev, ctx->P, state, fwd, nullptr, 0);
+    AdjWork w;
+    w.cnt = (int *)(b + l.cnt);
+    w.list = (int *)(b + l.list);
+    w.scr = (double *)(b + l.scr);
+    w.pgrad = (double *)(b + l.total);
+    w.stride = l.threads;
+    w.lmax = ctx->nlev;
+    w.cT = cot->g_dTdt;
+    w.cq = cot->g_dqdt;
+    w.cP = cot->g_prec;
+    w.gT = grad->g_T;
+    w.gq = grad->g_q;
+    const unsigned gcols = (unsigned)((ctx->ncol + BLOCK - 1) / BLOCK);
+    hipLaunchKernelGGL(k_adj_reset, dim3(1), dim3(NCOUNTERS), 0, st, w.cnt);
+    hipLaunchKernelGGL(k_adj_compact, dim3(gcols), dim3(BLOCK), 0, st, M, w);
+    hipLaunchKernelGGL(k_deep_adjoint, dim3((unsigned)(l.threads / BLOCK)), dim3(BLOCK), 0, st, M, w);
+    hipLaunchKernelGGL(k_adj_reduce, dim3(1), dim3(BLOCK), 0, st, (const double *)w.pgrad, ld,
+                       ctx->ncol, grad->g_params);
+    return check_launch();
+}
+
+}  // extern "C"

@@ -1,0 +1,125 @@
+// conv_internal.hpp -- types and helpers shared by the library's translation units (forward
+// kernels in conv.hip, adjoint kernels in conv_adjoint.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include "conv.h"
+#include "conv_physics.hpp"
+
+namespace cvk {
+
+constexpr int BLOCK = 256;
+constexpr int WAVE = 64;
+constexpr int NWAVES = BLOCK / WAVE;
+constexpr int NCOUNTERS = 64;
+
+// One grid of columns with its arrays and parameters.
+struct Member {
+    const double *T, *q, *pm, *pi, *z, *phis, *pblh, *tke;
+    int64_t ld;
+    double dt;
+    int64_t ncol;
+    int64_t tile0;  // first tile of this member in the launch's tile space
+    int nlev, pad_;
+    conv_params_t P;
+    conv_deep_out_t dout;
+    conv_shallow_out_t sout;
+};
+
+struct One {
+    Member m;
+    int64_t ntiles;
+    __device__ const Member &at(int) const { return m; }
+    __device__ int find(int64_t) const { return 0; }
+};
+
+struct Many {
+    const Member *ms;  // device table, ascending tile0
+    int nm;
+    int64_t ntiles;
+    __device__ const Member &at(int i) const { return ms[i]; }
+    __device__ int find(int64_t tile) const {
+        int i = 0;
+        while (i + 1 < nm && ms[i + 1].tile0 <= tile) ++i;
+        return i;
+    }
+};
+
+#define AT(arr, k) (arr)[(int64_t)(k) * ld + col]
+
+
+// ------------------------------------------------------------------ wavefront compaction
+// Appends the lanes with `pred` set to the list counted by *counter: one ballot, one popcount and
+// one atomicAdd per wavefront.  Must be reached by every lane of the wavefront.
+__device__ __forceinline__ int wave_append(bool pred, int *counter) {
+    const unsigned long long m = __ballot(pred);
+    if (m == 0ull) return -1;
+    const int lane = __lane_id();
+    const int leader = __ffsll((long long)m) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(counter, (int)__popcll(m));
+    base = __shfl(base, leader);
+    return pred ? base + (int)__popcll(m & ((1ull << lane) - 1ull)) : -1;
+}
+
+// Launch shape: persistent blocks per compute unit for the fused and the shallow-plume kernels.
+struct Launch {
+    int fused_bpc, shallow_bpc;
+};
+constexpr int MAX_BPC = 8;
+constexpr Launch DEFAULT_LAUNCH = {4, 2};
+
+struct Layout {
+    size_t cnt, dlist, dmem, dkb, dkt, dcape, dSA, dSB;
+    size_t slist, smem, sks, sflag, shs, sqs, scin, sMc, ssig2, members, dscr, sscr, total;
+    int64_t threads;  // largest persistent grid (threads) the launch shape allows
+    int lmax;
+};
+
+int device_cus();   // compute units of the current device (256 if it cannot be queried)
+int check_launch();  // CONV_OK, or CONV_EHIP after recording the pending launch error
+
+inline Member make_member(int64_t ncol, int nlev, const conv_params_t &P, const conv_state_t *s,
+                   const conv_deep_out_t *d, const conv_shallow_out_t *sh, int64_t tile0) {
+    Member m;
+    memset(&m, 0, sizeof(m));
+    m.T = s->T;
+    m.q = s->q;
+    m.pm = s->p_mid;
+    m.pi = s->p_int;
+    m.z = s->z;
+    m.phis = s->phis;
+    m.pblh = s->pblh;
+    m.tke = s->tke;
+    m.ld = s->ld;
+    m.dt = s->dt;
+    m.ncol = ncol;
+    m.tile0 = tile0;
+    m.nlev = nlev;
+    m.P = P;
+    if (d) m.dout = *d;
+    if (sh) m.sout = *sh;
+    return m;
+}
+
+}  // namespace cvk
+
+constexpr int CONV_NSTAGES = 4;  // reset, trigger, deep plume, shallow plume
+
+struct conv_ctx {
+    int64_t ncol;
+    int nlev;
+    conv_params_t P;
+    char *ws;
+    size_t ws_bytes;
+    cvk::Layout lay;
+    cvk::Launch launch;
+    int cus;
+    // Optional per-kernel timing: CONV_NSTAGES+1 events per recorded call.
+    hipEvent_t *ev;
+    int ev_cap, ev_used;
+};
+
