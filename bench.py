@@ -63,6 +63,78 @@ def cpu_baseline(st, threads):
     return st["ncol"] / dt, dt
 
 
+def time_events(torch, fn, reps, stream=None):
+    """Average ms of `fn()` over `reps` calls, bracketed by events on `stream` (default: current)."""
+    stream = stream or torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def bench_adjoint(torch, B, S, reps):
+    """Deep forward and hand-written adjoint on the 288x192 = 55,296-column x 30-level grid with the
+    loss sum(a*dTdt^2 + b*(Lv/cp*dqdt)^2), a, b ~ N(0,1)."""
+    st = S.grid_1deg(NLEV)
+    n = st["ncol"]
+    dev = B.to_device(st)
+    conv = B.Conv(n, NLEV)
+    out = conv.deep_forward(dev)
+    g = torch.Generator(device="cpu").manual_seed(4)
+    a = torch.randn(NLEV, n, generator=g, dtype=torch.float64).cuda()
+    b = torch.randn(NLEV, n, generator=g, dtype=torch.float64).cuda()
+    lvcp = 2.501e6 / 1004.64
+    cT = 2.0 * a * out["dTdt"]
+    cq = 2.0 * b * lvcp ** 2 * out["dqdt"]
+    for _ in range(3):
+        conv.deep_forward(dev, out)
+        conv.deep_backward(dev, out, cT, cq, None)
+    fwd = time_events(torch, lambda: conv.deep_forward(dev, out), reps)
+    bwd = time_events(torch, lambda: conv.deep_backward(dev, out, cT, cq, None), reps)
+    return {"workload": "deep adjoint, 288x192 = 55,296 columns x 30 levels",
+            "forward_ms": fwd, "backward_ms": bwd, "ratio": bwd / fwd,
+            "active_fraction": float((out["status"] == 0).double().mean())}
+
+
+def bench_ensemble(torch, B, S, main_state, main_deep, main_shallow, reps, tune=True):
+    """The 884,736-column grid plus 16 members of 55,296 columns (30/46/72 levels, tau 1800/3600/
+    7200 s) as one ensemble: autotuned launch shape, captured HIP graph, timed replays; and the
+    same members stepped one after the other for comparison."""
+    members = [dict(state=main_state, nlev=NLEV, ncol=main_state["ncol"],
+                    params=B.make_params(), deep=main_deep, shallow=main_shallow)]
+    for m in range(16):
+        sp = S.ensemble_member_spec(m)
+        members.append(dict(state=B.to_device(S.ensemble_member(m)), nlev=sp["nlev"],
+                            ncol=sp["ncol"], params=B.make_params(tau=sp["tau"])))
+    ens = B.Ensemble(members)
+    if tune:
+        ens.autotune(reps=5)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    ens.capture(side)
+    for _ in range(3):
+        ens.replay(side)
+    ms = time_events(torch, lambda: ens.replay(side), reps, stream=side)
+    convs = [B.Conv(m["ncol"], m["nlev"], m["params"]) for m in ens.members]
+
+    def separate():
+        for c, m in zip(convs, ens.members):
+            c.step(m["state"], m["deep"], m["shallow"])
+
+    separate()
+    sep = time_events(torch, separate, max(2, reps // 4))
+    ncol = sum(m["ncol"] for m in ens.members)
+    return {"workload": "884,736x30 grid + 16 members x 55,296 columns (nlev 30/46/72, "
+                        "tau 1800/3600/7200 s), one captured graph per step",
+            "columns": ncol, "ms_per_step": ms, "columns_per_s": ncol / (ms * 1e-3),
+            "launch_blocks_per_cu": list(ens.get_launch()), "separate_calls_ms": sep,
+            "batching_speedup": sep / ms}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -71,6 +143,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--ncol", type=int, default=NLON * NLAT)
     ap.add_argument("--launch", type=str, default="", help="deep,shallow plume blocks per CU")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default launch shape")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="time only the headline step (no adjoint, ensemble)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after timing, copy a MIB-MiB device buffer once (a plain copy kernel of "
                          "known size for scaling hardware byte counters)")
@@ -96,10 +171,12 @@ def main():
           file=sys.stderr, flush=True)
     dev = B.to_device(st)
     conv = B.Conv(n, NLEV)
-    if args.launch:
-        conv.set_launch(*[int(x) for x in args.launch.split(",")])
     deep = conv.alloc_deep(n)
     shallow = conv.alloc_shallow(n)
+    if args.launch:
+        conv.set_launch(*[int(x) for x in args.launch.split(",")])
+    elif not args.no_tune:
+        conv.autotune(dev, deep, shallow, reps=5)
     torch.cuda.synchronize()
 
     for _ in range(args.warmup):
@@ -172,6 +249,13 @@ def main():
                             "shallow": float((sst == 0).mean())},
         "wall_s_timed": wall,
     }
+
+    if not args.no_extras:
+        out["adjoint"] = bench_adjoint(torch, B, S, max(args.steps, 10))
+        print("[bench] adjoint done", file=sys.stderr, flush=True)
+        out["ensemble"] = bench_ensemble(torch, B, S, dev, deep, shallow, max(args.steps, 10),
+                                         tune=not args.no_tune)
+        print("[bench] ensemble done", file=sys.stderr, flush=True)
 
     if not args.no_cpu:
         threads = min(16, len(os.sched_getaffinity(0)))

@@ -154,6 +154,62 @@ int conv_deep_backward(conv_ctx_t *ctx, const conv_state_t *state, const conv_de
                        const conv_deep_cot_t *cot, conv_deep_grad_t *grad, void *workspace,
                        size_t ws_bytes, void *stream);
 
+/* ---------------------------------------------------------------- batched ensemble
+ * Several grids ("members", e.g. ensemble members of a forecast) with their own column counts,
+ * level counts (2..256), parameters and arrays, advanced by one conv_step each in the SAME kernel
+ * launches: the trigger launch covers every member's tiles and the plume launches run over one
+ * compacted list of active columns drawn from all members.  This is the batching counterpart of
+ * the paper's chunked column loop (Methodology, load balancing): uneven members share the GPU
+ * instead of running one after the other.  Per-column results are bit-identical to conv_step on
+ * each member alone. */
+typedef struct conv_ens conv_ens_t; /* opaque host-side handle */
+
+typedef struct {
+    int64_t ncol;                /* >= 0; a member with 0 columns may leave its pointers NULL */
+    int32_t nlev;                /* 2..256 */
+    conv_params_t params;
+    conv_state_t state;          /* device pointers, as for conv_step */
+    conv_deep_out_t deep;        /* device pointers, written */
+    conv_shallow_out_t shallow;  /* device pointers, written */
+} conv_member_t;
+
+/* Workspace bytes for these members (0 if any member is malformed). */
+size_t conv_ensemble_workspace_bytes(int n_members, const conv_member_t *members);
+
+/* Copies the member table (host array, 1..4096 entries) into the 256-byte aligned, caller-owned
+ * device workspace (a synchronous host-to-device copy on the current device) and returns a handle.
+ * The members' arrays must stay valid while the handle is used. */
+int conv_ensemble_create(int n_members, const conv_member_t *members, void *workspace,
+                         size_t ws_bytes, conv_ens_t **out);
+void conv_ensemble_destroy(conv_ens_t *e); /* frees the host handle and any captured graph */
+
+/* One step of every member on `stream` (four kernel launches in all, no host synchronisation, no
+ * memset nodes: capturable). */
+int conv_ensemble_step(conv_ens_t *e, void *stream);
+
+/* Persistent-grid shape (blocks per compute unit, 1..8) of the plume kernels.  Changing it drops a
+ * captured graph. */
+int conv_ensemble_set_launch(conv_ens_t *e, int fused_blocks_per_cu, int shallow_blocks_per_cu);
+int conv_ensemble_get_launch(conv_ens_t *e, int *fused_blocks_per_cu, int *shallow_blocks_per_cu);
+
+/* Autotuner: times conv_ensemble_step (median of `reps` runs, 1..1000) for every candidate shape
+ * in {1,2,3,4,6,8} x {1,2,4,8} and keeps the fastest.  Results are cached per process, keyed by
+ * device and member shapes; `force` != 0 re-tunes.  Runs steps (the outputs are overwritten) and
+ * waits on the host, so it may not be called during capture.  Outputs may be NULL. */
+int conv_ensemble_autotune(conv_ens_t *e, void *stream, int reps, int force,
+                           int *fused_blocks_per_cu, int *shallow_blocks_per_cu, float *ms);
+
+/* Captures one conv_ensemble_step on `stream` (not the null stream) into a HIP graph owned by the
+ * handle, replacing any earlier one; conv_ensemble_replay launches it (CONV_EINVAL if there is
+ * none).  A replay reads the member table and arrays as they are when it runs. */
+int conv_ensemble_capture(conv_ens_t *e, void *stream);
+int conv_ensemble_replay(conv_ens_t *e, void *stream);
+
+/* The same autotuner for a single context's conv_step on (state, deep, shallow). */
+int conv_autotune(conv_ctx_t *ctx, const conv_state_t *state, conv_deep_out_t *deep,
+                  conv_shallow_out_t *shallow, void *stream, int reps, int force,
+                  int *fused_blocks_per_cu, int *shallow_blocks_per_cu, float *ms);
+
 /* Launch shape of the persistent kernels: blocks of 256 threads per compute unit for the
  * deep-plume kernel and for the shallow-plume kernel (each 1..8; default 4 and 2).  The
  * workspace size does not depend on it.  Results do not depend on it (bit-identical). */

@@ -29,7 +29,10 @@ EXPORTS = ("conv_workspace_bytes", "conv_create", "conv_set_params", "conv_destr
            "conv_deep_forward", "conv_shallow_forward", "conv_step", "conv_set_launch",
            "conv_get_launch", "conv_timing_start",
            "conv_timing_read", "conv_strerror", "conv_last_hip_error",
-           "conv_backward_workspace_bytes", "conv_deep_backward")
+           "conv_backward_workspace_bytes", "conv_deep_backward", "conv_autotune",
+           "conv_ensemble_workspace_bytes", "conv_ensemble_create", "conv_ensemble_destroy",
+           "conv_ensemble_step", "conv_ensemble_set_launch", "conv_ensemble_get_launch",
+           "conv_ensemble_autotune", "conv_ensemble_capture", "conv_ensemble_replay")
 
 
 class Params(C.Structure):
@@ -58,6 +61,11 @@ class DeepCot(C.Structure):
 
 class DeepGrad(C.Structure):
     _fields_ = [(n, C.c_void_p) for n in ("g_T", "g_q", "g_params")]
+
+
+class Member(C.Structure):
+    _fields_ = [("ncol", C.c_int64), ("nlev", C.c_int32), ("params", Params), ("state", State),
+                ("deep", DeepOut), ("shallow", ShallowOut)]
 
 
 _lib = None
@@ -102,6 +110,28 @@ def lib():
         L.conv_deep_backward.argtypes = [C.c_void_p, C.POINTER(State), C.POINTER(DeepOut),
                                          C.POINTER(DeepCot), C.POINTER(DeepGrad), C.c_void_p,
                                          C.c_size_t, C.c_void_p]
+        I, P = C.c_int, C.POINTER(C.c_int)
+        L.conv_autotune.restype = I
+        L.conv_autotune.argtypes = [C.c_void_p, C.POINTER(State), C.POINTER(DeepOut),
+                                    C.POINTER(ShallowOut), C.c_void_p, I, I, P, P,
+                                    C.POINTER(C.c_float)]
+        L.conv_ensemble_workspace_bytes.restype = C.c_size_t
+        L.conv_ensemble_workspace_bytes.argtypes = [I, C.POINTER(Member)]
+        L.conv_ensemble_create.restype = I
+        L.conv_ensemble_create.argtypes = [I, C.POINTER(Member), C.c_void_p, C.c_size_t,
+                                           C.POINTER(C.c_void_p)]
+        L.conv_ensemble_destroy.restype = None
+        L.conv_ensemble_destroy.argtypes = [C.c_void_p]
+        for f in ("conv_ensemble_step", "conv_ensemble_capture", "conv_ensemble_replay"):
+            getattr(L, f).restype = I
+            getattr(L, f).argtypes = [C.c_void_p, C.c_void_p]
+        L.conv_ensemble_set_launch.restype = I
+        L.conv_ensemble_set_launch.argtypes = [C.c_void_p, I, I]
+        L.conv_ensemble_get_launch.restype = I
+        L.conv_ensemble_get_launch.argtypes = [C.c_void_p, P, P]
+        L.conv_ensemble_autotune.restype = I
+        L.conv_ensemble_autotune.argtypes = [C.c_void_p, C.c_void_p, I, I, P, P,
+                                             C.POINTER(C.c_float)]
         L.conv_strerror.restype = C.c_char_p
         L.conv_strerror.argtypes = [C.c_int]
         L.conv_last_hip_error.restype = C.c_int
@@ -150,6 +180,42 @@ def to_device(st: dict, device="cuda", ld: int | None = None):
     return out
 
 
+def alloc_deep(torch, device, nlev: int, ld: int) -> dict:
+    """Device output arrays of the deep scheme for `ld` columns."""
+    f = lambda *sh: torch.empty(*sh, dtype=torch.float64, device=device)
+    i = lambda n: torch.empty(n, dtype=torch.int32, device=device)
+    L = nlev
+    return dict(dTdt=f(L, ld), dqdt=f(L, ld), mu=f(L + 1, ld), md=f(L + 1, ld), prec=f(ld),
+                cape=f(ld), klaunch=i(ld), ktop=i(ld), trig=i(ld), status=i(ld))
+
+
+def alloc_shallow(torch, device, nlev: int, ld: int) -> dict:
+    """Device output arrays of the shallow scheme for `ld` columns."""
+    f = lambda *sh: torch.empty(*sh, dtype=torch.float64, device=device)
+    i = lambda n: torch.empty(n, dtype=torch.int32, device=device)
+    L = nlev
+    return dict(dTdt=f(L, ld), dqdt=f(L, ld), mu=f(L + 1, ld), prec=f(ld), cin=f(ld),
+                kbase=i(ld), ktop=i(ld), status=i(ld))
+
+
+def state_struct(torch, s: dict, nlev: int, ncol: int) -> State:
+    """conv_state_t over a device state dict, after checking shapes, dtypes and contiguity."""
+    T = s["T"]
+    if T.dim() != 2 or T.shape[0] != nlev or T.shape[1] < ncol:
+        raise ValueError("state arrays must be [nlev][ld] with ld >= ncol")
+    ld = T.shape[1]
+    for k, rows in (("T", nlev), ("q", nlev), ("p_mid", nlev), ("z", nlev), ("p_int", nlev + 1)):
+        a = s[k]
+        if a.dtype != torch.float64 or not a.is_contiguous() or tuple(a.shape) != (rows, ld):
+            raise ValueError(f"{k}: expected contiguous float64 [{rows}][{ld}]")
+    for k in ("phis", "pblh", "tke"):
+        a = s[k]
+        if a.dtype != torch.float64 or a.numel() < ld:
+            raise ValueError(f"{k}: expected float64 [{ld}]")
+    return State(*[s[k].data_ptr() for k in ("T", "q", "p_mid", "z", "p_int", "phis", "pblh",
+                                              "tke")], ld, float(s["dt"]))
+
+
 class Conv:
     """A context over `ncol` columns of `nlev` levels with a torch-allocated workspace."""
 
@@ -187,39 +253,15 @@ class Conv:
     def _f64(self, *shape):
         return self.torch.empty(*shape, dtype=self.torch.float64, device=self.device)
 
-    def _i32(self, n):
-        return self.torch.empty(n, dtype=self.torch.int32, device=self.device)
-
     def alloc_deep(self, ld: int):
-        L = self.nlev
-        return dict(dTdt=self._f64(L, ld), dqdt=self._f64(L, ld), mu=self._f64(L + 1, ld),
-                    md=self._f64(L + 1, ld), prec=self._f64(ld), cape=self._f64(ld),
-                    klaunch=self._i32(ld), ktop=self._i32(ld), trig=self._i32(ld),
-                    status=self._i32(ld))
+        return alloc_deep(self.torch, self.device, self.nlev, ld)
 
     def alloc_shallow(self, ld: int):
-        L = self.nlev
-        return dict(dTdt=self._f64(L, ld), dqdt=self._f64(L, ld), mu=self._f64(L + 1, ld),
-                    prec=self._f64(ld), cin=self._f64(ld), kbase=self._i32(ld),
-                    ktop=self._i32(ld), status=self._i32(ld))
+        return alloc_shallow(self.torch, self.device, self.nlev, ld)
 
     # -- marshalling ---------------------------------------------------------------------
     def _state(self, s: dict) -> State:
-        T = s["T"]
-        if T.dim() != 2 or T.shape[0] != self.nlev or T.shape[1] < self.ncol:
-            raise ValueError("state arrays must be [nlev][ld] with ld >= ncol")
-        ld = T.shape[1]
-        for k, rows in (("T", self.nlev), ("q", self.nlev), ("p_mid", self.nlev),
-                        ("z", self.nlev), ("p_int", self.nlev + 1)):
-            a = s[k]
-            if a.dtype != self.torch.float64 or not a.is_contiguous() or tuple(a.shape) != (rows, ld):
-                raise ValueError(f"{k}: expected contiguous float64 [{rows}][{ld}]")
-        for k in ("phis", "pblh", "tke"):
-            a = s[k]
-            if a.dtype != self.torch.float64 or a.numel() < ld:
-                raise ValueError(f"{k}: expected float64 [{ld}]")
-        return State(*[s[k].data_ptr() for k in ("T", "q", "p_mid", "z", "p_int", "phis", "pblh",
-                                                  "tke")], ld, float(s["dt"]))
+        return state_struct(self.torch, s, self.nlev, self.ncol)
 
     @staticmethod
     def _deep_struct(o):
@@ -287,6 +329,17 @@ class Conv:
                                    C.c_void_p(wptr), nbytes, _stream(torch)), "conv_deep_backward")
         return dict(g_T=gT, g_q=gq, g_tau=gp[0], g_eps=gp[1])
 
+    def autotune(self, s: dict, deep: dict, shallow: dict, reps: int = 5, force: bool = False):
+        """Pick the fastest persistent-grid shape for conv_step on these arrays (cached per
+        process); returns (fused_blocks_per_cu, shallow_blocks_per_cu, median_ms)."""
+        st = self._state(s)
+        d, h = self._deep_struct(deep), self._shallow_struct(shallow)
+        a, b, ms = C.c_int(0), C.c_int(0), C.c_float(0.0)
+        check(lib().conv_autotune(self.h, C.byref(st), C.byref(d), C.byref(h), _stream(self.torch),
+                                  int(reps), int(force), C.byref(a), C.byref(b), C.byref(ms)),
+              "conv_autotune")
+        return a.value, b.value, ms.value
+
     # -- instrumentation -----------------------------------------------------------------
     STAGES = ("reset", "trigger", "deep_plume", "shallow_plume")
 
@@ -353,3 +406,81 @@ def deep_conv(conv: "Conv", state: dict, T, q, tau, eps_deep):
     if _DeepConv is None:
         _DeepConv = _autograd()
     return _DeepConv.apply(T, q, tau, eps_deep, conv, state)
+
+
+class Ensemble:
+    """Several grids stepped by the same launches (conv_ensemble_*).  `members` is a list of dicts
+    with a device state (from to_device), `nlev`, and optionally `params`, `deep`, `shallow`
+    (output dicts as from Conv.alloc_*; allocated here when missing)."""
+
+    def __init__(self, members, device="cuda"):
+        torch = _torch()
+        self.torch = torch
+        self.device = device
+        self.members = []
+        tab = (Member * len(members))()
+        for i, m in enumerate(members):
+            s = m["state"]
+            nlev = int(m["nlev"])
+            ncol = int(m.get("ncol", s["ncol"]))
+            ld = s["T"].shape[1]
+            deep = m.get("deep") or alloc_deep(torch, device, nlev, ld)
+            shallow = m.get("shallow") or alloc_shallow(torch, device, nlev, ld)
+            params = m.get("params") or make_params()
+            tab[i] = Member(ncol, nlev, params, state_struct(torch, s, nlev, ncol),
+                            Conv._deep_struct(deep), Conv._shallow_struct(shallow))
+            self.members.append(dict(state=s, nlev=nlev, ncol=ncol, params=params, deep=deep,
+                                     shallow=shallow))
+        self.tab = tab
+        L = lib()
+        nbytes = L.conv_ensemble_workspace_bytes(len(members), tab)
+        if nbytes == 0:
+            raise ValueError("malformed ensemble members")
+        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        wptr = (self.ws.data_ptr() + 255) & ~255
+        h = C.c_void_p()
+        check(L.conv_ensemble_create(len(members), tab, C.c_void_p(wptr), nbytes, C.byref(h)),
+              "conv_ensemble_create")
+        self.h = h
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                lib().conv_ensemble_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+    def step(self, stream=None):
+        check(lib().conv_ensemble_step(self.h, self._s(stream)), "conv_ensemble_step")
+
+    def _s(self, stream):
+        if stream is None:
+            return _stream(self.torch)
+        return C.c_void_p(stream.cuda_stream)
+
+    def set_launch(self, fused: int, shallow: int):
+        check(lib().conv_ensemble_set_launch(self.h, int(fused), int(shallow)),
+              "conv_ensemble_set_launch")
+
+    def get_launch(self):
+        a, b = C.c_int(0), C.c_int(0)
+        check(lib().conv_ensemble_get_launch(self.h, C.byref(a), C.byref(b)),
+              "conv_ensemble_get_launch")
+        return a.value, b.value
+
+    def autotune(self, reps: int = 5, force: bool = False, stream=None):
+        a, b, ms = C.c_int(0), C.c_int(0), C.c_float(0.0)
+        check(lib().conv_ensemble_autotune(self.h, self._s(stream), int(reps), int(force),
+                                           C.byref(a), C.byref(b), C.byref(ms)),
+              "conv_ensemble_autotune")
+        return a.value, b.value, ms.value
+
+    def capture(self, stream):
+        """Capture one step into a HIP graph on `stream` (a torch.cuda.Stream, not the default)."""
+        check(lib().conv_ensemble_capture(self.h, C.c_void_p(stream.cuda_stream)),
+              "conv_ensemble_capture")
+
+    def replay(self, stream):
+        check(lib().conv_ensemble_replay(self.h, C.c_void_p(stream.cuda_stream)),
+              "conv_ensemble_replay")

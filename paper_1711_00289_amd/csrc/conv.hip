@@ -25,6 +25,12 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
 #include "conv.h"
 #include "conv_internal.hpp"
 
@@ -839,10 +845,8 @@ Layout make_layout(int64_t ncol, int lmax, int nmem, int cus) {
 
 namespace {
 
-Work make_work(const conv_ctx *c) {
+Work make_work(char *b, const Layout &l, const Launch &launch, int cus) {
     Work w;
-    char *b = c->ws;
-    const Layout &l = c->lay;
     w.cnt = (int *)(b + l.cnt);
     w.dlist = (int *)(b + l.dlist);
     w.dmem = (int *)(b + l.dmem);
@@ -862,8 +866,8 @@ Work make_work(const conv_ctx *c) {
     w.ssig2 = (double *)(b + l.ssig2);
     w.dscr = (double *)(b + l.dscr);
     w.sscr = (double *)(b + l.sscr);
-    const int64_t fd = (int64_t)c->cus * c->launch.fused_bpc * BLOCK;
-    const int64_t sh = (int64_t)c->cus * c->launch.shallow_bpc * BLOCK;
+    const int64_t fd = (int64_t)cus * launch.fused_bpc * BLOCK;
+    const int64_t sh = (int64_t)cus * launch.shallow_bpc * BLOCK;
     w.dstride = fd < l.threads ? fd : l.threads;
     w.sstride = sh < l.threads ? sh : l.threads;
     w.lmax = l.lmax;
@@ -889,13 +893,12 @@ bool shallow_ok(const conv_shallow_out_t *o) {
 
 int finish() { return check_launch(); }
 
+// The step's launches on `st`; `ev` (CONV_NSTAGES+1 events, may be null) brackets each stage.
 template <class Src, bool DEEP, bool SHALLOW>
-int launch_step(conv_ctx *c, const Src &src, const Work &w, hipStream_t st) {
+int launch_step(const Src &src, const Work &w, hipStream_t st, hipEvent_t *ev) {
     const unsigned gt = (unsigned)src.ntiles;
     const unsigned gd = (unsigned)(w.dstride / BLOCK);
     const unsigned gs = (unsigned)(w.sstride / BLOCK);
-    hipEvent_t *ev = nullptr;
-    if (c->ev && c->ev_used < c->ev_cap) ev = c->ev + (size_t)(c->ev_used++) * (CONV_NSTAGES + 1);
     if (ev) (void)hipEventRecord(ev[0], st);
     hipLaunchKernelGGL(k_reset, dim3(1), dim3(NCOUNTERS), 0, st, w.cnt);
     if (ev) (void)hipEventRecord(ev[1], st);
@@ -914,8 +917,95 @@ int run_one(conv_ctx *c, const conv_state_t *s, const conv_deep_out_t *d,
     One src;
     src.m = make_member(c->ncol, c->nlev, c->P, s, d, sh, 0);
     src.ntiles = (c->ncol + BLOCK - 1) / BLOCK;
-    const Work w = make_work(c);
-    return launch_step<One, DEEP, SHALLOW>(c, src, w, st);
+    const Work w = make_work(c->ws, c->lay, c->launch, c->cus);
+    hipEvent_t *ev = nullptr;
+    if (c->ev && c->ev_used < c->ev_cap) ev = c->ev + (size_t)(c->ev_used++) * (CONV_NSTAGES + 1);
+    return launch_step<One, DEEP, SHALLOW>(src, w, st, ev);
+}
+
+// ------------------------------------------------------------------ launch-shape autotuner
+// Candidate persistent-grid sizes (blocks per compute unit) for the deep-plume and shallow-plume
+// kernels; the trigger launch is one block per tile and has no shape to tune.
+constexpr int TUNE_FUSED[] = {1, 2, 3, 4, 6, 8};
+constexpr int TUNE_SHALLOW[] = {1, 2, 4, 8};
+
+struct TuneResult {
+    Launch launch;
+    float ms;
+};
+
+std::mutex g_tune_mu;
+std::map<std::string, TuneResult> g_tune_cache;  // per process, keyed by device and shapes
+
+// Times `run(shape)` (which enqueues one step on `st`) for every candidate shape: one untimed
+// call, then `reps` calls each bracketed by events; the score is the median.  Waits on the host.
+template <class Run>
+int tune(hipStream_t st, int reps, Run run, TuneResult *best) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        g_last_hip = (int)hipGetLastError();
+        return CONV_EHIP;
+    }
+    std::vector<float> t((size_t)reps);
+    TuneResult b{DEFAULT_LAUNCH, __builtin_inff()};
+    auto body = [&]() -> int {
+        for (int f : TUNE_FUSED) {
+            for (int sh : TUNE_SHALLOW) {
+                const Launch L{f, sh};
+                int rc = run(L);
+                if (rc != CONV_OK) return rc;
+                for (int r = 0; r < reps; ++r) {
+                    if (hipEventRecord(e0, st) != hipSuccess) return CONV_EHIP;
+                    rc = run(L);
+                    if (rc != CONV_OK) return rc;
+                    if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                        hipEventElapsedTime(&t[(size_t)r], e0, e1) != hipSuccess)
+                        return CONV_EHIP;
+                }
+                std::sort(t.begin(), t.end());
+                const float med = t[(size_t)reps / 2];
+                if (med < b.ms) b = TuneResult{L, med};
+            }
+        }
+        return CONV_OK;
+    };
+    const int rc = body();
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc == CONV_EHIP) g_last_hip = (int)hipGetLastError();
+    if (rc == CONV_OK) *best = b;
+    return rc;
+}
+
+std::string tune_key(const char *kind, int cus, const std::vector<std::pair<int64_t, int>> &shapes) {
+    int dev = -1;
+    (void)hipGetDevice(&dev);
+    std::string k = std::string(kind) + ":" + std::to_string(dev) + ":" + std::to_string(cus);
+    for (const auto &p : shapes) k += ":" + std::to_string(p.first) + "x" + std::to_string(p.second);
+    return k;
+}
+
+// Cached or freshly tuned shape for `key`.
+template <class Run>
+int tune_cached(const std::string &key, int force, hipStream_t st, int reps, Run run, TuneResult *out) {
+    if (!force) {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            *out = it->second;
+            return CONV_OK;
+        }
+    }
+    TuneResult r;
+    const int rc = tune(st, reps, run, &r);
+    if (rc != CONV_OK) return rc;
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        g_tune_cache[key] = r;
+    }
+    *out = r;
+    return CONV_OK;
 }
 
 void free_events(conv_ctx *c) {
@@ -925,6 +1015,73 @@ void free_events(conv_ctx *c) {
     }
     c->ev = nullptr;
     c->ev_cap = c->ev_used = 0;
+}
+
+}  // namespace
+
+// An ensemble: several grids (members) with their own column and level counts, parameters and
+// arrays, stepped by the same launches.  The member table lives in the workspace.
+struct conv_ens {
+    int nm;
+    int64_t ncol;  // all members
+    int64_t ntiles;
+    int lmax;
+    char *ws;
+    size_t ws_bytes;
+    cvk::Layout lay;
+    cvk::Launch launch;
+    int cus;
+    std::vector<std::pair<int64_t, int>> shapes;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+namespace {
+
+bool member_ok(const conv_member_t &m) {
+    if (m.ncol < 0 || m.ncol > INT32_MAX || m.nlev < 2 || m.nlev > 256) return false;
+    if (m.ncol == 0) return true;
+    return state_ok(m.ncol, &m.state, true) && deep_ok(&m.deep) && shallow_ok(&m.shallow);
+}
+
+// Totals of a member list; false if any member is malformed or the total is too large.
+bool ens_totals(int n, const conv_member_t *ms, int64_t *ncol, int64_t *ntiles, int *lmax) {
+    if (n < 1 || n > 4096 || !ms) return false;
+    int64_t c = 0, t = 0;
+    int l = 2;
+    for (int i = 0; i < n; ++i) {
+        if (!member_ok(ms[i])) return false;
+        c += ms[i].ncol;
+        t += (ms[i].ncol + BLOCK - 1) / BLOCK;
+        l = ms[i].nlev > l ? ms[i].nlev : l;
+    }
+    if (c > INT32_MAX) return false;
+    *ncol = c;
+    *ntiles = t;
+    *lmax = l;
+    return true;
+}
+
+int ens_launch(const conv_ens *e, const Launch &launch, hipStream_t st) {
+    if (e->ntiles == 0) return CONV_OK;
+    Many src;
+    src.ms = (const Member *)(e->ws + e->lay.members);
+    src.nm = e->nm;
+    src.ntiles = e->ntiles;
+    const Work w = make_work(e->ws, e->lay, launch, e->cus);
+    return launch_step<Many, true, true>(src, w, st, nullptr);
+}
+
+void ens_drop_graph(conv_ens *e) {
+    if (e->exec) (void)hipGraphExecDestroy(e->exec);
+    if (e->graph) (void)hipGraphDestroy(e->graph);
+    e->exec = nullptr;
+    e->graph = nullptr;
+}
+
+int hip_fail() {
+    g_last_hip = (int)hipGetLastError();
+    return CONV_EHIP;
 }
 
 }  // namespace
@@ -1054,5 +1211,147 @@ const char *conv_strerror(int code) {
 }
 
 int conv_last_hip_error(void) { return g_last_hip; }
+
+int conv_autotune(conv_ctx_t *ctx, const conv_state_t *state, conv_deep_out_t *deep,
+                  conv_shallow_out_t *shallow, void *stream, int reps, int force,
+                  int *fused_blocks_per_cu, int *shallow_blocks_per_cu, float *ms) {
+    if (!ctx || !state_ok(ctx->ncol, state, true) || !deep_ok(deep) || !shallow_ok(shallow) ||
+        reps < 1 || reps > 1000)
+        return CONV_EINVAL;
+    if (ctx->ncol == 0) return CONV_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    auto run = [&](const Launch &L) {
+        One src;
+        src.m = make_member(ctx->ncol, ctx->nlev, ctx->P, state, deep, shallow, 0);
+        src.ntiles = (ctx->ncol + BLOCK - 1) / BLOCK;
+        return launch_step<One, true, true>(src, make_work(ctx->ws, ctx->lay, L, ctx->cus), st,
+                                            nullptr);
+    };
+    TuneResult r;
+    const int rc = tune_cached(tune_key("step", ctx->cus, {{ctx->ncol, ctx->nlev}}), force, st, reps,
+                               run, &r);
+    if (rc != CONV_OK) return rc;
+    ctx->launch = r.launch;
+    if (fused_blocks_per_cu) *fused_blocks_per_cu = r.launch.fused_bpc;
+    if (shallow_blocks_per_cu) *shallow_blocks_per_cu = r.launch.shallow_bpc;
+    if (ms) *ms = r.ms;
+    return CONV_OK;
+}
+
+size_t conv_ensemble_workspace_bytes(int n_members, const conv_member_t *members) {
+    int64_t ncol, ntiles;
+    int lmax;
+    if (!ens_totals(n_members, members, &ncol, &ntiles, &lmax)) return 0;
+    return make_layout(ncol, lmax, n_members, device_cus()).total;
+}
+
+int conv_ensemble_create(int n_members, const conv_member_t *members, void *workspace,
+                         size_t ws_bytes, conv_ens_t **out) {
+    int64_t ncol, ntiles;
+    int lmax;
+    if (!out || !workspace || !ens_totals(n_members, members, &ncol, &ntiles, &lmax))
+        return CONV_EINVAL;
+    if (((uintptr_t)workspace & 255u) != 0) return CONV_EINVAL;
+    const int cus = device_cus();
+    const Layout l = make_layout(ncol, lmax, n_members, cus);
+    if (ws_bytes < l.total) return CONV_EINVAL;
+    std::vector<Member> tab((size_t)n_members);
+    int64_t tile0 = 0;
+    for (int i = 0; i < n_members; ++i) {
+        const conv_member_t &m = members[i];
+        tab[(size_t)i] = make_member(m.ncol, m.nlev, m.params, &m.state, &m.deep, &m.shallow, tile0);
+        tile0 += (m.ncol + BLOCK - 1) / BLOCK;
+    }
+    if (hipMemcpy((char *)workspace + l.members, tab.data(), tab.size() * sizeof(Member),
+                  hipMemcpyHostToDevice) != hipSuccess)
+        return hip_fail();
+    conv_ens *e = new conv_ens;
+    e->nm = n_members;
+    e->ncol = ncol;
+    e->ntiles = ntiles;
+    e->lmax = lmax;
+    e->ws = (char *)workspace;
+    e->ws_bytes = ws_bytes;
+    e->lay = l;
+    e->launch = DEFAULT_LAUNCH;
+    e->cus = cus;
+    for (int i = 0; i < n_members; ++i) e->shapes.emplace_back(members[i].ncol, members[i].nlev);
+    e->graph = nullptr;
+    e->exec = nullptr;
+    *out = e;
+    return CONV_OK;
+}
+
+void conv_ensemble_destroy(conv_ens_t *e) {
+    if (!e) return;
+    ens_drop_graph(e);
+    delete e;
+}
+
+int conv_ensemble_step(conv_ens_t *e, void *stream) {
+    if (!e) return CONV_EINVAL;
+    return ens_launch(e, e->launch, (hipStream_t)stream);
+}
+
+int conv_ensemble_set_launch(conv_ens_t *e, int fused_blocks_per_cu, int shallow_blocks_per_cu) {
+    if (!e || fused_blocks_per_cu < 1 || fused_blocks_per_cu > MAX_BPC || shallow_blocks_per_cu < 1 ||
+        shallow_blocks_per_cu > MAX_BPC)
+        return CONV_EINVAL;
+    e->launch = Launch{fused_blocks_per_cu, shallow_blocks_per_cu};
+    ens_drop_graph(e);
+    return CONV_OK;
+}
+
+int conv_ensemble_get_launch(conv_ens_t *e, int *fused_blocks_per_cu, int *shallow_blocks_per_cu) {
+    if (!e || !fused_blocks_per_cu || !shallow_blocks_per_cu) return CONV_EINVAL;
+    *fused_blocks_per_cu = e->launch.fused_bpc;
+    *shallow_blocks_per_cu = e->launch.shallow_bpc;
+    return CONV_OK;
+}
+
+int conv_ensemble_autotune(conv_ens_t *e, void *stream, int reps, int force,
+                           int *fused_blocks_per_cu, int *shallow_blocks_per_cu, float *ms) {
+    if (!e || reps < 1 || reps > 1000 || e->ntiles == 0) return CONV_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    auto run = [&](const Launch &L) { return ens_launch(e, L, st); };
+    TuneResult r;
+    const int rc = tune_cached(tune_key("ensemble", e->cus, e->shapes), force, st, reps, run, &r);
+    if (rc != CONV_OK) return rc;
+    if (r.launch.fused_bpc != e->launch.fused_bpc || r.launch.shallow_bpc != e->launch.shallow_bpc)
+        ens_drop_graph(e);
+    e->launch = r.launch;
+    if (fused_blocks_per_cu) *fused_blocks_per_cu = r.launch.fused_bpc;
+    if (shallow_blocks_per_cu) *shallow_blocks_per_cu = r.launch.shallow_bpc;
+    if (ms) *ms = r.ms;
+    return CONV_OK;
+}
+
+int conv_ensemble_capture(conv_ens_t *e, void *stream) {
+    if (!e || !stream) return CONV_EINVAL;
+    ens_drop_graph(e);
+    hipStream_t st = (hipStream_t)stream;
+    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) return hip_fail();
+    const int rc = ens_launch(e, e->launch, st);
+    hipGraph_t g = nullptr;
+    const hipError_t end = hipStreamEndCapture(st, &g);
+    if (rc != CONV_OK || end != hipSuccess || !g) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc != CONV_OK ? rc : hip_fail();
+    }
+    hipGraphExec_t x = nullptr;
+    if (hipGraphInstantiate(&x, g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return hip_fail();
+    }
+    e->graph = g;
+    e->exec = x;
+    return CONV_OK;
+}
+
+int conv_ensemble_replay(conv_ens_t *e, void *stream) {
+    if (!e || !e->exec) return CONV_EINVAL;
+    if (hipGraphLaunch(e->exec, (hipStream_t)stream) != hipSuccess) return hip_fail();
+    return CONV_OK;
+}
 
 }  // extern "C"

@@ -41,10 +41,16 @@ struct Many {
     int nm;
     int64_t ntiles;
     __device__ const Member &at(int i) const { return ms[i]; }
+    // The member holding `tile`: the last entry with tile0 <= tile (members without columns share
+    // their successor's tile0 and are skipped).
     __device__ int find(int64_t tile) const {
-        int i = 0;
-        while (i + 1 < nm && ms[i + 1].tile0 <= tile) ++i;
-        return i;
+        int lo = 0, hi = nm - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) / 2;
+            if (ms[mid].tile0 <= tile) lo = mid;
+            else hi = mid - 1;
+        }
+        return lo;
     }
 };
 

@@ -47,3 +47,58 @@ def test_argument_checks_without_gpu():
     assert L.conv_step(None, None, None, None, None) == binding.CONV_EINVAL
     assert L.conv_set_params(None, C.byref(p)) == binding.CONV_EINVAL
     assert L.conv_strerror(binding.CONV_EINVAL) == b"invalid argument"
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The binding's ctypes structures have the C compiler's sizes and offsets for every struct the
+    header declares (compiled here with gcc against include/conv.h)."""
+    import shutil
+    import subprocess
+
+    if not shutil.which("gcc"):
+        pytest.skip("no gcc")
+    checks = [("conv_params_t", binding.Params, [f for f, _ in binding.Params._fields_]),
+              ("conv_state_t", binding.State, [f for f, _ in binding.State._fields_]),
+              ("conv_deep_out_t", binding.DeepOut, [f for f, _ in binding.DeepOut._fields_]),
+              ("conv_shallow_out_t", binding.ShallowOut, [f for f, _ in binding.ShallowOut._fields_]),
+              ("conv_deep_cot_t", binding.DeepCot, [f for f, _ in binding.DeepCot._fields_]),
+              ("conv_deep_grad_t", binding.DeepGrad, [f for f, _ in binding.DeepGrad._fields_]),
+              ("conv_member_t", binding.Member, [f for f, _ in binding.Member._fields_])]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "conv.h"', "int main(void) {"]
+    for cname, _, fields in checks:
+        lines.append(f'printf("%zu\\n", sizeof({cname}));')
+        for f in fields:
+            lines.append(f'printf("%zu\\n", offsetof({cname}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    got = iter(int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True,
+                                              text=True).stdout.split())
+    for cname, cls, fields in checks:
+        assert next(got) == C.sizeof(cls), cname
+        for f in fields:
+            assert next(got) == getattr(cls, f).offset, (cname, f)
+
+
+def test_ensemble_argument_checks_without_gpu():
+    if not os.path.exists(binding.LIB_PATH):
+        pytest.skip("libconv.so not built")
+    L = binding.lib()
+    h = C.c_void_p()
+    m = (binding.Member * 2)()
+    m[0].ncol, m[0].nlev = 10, 30  # null arrays
+    m[1].ncol, m[1].nlev = 0, 30
+    assert L.conv_ensemble_workspace_bytes(2, m) == 0
+    assert L.conv_ensemble_create(2, m, C.c_void_p(256), 1 << 30, C.byref(h)) == binding.CONV_EINVAL
+    assert L.conv_ensemble_create(0, m, C.c_void_p(256), 1 << 30, C.byref(h)) == binding.CONV_EINVAL
+    m[0].ncol = 0
+    m[0].nlev = 1
+    assert L.conv_ensemble_workspace_bytes(2, m) == 0
+    assert L.conv_ensemble_step(None, None) == binding.CONV_EINVAL
+    assert L.conv_ensemble_replay(None, None) == binding.CONV_EINVAL
+    assert L.conv_ensemble_capture(None, None) == binding.CONV_EINVAL
+    assert L.conv_ensemble_set_launch(None, 1, 1) == binding.CONV_EINVAL
+    assert L.conv_autotune(None, None, None, None, None, 1, 0, None, None, None) == binding.CONV_EINVAL
