@@ -25,7 +25,7 @@ enum : int {
     U_ETA, U_HM, U_QM, U_TU, U_QU, U_Q1, U_SAT, U_E, U_C,   // updraft (U_E, U_C per layer)
     D_AD, D_HD, D_TD, D_QD, D_Q1, D_ED, D_E1,               // downdraft (D_ED, D_E1 per layer)
     X_DT1, X_DQ1, X_UPW,                                    // unit tendencies, upwind flags
-    G_T, G_Q, G_ETA, G_TU, G_QU, G_HU, G_AD, G_TD, G_QD, G_HD, G_C, G_E1, G_DT1, G_DQ1,
+    G_T, G_Q, G_ETA, G_TU, G_QU, G_AD, G_TD, G_QD, G_C, G_E1, G_DT1, G_DQ1,
     N_ADJ
 };
 
@@ -374,83 +374,98 @@ __global__ __launch_bounds__(BLOCK) void k_deep_adjoint(Member M, AdjWork w) {
             for (int k = kt + 1; k <= kb; ++k) S(G_C, k) += gC1;
             for (int k = kd; k <= kb - 1; ++k) S(G_E1, k) += gE1;
         }
-        // D6 downdraft recurrence, in reverse (bottom layer first).
+        // D6 downdraft recurrence, in reverse (bottom layer first).  What an iteration adds to the
+        // adjoints of the interface above it (ad, q_d, h_d) is carried in registers to the next
+        // iteration, not written back to the scratch.
         if (kd >= 0) {
+            double cad = 0.0, cqd = 0.0, chd = 0.0;  // recurrence parts at interface k+1
+            double adk1 = S(D_AD, kb), hdk1 = S(D_HD, kb), qdk1 = S(D_QD, kb), zlo = zi(kb);
             for (int k = kb - 1; k >= kd + 1; --k) {
-                const double adk = S(D_AD, k), adk1 = S(D_AD, k + 1);
-                const double hdk = S(D_HD, k), hdk1 = S(D_HD, k + 1);
-                const double Ed = S(D_ED, k), qdk = S(D_QD, k), qdk1 = S(D_QD, k + 1);
-                const double Q1 = S(D_Q1, k + 1), q = qk(k), h = hk(k);
-                const double ge1 = S(G_E1, k);
-                double gad1 = S(G_AD, k + 1) + ge1 * qdk1;
-                const double gqd1 = S(G_QD, k + 1) + ge1 * adk1;
+                const double adk = S(D_AD, k), hdk = S(D_HD, k), qdk = S(D_QD, k);
+                const double Ed = S(D_ED, k), Q1 = S(D_Q1, k + 1), q = qk(k), h = hk(k);
+                const double ge1 = S(G_E1, k), zk = zi(k);
+                double gad1 = S(G_AD, k + 1) + cad + ge1 * qdk1;
+                const double gqd1 = S(G_QD, k + 1) + cqd + ge1 * adk1;
                 double gad0 = -ge1 * qdk;
-                S(G_QD, k) += -ge1 * adk;
                 double gEd = -ge1 * q;
-                double gq = -ge1 * Ed;
+                const double gq = -ge1 * Ed;
                 const double gTd1 = S(G_TD, k + 1) + gqd1 * Q1;
-                const double ghd1 = S(G_HD, k + 1) + gTd1 / (CP + LV * Q1);
-                gad0 += ghd1 * hdk / adk1;
-                S(G_HD, k) += ghd1 * adk / adk1;
-                gEd += ghd1 * h / adk1;
-                const double gh = ghd1 * Ed / adk1;
-                gad1 += -ghd1 * hdk1 / adk1;
+                const double ghd1 = chd + gTd1 / (CP + LV * Q1);
+                const double rad1 = 1.0 / adk1;
+                gad0 += ghd1 * hdk * rad1;
+                gEd += ghd1 * h * rad1;
+                const double gh = ghd1 * Ed * rad1;
+                gad1 += -ghd1 * hdk1 * rad1;
                 gad0 += gad1;
                 gEd += gad1;
-                const double dz = zi(k) - zi(k + 1);
+                const double dz = zk - zlo;
                 geps += gEd * adk * dz;
                 gad0 += gEd * epsd * dz;
-                S(G_AD, k) += gad0;
+                cad = gad0;
+                cqd = -ge1 * adk;
+                chd = ghd1 * adk * rad1;
                 S(G_T, k) += CP * gh;
                 S(G_Q, k) += LV * gh + gq;
+                adk1 = adk;
+                hdk1 = hdk;
+                qdk1 = qdk;
+                zlo = zk;
             }
             // Start: h_d = h of layer kd at interface kd+1; e1_kd = q_d(kd+1) - q_kd.
             const double ge1 = S(G_E1, kd);
-            const double gqd1 = S(G_QD, kd + 1) + ge1;
+            const double gqd1 = S(G_QD, kd + 1) + cqd + ge1;
             const double Q1 = S(D_Q1, kd + 1);
             const double gTd1 = S(G_TD, kd + 1) + gqd1 * Q1;
-            const double ghd1 = S(G_HD, kd + 1) + gTd1 / (CP + LV * Q1);
+            const double ghd1 = chd + gTd1 / (CP + LV * Q1);
             S(G_T, kd) += CP * ghd1;
             S(G_Q, kd) += LV * ghd1 - ge1;
         }
-        // D5 updraft recurrence, in reverse (top interface first).
-        for (int k = kt + 1; k <= kb - 1; ++k) {
-            const double eta = S(U_ETA, k), etan1 = S(U_ETA, k + 1);
-            const double hm = S(U_HM, k), hu1 = S(U_HM, k + 1);
-            const double qm = S(U_QM, k), qu = S(U_QU, k), qu1 = S(U_QU, k + 1);
-            const double E = S(U_E, k), Q1 = S(U_Q1, k);
-            const double gc = S(G_C, k);
-            double geta = S(G_ETA, k) + gc * (qm - qu);
-            double gqm = gc * eta;
-            const double gqu = S(G_QU, k) - gc * eta;
-            double ghm = S(G_HU, k);
-            const double gTu = S(G_TU, k);
-            if (S(U_SAT, k) != 0.0) {
-                ghm += (gTu + gqu * Q1) / (CP + LV * Q1);
-            } else {
-                ghm += gTu / CP;
-                gqm += -LV * gTu / CP + gqu;
+        // D5 updraft recurrence, in reverse (top interface first), carrying what an iteration adds
+        // to the adjoints of the interface below it (eta, h_u, q_u) in registers.
+        double ceta = 0.0, chu = 0.0, cqu = 0.0;  // recurrence parts at interface k
+        {
+            double eta = S(U_ETA, kt + 1), zk = zi(kt + 1);
+            for (int k = kt + 1; k <= kb - 1; ++k) {
+                const double etan1 = S(U_ETA, k + 1);
+                const double hm = S(U_HM, k), hu1 = S(U_HM, k + 1);
+                const double qm = S(U_QM, k), qu = S(U_QU, k), qu1 = S(U_QU, k + 1);
+                const double E = S(U_E, k), Q1 = S(U_Q1, k), zlo = zi(k + 1);
+                const double gc = S(G_C, k);
+                double geta = S(G_ETA, k) + ceta + gc * (qm - qu);
+                double gqm = gc * eta;
+                const double gqu = S(G_QU, k) + cqu - gc * eta;
+                double ghm = chu;
+                const double gTu = S(G_TU, k);
+                if (S(U_SAT, k) != 0.0) {
+                    ghm += (gTu + gqu * Q1) / (CP + LV * Q1);
+                } else {
+                    ghm += gTu / CP;
+                    gqm += -LV * gTu / CP + gqu;
+                }
+                const double reta = 1.0 / eta;
+                double geta1 = (ghm * hu1 + gqm * qu1) * reta;
+                chu = ghm * etan1 * reta;
+                cqu = gqm * etan1 * reta;
+                double gE = (ghm * hk(k) + gqm * qk(k)) * reta;
+                const double gh = ghm * E * reta;
+                S(G_T, k) += CP * gh;
+                S(G_Q, k) += LV * gh + gqm * E * reta;
+                geta += -(ghm * hm + gqm * qm) * reta;
+                geta1 += geta;
+                gE += geta;
+                const double dz = zk - zlo;
+                geps += gE * etan1 * dz;
+                geta1 += gE * epsd * dz;
+                ceta = geta1;
+                eta = etan1;
+                zk = zlo;
             }
-            const double reta = 1.0 / eta;
-            S(G_ETA, k + 1) += (ghm * hu1 + gqm * qu1) * reta;
-            S(G_HU, k + 1) += ghm * etan1 * reta;
-            S(G_QU, k + 1) += gqm * etan1 * reta;
-            double gE = (ghm * hk(k) + gqm * qk(k)) * reta;
-            const double gh = ghm * E * reta;
-            S(G_T, k) += CP * gh;
-            S(G_Q, k) += LV * gh + gqm * E * reta;
-            geta += -(ghm * hm + gqm * qm) * reta;
-            S(G_ETA, k + 1) += geta;
-            gE += geta;
-            const double dz = zi(k) - zi(k + 1);
-            geps += gE * etan1 * dz;
-            S(G_ETA, k + 1) += gE * epsd * dz;
         }
         {
             // Launch interface kb: h_u = h_kb, q_m = q_kb, c_kb = q_kb - q_u(kb).
             const double gc = S(G_C, kb);
-            const double gqu = S(G_QU, kb) - gc;
-            double ghm = S(G_HU, kb);
+            const double gqu = S(G_QU, kb) + cqu - gc;
+            double ghm = chu;
             const double gTu = S(G_TU, kb), Q1 = S(U_Q1, kb);
             double gqm = 0.0;
             if (S(U_SAT, kb) != 0.0) {
@@ -476,16 +491,14 @@ __global__ __launch_bounds__(BLOCK) void k_deep_adjoint(Member M, AdjWork w) {
 #undef S
 }
 
-// dL/dtau and dL/deps: sums of the per-column values over columns 0..ncol-1 in a fixed order
-// (one block; each thread sums a strided subset in order, then a fixed-shape tree).
-__global__ __launch_bounds__(BLOCK) void k_adj_reduce(const double *pgrad, int64_t ld, int64_t ncol,
-                                                      double *out) {
+// dL/dtau and dL/deps: sums of the per-column values over columns 0..ncol-1 in a fixed order, so
+// the result is reproducible bit for bit.  Stage 1: block b sums the b-th of NPART contiguous
+// column ranges (each thread a strided subset in order, then a fixed-shape tree); stage 2 sums the
+// NPART partials with the same tree.
+constexpr int NPART = BLOCK;
+
+__device__ void block_tree_sum(double a, double b, double *out0, double *out1) {
     __shared__ double s0[BLOCK], s1[BLOCK];
-    double a = 0.0, b = 0.0;
-    for (int64_t c = threadIdx.x; c < ncol; c += BLOCK) {
-        a += pgrad[c];
-        b += pgrad[ld + c];
-    }
     s0[threadIdx.x] = a;
     s1[threadIdx.x] = b;
     __syncthreads();
@@ -497,13 +510,34 @@ __global__ __launch_bounds__(BLOCK) void k_adj_reduce(const double *pgrad, int64
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        out[0] = s0[0];
-        out[1] = s1[0];
+        *out0 = s0[0];
+        *out1 = s1[0];
     }
 }
 
+__global__ __launch_bounds__(BLOCK) void k_adj_partial(const double *pgrad, int64_t ld, int64_t ncol,
+                                                       double *part) {
+    const int64_t chunk = (ncol + NPART - 1) / NPART;
+    const int64_t c0 = (int64_t)blockIdx.x * chunk;
+    const int64_t c1 = c0 + chunk < ncol ? c0 + chunk : ncol;
+    double a = 0.0, b = 0.0;
+    for (int64_t c = c0 + threadIdx.x; c < c1; c += BLOCK) {
+        a += pgrad[c];
+        b += pgrad[ld + c];
+    }
+    block_tree_sum(a, b, &part[blockIdx.x], &part[NPART + blockIdx.x]);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_adj_final(const double *part, double *out) {
+    block_tree_sum(part[threadIdx.x], part[NPART + threadIdx.x], &out[0], &out[1]);
+}
+
+__global__ void k_adj_zero2(double *out) {
+    if (threadIdx.x < 2) out[threadIdx.x] = 0.0;
+}
+
 struct AdjLayout {
-    size_t cnt, list, pgrad, scr, total;
+    size_t cnt, part, list, pgrad, scr, total;
     int64_t threads;
 };
 
@@ -520,6 +554,7 @@ AdjLayout adj_layout(int64_t ncol, int nlev, int cus) {
         return o;
     };
     l.cnt = take(NCOUNTERS * sizeof(int));
+    l.part = take(2 * NPART * sizeof(double));
     l.list = take(n * sizeof(int));
     l.pgrad = 0;  // per-column values live in a [2][ld] region sized at call time
     l.scr = take((size_t)N_ADJ * (nlev + 1) * l.threads * sizeof(double));
@@ -556,8 +591,7 @@ int conv_deep_backward(conv_ctx_t *ctx, const conv_state_t *state, const conv_de
     if (ws_bytes < l.total + (size_t)2 * ld * sizeof(double)) return CONV_EINVAL;
     hipStream_t st = (hipStream_t)stream;
     if (ctx->ncol == 0) {
-        hipLaunchKernelGGL(k_adj_reduce, dim3(1), dim3(BLOCK), 0, st, (const double *)nullptr,
-                           (int64_t)0, (int64_t)0, grad->g_params);
+        hipLaunchKernelGGL(k_adj_zero2, dim3(1), dim3(64), 0, st, grad->g_params);
         return check_launch();
     }
     char *b = (char *)workspace;
@@ -578,8 +612,11 @@ int conv_deep_backward(conv_ctx_t *ctx, const conv_state_t *state, const conv_de
     hipLaunchKernelGGL(k_adj_reset, dim3(1), dim3(NCOUNTERS), 0, st, w.cnt);
     hipLaunchKernelGGL(k_adj_compact, dim3(gcols), dim3(BLOCK), 0, st, M, w);
     hipLaunchKernelGGL(k_deep_adjoint, dim3((unsigned)(l.threads / BLOCK)), dim3(BLOCK), 0, st, M, w);
-    hipLaunchKernelGGL(k_adj_reduce, dim3(1), dim3(BLOCK), 0, st, (const double *)w.pgrad, ld,
-                       ctx->ncol, grad->g_params);
+    double *part = (double *)(b + l.part);
+    hipLaunchKernelGGL(k_adj_partial, dim3(NPART), dim3(BLOCK), 0, st, (const double *)w.pgrad, ld,
+                       ctx->ncol, part);
+    hipLaunchKernelGGL(k_adj_final, dim3(1), dim3(BLOCK), 0, st, (const double *)part,
+                       grad->g_params);
     return check_launch();
 }
 
