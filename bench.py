@@ -135,6 +135,42 @@ def bench_ensemble(torch, B, S, main_state, main_deep, main_shallow, reps, tune=
             "batching_speedup": sep / ms}
 
 
+def bench_surrogate(torch, B, main_state, truth_deep, truth_shallow, conv_step_ms, n_train, epochs,
+                    reps):
+    """Train the MLP surrogate on n_train soundings labelled by conv_step (plus 100,000 held out),
+    then time its inference on the 884,736-column grid with and without the fallback to the scheme
+    and measure its error against the scheme's tendencies on that grid."""
+    from paper_1711_00289_amd import surrogate as SG
+
+    n = main_state["ncol"]
+    sur, rep = SG.build_and_train(torch, n_train, epochs, batch=16384, lr=1e-3, seed=105,
+                                  max_cols=n, chunk=131_072,
+                                  log=lambda m: print(f"[bench] surrogate {m}", file=sys.stderr,
+                                                      flush=True))
+    out = [torch.empty(NLEV, n, dtype=torch.float64, device="cuda") for _ in range(2)]
+    out.append(torch.empty(n, dtype=torch.float64, device="cuda"))
+    sur.infer(main_state, n, fallback=False, out=tuple(out))
+    ms_nofb = time_events(torch, lambda: sur.infer(main_state, n, fallback=False, out=tuple(out)),
+                          reps)
+    nfb = sur.infer(main_state, n, fallback=True, out=tuple(out))[3]
+    ms_fb = time_events(torch, lambda: sur.infer(main_state, n, fallback=True, out=tuple(out)), reps)
+    err = SG.errors(torch, tuple(out), truth_deep, truth_shallow, n)
+    flop_per_col = 2 * sum(SG.WIDTHS[i] * SG.WIDTHS[i + 1] for i in range(len(SG.WIDTHS) - 1))
+    infer_tf = flop_per_col * n / (ms_nofb * 1e-3) / 1e12
+    rep.pop("loss_per_epoch", None)
+    return {"workload": f"MLP {SG.WIDTHS} GELU, BF16 operands / FP32 accumulation, trained on "
+                        f"{n_train:,} soundings labelled by conv_step; inference on the "
+                        f"884,736-column grid",
+            "training": rep, "infer_ms": ms_nofb, "infer_with_fallback_ms": ms_fb,
+            "fallback_columns": nfb, "conv_step_ms": conv_step_ms,
+            "speedup_vs_scheme": conv_step_ms / ms_fb,
+            "infer_TFLOPs": infer_tf,
+            "mfma_roofline": {"bound": "mfma", "peak": 2500.0, "unit": "TFLOP/s",
+                              "infer_frac": infer_tf / 2500.0,
+                              "train_frac": rep["train_TFLOPs"] / 2500.0},
+            "error_vs_scheme": err}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -146,6 +182,9 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shape")
     ap.add_argument("--no-extras", action="store_true",
                     help="time only the headline step (no adjoint, ensemble)")
+    ap.add_argument("--surrogate-n", type=int, default=10_000_000,
+                    help="training soundings for the surrogate (0 skips it)")
+    ap.add_argument("--surrogate-epochs", type=int, default=10)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after timing, copy a MIB-MiB device buffer once (a plain copy kernel of "
                          "known size for scaling hardware byte counters)")
@@ -256,6 +295,12 @@ def main():
         out["ensemble"] = bench_ensemble(torch, B, S, dev, deep, shallow, max(args.steps, 10),
                                          tune=not args.no_tune)
         print("[bench] ensemble done", file=sys.stderr, flush=True)
+        if args.surrogate_n > 0:
+            conv.step(dev, deep, shallow)  # the truth on the grid (the ensemble rewrote it)
+            out["surrogate"] = bench_surrogate(torch, B, dev, deep, shallow, ms_step,
+                                               args.surrogate_n, args.surrogate_epochs,
+                                               max(args.steps, 10))
+            print("[bench] surrogate done", file=sys.stderr, flush=True)
 
     if not args.no_cpu:
         threads = min(16, len(os.sched_getaffinity(0)))

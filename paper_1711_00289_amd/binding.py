@@ -32,7 +32,13 @@ EXPORTS = ("conv_workspace_bytes", "conv_create", "conv_set_params", "conv_destr
            "conv_backward_workspace_bytes", "conv_deep_backward", "conv_autotune",
            "conv_ensemble_workspace_bytes", "conv_ensemble_create", "conv_ensemble_destroy",
            "conv_ensemble_step", "conv_ensemble_set_launch", "conv_ensemble_get_launch",
-           "conv_ensemble_autotune", "conv_ensemble_capture", "conv_ensemble_replay")
+           "conv_ensemble_autotune", "conv_ensemble_capture", "conv_ensemble_replay",
+           "mlp_workspace_bytes", "mlp_create", "mlp_destroy", "mlp_param_count", "mlp_set_params",
+           "mlp_get_params", "mlp_get_grads", "mlp_forward", "mlp_mse", "mlp_backward",
+           "mlp_adam_step", "mlp_gemm_nt", "mlp_strerror",
+           "surr_pack_inputs_raw", "surr_pack_targets_raw", "surr_col_stats_scratch_bytes",
+           "surr_col_stats", "surr_normalize", "surr_pack_inputs", "surr_workspace_bytes",
+           "surr_create", "surr_destroy", "surr_set_norm", "surr_infer")
 
 
 class Params(C.Structure):
@@ -132,6 +138,54 @@ def lib():
         L.conv_ensemble_autotune.restype = I
         L.conv_ensemble_autotune.argtypes = [C.c_void_p, C.c_void_p, I, I, P, P,
                                              C.POINTER(C.c_float)]
+        V, I64 = C.c_void_p, C.c_int64
+        L.mlp_workspace_bytes.restype = C.c_size_t
+        L.mlp_workspace_bytes.argtypes = [C.POINTER(C.c_int32), I, I64]
+        L.mlp_create.restype = I
+        L.mlp_create.argtypes = [C.POINTER(C.c_int32), I, I64, V, C.c_size_t, C.POINTER(V)]
+        L.mlp_destroy.restype = None
+        L.mlp_destroy.argtypes = [V]
+        L.mlp_param_count.restype = I64
+        L.mlp_param_count.argtypes = [V]
+        for f in ("mlp_set_params", "mlp_get_params", "mlp_get_grads"):
+            getattr(L, f).restype = I
+            getattr(L, f).argtypes = [V, V, V]
+        L.mlp_forward.restype = I
+        L.mlp_forward.argtypes = [V, V, V, I64, I, V]
+        L.mlp_mse.restype = I
+        L.mlp_mse.argtypes = [V, V, V, I64, I, V, V]
+        L.mlp_backward.restype = I
+        L.mlp_backward.argtypes = [V, I64, V]
+        L.mlp_adam_step.restype = I
+        L.mlp_adam_step.argtypes = [V, C.c_float, C.c_float, C.c_float, C.c_float, V]
+        L.mlp_gemm_nt.restype = I
+        L.mlp_gemm_nt.argtypes = [V, I64, V, I64, V, I64, C.c_int32, C.c_int32, I, V, I64, V, V]
+        L.mlp_strerror.restype = C.c_char_p
+        L.mlp_strerror.argtypes = [I]
+        L.surr_pack_inputs_raw.restype = I
+        L.surr_pack_inputs_raw.argtypes = [C.POINTER(State), C.c_int32, I64, C.c_int32, V, V]
+        L.surr_pack_targets_raw.restype = I
+        L.surr_pack_targets_raw.argtypes = [C.POINTER(DeepOut), C.POINTER(ShallowOut), C.c_int32, I64,
+                                            I64, C.c_int32, V, V]
+        L.surr_col_stats_scratch_bytes.restype = C.c_size_t
+        L.surr_col_stats_scratch_bytes.argtypes = [C.c_int32]
+        L.surr_col_stats.restype = I
+        L.surr_col_stats.argtypes = [V, I64, C.c_int32, C.c_int32, V, V, V, V, C.c_size_t, V]
+        L.surr_normalize.restype = I
+        L.surr_normalize.argtypes = [V, I64, C.c_int32, V, V, V, V]
+        L.surr_pack_inputs.restype = I
+        L.surr_pack_inputs.argtypes = [C.POINTER(State), C.c_int32, I64, C.c_int32, V, V, V, V]
+        L.surr_workspace_bytes.restype = C.c_size_t
+        L.surr_workspace_bytes.argtypes = [C.c_int32, C.c_int32, C.c_int32, I64, I64]
+        L.surr_create.restype = I
+        L.surr_create.argtypes = [V, C.c_int32, C.c_int32, C.c_int32, I64, I64, C.POINTER(Params), V,
+                                  C.c_size_t, C.POINTER(V)]
+        L.surr_destroy.restype = None
+        L.surr_destroy.argtypes = [V]
+        L.surr_set_norm.restype = I
+        L.surr_set_norm.argtypes = [V, V, V, V, V, C.c_double, C.c_double, V]
+        L.surr_infer.restype = I
+        L.surr_infer.argtypes = [V, C.POINTER(State), I64, V, V, V, I, C.POINTER(I64), V]
         L.conv_strerror.restype = C.c_char_p
         L.conv_strerror.argtypes = [C.c_int]
         L.conv_last_hip_error.restype = C.c_int
@@ -484,3 +538,107 @@ class Ensemble:
     def replay(self, stream):
         check(lib().conv_ensemble_replay(self.h, C.c_void_p(stream.cuda_stream)),
               "conv_ensemble_replay")
+
+
+def mlp_check(rc: int, what: str):
+    if rc != 0:
+        raise RuntimeError(f"{what}: {lib().mlp_strerror(rc).decode()}")
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+class MLP:
+    """The surrogate network (include/mlp.h) over a torch-allocated workspace.  Inputs are
+    torch.bfloat16 [batch][widths[0]]; outputs and targets float32 [batch][widths[-1]]."""
+
+    def __init__(self, widths, max_batch: int, device="cuda"):
+        torch = _torch()
+        self.torch = torch
+        self.widths = [int(w) for w in widths]
+        self.n = len(self.widths) - 1
+        self.max_batch = int(max_batch)
+        self.device = device
+        warr = (C.c_int32 * len(self.widths))(*self.widths)
+        self._warr = warr
+        L = lib()
+        nbytes = L.mlp_workspace_bytes(warr, self.n, self.max_batch)
+        if nbytes == 0:
+            raise ValueError("unsupported widths or batch")
+        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        h = C.c_void_p()
+        mlp_check(L.mlp_create(warr, self.n, self.max_batch,
+                               C.c_void_p((self.ws.data_ptr() + 255) & ~255), nbytes, C.byref(h)),
+                  "mlp_create")
+        self.h = h
+        self.P = int(L.mlp_param_count(h))
+        self.loss = torch.zeros(1, dtype=torch.float32, device=device)
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                lib().mlp_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+    def set_params(self, vec):
+        vec = vec.to(device=self.device, dtype=self.torch.float32).contiguous()
+        if vec.numel() != self.P:
+            raise ValueError(f"expected {self.P} parameters")
+        mlp_check(lib().mlp_set_params(self.h, _ptr(vec), _stream(self.torch)), "mlp_set_params")
+
+    def get_params(self):
+        out = self.torch.empty(self.P, dtype=self.torch.float32, device=self.device)
+        mlp_check(lib().mlp_get_params(self.h, _ptr(out), _stream(self.torch)), "mlp_get_params")
+        return out
+
+    def get_grads(self):
+        out = self.torch.empty(self.P, dtype=self.torch.float32, device=self.device)
+        mlp_check(lib().mlp_get_grads(self.h, _ptr(out), _stream(self.torch)), "mlp_get_grads")
+        return out
+
+    def forward(self, x, y=None, keep: bool = False):
+        torch = self.torch
+        if x.dtype != torch.bfloat16 or x.dim() != 2 or x.shape[1] != self.widths[0] or \
+                not x.is_contiguous():
+            raise ValueError("x: contiguous bfloat16 [batch][widths[0]]")
+        B = x.shape[0]
+        if y is None:
+            y = torch.empty(B, self.widths[-1], dtype=torch.float32, device=self.device)
+        self._x = x  # the backward pass reads the input of the last forward
+        mlp_check(lib().mlp_forward(self.h, _ptr(x), _ptr(y), B, int(keep), _stream(torch)),
+                  "mlp_forward")
+        return y
+
+    def mse(self, y, target, n_valid: int, out=None):
+        """Loss into `out` (a float32 device tensor of at least one element; default self.loss)."""
+        out = self.loss if out is None else out
+        mlp_check(lib().mlp_mse(self.h, _ptr(y), _ptr(target.contiguous()), y.shape[0], int(n_valid),
+                                _ptr(out), _stream(self.torch)), "mlp_mse")
+        return out
+
+    def backward(self, batch: int):
+        mlp_check(lib().mlp_backward(self.h, int(batch), _stream(self.torch)), "mlp_backward")
+
+    def adam_step(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        mlp_check(lib().mlp_adam_step(self.h, float(lr), float(beta1), float(beta2), float(eps),
+                                      _stream(self.torch)), "mlp_adam_step")
+
+
+def gemm_nt(a, b, bias=None, mode: int = 0, z: bool = False):
+    """acc = a . b^T (bfloat16 operands): mode 0 -> float32 acc + bias; mode 1 -> (bfloat16
+    gelu(acc + bias), float32 acc + bias or None)."""
+    torch = _torch()
+    M, K = a.shape
+    N = b.shape[0]
+    if mode == 0:
+        c = torch.empty(M, N, dtype=torch.float32, device=a.device)
+        zz = None
+    else:
+        c = torch.empty(M, N, dtype=torch.bfloat16, device=a.device)
+        zz = torch.empty(M, N, dtype=torch.float32, device=a.device) if z else None
+    mlp_check(lib().mlp_gemm_nt(_ptr(a), a.stride(0), _ptr(b), b.stride(0), _ptr(bias), M, N, K,
+                                mode, _ptr(c), N, _ptr(zz), _stream(torch)), "mlp_gemm_nt")
+    return c if mode == 0 else (c, zz)

@@ -1,0 +1,662 @@
+// mlp.hip -- the surrogate network's kernels for gfx950 (include/mlp.h): one tiled BF16 GEMM on
+// the matrix cores (v_mfma_f32_32x32x16_bf16, FP32 accumulation) with fused epilogues, used for the
+// forward layers (bias + GELU), the backward data gradient (times GELU') and, with transposed tile
+// loads and the batch split across blocks, the weight gradients; plus column sums, MSE and Adam.
+//
+// GEMM tiling: a 256-thread block computes a 128 x BN tile (BN = 128 or 64) with four wavefronts
+// in a 2 x 2 arrangement, each owning 64 x BN/2 as 2 x BN/64 MFMA tiles of 32 x 32.  K advances 32
+// at a time through double-buffered LDS tiles; the next K tile is fetched from global memory into
+// registers while the current one feeds the MFMAs.  Block ids are mapped so that the N tiles of one
+// M tile run on the same XCD (the hardware deals consecutive blocks to the 8 XCDs in turn), so an
+// activation tile is fetched into one XCD's L2 once and reused there.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <vector>
+
+#include "mlp.h"
+
+namespace {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
+
+constexpr int THREADS = 256;
+constexpr int BM = 128;
+constexpr int BK = 32;
+constexpr int LDK = BK + 8;  // LDS row stride in bf16 (80 bytes: 16-byte aligned rows)
+constexpr int NXCD = 8;
+
+thread_local int g_mlp_hip = 0;
+
+__device__ __forceinline__ uint16_t f2bf(float f) {  // round to nearest even
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+// GELU(z) = z Phi(z) with Phi(z) = erfc(-z/sqrt 2)/2 (the erfc form keeps full relative accuracy
+// in the negative tail, where 1 + erf(z/sqrt 2) would cancel).
+__device__ __forceinline__ float gelu(float z) {
+    return 0.5f * z * erfcf(-z * 0.70710678118654752f);
+}
+
+__device__ __forceinline__ float gelu_grad(float z) {
+    return 0.5f * erfcf(-z * 0.70710678118654752f) + z * 0.39894228040143268f * expf(-0.5f * z * z);
+}
+
+enum Mode : int {
+    EPI_F32 = 0,      // c (float) = acc + bias
+    EPI_GELU = 1,     // c (bf16) = gelu(acc + bias); z (float) = acc + bias
+    EPI_DGELU = 2,    // c (bf16) = acc * gelu'(z)
+    EPI_PARTIAL = 3,  // c (float) + blockIdx.y * split_stride = acc
+};
+
+struct GemmArgs {
+    const uint16_t *a, *b;
+    int64_t lda, ldb;
+    int64_t M;
+    int N, K;
+    int tiles_m, tiles_n;
+    int ksplit;  // > 0: blockIdx.y covers K range [y*ksplit, (y+1)*ksplit)
+    int mode;
+    const float *bias;
+    void *c;
+    int64_t ldc;
+    float *z;  // EPI_GELU output / EPI_DGELU input, leading dimension ldc
+    int64_t split_stride;
+};
+
+// Global -> register -> LDS staging of one operand tile of ROWS x BK.  NT: element (r, k) at
+// p[r*ld + k] (k contiguous, 8-element chunks); TN: at p[k*ld + r] (r contiguous, transposed on
+// the way into LDS).  Out-of-range chunks are zero.
+template <bool TN, int ROWS>
+struct Tile {
+    static constexpr int CHUNKS = ROWS * BK / 8;
+    static constexpr int PER = (CHUNKS + THREADS - 1) / THREADS;
+    uint4 v[PER];
+
+    __device__ __forceinline__ void load(const uint16_t *p, int64_t ld, int64_t r0, int64_t rlim,
+                                         int k0, int klim, int t) {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int idx = t + i * THREADS;
+            v[i] = make_uint4(0u, 0u, 0u, 0u);
+            if (idx >= CHUNKS) continue;
+            if (!TN) {
+                const int64_t r = r0 + (idx >> 2);
+                const int k = k0 + (idx & 3) * 8;
+                if (r < rlim && k < klim) v[i] = *(const uint4 *)(p + r * ld + k);
+            } else {
+                constexpr int RC = ROWS / 8;
+                const int k = k0 + idx / RC;
+                const int64_t r = r0 + (idx % RC) * 8;
+                if (k < klim && r < rlim) v[i] = *(const uint4 *)(p + (int64_t)k * ld + r);
+            }
+        }
+    }
+
+    __device__ __forceinline__ void store(uint16_t *s, int t) const {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int idx = t + i * THREADS;
+            if (idx >= CHUNKS) continue;
+            if (!TN) {
+                *(uint4 *)(s + (idx >> 2) * LDK + (idx & 3) * 8) = v[i];
+            } else {
+                constexpr int RC = ROWS / 8;
+                const int k = idx / RC, r = (idx % RC) * 8;
+                const uint16_t *h = (const uint16_t *)&v[i];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) s[(r + j) * LDK + k] = h[j];
+            }
+        }
+    }
+};
+
+template <bool TN, int BN>
+__global__ __launch_bounds__(THREADS) void k_gemm(GemmArgs g) {
+    constexpr int NTW = BN / 64;  // 32-wide MFMA tiles per wavefront along N
+    __shared__ __attribute__((aligned(16))) uint16_t As[2][BM * LDK];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[2][BN * LDK];
+
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6, wm = w >> 1, wn = w & 1;
+    const int64_t bid = blockIdx.x;
+    const int xcd = (int)(bid % NXCD);
+    const int64_t j = bid / NXCD;
+    const int tn = (int)(j % g.tiles_n);
+    const int64_t tm = (j / g.tiles_n) * NXCD + xcd;
+    if (tm >= g.tiles_m) return;
+    const int64_t m0 = tm * BM;
+    const int n0 = tn * BN;
+    int k0 = 0, k1 = g.K;
+    if (g.ksplit > 0) {
+        k0 = blockIdx.y * g.ksplit;
+        k1 = min(k0 + g.ksplit, g.K);
+    }
+
+    Tile<TN, BM> ta;
+    Tile<TN, BN> tb;
+    f32x16 acc[2][NTW];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < NTW; ++b)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
+
+    const int nk = k1 > k0 ? (k1 - k0 + BK - 1) / BK : 0;
+    if (nk > 0) {
+        ta.load(g.a, g.lda, m0, g.M, k0, k1, t);
+        tb.load(g.b, g.ldb, n0, g.N, k0, k1, t);
+        ta.store(As[0], t);
+        tb.store(Bs[0], t);
+    }
+    __syncthreads();
+    const int lrow = lane & 31, lk = 8 * (lane >> 5);
+    for (int kt = 0; kt < nk; ++kt) {
+        const int cur = kt & 1;
+        const bool more = kt + 1 < nk;
+        if (more) {
+            ta.load(g.a, g.lda, m0, g.M, k0 + (kt + 1) * BK, k1, t);
+            tb.load(g.b, g.ldb, n0, g.N, k0 + (kt + 1) * BK, k1, t);
+        }
+#pragma unroll
+        for (int ks = 0; ks < BK; ks += 16) {
+            bf16x8 af[2], bf[NTW];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+                af[a] = *(const bf16x8 *)&As[cur][(wm * 64 + a * 32 + lrow) * LDK + ks + lk];
+#pragma unroll
+            for (int b = 0; b < NTW; ++b)
+                bf[b] = *(const bf16x8 *)&Bs[cur][(wn * (BN / 2) + b * 32 + lrow) * LDK + ks + lk];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < NTW; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[a], bf[b], acc[a][b], 0, 0, 0);
+        }
+        if (more) {
+            ta.store(As[cur ^ 1], t);
+            tb.store(Bs[cur ^ 1], t);
+        }
+        __syncthreads();
+    }
+
+    // Accumulator layout of a 32x32 MFMA tile: register r of lane l holds
+    // row 8*(r/4) + 4*(l/32) + r%4, column l%32.
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+#pragma unroll
+        for (int b = 0; b < NTW; ++b) {
+            const int n = n0 + wn * (BN / 2) + b * 32 + lrow;
+            if (n >= g.N) continue;
+            const float bias = (g.bias && g.mode != EPI_PARTIAL && g.mode != EPI_DGELU) ? g.bias[n] : 0.0f;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int64_t m = m0 + wm * 64 + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                if (m >= g.M) continue;
+                const float v = acc[a][b][r];
+                const int64_t o = m * g.ldc + n;
+                if (g.mode == EPI_F32) {
+                    ((float *)g.c)[o] = v + bias;
+                } else if (g.mode == EPI_GELU) {
+                    const float zz = v + bias;
+                    if (g.z) g.z[o] = zz;
+                    ((uint16_t *)g.c)[o] = f2bf(gelu(zz));
+                } else if (g.mode == EPI_DGELU) {
+                    ((uint16_t *)g.c)[o] = f2bf(v * gelu_grad(g.z[o]));
+                } else {
+                    ((float *)g.c)[(int64_t)blockIdx.y * g.split_stride + o] = v;
+                }
+            }
+        }
+    }
+}
+
+int launch_gemm(bool tn, const GemmArgs &in, int splits, hipStream_t st) {
+    GemmArgs g = in;
+    const int BN = (g.N % 128 == 0) ? 128 : 64;
+    g.tiles_m = (int)((g.M + BM - 1) / BM);
+    g.tiles_n = (g.N + BN - 1) / BN;
+    const int64_t mgroups = (g.tiles_m + NXCD - 1) / NXCD;
+    const int64_t blocks = mgroups * NXCD * g.tiles_n;
+    if (blocks <= 0 || blocks > 0x7fffffff || splits < 1) return MLP_EINVAL;
+    const dim3 grid((unsigned)blocks, (unsigned)splits);
+    if (!tn && BN == 128) hipLaunchKernelGGL((k_gemm<false, 128>), grid, dim3(THREADS), 0, st, g);
+    else if (!tn) hipLaunchKernelGGL((k_gemm<false, 64>), grid, dim3(THREADS), 0, st, g);
+    else if (BN == 128) hipLaunchKernelGGL((k_gemm<true, 128>), grid, dim3(THREADS), 0, st, g);
+    else hipLaunchKernelGGL((k_gemm<true, 64>), grid, dim3(THREADS), 0, st, g);
+    return MLP_OK;
+}
+
+// ------------------------------------------------------------------ reductions, loss, optimiser
+// part[s][n] = sum over rows [s*chunk, min((s+1)*chunk, rows)) of x[r][n] (bf16), in row order.
+__global__ __launch_bounds__(THREADS) void k_colsum_partial(const uint16_t *x, int64_t rows, int n,
+                                                            int64_t chunk, float *part) {
+    const int c = blockIdx.x * THREADS + threadIdx.x;
+    if (c >= n) return;
+    const int64_t r0 = (int64_t)blockIdx.y * chunk;
+    const int64_t r1 = r0 + chunk < rows ? r0 + chunk : rows;
+    float s = 0.0f;
+    for (int64_t r = r0; r < r1; ++r) s += __uint_as_float((uint32_t)x[r * n + c] << 16);
+    part[(int64_t)blockIdx.y * n + c] = s;
+}
+
+// out[i] = sum_{s < S} part[s*len + i], in order of s.
+__global__ __launch_bounds__(THREADS) void k_sum_parts(const float *part, int S, int64_t len,
+                                                       float *out) {
+    const int64_t i = (int64_t)blockIdx.x * THREADS + threadIdx.x;
+    if (i >= len) return;
+    float s = 0.0f;
+    for (int k = 0; k < S; ++k) s += part[(int64_t)k * len + i];
+    out[i] = s;
+}
+
+__device__ float block_sum(float v) {  // fixed-shape tree over the block; result in thread 0
+    __shared__ float sh[THREADS];
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int h = THREADS / 2; h > 0; h /= 2) {
+        if ((int)threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
+        __syncthreads();
+    }
+    return sh[0];
+}
+
+// Per element of y[batch][w]: d = y - t; dz = bf16(scale * 2 d) for j < nv, else 0; block partial
+// sums of d^2 over j < nv.
+__global__ __launch_bounds__(THREADS) void k_mse(const float *y, const float *t, int64_t total, int w,
+                                                 int nv, float scale, uint16_t *dz, float *part) {
+    const int64_t i = (int64_t)blockIdx.x * THREADS + threadIdx.x;
+    float sq = 0.0f;
+    if (i < total) {
+        const int jj = (int)(i % w);
+        const float d = y[i] - t[i];
+        const bool ok = jj < nv;
+        dz[i] = ok ? f2bf(2.0f * d * scale) : (uint16_t)0;
+        sq = ok ? d * d : 0.0f;
+    }
+    const float s = block_sum(sq);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(THREADS) void k_mse_final(const float *part, int64_t n, float scale,
+                                                       float *loss) {
+    float s = 0.0f;
+    for (int64_t i = threadIdx.x; i < n; i += THREADS) s += part[i];
+    const float tot = block_sum(s);
+    if (threadIdx.x == 0) loss[0] = tot * scale;
+}
+
+__global__ __launch_bounds__(THREADS) void k_adam(float *p, const float *g, float *m, float *v,
+                                                  int64_t n, float lr, float b1, float b2, float eps,
+                                                  float bc1, float bc2) {
+    const int64_t i = (int64_t)blockIdx.x * THREADS + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+}
+
+// BF16 copies of W [rows][cols]: wb (same layout) and wt (transposed [cols][rows]).
+__global__ __launch_bounds__(THREADS) void k_to_bf16(const float *W, int rows, int cols, uint16_t *wb,
+                                                     uint16_t *wt) {
+    const int64_t i = (int64_t)blockIdx.x * THREADS + threadIdx.x;
+    if (i >= (int64_t)rows * cols) return;
+    const int r = (int)(i / cols), c = (int)(i % cols);
+    const uint16_t h = f2bf(W[i]);
+    wb[i] = h;
+    wt[(int64_t)c * rows + r] = h;
+}
+
+__global__ __launch_bounds__(THREADS) void k_fill0(float *p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * THREADS + threadIdx.x;
+    if (i < n) p[i] = 0.0f;
+}
+
+unsigned nblocks(int64_t n) { return (unsigned)((n + THREADS - 1) / THREADS); }
+size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
+
+int check() {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        g_mlp_hip = (int)e;
+        return MLP_EHIP;
+    }
+    return MLP_OK;
+}
+
+// Weight-gradient GEMM split: enough blocks to fill the chip, chunks a multiple of BK.
+void wgrad_split(int64_t batch, int M, int N, int *S, int *chunk) {
+    const int tiles = ((M + BM - 1) / BM) * ((N + 63) / 64);
+    int s = (512 + tiles - 1) / tiles;
+    if (s > 64) s = 64;
+    if (s < 1) s = 1;
+    int64_t c = (batch + s - 1) / s;
+    c = (c + BK - 1) / BK * BK;
+    if (c < BK) c = BK;
+    *chunk = (int)c;
+    *S = (int)((batch + c - 1) / c);
+    if (*S < 1) *S = 1;
+}
+
+constexpr int MAX_SPLIT = 64;
+
+struct Layout {
+    size_t params, grads, am, av, wb[MLP_MAX_LAYERS], wt[MLP_MAX_LAYERS];
+    size_t act[MLP_MAX_LAYERS], zf[MLP_MAX_LAYERS], dz[2], part, lpart, total;
+    int64_t P;
+    int64_t poff[MLP_MAX_LAYERS];  // offset of W_l in the parameter vector (b_l follows)
+};
+
+bool widths_ok(const int32_t *w, int n) {
+    if (!w || n < 1 || n > MLP_MAX_LAYERS) return false;
+    for (int i = 0; i <= n; ++i)
+        if (w[i] < 32 || w[i] > 4096 || w[i] % 32 != 0) return false;
+    return true;
+}
+
+Layout make_layout(const int32_t *w, int n, int64_t maxb) {
+    Layout l{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = al256(off + bytes);
+        return o;
+    };
+    int64_t P = 0;
+    int wmax = 0;
+    size_t pmax = 0;
+    for (int i = 0; i < n; ++i) {
+        l.poff[i] = P;
+        P += (int64_t)w[i + 1] * w[i] + w[i + 1];
+        size_t need = (size_t)MAX_SPLIT * w[i + 1] * w[i];
+        if (need > pmax) pmax = need;
+        need = (size_t)MAX_SPLIT * w[i + 1];
+        if (need > pmax) pmax = need;
+    }
+    for (int i = 0; i <= n; ++i) wmax = w[i] > wmax ? w[i] : wmax;
+    l.P = P;
+    l.params = take(P * sizeof(float));
+    l.grads = take(P * sizeof(float));
+    l.am = take(P * sizeof(float));
+    l.av = take(P * sizeof(float));
+    for (int i = 0; i < n; ++i) {
+        l.wb[i] = take((size_t)w[i + 1] * w[i] * 2);
+        l.wt[i] = take((size_t)w[i + 1] * w[i] * 2);
+    }
+    for (int i = 1; i < n; ++i) {
+        l.act[i] = take((size_t)maxb * w[i] * 2);
+        l.zf[i] = take((size_t)maxb * w[i] * 4);
+    }
+    l.dz[0] = take((size_t)maxb * wmax * 2);
+    l.dz[1] = take((size_t)maxb * wmax * 2);
+    l.part = take(pmax * sizeof(float));
+    l.lpart = take(((size_t)maxb * w[n] + THREADS - 1) / THREADS * sizeof(float));
+    l.total = off;
+    return l;
+}
+
+}  // namespace
+
+struct mlp {
+    int n;
+    int32_t w[MLP_MAX_LAYERS + 1];
+    int64_t maxb;
+    char *ws;
+    Layout lay;
+    int64_t t;             // Adam steps taken
+    const uint16_t *x;     // input of the last forward with keep
+    int64_t fwd_batch;
+    int dz_top;            // buffer holding the output gradient of the last mlp_mse
+};
+
+namespace {
+
+float *fp(mlp *m, size_t off) { return (float *)(m->ws + off); }
+uint16_t *hp(mlp *m, size_t off) { return (uint16_t *)(m->ws + off); }
+
+int refresh_bf16(mlp *m, hipStream_t st) {
+    for (int i = 0; i < m->n; ++i) {
+        const int64_t cnt = (int64_t)m->w[i + 1] * m->w[i];
+        hipLaunchKernelGGL(k_to_bf16, dim3(nblocks(cnt)), dim3(THREADS), 0, st,
+                           (const float *)fp(m, m->lay.params) + m->lay.poff[i], m->w[i + 1], m->w[i],
+                           hp(m, m->lay.wb[i]), hp(m, m->lay.wt[i]));
+    }
+    return check();
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t mlp_workspace_bytes(const int32_t *widths, int n_layers, int64_t max_batch) {
+    if (!widths_ok(widths, n_layers) || max_batch < 1 || max_batch > (1ll << 26)) return 0;
+    return make_layout(widths, n_layers, max_batch).total;
+}
+
+int mlp_create(const int32_t *widths, int n_layers, int64_t max_batch, void *workspace,
+               size_t ws_bytes, mlp_t **out) {
+    if (!out || !workspace || !widths_ok(widths, n_layers) || max_batch < 1 ||
+        max_batch > (1ll << 26))
+        return MLP_EINVAL;
+    if (((uintptr_t)workspace & 255u) != 0) return MLP_EINVAL;
+    const Layout l = make_layout(widths, n_layers, max_batch);
+    if (ws_bytes < l.total) return MLP_EINVAL;
+    mlp *m = new mlp;
+    m->n = n_layers;
+    for (int i = 0; i <= n_layers; ++i) m->w[i] = widths[i];
+    m->maxb = max_batch;
+    m->ws = (char *)workspace;
+    m->lay = l;
+    m->t = 0;
+    m->x = nullptr;
+    m->fwd_batch = 0;
+    m->dz_top = 0;
+    *out = m;
+    return MLP_OK;
+}
+
+void mlp_destroy(mlp_t *m) { delete m; }
+
+int64_t mlp_param_count(const mlp_t *m) { return m ? m->lay.P : -1; }
+
+int mlp_set_params(mlp_t *m, const float *params, void *stream) {
+    if (!m || !params) return MLP_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t P = m->lay.P;
+    if (hipMemcpyAsync(fp(m, m->lay.params), params, P * sizeof(float), hipMemcpyDeviceToDevice, st) !=
+        hipSuccess) {
+        g_mlp_hip = (int)hipGetLastError();
+        return MLP_EHIP;
+    }
+    hipLaunchKernelGGL(k_fill0, dim3(nblocks(P)), dim3(THREADS), 0, st, fp(m, m->lay.am), P);
+    hipLaunchKernelGGL(k_fill0, dim3(nblocks(P)), dim3(THREADS), 0, st, fp(m, m->lay.av), P);
+    hipLaunchKernelGGL(k_fill0, dim3(nblocks(P)), dim3(THREADS), 0, st, fp(m, m->lay.grads), P);
+    m->t = 0;
+    return refresh_bf16(m, st);
+}
+
+int mlp_get_params(const mlp_t *m, float *params, void *stream) {
+    if (!m || !params) return MLP_EINVAL;
+    if (hipMemcpyAsync(params, m->ws + m->lay.params, m->lay.P * sizeof(float),
+                       hipMemcpyDeviceToDevice, (hipStream_t)stream) != hipSuccess)
+        return MLP_EHIP;
+    return MLP_OK;
+}
+
+int mlp_get_grads(const mlp_t *m, float *grads, void *stream) {
+    if (!m || !grads) return MLP_EINVAL;
+    if (hipMemcpyAsync(grads, m->ws + m->lay.grads, m->lay.P * sizeof(float),
+                       hipMemcpyDeviceToDevice, (hipStream_t)stream) != hipSuccess)
+        return MLP_EHIP;
+    return MLP_OK;
+}
+
+int mlp_forward(mlp_t *m, const uint16_t *x, float *y, int64_t batch, int keep, void *stream) {
+    if (!m || !x || !y || batch < 1 || batch > m->maxb) return MLP_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    const uint16_t *in = x;
+    for (int i = 0; i < m->n; ++i) {
+        GemmArgs g{};
+        g.a = in;
+        g.lda = m->w[i];
+        g.b = hp(m, m->lay.wb[i]);
+        g.ldb = m->w[i];
+        g.M = batch;
+        g.N = m->w[i + 1];
+        g.K = m->w[i];
+        g.bias = fp(m, m->lay.params) + m->lay.poff[i] + (int64_t)m->w[i + 1] * m->w[i];
+        if (i + 1 < m->n) {
+            g.mode = EPI_GELU;
+            g.c = hp(m, m->lay.act[i + 1]);
+            g.z = keep ? fp(m, m->lay.zf[i + 1]) : nullptr;
+        } else {
+            g.mode = EPI_F32;
+            g.c = y;
+        }
+        g.ldc = m->w[i + 1];
+        const int rc = launch_gemm(false, g, 1, st);
+        if (rc != MLP_OK) return rc;
+        in = (const uint16_t *)g.c;
+    }
+    if (keep) {
+        m->x = x;
+        m->fwd_batch = batch;
+    }
+    return check();
+}
+
+int mlp_mse(mlp_t *m, const float *y, const float *target, int64_t batch, int n_valid, float *loss,
+            void *stream) {
+    if (!m || !y || !target || !loss || batch < 1 || batch > m->maxb || n_valid < 1 ||
+        n_valid > m->w[m->n])
+        return MLP_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    const int wo = m->w[m->n];
+    const int64_t total = batch * wo;
+    const unsigned nb = nblocks(total);
+    const float scale = (float)(1.0 / ((double)batch * n_valid));
+    hipLaunchKernelGGL(k_mse, dim3(nb), dim3(THREADS), 0, st, y, target, total, wo, n_valid, scale,
+                       hp(m, m->lay.dz[0]), fp(m, m->lay.lpart));
+    hipLaunchKernelGGL(k_mse_final, dim3(1), dim3(THREADS), 0, st, (const float *)fp(m, m->lay.lpart),
+                       (int64_t)nb, scale, loss);
+    m->dz_top = 0;
+    return check();
+}
+
+int mlp_backward(mlp_t *m, int64_t batch, void *stream) {
+    if (!m || !m->x || batch != m->fwd_batch) return MLP_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    int cur = m->dz_top;
+    float *part = fp(m, m->lay.part);
+    for (int i = m->n - 1; i >= 0; --i) {
+        const int no = m->w[i + 1], ni = m->w[i];
+        const uint16_t *dz = hp(m, m->lay.dz[cur]);
+        const uint16_t *ain = i == 0 ? m->x : hp(m, m->lay.act[i]);
+        float *gW = fp(m, m->lay.grads) + m->lay.poff[i];
+        float *gb = gW + (int64_t)no * ni;
+        // dW_i[no][ni] = sum_b dz[b][no] * ain[b][ni]
+        int S, chunk;
+        wgrad_split(batch, no, ni, &S, &chunk);
+        GemmArgs g{};
+        g.a = dz;
+        g.lda = no;
+        g.b = ain;
+        g.ldb = ni;
+        g.M = no;
+        g.N = ni;
+        g.K = (int)batch;
+        g.ksplit = chunk;
+        g.mode = EPI_PARTIAL;
+        g.c = part;
+        g.ldc = ni;
+        g.split_stride = (int64_t)no * ni;
+        int rc = launch_gemm(true, g, S, st);
+        if (rc != MLP_OK) return rc;
+        hipLaunchKernelGGL(k_sum_parts, dim3(nblocks((int64_t)no * ni)), dim3(THREADS), 0, st,
+                           (const float *)part, S, (int64_t)no * ni, gW);
+        // db_i[no] = sum_b dz[b][no]
+        const int64_t rchunk = (batch + MAX_SPLIT - 1) / MAX_SPLIT;
+        const int RS = (int)((batch + rchunk - 1) / rchunk);
+        hipLaunchKernelGGL(k_colsum_partial, dim3(nblocks(no), RS), dim3(THREADS), 0, st, dz, batch,
+                           no, rchunk, part);
+        hipLaunchKernelGGL(k_sum_parts, dim3(nblocks(no)), dim3(THREADS), 0, st, (const float *)part,
+                           RS, (int64_t)no, gb);
+        if (i == 0) break;
+        // dz_prev[b][ni] = (sum_n dz[b][n] W_i[n][ni]) * gelu'(z_i[b][ni])
+        GemmArgs d{};
+        d.a = dz;
+        d.lda = no;
+        d.b = hp(m, m->lay.wt[i]);
+        d.ldb = no;
+        d.M = batch;
+        d.N = ni;
+        d.K = no;
+        d.mode = EPI_DGELU;
+        d.c = hp(m, m->lay.dz[cur ^ 1]);
+        d.ldc = ni;
+        d.z = fp(m, m->lay.zf[i]);
+        rc = launch_gemm(false, d, 1, st);
+        if (rc != MLP_OK) return rc;
+        cur ^= 1;
+    }
+    return check();
+}
+
+int mlp_adam_step(mlp_t *m, float lr, float beta1, float beta2, float eps, void *stream) {
+    if (!m || !(lr >= 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) ||
+        !(eps > 0.0f))
+        return MLP_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    m->t += 1;
+    const float bc1 = (float)(1.0 - pow((double)beta1, (double)m->t));
+    const float bc2 = (float)(1.0 - pow((double)beta2, (double)m->t));
+    const int64_t P = m->lay.P;
+    hipLaunchKernelGGL(k_adam, dim3(nblocks(P)), dim3(THREADS), 0, st, fp(m, m->lay.params),
+                       (const float *)fp(m, m->lay.grads), fp(m, m->lay.am), fp(m, m->lay.av), P, lr,
+                       beta1, beta2, eps, bc1, bc2);
+    return refresh_bf16(m, st);
+}
+
+int mlp_gemm_nt(const uint16_t *a, int64_t lda, const uint16_t *b, int64_t ldb, const float *bias,
+                int64_t M, int32_t N, int32_t K, int mode, void *c, int64_t ldc, float *z,
+                void *stream) {
+    if (!a || !b || !c || M < 1 || N < 1 || K < 8 || K % 8 != 0 || lda < K || ldb < K || ldc < N ||
+        lda % 8 != 0 || ldb % 8 != 0 || (mode != EPI_F32 && mode != EPI_GELU))
+        return MLP_EINVAL;
+    GemmArgs g{};
+    g.a = a;
+    g.lda = lda;
+    g.b = b;
+    g.ldb = ldb;
+    g.M = M;
+    g.N = N;
+    g.K = K;
+    g.mode = mode;
+    g.bias = bias;
+    g.c = c;
+    g.ldc = ldc;
+    g.z = z;
+    const int rc = launch_gemm(false, g, 1, (hipStream_t)stream);
+    if (rc != MLP_OK) return rc;
+    return check();
+}
+
+const char *mlp_strerror(int code) {
+    switch (code) {
+        case MLP_OK: return "ok";
+        case MLP_EINVAL: return "invalid argument";
+        case MLP_EHIP: return "HIP launch failure";
+        default: return "unknown error";
+    }
+}
+
+}  // extern "C"

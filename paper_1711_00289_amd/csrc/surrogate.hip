@@ -1,0 +1,482 @@
+// surrogate.hip -- kernels and host logic of the learned surrogate (include/surrogate.h): feature
+// and target packing between the level-major column arrays and the network's row-major batches
+// (transposed through LDS so both sides are accessed contiguously), per-feature statistics,
+// normalisation, un-normalisation with the fallback test, and the gather / conv_step / scatter of
+// the columns that fall back to the FP64 scheme.
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+#include <string.h>
+
+#include "conv.h"
+#include "conv_internal.hpp"
+#include "mlp.h"
+#include "surrogate.h"
+
+using namespace cvk;
+
+namespace {
+
+constexpr int TB = 256;      // threads per block
+constexpr int TC = 64;       // columns per transposing block
+constexpr int WMAX = 256;    // widest feature row
+constexpr int SPART = 256;   // row chunks of the statistics reduction
+
+__device__ __forceinline__ uint16_t f2bf(float f) {  // round to nearest even
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+struct StateArgs {
+    const double *T, *q, *pm;
+    int64_t ld;
+};
+
+// Inputs of a block of 64 columns into LDS as [feature][column], then out as rows.
+// mode 0: raw FP32 rows; mode 1: normalised BF16 rows.
+__global__ __launch_bounds__(TB) void k_pack_in(StateArgs s, int L, int64_t ncol, int w, int mode,
+                                                const float *mean, const float *stdv, float *outf,
+                                                uint16_t *outb) {
+    __shared__ float sh[WMAX][TC + 1];
+    const int64_t c0 = (int64_t)blockIdx.x * TC;
+    const int lane = threadIdx.x % TC, grp = threadIdx.x / TC;
+    const int64_t c = c0 + lane;
+    const int64_t ld = s.ld;
+    for (int f = grp; f < w; f += TB / TC) {
+        double v = 0.0;
+        if (c < ncol) {
+            if (f < L) v = s.T[(int64_t)f * ld + c];
+            else if (f < 2 * L) v = s.q[(int64_t)(f - L) * ld + c];
+            else if (f < 3 * L) v = s.pm[(int64_t)(f - 2 * L) * ld + c];
+        }
+        sh[f][lane] = (float)v;
+    }
+    __syncthreads();
+    const int64_t nrows = ncol - c0 < TC ? ncol - c0 : TC;
+    for (int64_t i = threadIdx.x; i < nrows * w; i += TB) {
+        const int r = (int)(i / w), f = (int)(i % w);
+        const float v = sh[f][r];
+        const int64_t o = (c0 + r) * w + f;
+        if (mode == 0) {
+            outf[o] = v;
+        } else {
+            outb[o] = f < 3 * L ? f2bf((v - mean[f]) / stdv[f]) : (uint16_t)0;
+        }
+    }
+}
+
+struct OutArgs {
+    const double *dT_d, *dq_d, *pr_d, *dT_s, *dq_s, *pr_s;
+    int64_t ld;
+};
+
+__global__ __launch_bounds__(TB) void k_pack_tgt(OutArgs a, int L, int64_t ncol, int w, float *out) {
+    __shared__ float sh[WMAX][TC + 1];
+    const int64_t c0 = (int64_t)blockIdx.x * TC;
+    const int lane = threadIdx.x % TC, grp = threadIdx.x / TC;
+    const int64_t c = c0 + lane;
+    const int64_t ld = a.ld;
+    for (int f = grp; f < w; f += TB / TC) {
+        double v = 0.0;
+        if (c < ncol) {
+            if (f < L) v = a.dT_d[(int64_t)f * ld + c] + a.dT_s[(int64_t)f * ld + c];
+            else if (f < 2 * L) v = a.dq_d[(int64_t)(f - L) * ld + c] + a.dq_s[(int64_t)(f - L) * ld + c];
+            else if (f == 2 * L) v = a.pr_d[c] + a.pr_s[c];
+        }
+        sh[f][lane] = (float)v;
+    }
+    __syncthreads();
+    const int64_t nrows = ncol - c0 < TC ? ncol - c0 : TC;
+    for (int64_t i = threadIdx.x; i < nrows * w; i += TB) {
+        const int r = (int)(i / w), f = (int)(i % w);
+        out[(c0 + r) * w + f] = sh[f][r];
+    }
+}
+
+// Statistics in two passes (the one-pass E[v^2] - E[v]^2 cancels for features that are nearly or
+// exactly constant, such as the mid-level pressures of a grid with a common surface pressure).
+// Pass p: block b sums, for 64 features (blockIdx.y selects them), the rows of chunk b -- v when
+// center == NULL, else (v - center[j])^2 -- over four row groups combined in a fixed order.
+__global__ __launch_bounds__(TB) void k_stats_part(const float *a, int64_t n, int w, int64_t chunk,
+                                                   const double *center, double *part) {
+    __shared__ double s1[TB / TC][TC];
+    const int lane = threadIdx.x % TC, grp = threadIdx.x / TC;
+    const int j = blockIdx.y * TC + lane;
+    const int64_t r0 = (int64_t)blockIdx.x * chunk;
+    const int64_t r1 = r0 + chunk < n ? r0 + chunk : n;
+    double x1 = 0.0;
+    if (j < w) {
+        const double c = center ? center[j] : 0.0;
+        for (int64_t r = r0 + grp; r < r1; r += TB / TC) {
+            const double v = (double)a[r * w + j];
+            x1 += center ? (v - c) * (v - c) : v;
+        }
+    }
+    s1[grp][lane] = x1;
+    __syncthreads();
+    if (grp == 0 && j < w) {
+        double t1 = 0.0;
+        for (int g = 0; g < TB / TC; ++g) t1 += s1[g][lane];
+        part[(int64_t)blockIdx.x * w + j] = t1;
+    }
+}
+
+// Sum of the partials of feature j in order, divided by n, into out[j].
+__global__ __launch_bounds__(TB) void k_stats_reduce(const double *part, int nparts, int64_t n, int w,
+                                                     double *out) {
+    const int j = blockIdx.x * TB + threadIdx.x;
+    if (j >= w) return;
+    double t = 0.0;
+    for (int p = 0; p < nparts; ++p) t += part[(int64_t)p * w + j];
+    out[j] = t / (double)n;
+}
+
+__global__ __launch_bounds__(TB) void k_stats_final(const double *mean, const double *var, int w,
+                                                    int nvalid, float *meanf, float *stdf,
+                                                    float *rmsf) {
+    const int j = blockIdx.x * TB + threadIdx.x;
+    if (j >= w) return;
+    const double sd = var[j] > 0.0 ? sqrt(var[j]) : 0.0;
+    meanf[j] = j < nvalid ? (float)mean[j] : 0.0f;
+    stdf[j] = (j < nvalid && sd > 0.0) ? (float)sd : 1.0f;
+    if (rmsf) rmsf[j] = (float)sqrt(var[j] + mean[j] * mean[j]);
+}
+
+__global__ __launch_bounds__(TB) void k_normalize(float *a, int64_t total, int w, const float *mean,
+                                                  const float *stdv, uint16_t *outb) {
+    const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
+    if (i >= total) return;
+    const int j = (int)(i % w);
+    const float v = (a[i] - mean[j]) / stdv[j];
+    if (outb) outb[i] = f2bf(v);
+    else a[i] = v;
+}
+
+// Network output rows of 64 columns -> level-major FP64 tendencies; flags columns whose predicted
+// precipitation is outside [lo, hi] into the fallback list (first wavefront, one lane per column).
+__global__ __launch_bounds__(TB) void k_unpack(const float *y, int L, int64_t ncol, int w,
+                                               const float *mean, const float *stdv, double lo,
+                                               double hi, double *dTdt, double *dqdt, double *prec,
+                                               int64_t ld, int64_t col0, int *list, int *cnt) {
+    __shared__ float sh[WMAX][TC + 1];
+    const int64_t c0 = (int64_t)blockIdx.x * TC;
+    const int64_t nrows = ncol - c0 < TC ? ncol - c0 : TC;
+    const int nf = 2 * L + 1;
+    for (int64_t i = threadIdx.x; i < nrows * w; i += TB) {
+        const int r = (int)(i / w), f = (int)(i % w);
+        if (f < nf) sh[f][r] = y[(c0 + r) * w + f] * stdv[f] + mean[f];
+    }
+    __syncthreads();
+    const int lane = threadIdx.x % TC, grp = threadIdx.x / TC;
+    const int64_t c = c0 + lane;
+    const bool live = lane < nrows;
+    for (int f = grp; f < 2 * L; f += TB / TC) {
+        if (!live) continue;
+        const double v = (double)sh[f][lane];
+        if (f < L) dTdt[(int64_t)f * ld + col0 + c] = v;
+        else dqdt[(int64_t)(f - L) * ld + col0 + c] = v;
+    }
+    if (grp == 0) {
+        const double p = live ? (double)sh[2 * L][lane] : 0.0;
+        if (live) prec[col0 + c] = p > 0.0 ? p : 0.0;
+        const bool fb = live && (p < lo || p > hi);
+        const int slot = wave_append(fb, cnt);
+        if (slot >= 0) list[slot] = (int)(col0 + c);
+    }
+}
+
+struct Compact {
+    double *T, *q, *pm, *z, *pi, *phis, *pblh, *tke;
+    int64_t ld;
+};
+
+__global__ __launch_bounds__(TB) void k_gather(conv_state_t s, int L, const int *list, const int *cnt,
+                                               Compact d) {
+    const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
+    if (i >= *cnt) return;
+    const int64_t c = list[i];
+    const int64_t ls = s.ld, lc = d.ld;
+    for (int k = 0; k < L; ++k) {
+        d.T[k * lc + i] = s.T[k * ls + c];
+        d.q[k * lc + i] = s.q[k * ls + c];
+        d.pm[k * lc + i] = s.p_mid[k * ls + c];
+        d.z[k * lc + i] = s.z[k * ls + c];
+    }
+    for (int k = 0; k <= L; ++k) d.pi[k * lc + i] = s.p_int[k * ls + c];
+    d.phis[i] = s.phis[c];
+    d.pblh[i] = s.pblh[c];
+    d.tke[i] = s.tke[c];
+}
+
+__global__ __launch_bounds__(TB) void k_scatter(conv_deep_out_t dd, conv_shallow_out_t ss, int64_t lc,
+                                                int L, const int *list, const int *cnt, double *dTdt,
+                                                double *dqdt, double *prec, int64_t ld) {
+    const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
+    if (i >= *cnt) return;
+    const int64_t c = list[i];
+    for (int k = 0; k < L; ++k) {
+        dTdt[k * ld + c] = dd.dTdt[k * lc + i] + ss.dTdt[k * lc + i];
+        dqdt[k * ld + c] = dd.dqdt[k * lc + i] + ss.dqdt[k * lc + i];
+    }
+    prec[c] = dd.prec[i] + ss.prec[i];
+}
+
+__global__ void k_zero_int(int *p) {
+    if (threadIdx.x == 0) p[0] = 0;
+}
+
+unsigned nb(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+size_t al(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct SLayout {
+    size_t x, y, norm, list, cnt, cst, dout, sout, cws, total;
+    size_t cws_bytes;
+};
+
+SLayout surr_layout(int L, int w_in, int w_out, int64_t maxc, int64_t chunk, int cus) {
+    SLayout l{};
+    size_t off = 0;
+    auto take = [&](size_t b) {
+        const size_t o = off;
+        off = al(off + b);
+        return o;
+    };
+    const size_t m = (size_t)maxc;
+    l.x = take((size_t)chunk * w_in * 2);
+    l.y = take((size_t)chunk * w_out * 4);
+    l.norm = take((size_t)2 * (w_in + w_out) * 4);
+    l.list = take(m * 4);
+    l.cnt = take(256);
+    l.cst = take(((size_t)4 * L + (L + 1) + 3) * m * 8);
+    l.dout = take(((size_t)2 * L + 2 * (L + 1) + 2) * m * 8 + 4 * m * 4);
+    l.sout = take(((size_t)2 * L + (L + 1) + 2) * m * 8 + 3 * m * 4);
+    (void)cus;
+    l.cws_bytes = conv_workspace_bytes(maxc, L);
+    l.cws = take(l.cws_bytes);
+    l.total = off;
+    return l;
+}
+
+int hip_err() {
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? CONV_OK : CONV_EHIP;
+}
+
+}  // namespace
+
+struct surr {
+    mlp_t *net;
+    int L, w_in, w_out;
+    int64_t maxc, chunk;
+    conv_params_t P;
+    char *ws;
+    SLayout lay;
+    double lo, hi;
+};
+
+namespace {
+
+float *nrm(surr *s, int which) {  // 0 in_mean, 1 in_std, 2 out_mean, 3 out_std
+    float *b = (float *)(s->ws + s->lay.norm);
+    switch (which) {
+        case 0: return b;
+        case 1: return b + s->w_in;
+        case 2: return b + 2 * s->w_in;
+        default: return b + 2 * s->w_in + s->w_out;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int surr_pack_inputs_raw(const conv_state_t *s, int32_t nlev, int64_t ncol, int32_t w_in,
+                         float *out, void *stream) {
+    if (!s || !s->T || !s->q || !s->p_mid || !out || nlev < 2 || ncol < 0 || w_in < 3 * nlev ||
+        w_in > WMAX || s->ld < ncol)
+        return CONV_EINVAL;
+    if (ncol == 0) return CONV_OK;
+    StateArgs a{s->T, s->q, s->p_mid, s->ld};
+    hipLaunchKernelGGL(k_pack_in, dim3(nb(ncol, TC)), dim3(TB), 0, (hipStream_t)stream, a, nlev, ncol,
+                       w_in, 0, (const float *)nullptr, (const float *)nullptr, out, (uint16_t *)nullptr);
+    return hip_err();
+}
+
+int surr_pack_inputs(const conv_state_t *s, int32_t nlev, int64_t ncol, int32_t w_in,
+                     const float *mean, const float *std, uint16_t *x, void *stream) {
+    if (!s || !s->T || !s->q || !s->p_mid || !x || !mean || !std || nlev < 2 || ncol < 0 ||
+        w_in < 3 * nlev || w_in > WMAX || s->ld < ncol)
+        return CONV_EINVAL;
+    if (ncol == 0) return CONV_OK;
+    StateArgs a{s->T, s->q, s->p_mid, s->ld};
+    hipLaunchKernelGGL(k_pack_in, dim3(nb(ncol, TC)), dim3(TB), 0, (hipStream_t)stream, a, nlev, ncol,
+                       w_in, 1, mean, std, (float *)nullptr, x);
+    return hip_err();
+}
+
+int surr_pack_targets_raw(const conv_deep_out_t *d, const conv_shallow_out_t *sh, int32_t nlev,
+                          int64_t ld, int64_t ncol, int32_t w_out, float *out, void *stream) {
+    if (!d || !sh || !d->dTdt || !d->dqdt || !d->prec || !sh->dTdt || !sh->dqdt || !sh->prec || !out ||
+        nlev < 2 || ncol < 0 || ld < ncol || w_out < 2 * nlev + 1 || w_out > WMAX)
+        return CONV_EINVAL;
+    if (ncol == 0) return CONV_OK;
+    OutArgs a{d->dTdt, d->dqdt, d->prec, sh->dTdt, sh->dqdt, sh->prec, ld};
+    hipLaunchKernelGGL(k_pack_tgt, dim3(nb(ncol, TC)), dim3(TB), 0, (hipStream_t)stream, a, nlev, ncol,
+                       w_out, out);
+    return hip_err();
+}
+
+size_t surr_col_stats_scratch_bytes(int32_t w) {
+    return (w < 1 || w > WMAX) ? 0 : ((size_t)SPART * w + 2 * (size_t)w) * sizeof(double);
+}
+
+int surr_col_stats(const float *a, int64_t n, int32_t w, int32_t n_valid, float *mean, float *std,
+                   float *rms, void *scratch, size_t scratch_bytes, void *stream) {
+    if (!a || !mean || !std || !scratch || n < 1 || w < 1 || w > WMAX || n_valid < 0 || n_valid > w ||
+        scratch_bytes < surr_col_stats_scratch_bytes(w))
+        return CONV_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t chunk = (n + SPART - 1) / SPART;
+    const int parts = (int)((n + chunk - 1) / chunk);
+    double *part = (double *)scratch;
+    double *m64 = part + (size_t)SPART * w;
+    double *v64 = m64 + w;
+    const dim3 grid(parts, nb(w, TC));
+    hipLaunchKernelGGL(k_stats_part, grid, dim3(TB), 0, st, a, n, w, chunk, (const double *)nullptr, part);
+    hipLaunchKernelGGL(k_stats_reduce, dim3(nb(w, TB)), dim3(TB), 0, st, (const double *)part, parts, n, w,
+                       m64);
+    hipLaunchKernelGGL(k_stats_part, grid, dim3(TB), 0, st, a, n, w, chunk, (const double *)m64, part);
+    hipLaunchKernelGGL(k_stats_reduce, dim3(nb(w, TB)), dim3(TB), 0, st, (const double *)part, parts, n, w,
+                       v64);
+    hipLaunchKernelGGL(k_stats_final, dim3(nb(w, TB)), dim3(TB), 0, st, (const double *)m64,
+                       (const double *)v64, w, n_valid, mean, std, rms);
+    return hip_err();
+}
+
+int surr_normalize(float *a, int64_t n, int32_t w, const float *mean, const float *std,
+                   uint16_t *out_bf16, void *stream) {
+    if (!a || !mean || !std || n < 0 || w < 1) return CONV_EINVAL;
+    if (n == 0) return CONV_OK;
+    hipLaunchKernelGGL(k_normalize, dim3(nb(n * w, TB)), dim3(TB), 0, (hipStream_t)stream, a, n * w, w,
+                       mean, std, out_bf16);
+    return hip_err();
+}
+
+size_t surr_workspace_bytes(int32_t nlev, int32_t w_in, int32_t w_out, int64_t max_cols,
+                            int64_t chunk) {
+    if (nlev < 2 || w_in < 3 * nlev || w_in > WMAX || w_out < 2 * nlev + 1 || w_out > WMAX ||
+        max_cols < 1 || max_cols > INT32_MAX || chunk < 1)
+        return 0;
+    return surr_layout(nlev, w_in, w_out, max_cols, chunk, device_cus()).total;
+}
+
+int surr_create(mlp_t *net, int32_t nlev, int32_t w_in, int32_t w_out, int64_t max_cols,
+                int64_t chunk, const conv_params_t *params, void *workspace, size_t ws_bytes,
+                surr_t **out) {
+    if (!net || !params || !workspace || !out || nlev < 2 || w_in < 3 * nlev || w_in > WMAX ||
+        w_out < 2 * nlev + 1 || w_out > WMAX || max_cols < 1 || max_cols > INT32_MAX || chunk < 1)
+        return CONV_EINVAL;
+    if (((uintptr_t)workspace & 255u) != 0) return CONV_EINVAL;
+    const SLayout l = surr_layout(nlev, w_in, w_out, max_cols, chunk, device_cus());
+    if (ws_bytes < l.total || l.cws_bytes == 0) return CONV_EINVAL;
+    surr *s = new surr;
+    s->net = net;
+    s->L = nlev;
+    s->w_in = w_in;
+    s->w_out = w_out;
+    s->maxc = max_cols;
+    s->chunk = chunk;
+    s->P = *params;
+    s->ws = (char *)workspace;
+    s->lay = l;
+    s->lo = 0.0;
+    s->hi = 0.0;
+    *out = s;
+    return CONV_OK;
+}
+
+void surr_destroy(surr_t *s) { delete s; }
+
+int surr_set_norm(surr_t *s, const float *in_mean, const float *in_std, const float *out_mean,
+                  const float *out_std, double prec_lo, double prec_hi, void *stream) {
+    if (!s || !in_mean || !in_std || !out_mean || !out_std || !(prec_lo <= prec_hi)) return CONV_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    const float *src[4] = {in_mean, in_std, out_mean, out_std};
+    const int len[4] = {s->w_in, s->w_in, s->w_out, s->w_out};
+    for (int i = 0; i < 4; ++i)
+        if (hipMemcpyAsync(nrm(s, i), src[i], len[i] * sizeof(float), hipMemcpyDeviceToDevice, st) !=
+            hipSuccess)
+            return CONV_EHIP;
+    s->lo = prec_lo;
+    s->hi = prec_hi;
+    return CONV_OK;
+}
+
+int surr_infer(surr_t *s, const conv_state_t *state, int64_t ncol, double *dTdt, double *dqdt,
+               double *prec, int fallback, int64_t *n_fallback, void *stream) {
+    if (!s || !state || !state->T || !state->q || !state->p_mid || !dTdt || !dqdt || !prec ||
+        ncol < 0 || ncol > s->maxc || state->ld < ncol)
+        return CONV_EINVAL;
+    if (fallback && (!state->z || !state->p_int || !state->phis || !state->pblh || !state->tke))
+        return CONV_EINVAL;
+    if (ncol == 0) {
+        if (fallback && n_fallback) *n_fallback = 0;
+        return CONV_OK;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    const int L = s->L;
+    const int64_t ld = state->ld;
+    uint16_t *X = (uint16_t *)(s->ws + s->lay.x);
+    float *Y = (float *)(s->ws + s->lay.y);
+    int *list = (int *)(s->ws + s->lay.list);
+    int *cnt = (int *)(s->ws + s->lay.cnt);
+    hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, cnt);
+    for (int64_t c0 = 0; c0 < ncol; c0 += s->chunk) {
+        const int64_t n = ncol - c0 < s->chunk ? ncol - c0 : s->chunk;
+        StateArgs a{state->T + c0, state->q + c0, state->p_mid + c0, ld};
+        hipLaunchKernelGGL(k_pack_in, dim3(nb(n, TC)), dim3(TB), 0, st, a, L, n, s->w_in, 1,
+                           (const float *)nrm(s, 0), (const float *)nrm(s, 1), (float *)nullptr, X);
+        const int rc = mlp_forward(s->net, X, Y, n, 0, stream);
+        if (rc != MLP_OK) return rc == MLP_EINVAL ? CONV_EINVAL : CONV_EHIP;
+        hipLaunchKernelGGL(k_unpack, dim3(nb(n, TC)), dim3(TB), 0, st, (const float *)Y, L, n, s->w_out,
+                           (const float *)nrm(s, 2), (const float *)nrm(s, 3), s->lo, s->hi, dTdt, dqdt,
+                           prec, ld, c0, list, cnt);
+    }
+    if (hip_err() != CONV_OK) return CONV_EHIP;
+    if (!fallback) return CONV_OK;
+    int nfb = 0;
+    if (hipMemcpyAsync(&nfb, cnt, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return CONV_EHIP;
+    if (n_fallback) *n_fallback = nfb;
+    if (nfb == 0) return CONV_OK;
+    const int64_t m = s->maxc;
+    double *cb = (double *)(s->ws + s->lay.cst);
+    Compact cs{cb, cb + (int64_t)L * m, cb + (int64_t)2 * L * m, cb + (int64_t)3 * L * m,
+               cb + (int64_t)4 * L * m, cb + (int64_t)(5 * L + 1) * m, cb + (int64_t)(5 * L + 2) * m,
+               cb + (int64_t)(5 * L + 3) * m, m};
+    hipLaunchKernelGGL(k_gather, dim3(nb(nfb, TB)), dim3(TB), 0, st, *state, L, (const int *)list,
+                       (const int *)cnt, cs);
+    double *db = (double *)(s->ws + s->lay.dout);
+    int32_t *di = (int32_t *)(db + ((int64_t)2 * L + 2 * (L + 1) + 2) * m);
+    conv_deep_out_t dd{db, db + (int64_t)L * m, db + (int64_t)2 * L * m, db + (int64_t)(3 * L + 1) * m,
+                       db + (int64_t)(4 * L + 2) * m, db + (int64_t)(4 * L + 3) * m, di, di + m,
+                       di + 2 * m, di + 3 * m};
+    double *sb = (double *)(s->ws + s->lay.sout);
+    int32_t *si = (int32_t *)(sb + ((int64_t)2 * L + (L + 1) + 2) * m);
+    conv_shallow_out_t ss{sb, sb + (int64_t)L * m, sb + (int64_t)2 * L * m, sb + (int64_t)(3 * L + 1) * m,
+                          sb + (int64_t)(3 * L + 2) * m, si, si + m, si + 2 * m};
+    conv_state_t cst{cs.T, cs.q, cs.pm, cs.z, cs.pi, cs.phis, cs.pblh, cs.tke, m, state->dt};
+    conv_ctx_t *ctx = nullptr;
+    int rc = conv_create(nfb, L, &s->P, s->ws + s->lay.cws, s->lay.cws_bytes, &ctx);
+    if (rc != CONV_OK) return rc;
+    rc = conv_step(ctx, &cst, &dd, &ss, stream);
+    conv_destroy(ctx);
+    if (rc != CONV_OK) return rc;
+    hipLaunchKernelGGL(k_scatter, dim3(nb(nfb, TB)), dim3(TB), 0, st, dd, ss, m, L, (const int *)list,
+                       (const int *)cnt, dTdt, dqdt, prec, ld);
+    return hip_err();
+}
+
+}  // extern "C"
