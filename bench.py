@@ -190,8 +190,8 @@ def main():
                          "known size for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the column-sharded design "
-              "for more GPUs is described in DESIGN.md and not built", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the multi-GPU column "
+              "sharding is designed but not built", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -9,8 +9,10 @@
  * 2); shallow convection tests thermodynamic conditions at several points and zeroes the outputs of
  * columns that exit early (Algorithm 3); inputs and outputs travel as one structure of arrays with
  * resident parameters and static buffers (Methodology, "Proportional Partitioning": packing,
- * offloading only the needed data, static in/out variables).  The scheme computed (steps D1-D10 and
- * S1-S9) is the written reading in the design doc, section 2.
+ * offloading only the needed data, static in/out variables).  The paper gives the loop skeletons but
+ * not the physics; the scheme computed is a written reading of ZM-style deep and UW-style shallow
+ * convection in steps C0-C1 (grid, thermodynamics), D1-D10 (deep) and S1-S9 (shallow), which the
+ * oracle's source (oracle/conv_oracle.cpp) states step by step and the kernels cite.
  *
  * Conventions for every call:
  *  - All array pointers are DEVICE pointers owned by the caller.  The library never allocates or

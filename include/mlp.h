@@ -4,7 +4,7 @@
  *
  * The paper accelerates the convection schemes themselves (arXiv:1711.00289, Algorithms 2-3); this
  * network is an extension trained on (sounding -> tendency) pairs that those schemes generate, with
- * the FP64 schemes kept as the fallback and as the judge of its error.
+ * the FP64 schemes kept as the fallback and as the reference for its error.
  *
  * Conventions.
  *   widths[0..n_layers] are the layer widths (input first); each is a multiple of 32, at most 4096.

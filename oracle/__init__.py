@@ -2,16 +2,20 @@
 
 A plain, slow, single-threaded FP64 C++ implementation (``conv_oracle.cpp``) of the deep
 (Zhang-McFarlane-style) and shallow (UW bulk-plume-style) schemes whose loop skeletons the paper
-gives (arXiv:1711.00289, Algorithms 2 and 3; the scheme reading is DESIGN.md "Scheme", steps
-D1-D10 and S1-S9), wrapped with ctypes for numpy arrays.
+gives (arXiv:1711.00289, Algorithms 2 and 3), in the written reading's steps C0-C1, D1-D10 and
+S1-S9 stated in that source, wrapped with ctypes for numpy arrays.  ``mlp_ref`` is the numpy
+reference of the surrogate network.
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of ``bench.py`` may import
 this package.  It shares no code with the HIP library and never imports it.
 
-Parity status: every function here is pinned by ``tests/test_oracle_*.py`` against closed forms,
-conservation identities, finite differences, 50-digit evaluations and an independent brute-force
-implementation on tiny columns; fidelity to CAM5's own ZM/UW code is "parity unpinned" (no such code
-or reference output exists for this work).
+Parity status: every function here is pinned by ``tests/test_oracle_*.py`` against what the
+mathematics fixes independently of the code: closed forms (the vapour-pressure constant at 0 C,
+Clausius-Clapeyron, the dry-adiabat CAPE that telescopes, isothermal buoyancy, the Gaussian-tail
+closure), an independent empirical formula (Goff-Gratch), roots checked by their residuals,
+conservation of column energy and water, exit paths that must give exact zeros, and central finite
+differences (closure F, forward-mode tangents, the network's gradients).  Fidelity to CAM5's own
+ZM/UW code is "parity unpinned": no such code or reference output exists for this work.
 """
 from __future__ import annotations
 

@@ -9,9 +9,9 @@
  * skeletons: the deep scheme's entrainment loop and precipitation loop over columns x levels,
  * each calling an iterative inversion `ientropy` (Algorithm 2), and the shallow scheme's column
  * loop whose repeated thermodynamic checks send a column to an exit that zeroes its outputs
- * (Algorithm 3).  The physics filling those skeletons is the written reading in the design doc
- * ("Scheme"): steps C0-C1 (grid, thermodynamics), D1-D10 (deep) and S1-S9 (shallow).  Each
- * function below cites the step it implements.  The code follows the steps in order, with no
+ * (Algorithm 3).  The physics filling those skeletons is a written reading in steps C0-C1 (grid,
+ * thermodynamics), D1-D10 (deep) and S1-S9 (shallow), stated in the comments where each step is
+ * computed below.  The code follows the steps in order, with no
  * blocking or reordering, so it can be checked against the written steps by eye.
  *
  * Compiled with -O2 -ffp-contract=off (no fused multiply-add, no fast-math).

@@ -3,14 +3,14 @@
  * shallow (UW bulk-plume-style) cumulus convection schemes.
  *
  * TEST INFRASTRUCTURE ONLY.  This is a plain, slow, single-threaded FP64 reference used by the
- * tests, by the smoke check and by the benchmark's CPU baseline to judge the HIP path.  Nothing in
+ * tests, by the smoke check and by the benchmark's CPU baseline to check the HIP path.  Nothing in
  * the product library links, includes or calls it, and it shares no code with the HIP kernels.
  *
  * The paper (Ramesh et al., "Deep and Shallow convections in Atmosphere Models on Intel Xeon Phi
  * Coprocessor Systems", arXiv:1711.00289) names the two schemes (Background, "Deep Convection" /
  * "Shallow Convection") and gives their loop skeletons (Algorithms 2 and 3) but no physics; the
- * scheme computed here is the written reading frozen in DESIGN.md ("Scheme"), steps D1-D10 and
- * S1-S9.  All arrays are host arrays, level-major: element (k, col) at [k*ld + col], level 0 at
+ * scheme computed here is a written reading in steps C0-C1, D1-D10 and S1-S9, stated step by step
+ * in conv_oracle.cpp.  All arrays are host arrays, level-major: element (k, col) at [k*ld + col], level 0 at
  * the model top; interface arrays have nlev+1 rows.
  */
 #ifndef CONV_ORACLE_H
