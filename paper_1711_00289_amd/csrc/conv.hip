@@ -156,14 +156,8 @@ struct ShallowTrigger {
     }
 };
 
-__device__ void write_shallow_zero(const Member &M, int64_t col, int st, double cin, int ks) {
-    const int L = M.nlev;
-    const int64_t ld = M.ld;
-    for (int k = 0; k < L; ++k) {
-        AT(M.sout.dTdt, k) = 0.0;
-        AT(M.sout.dqdt, k) = 0.0;
-    }
-    for (int k = 0; k <= L; ++k) AT(M.sout.mu, k) = 0.0;
+// Scalar outputs of a column the shallow scheme leaves alone (its arrays were zeroed in sweep 1).
+__device__ void write_shallow_quiet(const Member &M, int64_t col, int st, double cin, int ks) {
     M.sout.prec[col] = 0.0;
     M.sout.cin[col] = (st == 3 || st == 4) ? cin : 0.0;
     M.sout.kbase[col] = (st == 6) ? -1 : ks;
@@ -171,18 +165,22 @@ __device__ void write_shallow_zero(const Member &M, int64_t col, int st, double 
     M.sout.status[col] = st;
 }
 
-__device__ void write_deep_zero(const Member &M, int64_t col) {
-    const int L = M.nlev;
-    const int64_t ld = M.ld;
-    for (int k = 0; k < L; ++k) {
+// Zero every output array of level k (and of interface k) of a column: the exact-zero outputs of
+// quiet columns, written while the sweep's loads are in flight; the plume passes overwrite only
+// the levels a plume touches.
+template <bool DEEP, bool SHALLOW>
+__device__ __forceinline__ void zero_level(const Member &M, int64_t ld, int64_t col, int k) {
+    if (DEEP) {
         AT(M.dout.dTdt, k) = 0.0;
         AT(M.dout.dqdt, k) = 0.0;
-    }
-    for (int k = 0; k <= L; ++k) {
         AT(M.dout.mu, k) = 0.0;
         AT(M.dout.md, k) = 0.0;
     }
-    M.dout.prec[col] = 0.0;
+    if (SHALLOW) {
+        AT(M.sout.dTdt, k) = 0.0;
+        AT(M.sout.dqdt, k) = 0.0;
+        AT(M.sout.mu, k) = 0.0;
+    }
 }
 
 // Stores the closure inputs of a shallow column that passed S1-S6 in list slot `slot`.
@@ -238,10 +236,18 @@ __global__ __launch_bounds__(BLOCK) void k_trigger(Src src, Work w) {
         valid = isfinite(phis);
         double pbot = AT(M.pi, L);
         double zbelow = 0.0;
+        if (DEEP) {
+            AT(M.dout.mu, L) = 0.0;
+            AT(M.dout.md, L) = 0.0;
+        }
+        if (SHALLOW) AT(M.sout.mu, L) = 0.0;
         for (int k0 = L - 1; k0 >= 0; k0 -= SWEEP1_CHUNK) {
             Lev v[SWEEP1_CHUNK];
 #pragma unroll
             for (int j = 0; j < SWEEP1_CHUNK; ++j) load_lev(v[j], M, ld, col, max(k0 - j, 0));
+#pragma unroll
+            for (int j = 0; j < SWEEP1_CHUNK; ++j)
+                if (k0 - j >= 0) zero_level<DEEP, SHALLOW>(M, ld, col, k0 - j);
 #pragma unroll
             for (int j = 0; j < SWEEP1_CHUNK; ++j) {
                 const int k = k0 - j;
@@ -345,7 +351,7 @@ __global__ __launch_bounds__(BLOCK) void k_trigger(Src src, Work w) {
             M.dout.ktop[col] = dscan ? kt : -1;
             M.dout.trig[col] = trig ? 1 : 0;
             M.dout.status[col] = st;
-            if (!trig) write_deep_zero(M, col);
+            if (!trig) M.dout.prec[col] = 0.0;
         }
         const int slot = wave_append(live && trig, &w.cnt[CNT_DEEP]);
         if (slot >= 0) {
@@ -369,7 +375,7 @@ __global__ __launch_bounds__(BLOCK) void k_trigger(Src src, Work w) {
             if (st < 0)
                 rho_s = AT(M.pi, sh.ks) / (RD * tv(AT(M.T, sh.ks), AT(M.q, sh.ks)));
             else
-                write_shallow_zero(M, col, st, sh.cin, sh.ks);
+                write_shallow_quiet(M, col, st, sh.cin, sh.ks);
         }
         const int slot = wave_append(mine && st < 0, &w.cnt[CNT_SHALLOW]);
         if (slot >= 0) shallow_enqueue(M, w, slot, mi, col, sh, rho_s, tke, 0);
@@ -596,17 +602,16 @@ __global__ __launch_bounds__(BLOCK) void k_deep_plume(Src src, Work w) {
                 const double Mc = cape / (P.tau * F);
                 Mb = Mc <= Mlim ? Mc : Mlim;
             }
-            // D10: every level of the column.
-            for (int k = 0; k < L; ++k) {
-                const bool in = st == 0 && k >= kt && k <= kb;
-                AT(M.dout.dTdt, k) = in ? Mb * SCR(2, k) : 0.0;
-                AT(M.dout.dqdt, k) = in ? Mb * SCR(5, k) : 0.0;
-            }
-            for (int i = 0; i <= L; ++i) {
-                const bool in = st == 0 && i >= kt + 1 && i <= kb;
-                const bool dn = in && kd >= 0 && i >= kd + 1;
-                AT(M.dout.mu, i) = in ? Mb * SCR(7, i) : 0.0;
-                AT(M.dout.md, i) = dn ? Mb * (alpha * SCR(6, i)) : 0.0;
+            // D10: the levels the plume touches (the trigger pass zeroed the whole column).
+            if (st == 0) {
+                for (int k = kt; k <= kb; ++k) {
+                    AT(M.dout.dTdt, k) = Mb * SCR(2, k);
+                    AT(M.dout.dqdt, k) = Mb * SCR(5, k);
+                }
+                for (int i = kt + 1; i <= kb; ++i) {
+                    AT(M.dout.mu, i) = Mb * SCR(7, i);
+                    if (kd >= 0 && i >= kd + 1) AT(M.dout.md, i) = Mb * (alpha * SCR(6, i));
+                }
             }
             M.dout.prec[col] = st == 0 ? Mb * P1 : 0.0;
             M.dout.status[col] = st;
@@ -662,7 +667,7 @@ __global__ __launch_bounds__(BLOCK) void k_deep_plume(Src src, Work w) {
                 if (sst < 0)
                     rho_s = AT(M.pi, sh.ks) / (RD * tv(Tn(sh.ks), qn(sh.ks)));
                 else
-                    write_shallow_zero(M, col, sst, sh.cin, sh.ks);
+                    write_shallow_quiet(M, col, sst, sh.cin, sh.ks);
             }
             const int sslot = wave_append(act && sst < 0, &w.cnt[CNT_SHALLOW]);
             if (sslot >= 0) shallow_enqueue(M, w, sslot, mi, col, sh, rho_s, tke, 1);
@@ -681,7 +686,6 @@ __global__ __launch_bounds__(BLOCK) void k_shallow_plume(Src src, Work w) {
 
     for (int64_t slot = gtid; slot < n; slot += nthreads) {
         const Member &M = src.at(w.smem[slot]);
-        const int L = M.nlev;
         const int64_t ld = M.ld;
         const conv_params_t &P = M.P;
         const int64_t col = w.slist[slot];
@@ -779,14 +783,12 @@ __global__ __launch_bounds__(BLOCK) void k_shallow_plume(Src src, Work w) {
         }
         const int st = (kt == ks - 1) ? 5 : 0;
         const double Mb = Mclos <= Mlim ? Mclos : Mlim;
-        for (int k = 0; k < L; ++k) {
-            const bool in = st == 0 && k >= kt && k <= ks;
-            AT(M.sout.dTdt, k) = in ? Mb * SCR(1, k) : 0.0;
-            AT(M.sout.dqdt, k) = in ? Mb * SCR(2, k) : 0.0;
-        }
-        for (int i = 0; i <= L; ++i) {
-            const bool in = st == 0 && i >= kt + 1 && i <= ks;
-            AT(M.sout.mu, i) = in ? Mb * SCR(0, i) : 0.0;
+        if (st == 0) {  // the trigger pass zeroed the column; write the plume's levels
+            for (int k = kt; k <= ks; ++k) {
+                AT(M.sout.dTdt, k) = Mb * SCR(1, k);
+                AT(M.sout.dqdt, k) = Mb * SCR(2, k);
+            }
+            for (int i = kt + 1; i <= ks; ++i) AT(M.sout.mu, i) = Mb * SCR(0, i);
         }
         M.sout.prec[col] = st == 0 ? Mb * P1 : 0.0;
         M.sout.cin[col] = cin;
