@@ -496,15 +496,16 @@ __global__ __launch_bounds__(BLOCK) void k_deep_plume(Src src, Work w) {
                 double E1 = qd - AT(M.q, kd);
                 SCR(5, kd) = E1;
                 int k = kd + 1;
-                double qn = AT(M.q, k), hn = SCR(8, k), zn = AT(M.z, min(k + 1, L - 1)),
-                       pn = AT(M.pi, k + 1);
+                double qn = AT(M.q, k), hn = SCR(8, k), zc = AT(M.z, k),
+                       zn = AT(M.z, min(k + 1, L - 1)), pn = AT(M.pi, k + 1);
                 for (; k <= kb - 1; ++k) {
-                    const double qk = qn, hkk = hn, zbelow = zn, pbel = pn;
+                    const double qk = qn, hkk = hn, zkk = zc, zbelow = zn, pbel = pn;
                     qn = AT(M.q, k + 1);
                     hn = SCR(8, k + 1);
+                    zc = zbelow;
                     zn = AT(M.z, min(k + 2, L - 1));
                     pn = AT(M.pi, min(k + 2, L));
-                    const double zlow = 0.5 * (AT(M.z, k) + zbelow);
+                    const double zlow = 0.5 * (zkk + zbelow);
                     const double Ed = epsd * ad * (zii - zlow);
                     const double adn = ad + Ed;
                     hd = (ad * hd + Ed * hkk) / adn;
@@ -548,7 +549,9 @@ __global__ __launch_bounds__(BLOCK) void k_deep_plume(Src src, Work w) {
                 t.c = SCR(2, kk);
                 t.e1 = SCR(5, kk);
             };
-            auto proc = [&](const TL &t, int k) {
+            // `t` holds layer k and interface k+1; `nx` (already loaded) holds layer k+1, the
+            // upwind layer where the compensating flow at interface k+1 points up.
+            auto proc = [&](const TL &t, const TL &nx, int k) {
                 double Fs = 0.0, Fq = 0.0;
                 const int i = k + 1;
                 if (i <= kb) {
@@ -556,8 +559,8 @@ __global__ __launch_bounds__(BLOCK) void k_deep_plume(Src src, Work w) {
                     const double ed = dn ? t.ed : 0.0;
                     const bool upw = t.et + alpha * ed >= 0.0;
                     const double s_up = upw ? CP * t.T + GRAV * t.z + phis
-                                            : CP * AT(M.T, i) + GRAV * AT(M.z, i) + phis;
-                    const double q_up = upw ? t.q : AT(M.q, i);
+                                            : CP * nx.T + GRAV * nx.z + phis;
+                    const double q_up = upw ? t.q : nx.q;
                     Fs = t.et * (t.su - s_up);
                     Fq = t.et * (t.qu - q_up);
                     if (dn) {
@@ -588,10 +591,10 @@ __global__ __launch_bounds__(BLOCK) void k_deep_plume(Src src, Work w) {
                 load_tl(A, kt);
                 for (int k = kt; k <= kb; k += 2) {
                     load_tl(B, k + 1);
-                    proc(A, k);
+                    proc(A, B, k);
                     if (k + 1 > kb) break;
                     load_tl(A, k + 2);
-                    proc(B, k + 1);
+                    proc(B, A, k + 1);
                 }
             }
             // D8: F from the launch-layer tendencies and the trigger's parcel sensitivities.
@@ -627,21 +630,31 @@ __global__ __launch_bounds__(BLOCK) void k_deep_plume(Src src, Work w) {
                 const double phis = M.phis[col];
                 const double pblh = M.pblh[col];
                 tke = M.tke[col];
-                const bool conv = st == 0;
-                auto Tn = [&](int k) {
-                    return (conv && k >= kt && k <= kb) ? AT(M.T, k) + M.dt * (Mb * SCR(2, k))
-                                                        : AT(M.T, k);
-                };
-                auto qn = [&](int k) {
-                    return (conv && k >= kt && k <= kb) ? AT(M.q, k) + M.dt * (Mb * SCR(5, k))
-                                                        : AT(M.q, k);
-                };
+                // The deep outputs were zeroed outside the plume's levels, so the updated state is
+                // T + dt*dTdt at every level (unconditional loads keep the wait counts exact).
+                auto Tn = [&](int k) { return AT(M.T, k) + M.dt * AT(M.dout.dTdt, k); };
+                auto qn = [&](int k) { return AT(M.q, k) + M.dt * AT(M.dout.dqdt, k); };
                 if (isfinite(pblh) && isfinite(tke)) {
+                    constexpr int PBLC = 4;  // levels of the boundary-layer scan loaded at once
                     double pbot = AT(M.pi, L);
-                    for (int k = L - 1; k >= 0 && (k == L - 1 || sh.inpbl); --k) {
-                        const double pt = AT(M.pi, k), z = AT(M.z, k), q = qn(k);
-                        sh.pbl(k, L, z, pblh, (CP * Tn(k) + GRAV * z + phis) + LV * q, q, pbot - pt);
-                        pbot = pt;
+                    for (int k0 = L - 1; k0 >= 0 && (k0 == L - 1 || sh.inpbl); k0 -= PBLC) {
+                        double pt[PBLC], z[PBLC], T[PBLC], q[PBLC];
+#pragma unroll
+                        for (int j = 0; j < PBLC; ++j) {
+                            const int kk = max(k0 - j, 0);
+                            pt[j] = AT(M.pi, kk);
+                            z[j] = AT(M.z, kk);
+                            T[j] = Tn(kk);
+                            q[j] = qn(kk);
+                        }
+#pragma unroll
+                        for (int j = 0; j < PBLC; ++j) {
+                            const int k = k0 - j;
+                            if (k < 0 || !(k == L - 1 || sh.inpbl)) break;
+                            sh.pbl(k, L, z[j], pblh, (CP * T[j] + GRAV * z[j] + phis) + LV * q[j], q[j],
+                                   pbot - pt[j]);
+                            pbot = pt[j];
+                        }
                     }
                     sh.start();
                     int k = sh.ks - 1;
