@@ -48,7 +48,8 @@ def kernel_bytes(L, n, trig, sh_status):
     return dict(
         trigger=int(n * (b["inputs"] + b["deep_scalars"]) + quiet.sum() * b["deep_arrays"] +
                     (quiet & sh_done).sum() * b["shallow"]),
-        deep_plume=int((~quiet).sum() * b["deep_arrays"] + ((~quiet) & sh_done).sum() * b["shallow"]),
+        deep_plume=int((~quiet).sum() * b["deep_arrays"]),
+        shallow_retrigger=int(((~quiet) & sh_done).sum() * b["shallow"]),
         shallow_plume=int((~sh_done).sum() * b["shallow"]),
         reset=0,
     )
@@ -252,7 +253,7 @@ def main():
     dst = deep["status"].cpu().numpy()
     sst = shallow["status"].cpu().numpy()
     kb = kernel_bytes(NLEV, n, trig, sst)
-    dom = max(("trigger", "deep_plume", "shallow_plume"), key=lambda k: kavg[k])
+    dom = max(("trigger", "deep_plume", "shallow_retrigger", "shallow_plume"), key=lambda k: kavg[k])
     achieved = kb[dom] / (kavg[dom] * 1e-3) / 1e9
     step_bytes = bytes_per_column(NLEV)["total"] * n
     value = n / (ms_step * 1e-3)

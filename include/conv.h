@@ -220,8 +220,10 @@ int conv_get_launch(conv_ctx_t *ctx, int *fused_blocks_per_cu, int *shallow_bloc
 
 /* Instrumentation: record HIP events on the call's stream around each kernel of the next
  * `max_calls` calls (0 turns recording off).  conv_timing_read() waits for the recorded calls and
- * returns, per stage, the summed milliseconds over those calls in ms[0..3] (counter reset, trigger
- * pass, deep-plume pass, shallow-plume pass) and the number of recorded calls in *ncalls.
+ * returns, per stage, the summed milliseconds over those calls in ms[0..4] (counter reset, trigger
+ * pass, deep-plume pass, shallow re-trigger of the deep columns, shallow-plume pass; a stage a call
+ * does not run reads as the time between its neighbours' events) and the number of recorded calls
+ * in *ncalls.
  * Events are host-side handles created here; no device memory is allocated. */
 int conv_timing_start(conv_ctx_t *ctx, int max_calls);
 int conv_timing_read(conv_ctx_t *ctx, double *ms, int *ncalls);

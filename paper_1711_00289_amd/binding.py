@@ -395,7 +395,7 @@ class Conv:
         return a.value, b.value, ms.value
 
     # -- instrumentation -----------------------------------------------------------------
-    STAGES = ("reset", "trigger", "deep_plume", "shallow_plume")
+    STAGES = ("reset", "trigger", "deep_plume", "shallow_retrigger", "shallow_plume")
 
     def set_launch(self, fused_blocks_per_cu: int, shallow_blocks_per_cu: int):
         check(lib().conv_set_launch(self.h, int(fused_blocks_per_cu), int(shallow_blocks_per_cu)),

@@ -74,11 +74,13 @@ struct Work {
     int *slist, *smem, *sks, *sflag;
     double *shs, *sqs, *scin, *sMc, *ssig2;
     double *dscr, *sscr;
-    int64_t dstride, sstride;  // threads of the fused / shallow-plume persistent grids
+    int64_t dstride, sstride;  // threads of the deep-plume / shallow-plume persistent grids
     int lmax;                  // level capacity of the scratch
+    int cus;                   // compute units of the device
 };
 
-constexpr int SWEEP1_CHUNK = 6;
+constexpr int RETRIGGER_BPC = 3;  // blocks per compute unit of the shallow re-trigger pass
+
 
 // The inputs of one level of one column (pt = p_int at the level's top interface).
 struct Lev {
@@ -224,9 +226,18 @@ __global__ __launch_bounds__(BLOCK) void k_trigger(Src src, Work w) {
     double hkb = 0.0, qkb = 0.0;
     ShallowTrigger sh;
     sh.init(L);
+    bool sstarted = false;
+    int kt = -1;
+    double S = 0.0, SA = 0.0, SB = 0.0, Skt = 0.0, SAkt = 0.0, SBkt = 0.0;
+    Hint hd;
+    hd.clear();
 
-    // Sweep 1 (bottom-up, every level): validity, h, launch layer, top limit, PBL.  Levels are
-    // loaded SWEEP1_CHUNK at a time so a wavefront has that many levels of loads in flight.
+    // One bottom-up sweep reads every level once: validity (C0), zero outputs, h, the launch
+    // layer (D1), the undilute parcel with CAPE and the closure's parcel sensitivities (D2-D4),
+    // the boundary-layer source (S1) and the shallow parcel (S2-S5).  The deep parcel rises from
+    // the best launch layer found so far and restarts whenever a higher-h layer of the launch
+    // region appears below it (a level the parcel has passed is never needed again: the parcel
+    // of the final launch layer starts above it).
     if (live) {
         phis = M.phis[col];
         if (SHALLOW) {
@@ -241,94 +252,88 @@ __global__ __launch_bounds__(BLOCK) void k_trigger(Src src, Work w) {
             AT(M.dout.md, L) = 0.0;
         }
         if (SHALLOW) AT(M.sout.mu, L) = 0.0;
-        for (int k0 = L - 1; k0 >= 0; k0 -= SWEEP1_CHUNK) {
-            Lev v[SWEEP1_CHUNK];
-#pragma unroll
-            for (int j = 0; j < SWEEP1_CHUNK; ++j) load_lev(v[j], M, ld, col, max(k0 - j, 0));
-#pragma unroll
-            for (int j = 0; j < SWEEP1_CHUNK; ++j)
-                if (k0 - j >= 0) zero_level<DEEP, SHALLOW>(M, ld, col, k0 - j);
-#pragma unroll
-            for (int j = 0; j < SWEEP1_CHUNK; ++j) {
-                const int k = k0 - j;
-                if (k < 0) break;
-                const double T = v[j].T, q = v[j].q, pm = v[j].pm, z = v[j].z, pt = v[j].pt;
-                valid = valid && isfinite(T) && isfinite(q) && isfinite(pm) && isfinite(z) &&
-                        isfinite(pbot) && T > 100.0 && T < 400.0 && q >= 0.0 && q < 1.0 &&
-                        pt < pm && pm < pbot && (k == L - 1 ? z > 0.0 : z > zbelow);
-                const double h = (CP * T + GRAV * z + phis) + LV * q;
-                if (DEEP && pm >= P.p_launch_min && (kb < 0 || h > hkb)) {
-                    kb = k;
+        auto step = [&](const Lev &v, int k) {
+            zero_level<DEEP, SHALLOW>(M, ld, col, k);
+            valid = valid && isfinite(v.T) && isfinite(v.q) && isfinite(v.pm) && isfinite(v.z) &&
+                    isfinite(pbot) && v.T > 100.0 && v.T < 400.0 && v.q >= 0.0 && v.q < 1.0 &&
+                    v.pt < v.pm && v.pm < pbot && (k == L - 1 ? v.z > 0.0 : v.z > zbelow);
+            const double h = (CP * v.T + GRAV * v.z + phis) + LV * v.q;
+            bool dd = false;
+            if (DEEP) {
+                if (v.pm >= P.p_top_min) klim = k;
+                if (v.pm >= P.p_launch_min && (kb < 0 || h > hkb)) {
+                    kb = k;  // a new launch layer: the parcel restarts above it
                     hkb = h;
-                    qkb = q;
+                    qkb = v.q;
+                    kt = -1;
+                    S = SA = SB = Skt = SAkt = SBkt = 0.0;
+                    hd.clear();
+                } else {
+                    dd = kb >= 0 && v.pm >= P.p_top_min;
                 }
-                if (pm >= P.p_top_min) klim = k;
-                if (SHALLOW) sh.pbl(k, L, z, pblh, h, q, pbot - pt);
-                zbelow = z;
-                pbot = pt;
             }
+            bool ss = false;
+            if (SHALLOW) {
+                if (!sstarted) {
+                    sh.pbl(k, L, v.z, pblh, h, v.q, pbot - v.pt);
+                    if (!sh.inpbl) {
+                        sh.start();
+                        sstarted = true;
+                    }
+                }
+                ss = sstarted && sh.wants(k, v.pm, P);
+            }
+            if (dd || ss) {
+                const double lam = log(pbot / v.pt);
+                const double tve = tv(v.T, v.q);
+                if (dd) {
+                    const Lifted r = lift(hkb - GRAV * v.z - phis, qkb, v.pm, hd);
+                    const double B = tv(r.T, r.qv) - tve;
+                    S += RD * B * lam;
+                    double ca, cb;
+                    if (r.sat) {
+                        const double c = (1.0 + CVIR * r.qv) + CVIR * r.T * r.dqs;
+                        const double rden = frcp(CP + LV * r.dqs);
+                        ca = c * CP * rden;
+                        cb = c * LV * rden;
+                    } else {
+                        ca = 1.0 + CVIR * r.qv;
+                        cb = CVIR * r.T;
+                    }
+                    SA += lam * ca;
+                    SB += lam * cb;
+                    if (B > 0.0) {
+                        kt = k;
+                        Skt = S;
+                        SAkt = SA;
+                        SBkt = SB;
+                    }
+                }
+                if (ss) sh.level(k, v.z, phis, tve, v.pm, lam, P);
+            }
+            zbelow = v.z;
+            pbot = v.pt;
+        };
+        // Three level buffers: levels k-1 and k-2 load while level k is worked on.  Loads are
+        // unconditional (level index clamped at 0) so the wait counts stay exact.
+        Lev b0, b1, b2;
+        load_lev(b0, M, ld, col, L - 1);
+        load_lev(b1, M, ld, col, L - 2);
+        for (int k = L - 1; k >= 0; k -= 3) {
+            load_lev(b2, M, ld, col, max(k - 2, 0));
+            step(b0, k);
+            if (k - 1 < 0) break;
+            load_lev(b0, M, ld, col, max(k - 3, 0));
+            step(b1, k - 1);
+            if (k - 2 < 0) break;
+            load_lev(b1, M, ld, col, max(k - 4, 0));
+            step(b2, k - 2);
         }
         valid = valid && isfinite(pbot) && pbot > 0.0;
+        if (SHALLOW && !sstarted) sh.start();  // the boundary layer reaches the model top
     }
     const bool svalid = valid && (!SHALLOW || (isfinite(pblh) && isfinite(tke)));
-
-    // Sweep 2 (bottom-up): deep parcel from kb (D2-D4), shallow parcel from the source (S2-S5),
-    // each at the layers it needs.
     const bool dscan = DEEP && valid && kb >= 0 && klim >= 0 && klim < kb;
-    int kt = -1;
-    double S = 0.0, SA = 0.0, SB = 0.0, Skt = 0.0, SAkt = 0.0, SBkt = 0.0;
-    Hint hd;
-    hd.clear();
-    if (SHALLOW && svalid) sh.start();
-    if (dscan || (SHALLOW && sh.act)) {
-        const int k0 = L - 2;
-        double lpb = log(AT(M.pi, k0 + 1));  // ln p_int below the current layer
-        // One level of the combined scan; false once neither scan needs a higher level.
-        auto step = [&](const Lev &v, int k) -> bool {
-            const double lpt = log(v.pt);
-            const double lam = lpb - lpt;
-            lpb = lpt;
-            const bool dd = dscan && k < kb && k >= klim;
-            const bool ss = SHALLOW && sh.wants(k, v.pm, P);
-            if (!dd && !ss) return !((!dscan || k < klim) && !(SHALLOW && sh.act));
-            const double tve = tv(v.T, v.q);
-            if (dd) {
-                const Lifted r = lift(hkb - GRAV * v.z - phis, qkb, v.pm, hd);
-                const double B = tv(r.T, r.qv) - tve;
-                S += RD * B * lam;
-                double ca, cb;
-                if (r.sat) {
-                    const double c = (1.0 + CVIR * r.qv) + CVIR * r.T * r.dqs;
-                    const double rden = frcp(CP + LV * r.dqs);
-                    ca = c * CP * rden;
-                    cb = c * LV * rden;
-                } else {
-                    ca = 1.0 + CVIR * r.qv;
-                    cb = CVIR * r.T;
-                }
-                SA += lam * ca;
-                SB += lam * cb;
-                if (B > 0.0) {
-                    kt = k;
-                    Skt = S;
-                    SAkt = SA;
-                    SBkt = SB;
-                }
-            }
-            if (ss) sh.level(k, v.z, phis, tve, v.pm, lam, P);
-            return true;
-        };
-        // Two level buffers: level k-1 loads while level k is worked on.
-        // Loads are unconditional (level index clamped at 0) so the wait counts stay exact.
-        Lev A, B;
-        load_lev(A, M, ld, col, k0);
-        for (int k = k0; k >= 0; k -= 2) {
-            load_lev(B, M, ld, col, max(k - 1, 0));
-            if (!step(A, k) || k == 0) break;
-            load_lev(A, M, ld, col, max(k - 2, 0));
-            if (!step(B, k - 1)) break;
-        }
-    }
 
     // Deep epilogue (D4): quiet columns get their zeros; triggered ones are compacted into the
     // deep list with what the plume pass needs.
@@ -382,9 +387,8 @@ __global__ __launch_bounds__(BLOCK) void k_trigger(Src src, Work w) {
     }
 }
 
-// Deep plume pass, persistent over the deep list (wavefront-uniform loop: every lane of a
-// wavefront iterates together so the shallow list's ballot is convergent).
-template <class Src, bool SHALLOW>
+// Deep plume pass, persistent over the deep list.
+template <class Src>
 __global__ __launch_bounds__(BLOCK) void k_deep_plume(Src src, Work w) {
     const int n = w.cnt[CNT_DEEP];
     const int64_t gtid = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
@@ -619,74 +623,93 @@ __global__ __launch_bounds__(BLOCK) void k_deep_plume(Src src, Work w) {
             M.dout.prec[col] = st == 0 ? Mb * P1 : 0.0;
             M.dout.status[col] = st;
         }
-
-        if (SHALLOW) {
-            // Shallow trigger on the deep-updated state T' = T + dt*dTdt, q' = q + dt*dqdt.
-            ShallowTrigger sh;
-            sh.init(L);
-            int sst = -1;
-            double rho_s = 0.0, tke = 0.0;
-            if (act) {
-                const double phis = M.phis[col];
-                const double pblh = M.pblh[col];
-                tke = M.tke[col];
-                // The deep outputs were zeroed outside the plume's levels, so the updated state is
-                // T + dt*dTdt at every level (unconditional loads keep the wait counts exact).
-                auto Tn = [&](int k) { return AT(M.T, k) + M.dt * AT(M.dout.dTdt, k); };
-                auto qn = [&](int k) { return AT(M.q, k) + M.dt * AT(M.dout.dqdt, k); };
-                if (isfinite(pblh) && isfinite(tke)) {
-                    constexpr int PBLC = 4;  // levels of the boundary-layer scan loaded at once
-                    double pbot = AT(M.pi, L);
-                    for (int k0 = L - 1; k0 >= 0 && (k0 == L - 1 || sh.inpbl); k0 -= PBLC) {
-                        double pt[PBLC], z[PBLC], T[PBLC], q[PBLC];
-#pragma unroll
-                        for (int j = 0; j < PBLC; ++j) {
-                            const int kk = max(k0 - j, 0);
-                            pt[j] = AT(M.pi, kk);
-                            z[j] = AT(M.z, kk);
-                            T[j] = Tn(kk);
-                            q[j] = qn(kk);
-                        }
-#pragma unroll
-                        for (int j = 0; j < PBLC; ++j) {
-                            const int k = k0 - j;
-                            if (k < 0 || !(k == L - 1 || sh.inpbl)) break;
-                            sh.pbl(k, L, z[j], pblh, (CP * T[j] + GRAV * z[j] + phis) + LV * q[j], q[j],
-                                   pbot - pt[j]);
-                            pbot = pt[j];
-                        }
-                    }
-                    sh.start();
-                    int k = sh.ks - 1;
-                    const int k0 = max(k, 0);
-                    double pmn = AT(M.pm, k0), zn = AT(M.z, k0), Tnn = Tn(k0), qnn = qn(k0),
-                           ptn = AT(M.pi, k0), pbn = AT(M.pi, k0 + 1);
-                    for (; k >= 0; --k) {
-                        const double pm = pmn, z = zn, Tk = Tnn, qk = qnn, pt = ptn, pb = pbn;
-                        if (!sh.wants(k, pm, P)) break;
-                        const int kn = max(k - 1, 0);
-                        pmn = AT(M.pm, kn);
-                        zn = AT(M.z, kn);
-                        Tnn = Tn(kn);
-                        qnn = qn(kn);
-                        ptn = AT(M.pi, kn);
-                        pbn = pt;
-                        sh.level(k, z, phis, tv(Tk, qk), pm, log(pb / pt), P);
-                    }
-                    sst = sh.status(tke, P);
-                } else {
-                    sst = 6;
-                }
-                if (sst < 0)
-                    rho_s = AT(M.pi, sh.ks) / (RD * tv(Tn(sh.ks), qn(sh.ks)));
-                else
-                    write_shallow_quiet(M, col, sst, sh.cin, sh.ks);
-            }
-            const int sslot = wave_append(act && sst < 0, &w.cnt[CNT_SHALLOW]);
-            if (sslot >= 0) shallow_enqueue(M, w, sslot, mi, col, sh, rho_s, tke, 1);
-        }
     }
 #undef SCR
+}
+
+// Shallow trigger (S1-S6) on the deep-updated state T' = T + dt*dTdt, q' = q + dt*dqdt of every
+// column of the deep list; persistent, wavefront-uniform loop so the shallow list's ballot is
+// convergent.  Its own kernel (not the tail of the deep plume pass) so that it runs at the
+// occupancy its few registers allow.
+template <class Src>
+__global__ __launch_bounds__(BLOCK) void k_shallow_retrigger(Src src, Work w) {
+    const int n = w.cnt[CNT_DEEP];
+    const int64_t gtid = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    const int64_t nthreads = (int64_t)gridDim.x * BLOCK;
+    const int64_t wave0 = gtid - (threadIdx.x % WAVE);
+    for (int64_t base = wave0; base < n; base += nthreads) {
+        const int64_t slot = base + (threadIdx.x % WAVE);
+        const bool act = slot < n;
+        const int mi = act ? w.dmem[slot] : 0;
+        const Member &M = src.at(mi);
+        const int L = M.nlev;
+        const int64_t ld = M.ld;
+        const conv_params_t &P = M.P;
+        const int64_t col = act ? w.dlist[slot] : 0;
+        // Shallow trigger on the deep-updated state T' = T + dt*dTdt, q' = q + dt*dqdt.
+        ShallowTrigger sh;
+        sh.init(L);
+        int sst = -1;
+        double rho_s = 0.0, tke = 0.0;
+        if (act) {
+            const double phis = M.phis[col];
+            const double pblh = M.pblh[col];
+            tke = M.tke[col];
+            // The deep outputs were zeroed outside the plume's levels, so the updated state is
+            // T + dt*dTdt at every level (unconditional loads keep the wait counts exact).
+            auto Tn = [&](int k) { return AT(M.T, k) + M.dt * AT(M.dout.dTdt, k); };
+            auto qn = [&](int k) { return AT(M.q, k) + M.dt * AT(M.dout.dqdt, k); };
+            if (isfinite(pblh) && isfinite(tke)) {
+                constexpr int PBLC = 4;  // levels of the boundary-layer scan loaded at once
+                double pbot = AT(M.pi, L);
+                for (int k0 = L - 1; k0 >= 0 && (k0 == L - 1 || sh.inpbl); k0 -= PBLC) {
+                    double pt[PBLC], z[PBLC], T[PBLC], q[PBLC];
+#pragma unroll
+                    for (int j = 0; j < PBLC; ++j) {
+                        const int kk = max(k0 - j, 0);
+                        pt[j] = AT(M.pi, kk);
+                        z[j] = AT(M.z, kk);
+                        T[j] = Tn(kk);
+                        q[j] = qn(kk);
+                    }
+#pragma unroll
+                    for (int j = 0; j < PBLC; ++j) {
+                        const int k = k0 - j;
+                        if (k < 0 || !(k == L - 1 || sh.inpbl)) break;
+                        sh.pbl(k, L, z[j], pblh, (CP * T[j] + GRAV * z[j] + phis) + LV * q[j], q[j],
+                               pbot - pt[j]);
+                        pbot = pt[j];
+                    }
+                }
+                sh.start();
+                int k = sh.ks - 1;
+                const int k0 = max(k, 0);
+                double pmn = AT(M.pm, k0), zn = AT(M.z, k0), Tnn = Tn(k0), qnn = qn(k0),
+                       ptn = AT(M.pi, k0), pbn = AT(M.pi, k0 + 1);
+                for (; k >= 0; --k) {
+                    const double pm = pmn, z = zn, Tk = Tnn, qk = qnn, pt = ptn, pb = pbn;
+                    if (!sh.wants(k, pm, P)) break;
+                    const int kn = max(k - 1, 0);
+                    pmn = AT(M.pm, kn);
+                    zn = AT(M.z, kn);
+                    Tnn = Tn(kn);
+                    qnn = qn(kn);
+                    ptn = AT(M.pi, kn);
+                    pbn = pt;
+                    sh.level(k, z, phis, tv(Tk, qk), pm, log(pb / pt), P);
+                }
+                sst = sh.status(tke, P);
+            } else {
+                sst = 6;
+            }
+            if (sst < 0)
+                rho_s = AT(M.pi, sh.ks) / (RD * tv(Tn(sh.ks), qn(sh.ks)));
+            else
+                write_shallow_quiet(M, col, sst, sh.cin, sh.ks);
+        }
+        const int sslot = wave_append(act && sst < 0, &w.cnt[CNT_SHALLOW]);
+        if (sslot >= 0) shallow_enqueue(M, w, sslot, mi, col, sh, rho_s, tke, 1);
+    }
 }
 
 template <class Src>
@@ -886,6 +909,7 @@ Work make_work(char *b, const Layout &l, const Launch &launch, int cus) {
     w.dstride = fd < l.threads ? fd : l.threads;
     w.sstride = sh < l.threads ? sh : l.threads;
     w.lmax = l.lmax;
+    w.cus = cus;
     return w;
 }
 
@@ -919,10 +943,16 @@ int launch_step(const Src &src, const Work &w, hipStream_t st, hipEvent_t *ev) {
     if (ev) (void)hipEventRecord(ev[1], st);
     hipLaunchKernelGGL((k_trigger<Src, DEEP, SHALLOW>), dim3(gt), dim3(BLOCK), 0, st, src, w);
     if (ev) (void)hipEventRecord(ev[2], st);
-    if (DEEP) hipLaunchKernelGGL((k_deep_plume<Src, SHALLOW>), dim3(gd), dim3(BLOCK), 0, st, src, w);
+    if (DEEP) hipLaunchKernelGGL((k_deep_plume<Src>), dim3(gd), dim3(BLOCK), 0, st, src, w);
     if (ev) (void)hipEventRecord(ev[3], st);
-    if (SHALLOW) hipLaunchKernelGGL((k_shallow_plume<Src>), dim3(gs), dim3(BLOCK), 0, st, src, w);
+    if (DEEP && SHALLOW) {
+        const int64_t cap = (int64_t)w.cus * RETRIGGER_BPC;
+        const unsigned gr = (unsigned)(src.ntiles < cap ? src.ntiles : cap);
+        hipLaunchKernelGGL((k_shallow_retrigger<Src>), dim3(gr), dim3(BLOCK), 0, st, src, w);
+    }
     if (ev) (void)hipEventRecord(ev[4], st);
+    if (SHALLOW) hipLaunchKernelGGL((k_shallow_plume<Src>), dim3(gs), dim3(BLOCK), 0, st, src, w);
+    if (ev) (void)hipEventRecord(ev[5], st);
     return finish();
 }
 

@@ -113,7 +113,7 @@ inline Member make_member(int64_t ncol, int nlev, const conv_params_t &P, const 
 
 }  // namespace cvk
 
-constexpr int CONV_NSTAGES = 4;  // reset, trigger, deep plume, shallow plume
+constexpr int CONV_NSTAGES = 5;  // reset, trigger, deep plume, shallow re-trigger, shallow plume
 
 struct conv_ctx {
     int64_t ncol;
