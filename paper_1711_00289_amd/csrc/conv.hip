@@ -314,20 +314,17 @@ __global__ __launch_bounds__(BLOCK) void k_trigger(Src src, Work w) {
             zbelow = v.z;
             pbot = v.pt;
         };
-        // Three level buffers: levels k-1 and k-2 load while level k is worked on.  Loads are
-        // unconditional (level index clamped at 0) so the wait counts stay exact.
-        Lev b0, b1, b2;
+        // Two level buffers: level k-1 loads while level k is worked on (a third buffer costs the
+        // registers of a third resident wavefront per SIMD).  Loads are unconditional (level
+        // index clamped at 0) so the wait counts stay exact.
+        Lev b0, b1;
         load_lev(b0, M, ld, col, L - 1);
-        load_lev(b1, M, ld, col, L - 2);
-        for (int k = L - 1; k >= 0; k -= 3) {
-            load_lev(b2, M, ld, col, max(k - 2, 0));
+        for (int k = L - 1; k >= 0; k -= 2) {
+            load_lev(b1, M, ld, col, max(k - 1, 0));
             step(b0, k);
             if (k - 1 < 0) break;
-            load_lev(b0, M, ld, col, max(k - 3, 0));
+            load_lev(b0, M, ld, col, max(k - 2, 0));
             step(b1, k - 1);
-            if (k - 2 < 0) break;
-            load_lev(b1, M, ld, col, max(k - 4, 0));
-            step(b2, k - 2);
         }
         valid = valid && isfinite(pbot) && pbot > 0.0;
         if (SHALLOW && !sstarted) sh.start();  // the boundary layer reaches the model top
