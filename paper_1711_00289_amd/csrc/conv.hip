@@ -62,14 +62,14 @@ int check_launch() {
 
 namespace {
 
-constexpr int DEEP_SCR = 9;     // su, qu, c->dT1, sd, qd, e1->dq1, eta_d, eta, h
+constexpr int DEEP_SCR = 10;    // deep plume profiles (enum DeepScr)
 constexpr int SHALLOW_SCR = 3;  // eta, dT1, dq1
 constexpr int CNT_DEEP = 0;
 constexpr int CNT_SHALLOW = 1;
 
 struct Work {
     int *cnt;
-    int *dlist, *dmem, *dkb, *dkt;
+    int *dlist, *dmem, *dkb, *dkt, *dkd;
     double *dcape, *dSA, *dSB;
     int *slist, *smem, *sks, *sflag;
     double *shs, *sqs, *scin, *sMc, *ssig2;
@@ -222,7 +222,7 @@ __global__ __launch_bounds__(BLOCK) void k_trigger(Src src, Work w) {
 
     bool valid = live;
     double phis = 0.0, pblh = 0.0, tke = 0.0;
-    int kb = -1, klim = -1;
+    int kb = -1;
     double hkb = 0.0, qkb = 0.0;
     ShallowTrigger sh;
     sh.init(L);
@@ -231,6 +231,10 @@ __global__ __launch_bounds__(BLOCK) void k_trigger(Src src, Work w) {
     double S = 0.0, SA = 0.0, SB = 0.0, Skt = 0.0, SAkt = 0.0, SBkt = 0.0;
     Hint hd;
     hd.clear();
+    // Downdraft start (D6): argmin h over the parcel's layers passed so far (kt+1 .. kb-1 once kt
+    // is fixed); scanning upward, a tie goes to the upper layer.
+    double hmin = 0.0;
+    int kmin = -1, kdkt = -1;
 
     // One bottom-up sweep reads every level once: validity (C0), zero outputs, h, the launch
     // layer (D1), the undilute parcel with CAPE and the closure's parcel sensitivities (D2-D4),
@@ -260,7 +264,6 @@ __global__ __launch_bounds__(BLOCK) void k_trigger(Src src, Work w) {
             const double h = (CP * v.T + GRAV * v.z + phis) + LV * v.q;
             bool dd = false;
             if (DEEP) {
-                if (v.pm >= P.p_top_min) klim = k;
                 if (v.pm >= P.p_launch_min && (kb < 0 || h > hkb)) {
                     kb = k;  // a new launch layer: the parcel restarts above it
                     hkb = h;
@@ -268,6 +271,7 @@ __global__ __launch_bounds__(BLOCK) void k_trigger(Src src, Work w) {
                     kt = -1;
                     S = SA = SB = Skt = SAkt = SBkt = 0.0;
                     hd.clear();
+                    kmin = kdkt = -1;
                 } else {
                     dd = kb >= 0 && v.pm >= P.p_top_min;
                 }
@@ -307,6 +311,11 @@ __global__ __launch_bounds__(BLOCK) void k_trigger(Src src, Work w) {
                         Skt = S;
                         SAkt = SA;
                         SBkt = SB;
+                        kdkt = kmin;
+                    }
+                    if (kmin < 0 || h <= hmin) {
+                        kmin = k;
+                        hmin = h;
                     }
                 }
                 if (ss) sh.level(k, v.z, phis, tve, v.pm, lam, P);
@@ -330,7 +339,8 @@ __global__ __launch_bounds__(BLOCK) void k_trigger(Src src, Work w) {
         if (SHALLOW && !sstarted) sh.start();  // the boundary layer reaches the model top
     }
     const bool svalid = valid && (!SHALLOW || (isfinite(pblh) && isfinite(tke)));
-    const bool dscan = DEEP && valid && kb >= 0 && klim >= 0 && klim < kb;
+    // (A column with no parcel layer at or below p_top_min above kb keeps kt = -1: not triggered.)
+    const bool dscan = DEEP && valid && kb >= 0;
 
     // Deep epilogue (D4): quiet columns get their zeros; triggered ones are compacted into the
     // deep list with what the plume pass needs.
@@ -361,6 +371,7 @@ __global__ __launch_bounds__(BLOCK) void k_trigger(Src src, Work w) {
             w.dmem[slot] = mi;
             w.dkb[slot] = kb;
             w.dkt[slot] = kt;
+            w.dkd[slot] = kdkt;
             w.dcape[slot] = cape;
             w.dSA[slot] = SAkt;
             w.dSB[slot] = SBkt;
@@ -384,7 +395,22 @@ __global__ __launch_bounds__(BLOCK) void k_trigger(Src src, Work w) {
     }
 }
 
-// Deep plume pass, persistent over the deep list.
+// Per-thread plume scratch of the deep pass ([profile][level][thread]).  Only the last three are
+// kept for every level of the plume; the others only for the downdraft region kd .. kb.
+enum DeepScr : int {
+    U_SU = 0, U_QU, U_C,   // updraft s, q_v and condensation at interfaces kd+1 .. kb
+    D_ED, D_SD, D_QD,      // downdraft eta_d (< 0), s, q at interfaces kd+1 .. kb
+    D_E1,                  // downdraft evaporation in layers kd .. kb-1
+    U_ETA,                 // updraft mass flux at interfaces kt+1 .. kb
+    X_DT1, X_DQ1,          // unit tendencies in layers kt .. kb
+};
+
+// Deep plume pass, persistent over the deep list.  Per column: the saturated downdraft (D6) from
+// the trigger's k_d down to the base; the entraining updraft (D5) from the base to the top, which
+// also completes the fluxes and tendencies (D7) of the layers above the downdraft, where the
+// downdraft strength alpha does not enter; then alpha and the layers k_d .. kb; then the closure
+// (D8), limiter (D9) and outputs (D10).  The updraft finishes an interface one level after
+// computing it, when the upwind layer's values (the next level up) have arrived.
 template <class Src>
 __global__ __launch_bounds__(BLOCK) void k_deep_plume(Src src, Work w) {
     const int n = w.cnt[CNT_DEEP];
@@ -393,233 +419,228 @@ __global__ __launch_bounds__(BLOCK) void k_deep_plume(Src src, Work w) {
     double *scr = w.dscr;
 #define SCR(arr, lev) scr[((int64_t)(arr) * (w.lmax + 1) + (lev)) * w.dstride + gtid]
 
-    const int64_t wave0 = gtid - (threadIdx.x % WAVE);
-    for (int64_t base = wave0; base < n; base += nthreads) {
-        const int64_t slot = base + (threadIdx.x % WAVE);
-        const bool act = slot < n;
-        const int mi = act ? w.dmem[slot] : 0;
-        const Member &M = src.at(mi);
-        const int L = M.nlev;
+    for (int64_t slot = gtid; slot < n; slot += nthreads) {
+        const Member &M = src.at(w.dmem[slot]);
         const int64_t ld = M.ld;
         const conv_params_t &P = M.P;
-        int64_t col = 0;
-        int st = 0, kb = 0, kt = 0;
-        double Mb = 0.0;
-        if (act) {
-            col = w.dlist[slot];
-            kb = w.dkb[slot];
-            kt = w.dkt[slot];
-            const double cape = w.dcape[slot];
-            const double SA = w.dSA[slot], SB = w.dSB[slot];
-            const double phis = M.phis[col];
-            const double epsd = P.eps_deep;
+        const int64_t col = w.dlist[slot];
+        const int kb = w.dkb[slot], kt = w.dkt[slot], kd = w.dkd[slot];
+        const double cape = w.dcape[slot];
+        const double SA = w.dSA[slot], SB = w.dSB[slot];
+        const double phis = M.phis[col];
+        const double epsd = P.eps_deep;
+        const double dt = M.dt;
 
-            // D5: updraft, interfaces kb .. kt+1.  At interface k the plume needs layer k's T, q, z
-            // (entrained air), z[k-1] (interface height) and p_int[k]; the next interface's values
-            // are loaded one step ahead.
+        // Accumulations of D7-D9.
+        double P1 = 0.0, Fenv = 0.0, Mlim = __builtin_inf(), dT1kb = 0.0, dq1kb = 0.0;
+        // One layer's unit tendencies from the fluxes at its top and bottom interfaces.
+        auto layer = [&](int k, double Fs_top, double Fq_top, double Fs_bot, double Fq_bot,
+                         double net, double T, double q, double p_top, double p_bot) {
+            const double dp = p_bot - p_top;
+            const double dT1 = (Fs_bot - Fs_top + LV * net) * GRAV / (CP * dp);
+            const double dq1 = (Fq_bot - Fq_top - net) * GRAV / dp;
+            SCR(X_DT1, k) = dT1;
+            SCR(X_DQ1, k) = dq1;
+            P1 += net;
+            if (k <= kb - 1) {
+                Fenv += log(p_bot / p_top) * ((1.0 + CVIR * q) * dT1 + CVIR * T * dq1);
+            } else {
+                dT1kb = dT1;
+                dq1kb = dq1;
+            }
+            if (dq1 < 0.0) Mlim = fmin(Mlim, q / (-dt * dq1));
+        };
+
+        // D6: saturated downdraft from interface kd+1 down to the base.
+        double E1 = 0.0;
+        if (kd >= 0) {
+            Hint hdn;
+            hdn.clear();
+            Sat s;
+            const double qkd = AT(M.q, kd);
+            const double zkd = AT(M.z, kd);
+            double hd = (CP * AT(M.T, kd) + GRAV * zkd + phis) + LV * qkd;
+            double zb = AT(M.z, kd + 1);
+            double zii = 0.5 * (zkd + zb);
+            double H = hd - GRAV * zii - phis;
+            double Td = tsat_h(H, AT(M.pi, kd + 1), (H - LV * qkd) * RCP_CP, s, hdn);
+            double ad = 1.0, qd = s.qs;
+            SCR(D_ED, kd + 1) = -1.0;
+            SCR(D_SD, kd + 1) = CP * Td + GRAV * zii + phis;
+            SCR(D_QD, kd + 1) = qd;
+            E1 = qd - qkd;
+            SCR(D_E1, kd) = E1;
+            // Loads are unconditional (indices clamped) so the wait counts stay exact.
+            int k = kd + 1;
+            double Tn = AT(M.T, k), qn = AT(M.q, k), zn = AT(M.z, min(k + 1, kb)), pn = AT(M.pi, k + 1);
+            for (; k <= kb - 1; ++k) {
+                const double Tk = Tn, qk = qn, zk = zb, zbelow = zn, pbel = pn;
+                Tn = AT(M.T, min(k + 1, kb));
+                qn = AT(M.q, min(k + 1, kb));
+                zn = AT(M.z, min(k + 2, kb));
+                pn = AT(M.pi, min(k + 2, kb + 1));
+                zb = zbelow;
+                const double hk = (CP * Tk + GRAV * zk + phis) + LV * qk;
+                const double zlow = 0.5 * (zk + zbelow);
+                const double Ed = epsd * ad * (zii - zlow);
+                const double adn = ad + Ed;
+                hd = (ad * hd + Ed * hk) / adn;
+                H = hd - GRAV * zlow - phis;
+                Td = tsat_h(H, pbel, (H - LV * qk) * RCP_CP, s, hdn);
+                const double e1 = adn * s.qs - ad * qd - Ed * qk;
+                SCR(D_E1, k) = e1;
+                SCR(D_ED, k + 1) = -adn;
+                SCR(D_SD, k + 1) = CP * Td + GRAV * zlow + phis;
+                SCR(D_QD, k + 1) = s.qs;
+                E1 += e1;
+                ad = adn;
+                qd = s.qs;
+                zii = zlow;
+            }
+        }
+
+        // D5 + the alpha-free part of D7: updraft from the base (interface kb) to interface kt+1.
+        // `u_*` hold the updraft at interface i+1, `e_*` the environment of layer i+1, `p_top` and
+        // `p_bot` its interface pressures, `Fs_b`/`Fq_b` the flux at interface i+2.
+        double C1;
+        double Fs_kd = 0.0, Fq_kd = 0.0, c_kd = 0.0;  // interface kd, for the downdraft region
+        {
             Hint hu;
             hu.clear();
-            const double qkb = AT(M.q, kb);
-            double zk1 = AT(M.z, kb);  // z of the layer below the current interface
+            const double qkb = AT(M.q, kb), Tkb = AT(M.T, kb), zkb = AT(M.z, kb);
             double zup = AT(M.z, kb - 1);
-            double hu_m = (CP * AT(M.T, kb) + GRAV * zk1 + phis) + LV * qkb;
-            double zlo = 0.5 * (zup + zk1);
-            double C1, qup;
+            double hu_m = (CP * Tkb + GRAV * zkb + phis) + LV * qkb;
+            double zlo = 0.5 * (zup + zkb);
+            double u_eta = 1.0, u_su, u_qu, u_c;
             {
                 const Lifted r = lift(hu_m - GRAV * zlo - phis, qkb, AT(M.pi, kb), hu);
-                qup = r.qv;
-                SCR(0, kb) = CP * r.T + GRAV * zlo + phis;
-                SCR(1, kb) = r.qv;
-                C1 = qkb - r.qv;
-                SCR(2, kb) = C1;
-                SCR(7, kb) = 1.0;
-                SCR(8, kb) = hu_m;  // h of the launch layer
+                u_su = CP * r.T + GRAV * zlo + phis;
+                u_qu = r.qv;
+                u_c = qkb - r.qv;
             }
-            double eta = 1.0;
-            {
-                // Loads are unconditional (level index clamped at 0) so the wait counts stay exact.
-                int k = kb - 1;
-                double Tn = AT(M.T, k), qn = AT(M.q, k), zn = zup, zn2 = AT(M.z, max(k - 1, 0)),
-                       pn = AT(M.pi, k);
-                for (; k >= kt + 1; --k) {
-                    const double Tk = Tn, qk = qn, zkk = zn, zabove = zn2, pik = pn;
-                    Tn = AT(M.T, k - 1);
-                    qn = AT(M.q, k - 1);
-                    zn = zabove;
-                    zn2 = AT(M.z, max(k - 2, 0));
-                    pn = AT(M.pi, k - 1);
-                    const double zk = 0.5 * (zabove + zkk);
-                    const double hkk = (CP * Tk + GRAV * zkk + phis) + LV * qk;
-                    const double E = epsd * eta * (zk - zlo);
-                    const double etan = eta + E;
-                    const double hm = (eta * hu_m + E * hkk) / etan;
-                    const double qm = (eta * qup + E * qk) / etan;
-                    const Lifted r = lift(hm - GRAV * zk - phis, qm, pik, hu);
-                    const double c = etan * (qm - r.qv);
-                    SCR(0, k) = CP * r.T + GRAV * zk + phis;
-                    SCR(1, k) = r.qv;
-                    SCR(2, k) = c;
-                    SCR(7, k) = etan;
-                    SCR(8, k) = hkk;
-                    C1 += c;
-                    eta = etan;
-                    hu_m = hm;
-                    qup = r.qv;
-                    zlo = zk;
-                }
+            C1 = u_c;
+            SCR(U_ETA, kb) = 1.0;
+            if (kd >= 0) {
+                SCR(U_SU, kb) = u_su;
+                SCR(U_QU, kb) = u_qu;
+                SCR(U_C, kb) = u_c;
             }
-
-            // D6: saturated downdraft from the minimum-h layer between top and base (h of the
-            // layers kt+1 .. kb-1 was kept by the updraft pass).
-            int kd = -1;
-            double alpha = 0.0;
-            if (kb - kt >= 2) {
-                kd = kt + 1;
-                double hkd = SCR(8, kd);
-                for (int k = kt + 2; k <= kb - 1; ++k) {
-                    const double h = SCR(8, k);
-                    if (h < hkd) {
-                        kd = k;
-                        hkd = h;
-                    }
+            double e_T = Tkb, e_q = qkb, p_top = AT(M.pi, kb), p_bot = AT(M.pi, kb + 1);
+            double Fs_b = 0.0, Fq_b = 0.0;
+            // Interface i+1 and layer i+1, with the environment of layer i (the upwind layer:
+            // the compensating flow points up where there is no downdraft).
+            auto finish = [&](int i, double Ti, double qi, double zi_) {
+                const int j = i + 1;
+                if (kd >= 0 && j >= kd + 1) return;  // downdraft region: after alpha
+                const double s_up = CP * Ti + GRAV * zi_ + phis;
+                const double Fs = u_eta * (u_su - s_up);
+                const double Fq = u_eta * (u_qu - qi);
+                if (kd < 0 || j <= kd - 1) {
+                    layer(j, Fs, Fq, Fs_b, Fq_b, u_c, e_T, e_q, p_top, p_bot);
+                } else {  // j == kd
+                    Fs_kd = Fs;
+                    Fq_kd = Fq;
+                    c_kd = u_c;
                 }
-                Hint hdn;
-                hdn.clear();
-                double ad = 1.0, hd = hkd;
-                double zii = 0.5 * (AT(M.z, kd) + AT(M.z, kd + 1));
-                Sat s;
-                double H = hd - GRAV * zii - phis;
-                double Td = tsat_h(H, AT(M.pi, kd + 1), (H - LV * AT(M.q, kd)) * RCP_CP, s, hdn);
-                double qd = s.qs;
-                SCR(3, kd + 1) = CP * Td + GRAV * zii + phis;
-                SCR(4, kd + 1) = qd;
-                SCR(6, kd + 1) = -ad;
-                double E1 = qd - AT(M.q, kd);
-                SCR(5, kd) = E1;
-                int k = kd + 1;
-                double qn = AT(M.q, k), hn = SCR(8, k), zc = AT(M.z, k),
-                       zn = AT(M.z, min(k + 1, L - 1)), pn = AT(M.pi, k + 1);
-                for (; k <= kb - 1; ++k) {
-                    const double qk = qn, hkk = hn, zkk = zc, zbelow = zn, pbel = pn;
-                    qn = AT(M.q, k + 1);
-                    hn = SCR(8, k + 1);
-                    zc = zbelow;
-                    zn = AT(M.z, min(k + 2, L - 1));
-                    pn = AT(M.pi, min(k + 2, L));
-                    const double zlow = 0.5 * (zkk + zbelow);
-                    const double Ed = epsd * ad * (zii - zlow);
-                    const double adn = ad + Ed;
-                    hd = (ad * hd + Ed * hkk) / adn;
-                    H = hd - GRAV * zlow - phis;
-                    Td = tsat_h(H, pbel, (H - LV * qk) * RCP_CP, s, hdn);
-                    const double e1 = adn * s.qs - ad * qd - Ed * qk;
-                    SCR(5, k) = e1;
-                    SCR(3, k + 1) = CP * Td + GRAV * zlow + phis;
-                    SCR(4, k + 1) = s.qs;
-                    SCR(6, k + 1) = -adn;
-                    E1 += e1;
-                    ad = adn;
-                    qd = s.qs;
-                    zii = zlow;
-                }
-                alpha = P.alpha_dd;
-                if (P.alpha_dd * E1 > P.evap_max_frac * C1) alpha = P.evap_max_frac * C1 / E1;
-            }
-
-            // D7 with the D8/D9 accumulations: top-down over layers kt .. kb, two level buffers.
-            double Fs_top = 0.0, Fq_top = 0.0, P1 = 0.0, Fenv = 0.0;
-            double Mlim = __builtin_inf();
-            double dT1 = 0.0, dq1 = 0.0;
-            double pi_top = AT(M.pi, kt);
-            struct TL {
-                double T, q, z, pib, et, ed, su, qu, sd, qd, c, e1;
+                Fs_b = Fs;
+                Fq_b = Fq;
             };
-            auto load_tl = [&](TL &t, int k) {
-                const int kk = min(k, kb);
-                const int i = kk + 1;
-                t.T = AT(M.T, kk);
-                t.q = AT(M.q, kk);
-                t.z = AT(M.z, kk);
-                t.pib = AT(M.pi, i);
-                t.et = SCR(7, i);
-                t.ed = SCR(6, i);
-                t.su = SCR(0, i);
-                t.qu = SCR(1, i);
-                t.sd = SCR(3, i);
-                t.qd = SCR(4, i);
-                t.c = SCR(2, kk);
-                t.e1 = SCR(5, kk);
-            };
-            // `t` holds layer k and interface k+1; `nx` (already loaded) holds layer k+1, the
-            // upwind layer where the compensating flow at interface k+1 points up.
-            auto proc = [&](const TL &t, const TL &nx, int k) {
-                double Fs = 0.0, Fq = 0.0;
-                const int i = k + 1;
-                if (i <= kb) {
-                    const bool dn = kd >= 0 && i >= kd + 1;
-                    const double ed = dn ? t.ed : 0.0;
-                    const bool upw = t.et + alpha * ed >= 0.0;
-                    const double s_up = upw ? CP * t.T + GRAV * t.z + phis
-                                            : CP * nx.T + GRAV * nx.z + phis;
-                    const double q_up = upw ? t.q : nx.q;
-                    Fs = t.et * (t.su - s_up);
-                    Fq = t.et * (t.qu - q_up);
-                    if (dn) {
-                        Fs += alpha * ed * (t.sd - s_up);
-                        Fq += alpha * ed * (t.qd - q_up);
-                    }
+            int k = kb - 1;
+            double Tn = AT(M.T, k), qn = AT(M.q, k), zn = zup, zn2 = AT(M.z, max(k - 1, 0)),
+                   pn = AT(M.pi, k);
+            for (; k >= kt + 1; --k) {
+                const double Tk = Tn, qk = qn, zkk = zn, zabove = zn2, pik = pn;
+                Tn = AT(M.T, k - 1);
+                qn = AT(M.q, k - 1);
+                zn = zabove;
+                zn2 = AT(M.z, max(k - 2, 0));
+                pn = AT(M.pi, k - 1);
+                finish(k, Tk, qk, zkk);
+                const double zk = 0.5 * (zabove + zkk);
+                const double hkk = (CP * Tk + GRAV * zkk + phis) + LV * qk;
+                const double E = epsd * u_eta * (zk - zlo);
+                const double etan = u_eta + E;
+                const double hm = (u_eta * hu_m + E * hkk) / etan;
+                const double qm = (u_eta * u_qu + E * qk) / etan;
+                const Lifted r = lift(hm - GRAV * zk - phis, qm, pik, hu);
+                u_eta = etan;
+                u_su = CP * r.T + GRAV * zk + phis;
+                u_qu = r.qv;
+                u_c = etan * (qm - r.qv);
+                C1 += u_c;
+                SCR(U_ETA, k) = etan;
+                if (kd >= 0 && k >= kd + 1) {
+                    SCR(U_SU, k) = u_su;
+                    SCR(U_QU, k) = u_qu;
+                    SCR(U_C, k) = u_c;
                 }
-                const double c = (k >= kt + 1) ? t.c : 0.0;
-                const double e1 = (kd >= 0 && k >= kd && k <= kb - 1) ? t.e1 : 0.0;
-                const double net = c - alpha * e1;
-                const double dp = t.pib - pi_top;
-                dT1 = (Fs - Fs_top + LV * net) * GRAV / (CP * dp);
-                dq1 = (Fq - Fq_top - net) * GRAV / dp;
-                SCR(2, k) = dT1;
-                SCR(5, k) = dq1;
-                P1 += net;
-                if (k <= kb - 1) {
-                    const double lam = log(t.pib / pi_top);
-                    Fenv += lam * ((1.0 + CVIR * t.q) * dT1 + CVIR * t.T * dq1);
-                }
-                if (dq1 < 0.0) Mlim = fmin(Mlim, t.q / (-M.dt * dq1));
-                Fs_top = Fs;
-                Fq_top = Fq;
-                pi_top = t.pib;
-            };
-            {
-                TL A, B;
-                load_tl(A, kt);
-                for (int k = kt; k <= kb; k += 2) {
-                    load_tl(B, k + 1);
-                    proc(A, B, k);
-                    if (k + 1 > kb) break;
-                    load_tl(A, k + 2);
-                    proc(B, A, k + 1);
-                }
+                hu_m = hm;
+                zlo = zk;
+                e_T = Tk;
+                e_q = qk;
+                p_bot = p_top;
+                p_top = pik;
             }
-            // D8: F from the launch-layer tendencies and the trigger's parcel sensitivities.
-            const double F = -RD * (dT1 * SA + dq1 * SB - Fenv);
-            if (!(F > 0.0)) {
-                st = 2;
-            } else {
-                const double Mc = cape / (P.tau * F);
-                Mb = Mc <= Mlim ? Mc : Mlim;
-            }
-            // D10: the levels the plume touches (the trigger pass zeroed the whole column).
-            if (st == 0) {
-                for (int k = kt; k <= kb; ++k) {
-                    AT(M.dout.dTdt, k) = Mb * SCR(2, k);
-                    AT(M.dout.dqdt, k) = Mb * SCR(5, k);
-                }
-                for (int i = kt + 1; i <= kb; ++i) {
-                    AT(M.dout.mu, i) = Mb * SCR(7, i);
-                    if (kd >= 0 && i >= kd + 1) AT(M.dout.md, i) = Mb * (alpha * SCR(6, i));
-                }
-            }
-            M.dout.prec[col] = st == 0 ? Mb * P1 : 0.0;
-            M.dout.status[col] = st;
+            // Interface kt+1 and layer kt+1 with layer kt's environment (loaded ahead), then the
+            // top layer kt, whose upper flux is zero and which has no source.
+            finish(kt, Tn, qn, zn);
+            layer(kt, 0.0, 0.0, Fs_b, Fq_b, 0.0, Tn, qn, pn, p_top);
         }
+
+        // D6 strength, then D7 for the downdraft region: layers kd .. kb.
+        double alpha = 0.0;
+        if (kd >= 0) {
+            alpha = P.alpha_dd;
+            if (P.alpha_dd * E1 > P.evap_max_frac * C1) alpha = P.evap_max_frac * C1 / E1;
+            double Fs_t = Fs_kd, Fq_t = Fq_kd;
+            double Tk = AT(M.T, kd), qk = AT(M.q, kd), zk = AT(M.z, kd), pt = AT(M.pi, kd);
+            for (int k = kd; k <= kb; ++k) {
+                const int i = k + 1;  // the layer's bottom interface
+                const int kn = min(i, kb);
+                const double Tb = AT(M.T, kn), qb = AT(M.q, kn), zbl = AT(M.z, kn), pb = AT(M.pi, i);
+                double Fs = 0.0, Fq = 0.0;
+                if (i <= kb) {
+                    const double et = SCR(U_ETA, i), ed = SCR(D_ED, i);
+                    const bool upw = et + alpha * ed >= 0.0;
+                    const double s_up = upw ? CP * Tk + GRAV * zk + phis : CP * Tb + GRAV * zbl + phis;
+                    const double q_up = upw ? qk : qb;
+                    Fs = et * (SCR(U_SU, i) - s_up) + alpha * ed * (SCR(D_SD, i) - s_up);
+                    Fq = et * (SCR(U_QU, i) - q_up) + alpha * ed * (SCR(D_QD, i) - q_up);
+                }
+                const double c = k == kd ? c_kd : SCR(U_C, k);
+                const double e1 = k <= kb - 1 ? SCR(D_E1, k) : 0.0;
+                layer(k, Fs_t, Fq_t, Fs, Fq, c - alpha * e1, Tk, qk, pt, pb);
+                Fs_t = Fs;
+                Fq_t = Fq;
+                Tk = Tb;
+                qk = qb;
+                zk = zbl;
+                pt = pb;
+            }
+        }
+
+        // D8: F from the launch-layer tendencies and the trigger's parcel sensitivities; D9, D10.
+        const double F = -RD * (dT1kb * SA + dq1kb * SB - Fenv);
+        int st = 0;
+        double Mb = 0.0;
+        if (!(F > 0.0)) {
+            st = 2;
+        } else {
+            const double Mc = cape / (P.tau * F);
+            Mb = Mc <= Mlim ? Mc : Mlim;
+        }
+        if (st == 0) {  // the trigger pass zeroed the whole column
+            for (int k = kt; k <= kb; ++k) {
+                AT(M.dout.dTdt, k) = Mb * SCR(X_DT1, k);
+                AT(M.dout.dqdt, k) = Mb * SCR(X_DQ1, k);
+            }
+            for (int i = kt + 1; i <= kb; ++i) {
+                AT(M.dout.mu, i) = Mb * SCR(U_ETA, i);
+                if (kd >= 0 && i >= kd + 1) AT(M.dout.md, i) = Mb * (alpha * SCR(D_ED, i));
+            }
+        }
+        M.dout.prec[col] = st == 0 ? Mb * P1 : 0.0;
+        M.dout.status[col] = st;
     }
 #undef SCR
 }
@@ -857,6 +878,7 @@ Layout make_layout(int64_t ncol, int lmax, int nmem, int cus) {
     l.dmem = take(n * sizeof(int));
     l.dkb = take(n * sizeof(int));
     l.dkt = take(n * sizeof(int));
+    l.dkd = take(n * sizeof(int));
     l.dcape = take(n * sizeof(double));
     l.dSA = take(n * sizeof(double));
     l.dSB = take(n * sizeof(double));
@@ -887,6 +909,7 @@ Work make_work(char *b, const Layout &l, const Launch &launch, int cus) {
     w.dmem = (int *)(b + l.dmem);
     w.dkb = (int *)(b + l.dkb);
     w.dkt = (int *)(b + l.dkt);
+    w.dkd = (int *)(b + l.dkd);
     w.dcape = (double *)(b + l.dcape);
     w.dSA = (double *)(b + l.dSA);
     w.dSB = (double *)(b + l.dSB);

@@ -79,7 +79,7 @@ constexpr int MAX_BPC = 8;
 constexpr Launch DEFAULT_LAUNCH = {4, 2};
 
 struct Layout {
-    size_t cnt, dlist, dmem, dkb, dkt, dcape, dSA, dSB;
+    size_t cnt, dlist, dmem, dkb, dkt, dkd, dcape, dSA, dSB;
     size_t slist, smem, sks, sflag, shs, sqs, scin, sMc, ssig2, members, dscr, sscr, total;
     int64_t threads;  // largest persistent grid (threads) the launch shape allows
     int lmax;
