@@ -28,6 +28,37 @@ NLEV = 30
 NLON, NLAT = 1152, 768
 
 
+# HBM traffic per launch measured with rocprofv3 on the 884,736 x 30 step (FETCH_SIZE and
+# WRITE_SIZE in KiB per dispatch, scaled by what a plain 1 GiB copy kernel reads on the same
+# counters: x2.0 and x1.0; profiles/conv_step_884736x30_hbm_traffic.md).  Valid only while the
+# kernel sources hash to `sources_sha256`; otherwise `traffic` is reported as null.
+TRAFFIC_SOURCES = ("paper_1711_00289_amd/csrc/conv.hip", "paper_1711_00289_amd/csrc/conv_physics.hpp",
+                   "paper_1711_00289_amd/csrc/conv_internal.hpp")
+MEASURED_TRAFFIC = {
+    "sources_sha256": "c37cb9fb9fe1282aacfc01ceb1c3a642efa81ff289a34b557fb6e84e33496316",
+    "fetch_factor": 2.0, "write_factor": 1.0,
+    "k_trigger": (533465, 1530024),
+    "k_deep_plume": (248959, 341522),
+    "k_shallow_retrigger": (120983, 9265),
+    "k_shallow_plume": (48031, 18119),
+}
+
+
+def measured_traffic(kernel: str):
+    """Calibrated HBM bytes per launch of `kernel`, or None if the sources changed since."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for p in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    m = MEASURED_TRAFFIC
+    if h.hexdigest() != m["sources_sha256"] or kernel not in m:
+        return None
+    fetch, write = m[kernel]
+    return int((fetch * m["fetch_factor"] + write * m["write_factor"]) * 1024)
+
+
 def bytes_per_column(L: int):
     """Algorithmic HBM bytes per column of the fused step: every input read once, every output
     written once."""
@@ -276,7 +307,7 @@ def main():
                    "ncol": n, "nlev": NLEV},
         "roofline": {"bound": "hbm", "kernel": f"k_{dom}", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None,
+                     "traffic": measured_traffic(f"k_{dom}"),
                      "algorithmic_bytes_per_launch": int(kb[dom]),
                      "avg_launch_ms": kavg[dom]},
         "step_roofline": {"algorithmic_bytes": int(step_bytes),

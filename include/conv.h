@@ -213,7 +213,7 @@ int conv_autotune(conv_ctx_t *ctx, const conv_state_t *state, conv_deep_out_t *d
                   int *fused_blocks_per_cu, int *shallow_blocks_per_cu, float *ms);
 
 /* Launch shape of the persistent kernels: blocks of 256 threads per compute unit for the
- * deep-plume kernel and for the shallow-plume kernel (each 1..8; default 4 and 2).  The
+ * deep-plume kernel and for the shallow-plume kernel (each 1..8; default 1 and 8).  The
  * workspace size does not depend on it.  Results do not depend on it (bit-identical). */
 int conv_set_launch(conv_ctx_t *ctx, int fused_blocks_per_cu, int shallow_blocks_per_cu);
 int conv_get_launch(conv_ctx_t *ctx, int *fused_blocks_per_cu, int *shallow_blocks_per_cu);

@@ -76,7 +76,7 @@ struct Launch {
     int fused_bpc, shallow_bpc;
 };
 constexpr int MAX_BPC = 8;
-constexpr Launch DEFAULT_LAUNCH = {4, 2};
+constexpr Launch DEFAULT_LAUNCH = {1, 8};
 
 struct Layout {
     size_t cnt, dlist, dmem, dkb, dkt, dkd, dcape, dSA, dSB;
