@@ -70,9 +70,11 @@ struct GemmArgs {
     int64_t split_stride;
 };
 
-// Global -> register -> LDS staging of one operand tile of ROWS x BK.  NT: element (r, k) at
-// p[r*ld + k] (k contiguous, 8-element chunks); TN: at p[k*ld + r] (r contiguous, transposed on
-// the way into LDS).  Out-of-range chunks are zero.
+// Global -> register -> LDS staging of one operand tile of ROWS x BK, as chunks of 8 consecutive
+// k of one row (what one lane's MFMA fragment reads).  NT: element (r, k) at p[r*ld + k], a chunk
+// is one 16-byte load.  TN: element (r, k) at p[k*ld + r]; a chunk is gathered by 8 two-byte loads,
+// each coalesced across the wavefront (consecutive lanes take consecutive r), so that LDS receives
+// one 16-byte store per chunk in both cases.  Out-of-range elements are zero.
 template <bool TN, int ROWS>
 struct Tile {
     static constexpr int CHUNKS = ROWS * BK / 8;
@@ -91,10 +93,16 @@ struct Tile {
                 const int k = k0 + (idx & 3) * 8;
                 if (r < rlim && k < klim) v[i] = *(const uint4 *)(p + r * ld + k);
             } else {
-                constexpr int RC = ROWS / 8;
-                const int k = k0 + idx / RC;
-                const int64_t r = r0 + (idx % RC) * 8;
-                if (k < klim && r < rlim) v[i] = *(const uint4 *)(p + (int64_t)k * ld + r);
+                const int64_t r = r0 + idx % ROWS;
+                const int kc = k0 + (idx / ROWS) * 8;
+                if (r < rlim) {
+                    uint16_t h[8];
+#pragma unroll
+                    for (int j = 0; j < 8; ++j)
+                        h[j] = (kc + j < klim) ? p[(int64_t)(kc + j) * ld + r] : (uint16_t)0;
+                    v[i] = make_uint4(h[0] | ((uint32_t)h[1] << 16), h[2] | ((uint32_t)h[3] << 16),
+                                      h[4] | ((uint32_t)h[5] << 16), h[6] | ((uint32_t)h[7] << 16));
+                }
             }
         }
     }
@@ -104,15 +112,8 @@ struct Tile {
         for (int i = 0; i < PER; ++i) {
             const int idx = t + i * THREADS;
             if (idx >= CHUNKS) continue;
-            if (!TN) {
-                *(uint4 *)(s + (idx >> 2) * LDK + (idx & 3) * 8) = v[i];
-            } else {
-                constexpr int RC = ROWS / 8;
-                const int k = idx / RC, r = (idx % RC) * 8;
-                const uint16_t *h = (const uint16_t *)&v[i];
-#pragma unroll
-                for (int j = 0; j < 8; ++j) s[(r + j) * LDK + k] = h[j];
-            }
+            if (!TN) *(uint4 *)(s + (idx >> 2) * LDK + (idx & 3) * 8) = v[i];
+            else *(uint4 *)(s + (idx % ROWS) * LDK + (idx / ROWS) * 8) = v[i];
         }
     }
 };
@@ -233,6 +234,28 @@ int launch_gemm(bool tn, const GemmArgs &in, int splits, hipStream_t st) {
     return MLP_OK;
 }
 
+// out[c][r] = in[r][c] for r < rows, c < cols; out[c][r] = 0 for rows <= r < ldo (row padding).
+// 64 x 64 tiles through LDS so that both sides are read and written along rows.
+constexpr int TT = 64;
+__global__ __launch_bounds__(THREADS) void k_transpose(const uint16_t *in, int64_t rows, int cols,
+                                                       int64_t ldo, uint16_t *out) {
+    __shared__ uint16_t sh[TT][TT + 2];
+    const int c0 = blockIdx.x * TT;
+    const int64_t r0 = (int64_t)blockIdx.y * TT;
+    const int j = threadIdx.x % TT, i0 = threadIdx.x / TT;
+    for (int i = i0; i < TT; i += THREADS / TT) {
+        const int64_t r = r0 + i;
+        const int c = c0 + j;
+        sh[i][j] = (r < rows && c < cols) ? in[r * cols + c] : (uint16_t)0;
+    }
+    __syncthreads();
+    for (int i = i0; i < TT; i += THREADS / TT) {
+        const int c = c0 + i;
+        const int64_t r = r0 + j;
+        if (c < cols && r < ldo) out[(int64_t)c * ldo + r] = sh[j][i];
+    }
+}
+
 // ------------------------------------------------------------------ reductions, loss, optimiser
 // part[s][n] = sum over rows [s*chunk, min((s+1)*chunk, rows)) of x[r][n] (bf16), in row order.
 __global__ __launch_bounds__(THREADS) void k_colsum_partial(const uint16_t *x, int64_t rows, int n,
@@ -242,6 +265,7 @@ __global__ __launch_bounds__(THREADS) void k_colsum_partial(const uint16_t *x, i
     const int64_t r0 = (int64_t)blockIdx.y * chunk;
     const int64_t r1 = r0 + chunk < rows ? r0 + chunk : rows;
     float s = 0.0f;
+#pragma unroll 8
     for (int64_t r = r0; r < r1; ++r) s += __uint_as_float((uint32_t)x[r * n + c] << 16);
     part[(int64_t)blockIdx.y * n + c] = s;
 }
@@ -348,10 +372,11 @@ void wgrad_split(int64_t batch, int M, int N, int *S, int *chunk) {
 }
 
 constexpr int MAX_SPLIT = 64;
+constexpr int COLSUM_ROWS = 64;  // rows per partial of the bias-gradient column sums
 
 struct Layout {
     size_t params, grads, am, av, wb[MLP_MAX_LAYERS], wt[MLP_MAX_LAYERS];
-    size_t act[MLP_MAX_LAYERS], zf[MLP_MAX_LAYERS], dz[2], part, lpart, total;
+    size_t act[MLP_MAX_LAYERS], zf[MLP_MAX_LAYERS], dz[2], tr[2], part, lpart, total;
     int64_t P;
     int64_t poff[MLP_MAX_LAYERS];  // offset of W_l in the parameter vector (b_l follows)
 };
@@ -379,7 +404,7 @@ Layout make_layout(const int32_t *w, int n, int64_t maxb) {
         P += (int64_t)w[i + 1] * w[i] + w[i + 1];
         size_t need = (size_t)MAX_SPLIT * w[i + 1] * w[i];
         if (need > pmax) pmax = need;
-        need = (size_t)MAX_SPLIT * w[i + 1];
+        need = (size_t)((maxb + COLSUM_ROWS - 1) / COLSUM_ROWS) * w[i + 1];
         if (need > pmax) pmax = need;
     }
     for (int i = 0; i <= n; ++i) wmax = w[i] > wmax ? w[i] : wmax;
@@ -397,6 +422,8 @@ Layout make_layout(const int32_t *w, int n, int64_t maxb) {
         l.zf[i] = take((size_t)maxb * w[i] * 4);
     }
     l.dz[0] = take((size_t)maxb * wmax * 2);
+    l.tr[0] = take((size_t)(maxb + TT) * wmax * 2);  // transposed copies for the weight gradient
+    l.tr[1] = take((size_t)(maxb + TT) * wmax * 2);
     l.dz[1] = take((size_t)maxb * wmax * 2);
     l.part = take(pmax * sizeof(float));
     l.lpart = take(((size_t)maxb * w[n] + THREADS - 1) / THREADS * sizeof(float));
@@ -563,28 +590,35 @@ int mlp_backward(mlp_t *m, int64_t batch, void *stream) {
         const uint16_t *ain = i == 0 ? m->x : hp(m, m->lay.act[i]);
         float *gW = fp(m, m->lay.grads) + m->lay.poff[i];
         float *gb = gW + (int64_t)no * ni;
-        // dW_i[no][ni] = sum_b dz[b][no] * ain[b][ni]
+        // dW_i[no][ni] = sum_b dz[b][no] * ain[b][ni]: both factors transposed to batch-contiguous
+        // rows (zero-padded to a multiple of 8), then the NT kernel with the batch split.
+        const int64_t ldt = (batch + 7) / 8 * 8;
+        uint16_t *dzT = hp(m, m->lay.tr[0]), *aT = hp(m, m->lay.tr[1]);
+        hipLaunchKernelGGL(k_transpose, dim3((no + TT - 1) / TT, (unsigned)((ldt + TT - 1) / TT)),
+                           dim3(THREADS), 0, st, dz, batch, no, ldt, dzT);
+        hipLaunchKernelGGL(k_transpose, dim3((ni + TT - 1) / TT, (unsigned)((ldt + TT - 1) / TT)),
+                           dim3(THREADS), 0, st, ain, batch, ni, ldt, aT);
         int S, chunk;
-        wgrad_split(batch, no, ni, &S, &chunk);
+        wgrad_split(ldt, no, ni, &S, &chunk);
         GemmArgs g{};
-        g.a = dz;
-        g.lda = no;
-        g.b = ain;
-        g.ldb = ni;
+        g.a = dzT;
+        g.lda = ldt;
+        g.b = aT;
+        g.ldb = ldt;
         g.M = no;
         g.N = ni;
-        g.K = (int)batch;
+        g.K = (int)ldt;
         g.ksplit = chunk;
         g.mode = EPI_PARTIAL;
         g.c = part;
         g.ldc = ni;
         g.split_stride = (int64_t)no * ni;
-        int rc = launch_gemm(true, g, S, st);
+        int rc = launch_gemm(false, g, S, st);
         if (rc != MLP_OK) return rc;
         hipLaunchKernelGGL(k_sum_parts, dim3(nblocks((int64_t)no * ni)), dim3(THREADS), 0, st,
                            (const float *)part, S, (int64_t)no * ni, gW);
-        // db_i[no] = sum_b dz[b][no]
-        const int64_t rchunk = (batch + MAX_SPLIT - 1) / MAX_SPLIT;
+        // db_i[no] = sum_b dz[b][no], in chunks of COLSUM_ROWS rows, then over the chunks
+        const int64_t rchunk = COLSUM_ROWS;
         const int RS = (int)((batch + rchunk - 1) / rchunk);
         hipLaunchKernelGGL(k_colsum_partial, dim3(nblocks(no), RS), dim3(THREADS), 0, st, dz, batch,
                            no, rchunk, part);
