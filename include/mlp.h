@@ -71,6 +71,13 @@ int mlp_backward(mlp_t *m, int64_t batch, void *stream);
  * then refreshes the BF16 copies. */
 int mlp_adam_step(mlp_t *m, float lr, float beta1, float beta2, float eps, void *stream);
 
+/* One training step in one call: mlp_forward (keep), mlp_mse, mlp_backward and mlp_adam_step on
+ * the same stream, with the same results; y [batch][widths[n]] receives the network output and
+ * loss[0] the loss.  Returns the first error. */
+int mlp_train_step(mlp_t *m, const uint16_t *x, const float *target, int64_t batch, int n_valid,
+                   float lr, float beta1, float beta2, float eps, float *y, float *loss,
+                   void *stream);
+
 /* The layer kernel on its own, for tests: acc[M][N] = A[M][K] . B[N][K]^T with BF16 operands
  * (row-major, K contiguous, K a multiple of 8, lda/ldb multiples of 8) and FP32 accumulation;
  * mode 0 writes acc + bias as FP32 to c; mode 1 writes bf16(gelu(acc + bias)) to c (uint16_t) and,

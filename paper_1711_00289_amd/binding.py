@@ -35,7 +35,7 @@ EXPORTS = ("conv_workspace_bytes", "conv_create", "conv_set_params", "conv_destr
            "conv_ensemble_autotune", "conv_ensemble_capture", "conv_ensemble_replay",
            "mlp_workspace_bytes", "mlp_create", "mlp_destroy", "mlp_param_count", "mlp_set_params",
            "mlp_get_params", "mlp_get_grads", "mlp_forward", "mlp_mse", "mlp_backward",
-           "mlp_adam_step", "mlp_gemm_nt", "mlp_strerror",
+           "mlp_adam_step", "mlp_train_step", "mlp_gemm_nt", "mlp_strerror",
            "surr_pack_inputs_raw", "surr_pack_targets_raw", "surr_col_stats_scratch_bytes",
            "surr_col_stats", "surr_normalize", "surr_pack_inputs", "surr_workspace_bytes",
            "surr_create", "surr_destroy", "surr_set_norm", "surr_infer")
@@ -158,6 +158,9 @@ def lib():
         L.mlp_backward.argtypes = [V, I64, V]
         L.mlp_adam_step.restype = I
         L.mlp_adam_step.argtypes = [V, C.c_float, C.c_float, C.c_float, C.c_float, V]
+        L.mlp_train_step.restype = I
+        L.mlp_train_step.argtypes = [V, V, V, I64, I, C.c_float, C.c_float, C.c_float, C.c_float,
+                                     V, V, V]
         L.mlp_gemm_nt.restype = I
         L.mlp_gemm_nt.argtypes = [V, I64, V, I64, V, I64, C.c_int32, C.c_int32, I, V, I64, V, V]
         L.mlp_strerror.restype = C.c_char_p
@@ -621,6 +624,22 @@ class MLP:
 
     def backward(self, batch: int):
         mlp_check(lib().mlp_backward(self.h, int(batch), _stream(self.torch)), "mlp_backward")
+
+    def train_step(self, x, target, n_valid: int, lr, beta1=0.9, beta2=0.999, eps=1e-8, y=None,
+                   loss=None):
+        """forward + MSE + backward + Adam in one library call; returns (y, loss)."""
+        torch = self.torch
+        B = x.shape[0]
+        if x.dtype != torch.bfloat16 or not x.is_contiguous() or x.shape[1] != self.widths[0]:
+            raise ValueError("x: contiguous bfloat16 [batch][widths[0]]")
+        if y is None:
+            y = torch.empty(B, self.widths[-1], dtype=torch.float32, device=self.device)
+        loss = self.loss if loss is None else loss
+        self._x = x
+        mlp_check(lib().mlp_train_step(self.h, _ptr(x), _ptr(target.contiguous()), B, int(n_valid),
+                                       float(lr), float(beta1), float(beta2), float(eps), _ptr(y),
+                                       _ptr(loss), _stream(torch)), "mlp_train_step")
+        return y, loss
 
     def adam_step(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
         mlp_check(lib().mlp_adam_step(self.h, float(lr), float(beta1), float(beta2), float(eps),

@@ -257,17 +257,35 @@ __global__ __launch_bounds__(THREADS) void k_transpose(const uint16_t *in, int64
 }
 
 // ------------------------------------------------------------------ reductions, loss, optimiser
-// part[s][n] = sum over rows [s*chunk, min((s+1)*chunk, rows)) of x[r][n] (bf16), in row order.
+// part[s][n] = sum over rows [s*chunk, min((s+1)*chunk, rows)) of x[r][n] (bf16): four running
+// sums over rows r = 4j + {0,1,2,3} (independent, so the loads overlap), then added in order.
 __global__ __launch_bounds__(THREADS) void k_colsum_partial(const uint16_t *x, int64_t rows, int n,
                                                             int64_t chunk, float *part) {
     const int c = blockIdx.x * THREADS + threadIdx.x;
     if (c >= n) return;
     const int64_t r0 = (int64_t)blockIdx.y * chunk;
     const int64_t r1 = r0 + chunk < rows ? r0 + chunk : rows;
-    float s = 0.0f;
-#pragma unroll 8
-    for (int64_t r = r0; r < r1; ++r) s += __uint_as_float((uint32_t)x[r * n + c] << 16);
-    part[(int64_t)blockIdx.y * n + c] = s;
+    float s[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll 4
+    for (int64_t r = r0; r < r1; ++r) s[(r - r0) & 3] += __uint_as_float((uint32_t)x[r * n + c] << 16);
+    part[(int64_t)blockIdx.y * n + c] = (s[0] + s[1]) + (s[2] + s[3]);
+}
+
+// out[i] = sum over s < S of part[s*len + i] for few outputs and many partials: one block per
+// output, a strided sum per thread and a fixed-shape tree.
+__global__ __launch_bounds__(THREADS) void k_sum_parts_tree(const float *part, int S, int64_t len,
+                                                            float *out) {
+    __shared__ float sh[THREADS];
+    const int64_t i = blockIdx.x;
+    float v = 0.0f;
+    for (int k = threadIdx.x; k < S; k += THREADS) v += part[(int64_t)k * len + i];
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int h = THREADS / 2; h > 0; h /= 2) {
+        if ((int)threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[i] = sh[0];
 }
 
 // out[i] = sum_{s < S} part[s*len + i], in order of s.
@@ -622,8 +640,8 @@ int mlp_backward(mlp_t *m, int64_t batch, void *stream) {
         const int RS = (int)((batch + rchunk - 1) / rchunk);
         hipLaunchKernelGGL(k_colsum_partial, dim3(nblocks(no), RS), dim3(THREADS), 0, st, dz, batch,
                            no, rchunk, part);
-        hipLaunchKernelGGL(k_sum_parts, dim3(nblocks(no)), dim3(THREADS), 0, st, (const float *)part,
-                           RS, (int64_t)no, gb);
+        hipLaunchKernelGGL(k_sum_parts_tree, dim3(no), dim3(THREADS), 0, st, (const float *)part, RS,
+                           (int64_t)no, gb);
         if (i == 0) break;
         // dz_prev[b][ni] = (sum_n dz[b][n] W_i[n][ni]) * gelu'(z_i[b][ni])
         GemmArgs d{};
@@ -658,6 +676,17 @@ int mlp_adam_step(mlp_t *m, float lr, float beta1, float beta2, float eps, void 
                        (const float *)fp(m, m->lay.grads), fp(m, m->lay.am), fp(m, m->lay.av), P, lr,
                        beta1, beta2, eps, bc1, bc2);
     return refresh_bf16(m, st);
+}
+
+int mlp_train_step(mlp_t *m, const uint16_t *x, const float *target, int64_t batch, int n_valid,
+                   float lr, float beta1, float beta2, float eps, float *y, float *loss,
+                   void *stream) {
+    if (!m || !x || !target || !y || !loss) return MLP_EINVAL;
+    int rc = mlp_forward(m, x, y, batch, 1, stream);
+    if (rc == MLP_OK) rc = mlp_mse(m, y, target, batch, n_valid, loss, stream);
+    if (rc == MLP_OK) rc = mlp_backward(m, batch, stream);
+    if (rc == MLP_OK) rc = mlp_adam_step(m, lr, beta1, beta2, eps, stream);
+    return rc;
 }
 
 int mlp_gemm_nt(const uint16_t *a, int64_t lda, const uint16_t *b, int64_t ldb, const float *bias,

@@ -139,14 +139,12 @@ def train(torch, net, Xb, Yn, epochs: int, batch: int, lr: float, seed: int = 0,
     rng = np.random.default_rng(seed)
     t0 = time.perf_counter()
     k = 0
+    y = torch.empty(batch, WIDTHS[-1], dtype=torch.float32, device="cuda")
     for ep in range(epochs):
         for b in rng.permutation(nb):
             sl = slice(int(b) * batch, int(b + 1) * batch)
-            y = net.forward(Xb[sl], keep=True)
-            net.mse(y, Yn[sl], N_OUT, out=hist[k:k + 1])
-            net.backward(batch)
             a = 0.5 * (1.0 + math.cos(math.pi * k / steps))
-            net.adam_step(lr * (0.02 + 0.98 * a))
+            net.train_step(Xb[sl], Yn[sl], N_OUT, lr * (0.02 + 0.98 * a), y=y, loss=hist[k:k + 1])
             k += 1
         if log:
             torch.cuda.synchronize()

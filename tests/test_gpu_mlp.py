@@ -128,6 +128,21 @@ def test_gradients_reproducible_bit_for_bit(torch):
     assert np.array_equal(out[0], out[1])
 
 
+def test_train_step_equals_the_separate_calls(torch):
+    net1, params, x, t = _net(torch, 777, 16)
+    net2, _, _, _ = _net(torch, 777, 16)
+    xd, td = bf16_dev(torch, x), torch.from_numpy(t).cuda()
+    for step in range(3):
+        y1 = net1.forward(xd, keep=True)
+        l1 = net1.mse(y1, td, 61).clone()
+        net1.backward(777)
+        net1.adam_step(1e-3)
+        y2, l2 = net2.train_step(xd, td, 61, 1e-3)
+        torch.cuda.synchronize()
+        assert torch.equal(y1, y2) and torch.equal(l1, l2)
+    assert torch.equal(net1.get_params(), net2.get_params())
+
+
 def test_adam_step_against_reference(torch):
     net, params, x, t = _net(torch, 512, 13)
     xd, td = bf16_dev(torch, x), torch.from_numpy(t).cuda()
