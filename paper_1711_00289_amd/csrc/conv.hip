@@ -11,9 +11,10 @@
 //                    atomic per wavefront, so the imbalance between convecting and quiet columns
 //                    (the paper's Methodology, "Load Balancing Convections") is removed by
 //                    compaction rather than by scheduling individual columns.
-//   k_deep_plume     persistent over the deep list, every lane busy: updraft (D5), downdraft (D6),
-//                    flux-form tendencies (D7), closure (D8), limiter (D9), outputs (D10), then the
-//                    shallow trigger on the deep-updated state.
+//   k_deep_plume     persistent; wavefronts claim 64 consecutive slots of the deep list at a time:
+//                    updraft (D5), downdraft (D6), flux-form tendencies (D7), closure (D8),
+//                    limiter (D9), outputs (D10).
+//   k_shallow_retrigger  the shallow trigger (S1-S6) of the deep columns on the deep-updated state.
 //   k_shallow_plume  persistent over the shallow list: plume, tendencies, limiter (S7-S9).
 // Per-level plume profiles live in a per-thread scratch region of the caller's workspace laid out
 // [array][level][thread], so a wavefront's accesses to one level are contiguous.  Level loops load
@@ -66,6 +67,7 @@ constexpr int DEEP_SCR = 10;    // deep plume profiles (enum DeepScr)
 constexpr int SHALLOW_SCR = 3;  // eta, dT1, dq1
 constexpr int CNT_DEEP = 0;
 constexpr int CNT_SHALLOW = 1;
+constexpr int CNT_DGRAB = 2;  // deep-list slots claimed by the deep plume past its first round
 
 struct Work {
     int *cnt;
@@ -415,11 +417,18 @@ template <class Src>
 __global__ __launch_bounds__(BLOCK) void k_deep_plume(Src src, Work w) {
     const int n = w.cnt[CNT_DEEP];
     const int64_t gtid = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    const int64_t nthreads = (int64_t)gridDim.x * BLOCK;
+    const int lane = threadIdx.x % WAVE;
     double *scr = w.dscr;
 #define SCR(arr, lev) scr[((int64_t)(arr) * (w.lmax + 1) + (lev)) * w.dstride + gtid]
 
-    for (int64_t slot = gtid; slot < n; slot += nthreads) {
+    // Wavefront g takes slots 64g .. 64g+63 of the deep list, then claims the next 64 unclaimed
+    // slots past the grid's first round until the list runs out (list order keeps a wavefront's
+    // columns close in memory).  Lane 0 holds the smallest slot, so it is active whenever any
+    // lane is.
+    const int64_t first_round = (int64_t)gridDim.x * BLOCK;
+    for (int64_t slot0 = gtid - lane;;) {
+        const int64_t slot = slot0 + lane;
+        if (slot >= n) break;
         const Member &M = src.at(w.dmem[slot]);
         const int64_t ld = M.ld;
         const conv_params_t &P = M.P;
@@ -641,6 +650,10 @@ __global__ __launch_bounds__(BLOCK) void k_deep_plume(Src src, Work w) {
         }
         M.dout.prec[col] = st == 0 ? Mb * P1 : 0.0;
         M.dout.status[col] = st;
+
+        int claim = 0;
+        if (lane == 0) claim = atomicAdd(&w.cnt[CNT_DGRAB], WAVE);
+        slot0 = first_round + __builtin_amdgcn_readfirstlane(claim);
     }
 #undef SCR
 }
