@@ -1,20 +1,24 @@
 // mlp.hip -- the surrogate network's kernels for gfx950 (include/mlp.h): one tiled BF16 GEMM on
 // the matrix cores (v_mfma_f32_32x32x16_bf16, FP32 accumulation) with fused epilogues, used for the
-// forward layers (bias + GELU), the backward data gradient (times GELU') and, with transposed tile
-// loads and the batch split across blocks, the weight gradients; plus column sums, MSE and Adam.
+// forward layers (bias + GELU), the backward data gradient (times GELU') and, on transposed copies
+// with the batch split across blocks, the weight gradients; plus column sums, MSE and Adam.
 //
-// GEMM tiling: a 256-thread block computes a 128 x BN tile (BN = 128 or 64) with four wavefronts
-// in a 2 x 2 arrangement, each owning 64 x BN/2 as 2 x BN/64 MFMA tiles of 32 x 32.  K advances 32
-// at a time through double-buffered LDS tiles; the next K tile is fetched from global memory into
-// registers while the current one feeds the MFMAs.  Block ids are mapped so that the N tiles of one
-// M tile run on the same XCD (the hardware deals consecutive blocks to the 8 XCDs in turn), so an
-// activation tile is fetched into one XCD's L2 once and reused there.
+// GEMM tiling: a block computes a BM x BN tile (128 x 128, 256 x 256 or 128 x 64, chosen by shape)
+// with its wavefronts in a WM x WN arrangement, each owning (BM/WM) x (BN/WN) as 32 x 32 MFMA
+// tiles.  K advances 64 at a time through double-buffered LDS tiles; the next K tile is fetched
+// from global memory into registers while the current one feeds the MFMAs, and every row of a tile
+// is one full 128-byte line.  Block ids are mapped so that the N tiles of one M tile run on the
+// same XCD (the hardware deals consecutive blocks to the 8 XCDs in turn), so an activation tile is
+// fetched into one XCD's L2 once and reused there.  The epilogue stages each wavefront's
+// accumulators in LDS 32 rows at a time and finishes them in chunks of 8 consecutive columns of a
+// row, so that bias, pre-activation and outputs move in 16-byte loads and stores.
 #include <hip/hip_runtime.h>
 
 #include <math.h>
 #include <stdint.h>
 #include <string.h>
 
+#include <atomic>
 #include <vector>
 
 #include "mlp.h"
@@ -24,10 +28,9 @@ namespace {
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
 
-constexpr int THREADS = 256;
-constexpr int BM = 128;
-constexpr int BK = 32;
-constexpr int LDK = BK + 8;  // LDS row stride in bf16 (80 bytes: 16-byte aligned rows)
+constexpr int THREADS = 256;  // block size of the elementwise and reduction kernels
+constexpr int BK = 64;
+constexpr int LDK = BK + 8;  // LDS row stride in bf16 (144 bytes: 16-byte aligned, conflict-free)
 constexpr int NXCD = 8;
 
 thread_local int g_mlp_hip = 0;
@@ -38,14 +41,35 @@ __device__ __forceinline__ uint16_t f2bf(float f) {  // round to nearest even
     return (uint16_t)(u >> 16);
 }
 
+// erfc(x) by the Chebyshev-fitted form of Press et al., Numerical Recipes (erfcc, fractional error
+// below 1.2e-7 everywhere): erfc(x) = t exp(-x^2 + P(t)) with t = 1/(1 + |x|/2), reflected as
+// 2 - erfc(-x) for x < 0.  Branch-free: one reciprocal and one exponential.
+__device__ __forceinline__ float erfc_cheb(float x) {
+    const float ax = fabsf(x);
+    const float t = __builtin_amdgcn_rcpf(1.0f + 0.5f * ax);
+    float p = 0.17087277f;
+    p = fmaf(p, t, -0.82215223f);
+    p = fmaf(p, t, 1.48851587f);
+    p = fmaf(p, t, -1.13520398f);
+    p = fmaf(p, t, 0.27886807f);
+    p = fmaf(p, t, -0.18628806f);
+    p = fmaf(p, t, 0.09678418f);
+    p = fmaf(p, t, 0.37409196f);
+    p = fmaf(p, t, 1.00002368f);
+    p = fmaf(p, t, -1.26551223f);
+    const float r = t * __expf(fmaf(-ax, ax, p));
+    return x >= 0.0f ? r : 2.0f - r;
+}
+
 // GELU(z) = z Phi(z) with Phi(z) = erfc(-z/sqrt 2)/2 (the erfc form keeps full relative accuracy
 // in the negative tail, where 1 + erf(z/sqrt 2) would cancel).
 __device__ __forceinline__ float gelu(float z) {
-    return 0.5f * z * erfcf(-z * 0.70710678118654752f);
+    return 0.5f * z * erfc_cheb(-z * 0.70710678118654752f);
 }
 
 __device__ __forceinline__ float gelu_grad(float z) {
-    return 0.5f * erfcf(-z * 0.70710678118654752f) + z * 0.39894228040143268f * expf(-0.5f * z * z);
+    return 0.5f * erfc_cheb(-z * 0.70710678118654752f) +
+           z * 0.39894228040143268f * __expf(-0.5f * z * z);
 }
 
 enum Mode : int {
@@ -63,6 +87,7 @@ struct GemmArgs {
     int tiles_m, tiles_n;
     int ksplit;  // > 0: blockIdx.y covers K range [y*ksplit, (y+1)*ksplit)
     int mode;
+    int vec;     // 16-byte epilogue accesses allowed (alignment of c, z, bias, ldc, split_stride)
     const float *bias;
     void *c;
     int64_t ldc;
@@ -70,61 +95,54 @@ struct GemmArgs {
     int64_t split_stride;
 };
 
-// Global -> register -> LDS staging of one operand tile of ROWS x BK, as chunks of 8 consecutive
-// k of one row (what one lane's MFMA fragment reads).  NT: element (r, k) at p[r*ld + k], a chunk
-// is one 16-byte load.  TN: element (r, k) at p[k*ld + r]; a chunk is gathered by 8 two-byte loads,
-// each coalesced across the wavefront (consecutive lanes take consecutive r), so that LDS receives
-// one 16-byte store per chunk in both cases.  Out-of-range elements are zero.
-template <bool TN, int ROWS>
+// Global -> register -> LDS staging of one operand tile of ROWS x BK (element (r, k) at
+// p[r*ld + k]) as chunks of 8 consecutive k of one row: one 16-byte load per chunk, eight lanes per
+// 128-byte row.  Out-of-range chunks are zero (K limits are multiples of 8).
+template <int ROWS, int NT>
 struct Tile {
     static constexpr int CHUNKS = ROWS * BK / 8;
-    static constexpr int PER = (CHUNKS + THREADS - 1) / THREADS;
+    static constexpr int PER = CHUNKS / NT;
+    static_assert(CHUNKS % NT == 0, "tile chunks must divide among the threads");
     uint4 v[PER];
 
     __device__ __forceinline__ void load(const uint16_t *p, int64_t ld, int64_t r0, int64_t rlim,
                                          int k0, int klim, int t) {
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
-            const int idx = t + i * THREADS;
+            const int idx = t + i * NT;
+            const int64_t r = r0 + (idx >> 3);
+            const int k = k0 + (idx & 7) * 8;
             v[i] = make_uint4(0u, 0u, 0u, 0u);
-            if (idx >= CHUNKS) continue;
-            if (!TN) {
-                const int64_t r = r0 + (idx >> 2);
-                const int k = k0 + (idx & 3) * 8;
-                if (r < rlim && k < klim) v[i] = *(const uint4 *)(p + r * ld + k);
-            } else {
-                const int64_t r = r0 + idx % ROWS;
-                const int kc = k0 + (idx / ROWS) * 8;
-                if (r < rlim) {
-                    uint16_t h[8];
-#pragma unroll
-                    for (int j = 0; j < 8; ++j)
-                        h[j] = (kc + j < klim) ? p[(int64_t)(kc + j) * ld + r] : (uint16_t)0;
-                    v[i] = make_uint4(h[0] | ((uint32_t)h[1] << 16), h[2] | ((uint32_t)h[3] << 16),
-                                      h[4] | ((uint32_t)h[5] << 16), h[6] | ((uint32_t)h[7] << 16));
-                }
-            }
+            if (r < rlim && k < klim) v[i] = *(const uint4 *)(p + r * ld + k);
         }
     }
 
     __device__ __forceinline__ void store(uint16_t *s, int t) const {
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
-            const int idx = t + i * THREADS;
-            if (idx >= CHUNKS) continue;
-            if (!TN) *(uint4 *)(s + (idx >> 2) * LDK + (idx & 3) * 8) = v[i];
-            else *(uint4 *)(s + (idx % ROWS) * LDK + (idx / ROWS) * 8) = v[i];
+            const int idx = t + i * NT;
+            *(uint4 *)(s + (idx >> 3) * LDK + (idx & 7) * 8) = v[i];
         }
     }
 };
 
-template <bool TN, int BN>
-__global__ __launch_bounds__(THREADS) void k_gemm(GemmArgs g) {
-    constexpr int NTW = BN / 64;  // 32-wide MFMA tiles per wavefront along N
-    __shared__ __attribute__((aligned(16))) uint16_t As[2][BM * LDK];
-    __shared__ __attribute__((aligned(16))) uint16_t Bs[2][BN * LDK];
+template <int BM, int BN, int WM, int WN>
+constexpr size_t gemm_lds_bytes() {
+    return (size_t)2 * (BM + BN) * LDK * sizeof(uint16_t);
+}
 
-    const int t = threadIdx.x, lane = t & 63, w = t >> 6, wm = w >> 1, wn = w & 1;
+template <int BM, int BN, int WM, int WN>
+__global__ __launch_bounds__(WM * WN * 64) void k_gemm(GemmArgs g) {
+    constexpr int NT = WM * WN * 64;
+    constexpr int TM = BM / WM / 32, TN = BN / WN / 32;  // 32 x 32 MFMA tiles per wavefront
+    constexpr int SW = 32 * TN, SLD = SW + 4;  // epilogue strip: 32 rows x SW columns (floats)
+    static_assert(WM * WN * 32 * SLD * sizeof(float) <= gemm_lds_bytes<BM, BN, WM, WN>(),
+                  "epilogue strips must fit in the operand buffers");
+    extern __shared__ __attribute__((aligned(16))) uint16_t smem[];
+    uint16_t *const A0 = smem, *const A1 = smem + BM * LDK;
+    uint16_t *const B0 = smem + 2 * BM * LDK, *const B1 = B0 + BN * LDK;
+
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6, wm = w / WN, wn = w % WN;
     const int64_t bid = blockIdx.x;
     const int xcd = (int)(bid % NXCD);
     const int64_t j = bid / NXCD;
@@ -139,13 +157,13 @@ __global__ __launch_bounds__(THREADS) void k_gemm(GemmArgs g) {
         k1 = min(k0 + g.ksplit, g.K);
     }
 
-    Tile<TN, BM> ta;
-    Tile<TN, BN> tb;
-    f32x16 acc[2][NTW];
+    Tile<BM, NT> ta;
+    Tile<BN, NT> tb;
+    f32x16 acc[TM][TN];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < TM; ++a)
 #pragma unroll
-        for (int b = 0; b < NTW; ++b)
+        for (int b = 0; b < TN; ++b)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
 
@@ -153,13 +171,14 @@ __global__ __launch_bounds__(THREADS) void k_gemm(GemmArgs g) {
     if (nk > 0) {
         ta.load(g.a, g.lda, m0, g.M, k0, k1, t);
         tb.load(g.b, g.ldb, n0, g.N, k0, k1, t);
-        ta.store(As[0], t);
-        tb.store(Bs[0], t);
+        ta.store(A0, t);
+        tb.store(B0, t);
     }
     __syncthreads();
     const int lrow = lane & 31, lk = 8 * (lane >> 5);
     for (int kt = 0; kt < nk; ++kt) {
-        const int cur = kt & 1;
+        const bool odd = kt & 1;
+        const uint16_t *Ac = odd ? A1 : A0, *Bc = odd ? B1 : B0;
         const bool more = kt + 1 < nk;
         if (more) {
             ta.load(g.a, g.lda, m0, g.M, k0 + (kt + 1) * BK, k1, t);
@@ -167,71 +186,157 @@ __global__ __launch_bounds__(THREADS) void k_gemm(GemmArgs g) {
         }
 #pragma unroll
         for (int ks = 0; ks < BK; ks += 16) {
-            bf16x8 af[2], bf[NTW];
+            bf16x8 af[TM], bf[TN];
 #pragma unroll
-            for (int a = 0; a < 2; ++a)
-                af[a] = *(const bf16x8 *)&As[cur][(wm * 64 + a * 32 + lrow) * LDK + ks + lk];
+            for (int a = 0; a < TM; ++a)
+                af[a] = *(const bf16x8 *)&Ac[(wm * (BM / WM) + a * 32 + lrow) * LDK + ks + lk];
 #pragma unroll
-            for (int b = 0; b < NTW; ++b)
-                bf[b] = *(const bf16x8 *)&Bs[cur][(wn * (BN / 2) + b * 32 + lrow) * LDK + ks + lk];
+            for (int b = 0; b < TN; ++b)
+                bf[b] = *(const bf16x8 *)&Bc[(wn * (BN / WN) + b * 32 + lrow) * LDK + ks + lk];
 #pragma unroll
-            for (int a = 0; a < 2; ++a)
+            for (int a = 0; a < TM; ++a)
 #pragma unroll
-                for (int b = 0; b < NTW; ++b)
+                for (int b = 0; b < TN; ++b)
                     acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[a], bf[b], acc[a][b], 0, 0, 0);
         }
         if (more) {
-            ta.store(As[cur ^ 1], t);
-            tb.store(Bs[cur ^ 1], t);
+            ta.store(odd ? A0 : A1, t);
+            tb.store(odd ? B0 : B1, t);
         }
         __syncthreads();
     }
 
-    // Accumulator layout of a 32x32 MFMA tile: register r of lane l holds
-    // row 8*(r/4) + 4*(l/32) + r%4, column l%32.
+    // Epilogue.  Accumulator layout of a 32x32 MFMA tile: register r of lane l holds row
+    // 8*(r/4) + 4*(l/32) + r%4, column l%32.  Each wavefront writes one 32-row strip of its tile to
+    // its own LDS region, then each lane finishes chunks of 8 consecutive columns of one row.
+    float *strip = (float *)smem + w * 32 * SLD;
+    constexpr int CPR = SW / 8;          // chunks per strip row
+    constexpr int NCH = 32 * CPR / 64;   // chunks per lane per strip
+    static_assert((32 * CPR) % 64 == 0, "strip chunks must divide among the lanes");
+    const bool use_bias = g.bias && (g.mode == EPI_F32 || g.mode == EPI_GELU);
 #pragma unroll
-    for (int a = 0; a < 2; ++a) {
+    for (int a = 0; a < TM; ++a) {
 #pragma unroll
-        for (int b = 0; b < NTW; ++b) {
-            const int n = n0 + wn * (BN / 2) + b * 32 + lrow;
-            if (n >= g.N) continue;
-            const float bias = (g.bias && g.mode != EPI_PARTIAL && g.mode != EPI_DGELU) ? g.bias[n] : 0.0f;
+        for (int b = 0; b < TN; ++b)
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int64_t m = m0 + wm * 64 + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                if (m >= g.M) continue;
-                const float v = acc[a][b][r];
-                const int64_t o = m * g.ldc + n;
-                if (g.mode == EPI_F32) {
-                    ((float *)g.c)[o] = v + bias;
-                } else if (g.mode == EPI_GELU) {
-                    const float zz = v + bias;
-                    if (g.z) g.z[o] = zz;
-                    ((uint16_t *)g.c)[o] = f2bf(gelu(zz));
-                } else if (g.mode == EPI_DGELU) {
-                    ((uint16_t *)g.c)[o] = f2bf(v * gelu_grad(g.z[o]));
+            for (int r = 0; r < 16; ++r)
+                strip[(8 * (r >> 2) + 4 * (lane >> 5) + (r & 3)) * SLD + b * 32 + lrow] = acc[a][b][r];
+        __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): the strip is written
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int i = 0; i < NCH; ++i) {
+            const int ch = lane + i * 64;
+            const int rr = ch / CPR, cc = (ch % CPR) * 8;
+            const int64_t m = m0 + wm * (BM / WM) + a * 32 + rr;
+            const int n = n0 + wn * (BN / WN) + cc;
+            if (m >= g.M || n >= g.N) continue;
+            const int cnt = min(8, g.N - n);
+            const bool full = g.vec && cnt == 8;
+            float v[8], x[8];
+            *(float4 *)&v[0] = *(const float4 *)&strip[rr * SLD + cc];
+            *(float4 *)&v[4] = *(const float4 *)&strip[rr * SLD + cc + 4];
+            if (use_bias) {
+                if (full) {
+                    *(float4 *)&x[0] = *(const float4 *)&g.bias[n];
+                    *(float4 *)&x[4] = *(const float4 *)&g.bias[n + 4];
                 } else {
-                    ((float *)g.c)[(int64_t)blockIdx.y * g.split_stride + o] = v;
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) x[e] = e < cnt ? g.bias[n + e] : 0.0f;
                 }
+#pragma unroll
+                for (int e = 0; e < 8; ++e) v[e] += x[e];
+            }
+            const int64_t o = m * g.ldc + n;
+            if (g.mode == EPI_F32 || g.mode == EPI_PARTIAL) {
+                float *c = (float *)g.c + o;
+                if (g.mode == EPI_PARTIAL) c += (int64_t)blockIdx.y * g.split_stride;
+                if (full) {
+                    *(float4 *)&c[0] = *(float4 *)&v[0];
+                    *(float4 *)&c[4] = *(float4 *)&v[4];
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 8; ++e)
+                        if (e < cnt) c[e] = v[e];
+                }
+                continue;
+            }
+            if (g.mode == EPI_GELU) {
+                if (g.z) {
+                    if (full) {
+                        *(float4 *)&g.z[o] = *(float4 *)&v[0];
+                        *(float4 *)&g.z[o + 4] = *(float4 *)&v[4];
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < 8; ++e)
+                            if (e < cnt) g.z[o + e] = v[e];
+                    }
+                }
+#pragma unroll
+                for (int e = 0; e < 8; ++e) v[e] = gelu(v[e]);
+            } else {  // EPI_DGELU
+                if (full) {
+                    *(float4 *)&x[0] = *(const float4 *)&g.z[o];
+                    *(float4 *)&x[4] = *(const float4 *)&g.z[o + 4];
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) x[e] = e < cnt ? g.z[o + e] : 0.0f;
+                }
+#pragma unroll
+                for (int e = 0; e < 8; ++e) v[e] *= gelu_grad(x[e]);
+            }
+            uint16_t *c = (uint16_t *)g.c + o;
+            if (full) {
+                uint32_t h[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    h[e] = (uint32_t)f2bf(v[2 * e]) | ((uint32_t)f2bf(v[2 * e + 1]) << 16);
+                *(uint4 *)c = make_uint4(h[0], h[1], h[2], h[3]);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 8; ++e)
+                    if (e < cnt) c[e] = f2bf(v[e]);
             }
         }
+        __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): the strip is read before it is reused
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
-int launch_gemm(bool tn, const GemmArgs &in, int splits, hipStream_t st) {
-    GemmArgs g = in;
-    const int BN = (g.N % 128 == 0) ? 128 : 64;
+template <int BM, int BN, int WM, int WN>
+int launch_tiles(GemmArgs g, int splits, hipStream_t st) {
     g.tiles_m = (int)((g.M + BM - 1) / BM);
     g.tiles_n = (g.N + BN - 1) / BN;
     const int64_t mgroups = (g.tiles_m + NXCD - 1) / NXCD;
     const int64_t blocks = mgroups * NXCD * g.tiles_n;
     if (blocks <= 0 || blocks > 0x7fffffff || splits < 1) return MLP_EINVAL;
-    const dim3 grid((unsigned)blocks, (unsigned)splits);
-    if (!tn && BN == 128) hipLaunchKernelGGL((k_gemm<false, 128>), grid, dim3(THREADS), 0, st, g);
-    else if (!tn) hipLaunchKernelGGL((k_gemm<false, 64>), grid, dim3(THREADS), 0, st, g);
-    else if (BN == 128) hipLaunchKernelGGL((k_gemm<true, 128>), grid, dim3(THREADS), 0, st, g);
-    else hipLaunchKernelGGL((k_gemm<true, 64>), grid, dim3(THREADS), 0, st, g);
+    constexpr size_t lds = gemm_lds_bytes<BM, BN, WM, WN>();
+    // The LDS limit above 64 KiB is a per-device function attribute: set once per device.
+    static std::atomic<uint64_t> done{0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return MLP_EHIP;
+    if (!(done.load() & (1ull << dev))) {
+        if (hipFuncSetAttribute((const void *)k_gemm<BM, BN, WM, WN>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+            return MLP_EHIP;
+        done.fetch_or(1ull << dev);
+    }
+    hipLaunchKernelGGL((k_gemm<BM, BN, WM, WN>), dim3((unsigned)blocks, (unsigned)splits),
+                       dim3(WM * WN * 64), lds, st, g);
     return MLP_OK;
+}
+
+bool al16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+// Tile shape by problem shape: 128 x 64 for narrow outputs, 256 x 256 when the grid still has
+// several blocks per compute unit, else 128 x 128.
+int launch_gemm(const GemmArgs &in, int splits, hipStream_t st) {
+    GemmArgs g = in;
+    g.vec = al16(g.c) && (!g.z || al16(g.z)) && (!g.bias || al16(g.bias)) && g.ldc % 8 == 0 &&
+            g.split_stride % 8 == 0;
+    if (g.N <= 64) return launch_tiles<128, 64, 2, 2>(g, splits, st);
+    const int64_t big = ((g.M + 255) / 256) * ((g.N + 255) / 256) * splits;
+    if (g.N % 256 == 0 && big >= 1024) return launch_tiles<256, 256, 4, 2>(g, splits, st);
+    return launch_tiles<128, 128, 2, 2>(g, splits, st);
 }
 
 // out[c][r] = in[r][c] for r < rows, c < cols; out[c][r] = 0 for rows <= r < ldo (row padding).
@@ -377,7 +482,7 @@ int check() {
 
 // Weight-gradient GEMM split: enough blocks to fill the chip, chunks a multiple of BK.
 void wgrad_split(int64_t batch, int M, int N, int *S, int *chunk) {
-    const int tiles = ((M + BM - 1) / BM) * ((N + 63) / 64);
+    const int tiles = ((M + 127) / 128) * (N <= 64 ? 1 : (N + 127) / 128);
     int s = (512 + tiles - 1) / tiles;
     if (s > 64) s = 64;
     if (s < 1) s = 1;
@@ -568,7 +673,7 @@ int mlp_forward(mlp_t *m, const uint16_t *x, float *y, int64_t batch, int keep, 
             g.c = y;
         }
         g.ldc = m->w[i + 1];
-        const int rc = launch_gemm(false, g, 1, st);
+        const int rc = launch_gemm(g, 1, st);
         if (rc != MLP_OK) return rc;
         in = (const uint16_t *)g.c;
     }
@@ -631,7 +736,7 @@ int mlp_backward(mlp_t *m, int64_t batch, void *stream) {
         g.c = part;
         g.ldc = ni;
         g.split_stride = (int64_t)no * ni;
-        int rc = launch_gemm(false, g, S, st);
+        int rc = launch_gemm(g, S, st);
         if (rc != MLP_OK) return rc;
         hipLaunchKernelGGL(k_sum_parts, dim3(nblocks((int64_t)no * ni)), dim3(THREADS), 0, st,
                            (const float *)part, S, (int64_t)no * ni, gW);
@@ -656,7 +761,7 @@ int mlp_backward(mlp_t *m, int64_t batch, void *stream) {
         d.c = hp(m, m->lay.dz[cur ^ 1]);
         d.ldc = ni;
         d.z = fp(m, m->lay.zf[i]);
-        rc = launch_gemm(false, d, 1, st);
+        rc = launch_gemm(d, 1, st);
         if (rc != MLP_OK) return rc;
         cur ^= 1;
     }
@@ -708,7 +813,7 @@ int mlp_gemm_nt(const uint16_t *a, int64_t lda, const uint16_t *b, int64_t ldb, 
     g.c = c;
     g.ldc = ldc;
     g.z = z;
-    const int rc = launch_gemm(false, g, 1, (hipStream_t)stream);
+    const int rc = launch_gemm(g, 1, (hipStream_t)stream);
     if (rc != MLP_OK) return rc;
     return check();
 }
