@@ -8,6 +8,10 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <mutex>
+#include <set>
+#include <utility>
+
 #include "conv.h"
 #include "conv_internal.hpp"
 #include "mlp.h"
@@ -33,36 +37,57 @@ struct StateArgs {
     int64_t ld;
 };
 
-// Inputs of a block of 64 columns into LDS as [feature][column], then out as rows.
-// mode 0: raw FP32 rows; mode 1: normalised BF16 rows.
+// Inputs of a block of TC columns into LDS as [feature][column] (normalised in mode 1), then out
+// as rows.  mode 0: raw FP32 rows; mode 1: normalised BF16 rows.  With `vec` (row width a multiple
+// of 8 and a 16-byte aligned output) each lane writes 8 BF16 or 4 FP32 features per store.
 __global__ __launch_bounds__(TB) void k_pack_in(StateArgs s, int L, int64_t ncol, int w, int mode,
                                                 const float *mean, const float *stdv, float *outf,
-                                                uint16_t *outb) {
-    __shared__ float sh[WMAX][TC + 1];
+                                                uint16_t *outb, int vec) {
+    extern __shared__ float sh[];  // [w][TC + 1]
+    constexpr int SL = TC + 1;
     const int64_t c0 = (int64_t)blockIdx.x * TC;
     const int lane = threadIdx.x % TC, grp = threadIdx.x / TC;
     const int64_t c = c0 + lane;
     const int64_t ld = s.ld;
     for (int f = grp; f < w; f += TB / TC) {
-        double v = 0.0;
-        if (c < ncol) {
-            if (f < L) v = s.T[(int64_t)f * ld + c];
-            else if (f < 2 * L) v = s.q[(int64_t)(f - L) * ld + c];
-            else if (f < 3 * L) v = s.pm[(int64_t)(f - 2 * L) * ld + c];
+        float v = 0.0f;
+        if (c < ncol && f < 3 * L) {
+            double d;
+            if (f < L) d = s.T[(int64_t)f * ld + c];
+            else if (f < 2 * L) d = s.q[(int64_t)(f - L) * ld + c];
+            else d = s.pm[(int64_t)(f - 2 * L) * ld + c];
+            v = mode == 0 ? (float)d : ((float)d - mean[f]) / stdv[f];
         }
-        sh[f][lane] = (float)v;
+        sh[f * SL + lane] = v;
     }
     __syncthreads();
-    const int64_t nrows = ncol - c0 < TC ? ncol - c0 : TC;
-    for (int64_t i = threadIdx.x; i < nrows * w; i += TB) {
-        const int r = (int)(i / w), f = (int)(i % w);
-        const float v = sh[f][r];
-        const int64_t o = (c0 + r) * w + f;
-        if (mode == 0) {
-            outf[o] = v;
-        } else {
-            outb[o] = f < 3 * L ? f2bf((v - mean[f]) / stdv[f]) : (uint16_t)0;
+    const int nrows = (int)(ncol - c0 < TC ? ncol - c0 : TC);
+    if (vec) {
+        const int per = mode == 0 ? 4 : 8;  // features per 16-byte store
+        const int cpr = w / per;
+        for (int i = threadIdx.x; i < nrows * cpr; i += TB) {
+            const int r = i / cpr, f0 = (i % cpr) * per;
+            const int64_t o = (c0 + r) * w + f0;
+            if (mode == 0) {
+                *(float4 *)&outf[o] = make_float4(sh[f0 * SL + r], sh[(f0 + 1) * SL + r],
+                                                  sh[(f0 + 2) * SL + r], sh[(f0 + 3) * SL + r]);
+            } else {
+                uint32_t h[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    h[e] = (uint32_t)f2bf(sh[(f0 + 2 * e) * SL + r]) |
+                           ((uint32_t)f2bf(sh[(f0 + 2 * e + 1) * SL + r]) << 16);
+                *(uint4 *)&outb[o] = make_uint4(h[0], h[1], h[2], h[3]);
+            }
         }
+        return;
+    }
+    for (int i = threadIdx.x; i < nrows * w; i += TB) {
+        const int r = i / w, f = i % w;
+        const float v = sh[f * SL + r];
+        const int64_t o = (c0 + r) * w + f;
+        if (mode == 0) outf[o] = v;
+        else outb[o] = f2bf(v);
     }
 }
 
@@ -153,19 +178,33 @@ __global__ __launch_bounds__(TB) void k_normalize(float *a, int64_t total, int w
     else a[i] = v;
 }
 
-// Network output rows of 64 columns -> level-major FP64 tendencies; flags columns whose predicted
+// Network output rows of TC columns -> level-major FP64 tendencies; flags columns whose predicted
 // precipitation is outside [lo, hi] into the fallback list (first wavefront, one lane per column).
+// With `vec` (row width a multiple of 4, 16-byte aligned rows) rows are read 4 outputs per load.
 __global__ __launch_bounds__(TB) void k_unpack(const float *y, int L, int64_t ncol, int w,
                                                const float *mean, const float *stdv, double lo,
                                                double hi, double *dTdt, double *dqdt, double *prec,
-                                               int64_t ld, int64_t col0, int *list, int *cnt) {
-    __shared__ float sh[WMAX][TC + 1];
+                                               int64_t ld, int64_t col0, int *list, int *cnt, int vec) {
+    extern __shared__ float sh[];  // [2L+1][TC + 1]
+    constexpr int SL = TC + 1;
     const int64_t c0 = (int64_t)blockIdx.x * TC;
-    const int64_t nrows = ncol - c0 < TC ? ncol - c0 : TC;
+    const int nrows = (int)(ncol - c0 < TC ? ncol - c0 : TC);
     const int nf = 2 * L + 1;
-    for (int64_t i = threadIdx.x; i < nrows * w; i += TB) {
-        const int r = (int)(i / w), f = (int)(i % w);
-        if (f < nf) sh[f][r] = y[(c0 + r) * w + f] * stdv[f] + mean[f];
+    if (vec) {
+        const int cpr = (nf + 3) / 4;  // f0 < nf <= w and w % 4 == 0, so f0 + 3 < w
+        for (int i = threadIdx.x; i < nrows * cpr; i += TB) {
+            const int r = i / cpr, f0 = (i % cpr) * 4;
+            const float4 v = *(const float4 *)&y[(c0 + r) * w + f0];
+            const float e[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (f0 + k < nf) sh[(f0 + k) * SL + r] = e[k] * stdv[f0 + k] + mean[f0 + k];
+        }
+    } else {
+        for (int i = threadIdx.x; i < nrows * w; i += TB) {
+            const int r = i / w, f = i % w;
+            if (f < nf) sh[f * SL + r] = y[(c0 + r) * w + f] * stdv[f] + mean[f];
+        }
     }
     __syncthreads();
     const int lane = threadIdx.x % TC, grp = threadIdx.x / TC;
@@ -173,12 +212,12 @@ __global__ __launch_bounds__(TB) void k_unpack(const float *y, int L, int64_t nc
     const bool live = lane < nrows;
     for (int f = grp; f < 2 * L; f += TB / TC) {
         if (!live) continue;
-        const double v = (double)sh[f][lane];
+        const double v = (double)sh[f * SL + lane];
         if (f < L) dTdt[(int64_t)f * ld + col0 + c] = v;
         else dqdt[(int64_t)(f - L) * ld + col0 + c] = v;
     }
     if (grp == 0) {
-        const double p = live ? (double)sh[2 * L][lane] : 0.0;
+        const double p = live ? (double)sh[2 * L * SL + lane] : 0.0;
         if (live) prec[col0 + c] = p > 0.0 ? p : 0.0;
         const bool fb = live && (p < lo || p > hi);
         const int slot = wave_append(fb, cnt);
@@ -227,6 +266,26 @@ __global__ void k_zero_int(int *p) {
 }
 
 unsigned nb(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+bool al16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+size_t pack_lds(int w) { return (size_t)w * (TC + 1) * sizeof(float); }
+size_t unpack_lds(int L) { return (size_t)(2 * L + 1) * (TC + 1) * sizeof(float); }
+
+// Allows `bytes` of dynamic LDS for `fn` on the current device (above 64 KiB a function attribute
+// must be raised; done once per device and kernel).
+int lds_limit(const void *fn, size_t bytes) {
+    if (bytes <= 65536) return CONV_OK;
+    static std::mutex mu;
+    static std::set<std::pair<int, const void *>> done;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return CONV_EHIP;
+    std::lock_guard<std::mutex> g(mu);
+    if (done.count({dev, fn})) return CONV_OK;
+    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) != hipSuccess)
+        return CONV_EHIP;
+    done.insert({dev, fn});
+    return CONV_OK;
+}
 size_t al(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct SLayout {
@@ -298,8 +357,10 @@ int surr_pack_inputs_raw(const conv_state_t *s, int32_t nlev, int64_t ncol, int3
         return CONV_EINVAL;
     if (ncol == 0) return CONV_OK;
     StateArgs a{s->T, s->q, s->p_mid, s->ld};
-    hipLaunchKernelGGL(k_pack_in, dim3(nb(ncol, TC)), dim3(TB), 0, (hipStream_t)stream, a, nlev, ncol,
-                       w_in, 0, (const float *)nullptr, (const float *)nullptr, out, (uint16_t *)nullptr);
+    if (lds_limit((const void *)k_pack_in, pack_lds(w_in)) != CONV_OK) return CONV_EHIP;
+    hipLaunchKernelGGL(k_pack_in, dim3(nb(ncol, TC)), dim3(TB), pack_lds(w_in), (hipStream_t)stream, a,
+                       nlev, ncol, w_in, 0, (const float *)nullptr, (const float *)nullptr, out,
+                       (uint16_t *)nullptr, (int)(w_in % 4 == 0 && al16(out)));
     return hip_err();
 }
 
@@ -310,8 +371,10 @@ int surr_pack_inputs(const conv_state_t *s, int32_t nlev, int64_t ncol, int32_t 
         return CONV_EINVAL;
     if (ncol == 0) return CONV_OK;
     StateArgs a{s->T, s->q, s->p_mid, s->ld};
-    hipLaunchKernelGGL(k_pack_in, dim3(nb(ncol, TC)), dim3(TB), 0, (hipStream_t)stream, a, nlev, ncol,
-                       w_in, 1, mean, std, (float *)nullptr, x);
+    if (lds_limit((const void *)k_pack_in, pack_lds(w_in)) != CONV_OK) return CONV_EHIP;
+    hipLaunchKernelGGL(k_pack_in, dim3(nb(ncol, TC)), dim3(TB), pack_lds(w_in), (hipStream_t)stream, a,
+                       nlev, ncol, w_in, 1, mean, std, (float *)nullptr, x,
+                       (int)(w_in % 8 == 0 && al16(x)));
     return hip_err();
 }
 
@@ -431,17 +494,21 @@ int surr_infer(surr_t *s, const conv_state_t *state, int64_t ncol, double *dTdt,
     float *Y = (float *)(s->ws + s->lay.y);
     int *list = (int *)(s->ws + s->lay.list);
     int *cnt = (int *)(s->ws + s->lay.cnt);
+    if (lds_limit((const void *)k_pack_in, pack_lds(s->w_in)) != CONV_OK ||
+        lds_limit((const void *)k_unpack, unpack_lds(L)) != CONV_OK)
+        return CONV_EHIP;
     hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, cnt);
     for (int64_t c0 = 0; c0 < ncol; c0 += s->chunk) {
         const int64_t n = ncol - c0 < s->chunk ? ncol - c0 : s->chunk;
         StateArgs a{state->T + c0, state->q + c0, state->p_mid + c0, ld};
-        hipLaunchKernelGGL(k_pack_in, dim3(nb(n, TC)), dim3(TB), 0, st, a, L, n, s->w_in, 1,
-                           (const float *)nrm(s, 0), (const float *)nrm(s, 1), (float *)nullptr, X);
+        hipLaunchKernelGGL(k_pack_in, dim3(nb(n, TC)), dim3(TB), pack_lds(s->w_in), st, a, L, n,
+                           s->w_in, 1, (const float *)nrm(s, 0), (const float *)nrm(s, 1),
+                           (float *)nullptr, X, (int)(s->w_in % 8 == 0));
         const int rc = mlp_forward(s->net, X, Y, n, 0, stream);
         if (rc != MLP_OK) return rc == MLP_EINVAL ? CONV_EINVAL : CONV_EHIP;
-        hipLaunchKernelGGL(k_unpack, dim3(nb(n, TC)), dim3(TB), 0, st, (const float *)Y, L, n, s->w_out,
-                           (const float *)nrm(s, 2), (const float *)nrm(s, 3), s->lo, s->hi, dTdt, dqdt,
-                           prec, ld, c0, list, cnt);
+        hipLaunchKernelGGL(k_unpack, dim3(nb(n, TC)), dim3(TB), unpack_lds(L), st, (const float *)Y, L,
+                           n, s->w_out, (const float *)nrm(s, 2), (const float *)nrm(s, 3), s->lo,
+                           s->hi, dTdt, dqdt, prec, ld, c0, list, cnt, (int)(s->w_out % 4 == 0));
     }
     if (hip_err() != CONV_OK) return CONV_EHIP;
     if (!fallback) return CONV_OK;
