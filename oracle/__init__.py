@@ -131,6 +131,14 @@ def lib():
         L.oracle_deep_column_jvp.argtypes = ([C.c_int, C.POINTER(Params)] + [dp] * 5 +
                                              [C.c_double, C.c_double, dp, dp, C.c_double,
                                               C.c_double, dp, dp, dp])
+        L.oracle_shallow_column_jvp.restype = C.c_int
+        L.oracle_shallow_column_jvp.argtypes = ([C.c_int, C.POINTER(Params)] + [dp] * 5 +
+                                                [C.c_double] * 4 + [dp, dp, C.c_double,
+                                                                    C.c_double, dp, dp, dp])
+        L.oracle_step_column_jvp.restype = C.c_int
+        L.oracle_step_column_jvp.argtypes = ([C.c_int, C.POINTER(Params)] + [dp] * 5 +
+                                             [C.c_double] * 4 + [dp] * 5 +
+                                             [C.POINTER(C.c_int32)])
         _lib = L
     return _lib
 
@@ -296,6 +304,45 @@ def deep_column_jvp(col: dict, dT, dq, dtau=0.0, deps=0.0, params: Params | None
                                       _ptr(dT), _ptr(dq), float(dtau), float(deps), _ptr(tT),
                                       _ptr(tq), C.byref(tp))
     return dict(dTdt=tT, dqdt=tq, prec=tp.value, status=st)
+
+
+def shallow_column_jvp(col: dict, dT, dq, deps_sh=0.0, ddelta_sh=0.0,
+                       params: Params | None = None):
+    """Forward-mode tangent of the shallow scheme's (dTdt, dqdt, prec) along (dT, dq, d eps_sh,
+    d delta_sh), every integer decision of the run held fixed."""
+    params = params or make_params()
+    L = len(col["T"])
+    T, q, pm, pi, z = (_c64(col[k]) for k in ("T", "q", "p_mid", "p_int", "z"))
+    dT, dq = _c64(dT), _c64(dq)
+    tT, tq = np.zeros(L), np.zeros(L)
+    tp = C.c_double(0.0)
+    st = lib().oracle_shallow_column_jvp(L, C.byref(params), _ptr(T), _ptr(q), _ptr(pm), _ptr(pi),
+                                         _ptr(z), col.get("phis", 0.0), col.get("pblh", 800.0),
+                                         col.get("tke", 1.0), col.get("dt", 1800.0), _ptr(dT),
+                                         _ptr(dq), float(deps_sh), float(ddelta_sh), _ptr(tT),
+                                         _ptr(tq), C.byref(tp))
+    return dict(dTdt=tT, dqdt=tq, prec=tp.value, status=st)
+
+
+def step_column_jvp(col: dict, dT, dq, dpar=(0.0, 0.0, 0.0, 0.0), params: Params | None = None):
+    """Forward-mode tangent of one column of the step (deep, state update, shallow) along
+    (dT, dq) and the parameter tangents dpar = (d tau, d eps_deep, d eps_sh, d delta_sh).
+    Returns {"deep": {dTdt, dqdt, prec}, "shallow": {...}, "status": (deep, shallow)}."""
+    params = params or make_params()
+    L = len(col["T"])
+    T, q, pm, pi, z = (_c64(col[k]) for k in ("T", "q", "p_mid", "p_int", "z"))
+    dT, dq, dp_ = _c64(dT), _c64(dq), _c64(dpar)
+    td, ts = np.zeros(2 * L + 1), np.zeros(2 * L + 1)
+    status = np.zeros(2, dtype=np.int32)
+    rc = lib().oracle_step_column_jvp(L, C.byref(params), _ptr(T), _ptr(q), _ptr(pm), _ptr(pi),
+                                      _ptr(z), col.get("phis", 0.0), col.get("pblh", 800.0),
+                                      col.get("tke", 1.0), col.get("dt", 1800.0), _ptr(dT),
+                                      _ptr(dq), _ptr(dp_), _ptr(td), _ptr(ts),
+                                      status.ctypes.data_as(C.POINTER(C.c_int32)))
+    if rc != 0:
+        raise ValueError("oracle_step_column_jvp: bad arguments")
+    split = lambda t: dict(dTdt=t[:L], dqdt=t[L:2 * L], prec=float(t[2 * L]))
+    return dict(deep=split(td), shallow=split(ts), status=(int(status[0]), int(status[1])))
 
 
 def es(T: float) -> float:

@@ -412,10 +412,13 @@ template <class R> struct ShallowRes {
 // `state_checked`: the column's validity (C0) was already decided on the input state of the step;
 // the deep-updated state of a valid column is not re-validated (its humidity can sit a rounding
 // error below zero where the deep limiter binds).
+// The mixing rates eps_sh and delta_sh are passed separately (as R) so that the forward-mode
+// derivative can carry tangents along them.
 template <class R>
-void shallow_column(int L, const oracle_params_t &P, const R *T, const R *q, const double *pm,
-                    const double *pi, const double *z, double phis, double pblh, double tke,
-                    double dt, ShallowRes<R> &o, bool state_checked = false) {
+void shallow_column(int L, const oracle_params_t &P, const R &eps_sh, const R &delta_sh,
+                    const R *T, const R *q, const double *pm, const double *pi, const double *z,
+                    double phis, double pblh, double tke, double dt, ShallowRes<R> &o,
+                    bool state_checked = false) {
     o.dTdt.assign(L, R(0.0));
     o.dqdt.assign(L, R(0.0));
     o.mu.assign(L + 1, R(0.0));
@@ -511,8 +514,8 @@ void shallow_column(int L, const oracle_params_t &P, const R *T, const R *q, con
     R w2 = sigw2 + 2.0 * P.a_buoy * cin;
     int kt = -1;
     for (int k = ks - 1; k >= 0; --k) {
-        R E = P.eps_sh * eta[k + 1] * g.dz[k];
-        R D = P.delta_sh * eta[k + 1] * g.dz[k];
+        R E = eps_sh * eta[k + 1] * g.dz[k];
+        R D = delta_sh * eta[k + 1] * g.dz[k];
         R en = eta[k + 1] + E - D;
         if (pi[k] < P.p_sh_top_min || k == 0 || !(val(en) > 0.0)) {
             kt = k;
@@ -527,7 +530,7 @@ void shallow_column(int L, const oracle_params_t &P, const R *T, const R *q, con
         R Trho = pt.T * (1.0 + CVIR * pt.qv - (ql - r));
         R Tve = tv_(T[k], q[k]);
         R Bk = GRAV * (Trho - Tve) / Tve;
-        R w2n = w2 + 2.0 * g.dz[k] * (P.a_buoy * Bk - P.b_drag * P.eps_sh * w2);
+        R w2n = w2 + 2.0 * g.dz[k] * (P.a_buoy * Bk - P.b_drag * eps_sh * w2);
         if (!(val(w2n) > 0.0)) {
             kt = k;
             break;
@@ -659,11 +662,13 @@ void step_one(int L, const oracle_params_t *p, const oracle_state_t *s, int64_t 
     // the shallow scheme too; a valid one stays valid after the deep update.
     ShallowRes<double> sh;
     if (d.status == 3)
-        shallow_column<double>(L, *p, col.T.data(), col.q.data(), col.pm.data(), col.pi.data(),
-                               col.z.data(), col.phis, col.pblh, col.tke, s->dt, sh);
+        shallow_column<double>(L, *p, p->eps_sh, p->delta_sh, col.T.data(), col.q.data(),
+                               col.pm.data(), col.pi.data(), col.z.data(), col.phis, col.pblh,
+                               col.tke, s->dt, sh);
     else
-        shallow_column<double>(L, *p, T2.data(), q2.data(), col.pm.data(), col.pi.data(),
-                               col.z.data(), col.phis, col.pblh, col.tke, s->dt, sh, true);
+        shallow_column<double>(L, *p, p->eps_sh, p->delta_sh, T2.data(), q2.data(), col.pm.data(),
+                               col.pi.data(), col.z.data(), col.phis, col.pblh, col.tke, s->dt, sh,
+                               true);
     scatter_shallow(sh, L, s->ld, c, os);
 }
 
@@ -693,8 +698,9 @@ int oracle_shallow(int64_t ncol, int nlev, const oracle_params_t *p, const oracl
     for (int64_t c = 0; c < ncol; ++c) {
         gather(s, nlev, c, col);
         ShallowRes<double> r;
-        shallow_column<double>(nlev, *p, col.T.data(), col.q.data(), col.pm.data(), col.pi.data(),
-                               col.z.data(), col.phis, col.pblh, col.tke, s->dt, r);
+        shallow_column<double>(nlev, *p, p->eps_sh, p->delta_sh, col.T.data(), col.q.data(),
+                               col.pm.data(), col.pi.data(), col.z.data(), col.phis, col.pblh,
+                               col.tke, s->dt, r);
         scatter_shallow(r, nlev, s->ld, c, o);
     }
     return 0;
@@ -762,7 +768,8 @@ int oracle_shallow_column(int nlev, const oracle_params_t *p, const double *T, c
                           double *mu, double *prec, oracle_shallow_diag_t *diag) {
     if (nlev < 2 || !p) return -1;
     ShallowRes<double> r;
-    shallow_column<double>(nlev, *p, T, q, p_mid, p_int, z, phis, pblh, tke, dt, r);
+    shallow_column<double>(nlev, *p, p->eps_sh, p->delta_sh, T, q, p_mid, p_int, z, phis, pblh,
+                           tke, dt, r);
     for (int k = 0; k < nlev; ++k) {
         if (dTdt) dTdt[k] = r.dTdt[k];
         if (dqdt) dqdt[k] = r.dqdt[k];
@@ -836,6 +843,71 @@ int oracle_deep_column_jvp(int nlev, const oracle_params_t *p, const double *T, 
     }
     *t_prec = d.prec.d;
     return d.status;
+}
+
+int oracle_shallow_column_jvp(int nlev, const oracle_params_t *p, const double *T,
+                              const double *q, const double *p_mid, const double *p_int,
+                              const double *z, double phis, double pblh, double tke, double dt,
+                              const double *dT, const double *dq, double deps_sh,
+                              double ddelta_sh, double *t_dTdt, double *t_dqdt, double *t_prec) {
+    if (nlev < 2 || !p) return -1;
+    std::vector<Dual> Td(nlev), qd(nlev);
+    for (int k = 0; k < nlev; ++k) {
+        Td[k] = Dual(T[k], dT ? dT[k] : 0.0);
+        qd[k] = Dual(q[k], dq ? dq[k] : 0.0);
+    }
+    ShallowRes<Dual> r;
+    shallow_column<Dual>(nlev, *p, Dual(p->eps_sh, deps_sh), Dual(p->delta_sh, ddelta_sh),
+                         Td.data(), qd.data(), p_mid, p_int, z, phis, pblh, tke, dt, r);
+    for (int k = 0; k < nlev; ++k) {
+        t_dTdt[k] = r.dTdt[k].d;
+        t_dqdt[k] = r.dqdt[k].d;
+    }
+    *t_prec = r.prec.d;
+    return r.status;
+}
+
+// One column of the step (deep, the state update T + dt dTdt, q + dt dqdt, shallow on the
+// updated state: Algorithm 1 order) with the tangent carried through all three.
+int oracle_step_column_jvp(int nlev, const oracle_params_t *p, const double *T, const double *q,
+                           const double *p_mid, const double *p_int, const double *z, double phis,
+                           double pblh, double tke, double dt, const double *dT, const double *dq,
+                           const double *dpar, double *t_deep, double *t_shallow,
+                           int32_t *status) {
+    if (nlev < 2 || !p || !dpar || !t_deep || !t_shallow || !status) return -1;
+    const int L = nlev;
+    std::vector<Dual> Td(L), qd(L);
+    for (int k = 0; k < L; ++k) {
+        Td[k] = Dual(T[k], dT ? dT[k] : 0.0);
+        qd[k] = Dual(q[k], dq ? dq[k] : 0.0);
+    }
+    DeepRes<Dual> d;
+    deep_column<Dual>(L, *p, Dual(p->tau, dpar[0]), Dual(p->eps_deep, dpar[1]), Td.data(),
+                      qd.data(), p_mid, p_int, z, phis, dt, d);
+    std::vector<Dual> T2(L), q2(L);
+    for (int k = 0; k < L; ++k) {
+        T2[k] = Td[k] + dt * d.dTdt[k];
+        q2[k] = qd[k] + dt * d.dqdt[k];
+    }
+    ShallowRes<Dual> sh;
+    const Dual es(p->eps_sh, dpar[2]), ds(p->delta_sh, dpar[3]);
+    if (d.status == 3)
+        shallow_column<Dual>(L, *p, es, ds, Td.data(), qd.data(), p_mid, p_int, z, phis, pblh,
+                             tke, dt, sh);
+    else
+        shallow_column<Dual>(L, *p, es, ds, T2.data(), q2.data(), p_mid, p_int, z, phis, pblh,
+                             tke, dt, sh, true);
+    for (int k = 0; k < L; ++k) {
+        t_deep[k] = d.dTdt[k].d;
+        t_deep[L + k] = d.dqdt[k].d;
+        t_shallow[k] = sh.dTdt[k].d;
+        t_shallow[L + k] = sh.dqdt[k].d;
+    }
+    t_deep[2 * L] = d.prec.d;
+    t_shallow[2 * L] = sh.prec.d;
+    status[0] = d.status;
+    status[1] = sh.status;
+    return 0;
 }
 
 double oracle_es(double T) { return es_(T); }

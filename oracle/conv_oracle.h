@@ -97,6 +97,26 @@ int oracle_deep_column_jvp(int nlev, const oracle_params_t *p, const double *T, 
                            double dt, const double *dT, const double *dq, double dtau, double deps,
                            double *t_dTdt, double *t_dqdt, double *t_prec);
 
+/* Forward-mode derivative of the shallow scheme (S1-S9) of one column along (dT, dq, d eps_sh,
+ * d delta_sh), with every integer decision of the run held fixed: source layers, lifting
+ * condensation and free-convection levels, the levels counted in CIN, saturation and rain-out
+ * flags, the plume top and the base-flux branch with its limiting layer.  Returns the status. */
+int oracle_shallow_column_jvp(int nlev, const oracle_params_t *p, const double *T,
+                              const double *q, const double *p_mid, const double *p_int,
+                              const double *z, double phis, double pblh, double tke, double dt,
+                              const double *dT, const double *dq, double deps_sh,
+                              double ddelta_sh, double *t_dTdt, double *t_dqdt, double *t_prec);
+
+/* Forward-mode derivative of one column of the step: deep scheme, state update, shallow scheme on
+ * the updated state (Algorithm 1).  dpar[4] = tangents of (tau, eps_deep, eps_sh, delta_sh);
+ * t_deep and t_shallow [2*nlev+1] receive the tangents of (dTdt, dqdt, prec) of each scheme;
+ * status[2] the deep and shallow statuses.  Returns 0, or -1 on bad arguments. */
+int oracle_step_column_jvp(int nlev, const oracle_params_t *p, const double *T, const double *q,
+                           const double *p_mid, const double *p_int, const double *z, double phis,
+                           double pblh, double tke, double dt, const double *dT, const double *dq,
+                           const double *dpar, double *t_deep, double *t_shallow,
+                           int32_t *status);
+
 /* Thermodynamics (C1 of the scheme). */
 double oracle_es(double T);
 double oracle_qs(double T, double p);

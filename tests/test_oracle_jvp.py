@@ -99,3 +99,116 @@ def test_tau_tangent_vanishes_where_the_limiter_sets_the_base_flux():
             r = oracle.deep_column(col, p)
             assert np.allclose(j["dTdt"], -r["dTdt"] / p.tau, rtol=1e-12, atol=1e-30)
     assert hits > 0
+
+
+# ------------------------------------------------------------------ shallow scheme and the step
+# The same pin for the shallow scheme's tangent (S1-S9, decisions fixed) and for the step's
+# (deep, the state update, shallow on the updated state): a central difference of the oracle's own
+# forward scheme along a random direction in (T, q) and the mixing parameters.  Two things make
+# these outputs harder to difference than the deep ones: the shallow base flux carries
+# exp(-a CIN / sigma_w^2), which with sigma_w^2 down to 0.1 m2 s-2 is strongly curved along the
+# direction, and the source layer's tendencies are differences of nearly equal fluxes, which
+# amplifies the forward run's rounding.  The step h = 1e-5 balances the two: with the curvature
+# filter below (second difference under 1e-3 of the first) the truncation error is below ~2e-7 of
+# the block's largest tangent, and the measured rounding error (which grows as 1/h) below ~1e-6.
+# A dropped term or a wrong sign still shows as an O(1) mismatch against the 2e-6 bound.
+H_SH = 1e-5
+TOL_SH = 2e-6
+
+@pytest.fixture(scope="module")
+def grid1():
+    st = S.grid_1deg()
+    osh = oracle.shallow(st)
+    od, ostep = oracle.step(st, threads=8, chunk=16)
+    return st, np.nonzero(osh["status"] == 0)[0], od, ostep
+
+
+def _sh_fwd(col, T, q, eps_sh, delta_sh):
+    c = dict(col)
+    c["T"], c["q"] = T, q
+    r = oracle.shallow_column(c, oracle.make_params(eps_sh=eps_sh, delta_sh=delta_sh))
+    d = r["diag"]
+    return _flat(r), (d["ks"], d["klcl"], d["klfc"], d["kt"], d["status"])
+
+
+def test_shallow_tangent_matches_central_difference(grid1):
+    st, act, _, _ = grid1
+    rng = np.random.default_rng(11)
+    p = oracle.make_params()
+    checked = 0
+    for c in act[:64]:
+        col = oracle.column(st, int(c))
+        L = len(col["T"])
+        dT, dq = rng.standard_normal(L), rng.standard_normal(L) * 1e-2 * col["q"]
+        de, dd = rng.standard_normal() * 1e-5, rng.standard_normal() * 1e-5
+        j = _flat(oracle.shallow_column_jvp(col, dT, dq, de, dd))
+        h = H_SH
+        f0, i0 = _sh_fwd(col, col["T"], col["q"], p.eps_sh, p.delta_sh)
+        fp, ip = _sh_fwd(col, col["T"] + h * dT, col["q"] + h * dq, p.eps_sh + h * de,
+                         p.delta_sh + h * dd)
+        fm, im = _sh_fwd(col, col["T"] - h * dT, col["q"] - h * dq, p.eps_sh - h * de,
+                         p.delta_sh - h * dd)
+        scale = np.abs(j).max()
+        assert scale > 0.0
+        smooth = ip == i0 == im and np.abs((fp - f0) - (f0 - fm)).max() / h < 1e-3 * scale
+        if not smooth:
+            continue
+        fd = (fp - fm) / (2 * h)
+        assert np.abs(fd - j).max() <= TOL_SH * scale, int(c)
+        checked += 1
+    assert checked >= 40
+
+
+def _column_state(col, T, q):
+    """A one-column level-major state for the oracle's step driver."""
+    a = lambda v: np.asarray(v, dtype=np.float64).reshape(-1, 1).copy()
+    return dict(T=a(T), q=a(q), p_mid=a(col["p_mid"]), p_int=a(col["p_int"]), z=a(col["z"]),
+                phis=np.array([col["phis"]]), pblh=np.array([col["pblh"]]),
+                tke=np.array([col["tke"]]), dt=col["dt"], ncol=1)
+
+
+def _step_fwd(col, T, q, par):
+    p = oracle.make_params(tau=par[0], eps_deep=par[1], eps_sh=par[2], delta_sh=par[3])
+    od, osh = oracle.step(_column_state(col, T, q), p)
+    f = np.concatenate([od["dTdt"][:, 0], od["dqdt"][:, 0] * 1e3, [od["prec"][0] * 1e3],
+                        osh["dTdt"][:, 0], osh["dqdt"][:, 0] * 1e3, [osh["prec"][0] * 1e3]])
+    ints = (int(od["klaunch"][0]), int(od["ktop"][0]), int(od["status"][0]),
+            int(osh["kbase"][0]), int(osh["ktop"][0]), int(osh["status"][0]))
+    return f, ints
+
+
+def test_step_tangent_matches_central_difference(grid1):
+    st, _, od, ostep = grid1
+    both = np.nonzero((ostep["status"] == 0))[0]
+    deep_only = np.nonzero((od["status"] == 0) & (ostep["status"] != 0))[0]
+    rng = np.random.default_rng(12)
+    p = oracle.make_params()
+    par0 = np.array([p.tau, p.eps_deep, p.eps_sh, p.delta_sh])
+    h = H_SH
+    L = st["T"].shape[0]
+    blocks = (slice(0, 2 * L + 1), slice(2 * L + 1, 4 * L + 2))  # deep outputs, shallow outputs
+    checked = {0: 0, 1: 0}
+    for c in list(both[:48]) + list(deep_only[:16]):
+        col = oracle.column(st, int(c))
+        dT, dq = rng.standard_normal(L), rng.standard_normal(L) * 1e-2 * col["q"]
+        dpar = rng.standard_normal(4) * np.array([36.0, 1e-6, 1e-5, 1e-5])
+        r = oracle.step_column_jvp(col, dT, dq, dpar)
+        j = np.concatenate([_flat(r["deep"]), _flat(r["shallow"])])
+        f0, i0 = _step_fwd(col, col["T"], col["q"], par0)
+        fp, ip = _step_fwd(col, col["T"] + h * dT, col["q"] + h * dq, par0 + h * dpar)
+        fm, im = _step_fwd(col, col["T"] - h * dT, col["q"] - h * dq, par0 - h * dpar)
+        assert r["status"] == (i0[2], i0[5])
+        if not ip == i0 == im:
+            continue
+        for b, sl in enumerate(blocks):
+            scale = np.abs(j[sl]).max()
+            if scale == 0.0:
+                assert np.all(fp[sl] == f0[sl]) and np.all(fm[sl] == f0[sl])
+                continue
+            curv = np.abs((fp[sl] - f0[sl]) - (f0[sl] - fm[sl])).max() / h
+            if curv >= 1e-3 * scale:
+                continue
+            fd = (fp[sl] - fm[sl]) / (2 * h)
+            assert np.abs(fd - j[sl]).max() <= TOL_SH * scale, (int(c), b)
+            checked[b] += 1
+    assert checked[0] >= 40 and checked[1] >= 30, checked
