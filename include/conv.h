@@ -138,7 +138,8 @@ typedef struct {
     double *g_params;  /* [2]         dL/dtau, dL/deps_deep summed over columns */
 } conv_deep_grad_t;
 
-/* Device workspace (bytes) conv_deep_backward needs for a context over (ncol, nlev) and state
+/* Device workspace (bytes) the backward calls (conv_deep_backward, conv_shallow_backward,
+ * conv_step_backward) need for a context over (ncol, nlev) and state
  * arrays of leading dimension ld. */
 size_t conv_backward_workspace_bytes(int64_t ncol, int32_t nlev, int64_t ld);
 
@@ -154,6 +155,51 @@ size_t conv_backward_workspace_bytes(int64_t ncol, int32_t nlev, int64_t ld);
  * workspace.  The paper's deep convection (Algorithm 2) is the forward this differentiates. */
 int conv_deep_backward(conv_ctx_t *ctx, const conv_state_t *state, const conv_deep_out_t *fwd,
                        const conv_deep_cot_t *cot, conv_deep_grad_t *grad, void *workspace,
+                       size_t ws_bytes, void *stream);
+
+/* Cotangents of the shallow scheme's outputs (device [nlev][ld] / [ld]; any may be NULL = 0) and
+ * the gradients of its adjoint (g_T, g_q [nlev][ld], written for every column 0..ncol-1;
+ * g_params: device double[2] = dL/d eps_sh, dL/d delta_sh). */
+typedef struct {
+    const double *g_dTdt, *g_dqdt, *g_prec;
+} conv_shallow_cot_t;
+typedef struct {
+    double *g_T, *g_q;
+    double *g_params;
+} conv_shallow_grad_t;
+
+/* Hand-written adjoint of the shallow scheme (steps S1-S9) alone: the gradient of
+ * L = sum(g_dTdt*dTdt) + sum(g_dqdt*dqdt) + sum(g_prec*prec) over conv_shallow_forward's outputs with
+ * respect to its input T, q and the mixing rates eps_sh, delta_sh, through the branch the forward
+ * run took (source layers, lifting-condensation and free-convection levels, the levels counted in
+ * CIN, saturation and rain-out flags, plume top, base-flux branch and limiting layer held fixed).
+ * `fwd` must hold the status, kbase and ktop outputs of conv_shallow_forward on the same state and
+ * parameters; everything else is recomputed per column.  Columns whose shallow status is not 0 get
+ * zero gradients.  Workspace as for conv_deep_backward.  The paper's shallow convection
+ * (Algorithm 3) is the forward this differentiates. */
+int conv_shallow_backward(conv_ctx_t *ctx, const conv_state_t *state,
+                          const conv_shallow_out_t *fwd, const conv_shallow_cot_t *cot,
+                          conv_shallow_grad_t *grad, void *workspace, size_t ws_bytes,
+                          void *stream);
+
+/* Gradients of the adjoint of a whole step: g_T, g_q [nlev][ld] for every column; g_params: device
+ * double[4] = dL/d tau, dL/d eps_deep, dL/d eps_sh, dL/d delta_sh. */
+typedef struct {
+    double *g_T, *g_q;
+    double *g_params;
+} conv_step_grad_t;
+
+/* Hand-written adjoint of conv_step (Algorithm 1 order: deep, the state update T' = T + dt*dTdt,
+ * q' = q + dt*dqdt, shallow on the updated state): the gradient of a loss with cotangents on both
+ * schemes' outputs (`dcot`, `scot`; any array may be NULL) with respect to T, q and the four
+ * parameters.  The shallow adjoint runs first, at the updated state; its gradient is then carried
+ * through the update (identity plus dt times the deep tendencies' cotangent) into the deep
+ * adjoint.  Branches are held fixed as for the two schemes' adjoints.  `dfwd` and `sfwd` must hold
+ * the outputs of conv_step on the same state and parameters (status, klaunch, ktop, dTdt, dqdt of
+ * the deep scheme; status, kbase, ktop of the shallow one).  Workspace as for conv_deep_backward. */
+int conv_step_backward(conv_ctx_t *ctx, const conv_state_t *state, const conv_deep_out_t *dfwd,
+                       const conv_shallow_out_t *sfwd, const conv_deep_cot_t *dcot,
+                       const conv_shallow_cot_t *scot, conv_step_grad_t *grad, void *workspace,
                        size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------------- batched ensemble

@@ -29,7 +29,8 @@ EXPORTS = ("conv_workspace_bytes", "conv_create", "conv_set_params", "conv_destr
            "conv_deep_forward", "conv_shallow_forward", "conv_step", "conv_set_launch",
            "conv_get_launch", "conv_timing_start",
            "conv_timing_read", "conv_strerror", "conv_last_hip_error",
-           "conv_backward_workspace_bytes", "conv_deep_backward", "conv_autotune",
+           "conv_backward_workspace_bytes", "conv_deep_backward", "conv_shallow_backward",
+           "conv_step_backward", "conv_autotune",
            "conv_ensemble_workspace_bytes", "conv_ensemble_create", "conv_ensemble_destroy",
            "conv_ensemble_step", "conv_ensemble_set_launch", "conv_ensemble_get_launch",
            "conv_ensemble_autotune", "conv_ensemble_capture", "conv_ensemble_replay",
@@ -67,6 +68,11 @@ class DeepCot(C.Structure):
 
 class DeepGrad(C.Structure):
     _fields_ = [(n, C.c_void_p) for n in ("g_T", "g_q", "g_params")]
+
+
+ShallowCot = DeepCot    # {g_dTdt, g_dqdt, g_prec}: the same three device pointers
+ShallowGrad = DeepGrad  # {g_T, g_q, g_params}; g_params has 2 entries (eps_sh, delta_sh)
+StepGrad = DeepGrad     # {g_T, g_q, g_params}; g_params has 4 entries
 
 
 class Member(C.Structure):
@@ -112,6 +118,15 @@ def lib():
         L.conv_timing_read.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int)]
         L.conv_backward_workspace_bytes.restype = C.c_size_t
         L.conv_backward_workspace_bytes.argtypes = [C.c_int64, C.c_int32, C.c_int64]
+        L.conv_shallow_backward.restype = C.c_int
+        L.conv_shallow_backward.argtypes = [C.c_void_p, C.POINTER(State), C.POINTER(ShallowOut),
+                                            C.POINTER(ShallowCot), C.POINTER(ShallowGrad),
+                                            C.c_void_p, C.c_size_t, C.c_void_p]
+        L.conv_step_backward.restype = C.c_int
+        L.conv_step_backward.argtypes = [C.c_void_p, C.POINTER(State), C.POINTER(DeepOut),
+                                         C.POINTER(ShallowOut), C.POINTER(DeepCot),
+                                         C.POINTER(ShallowCot), C.POINTER(StepGrad), C.c_void_p,
+                                         C.c_size_t, C.c_void_p]
         L.conv_deep_backward.restype = C.c_int
         L.conv_deep_backward.argtypes = [C.c_void_p, C.POINTER(State), C.POINTER(DeepOut),
                                          C.POINTER(DeepCot), C.POINTER(DeepGrad), C.c_void_p,
@@ -354,13 +369,8 @@ class Conv:
               "conv_step")
         return deep, shallow
 
-    def deep_backward(self, s: dict, fwd: dict, g_dTdt=None, g_dqdt=None, g_prec=None):
-        """Adjoint of deep_forward at state `s` (with `fwd` its outputs): returns dict(g_T, g_q,
-        g_tau, g_eps) for the cotangents given (None = zero)."""
+    def _cotangents(self, ld, g_dTdt, g_dqdt, g_prec):
         torch = self.torch
-        st = self._state(s)
-        ld = st.ld
-        L = lib()
 
         def cot(a, shape):
             if a is None:
@@ -369,22 +379,68 @@ class Conv:
                 raise ValueError(f"cotangent: expected float64 {shape}")
             return a.contiguous()
 
-        cT = cot(g_dTdt, (self.nlev, ld))
-        cq = cot(g_dqdt, (self.nlev, ld))
-        cP = cot(g_prec, (ld,))
-        nbytes = L.conv_backward_workspace_bytes(self.ncol, self.nlev, ld)
+        return (cot(g_dTdt, (self.nlev, ld)), cot(g_dqdt, (self.nlev, ld)), cot(g_prec, (ld,)))
+
+    @staticmethod
+    def _cot_struct(cs):
+        return DeepCot(*[a.data_ptr() if a is not None else None for a in cs])
+
+    def _backward_workspace(self, ld):
+        nbytes = lib().conv_backward_workspace_bytes(self.ncol, self.nlev, ld)
         if nbytes == 0:
             raise ValueError("unsupported size")
         if getattr(self, "_bws", None) is None or self._bws.numel() < nbytes + 256:
-            self._bws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
-        wptr = (self._bws.data_ptr() + 255) & ~255
+            self._bws = self.torch.empty(nbytes + 256, dtype=self.torch.uint8, device=self.device)
+        return C.c_void_p((self._bws.data_ptr() + 255) & ~255), nbytes
+
+    def deep_backward(self, s: dict, fwd: dict, g_dTdt=None, g_dqdt=None, g_prec=None):
+        """Adjoint of deep_forward at state `s` (with `fwd` its outputs): returns dict(g_T, g_q,
+        g_tau, g_eps) for the cotangents given (None = zero)."""
+        st = self._state(s)
+        ld = st.ld
+        cs = self._cotangents(ld, g_dTdt, g_dqdt, g_prec)
+        wptr, nbytes = self._backward_workspace(ld)
         gT, gq, gp = self._f64(self.nlev, ld), self._f64(self.nlev, ld), self._f64(2)
-        c = DeepCot(*[a.data_ptr() if a is not None else None for a in (cT, cq, cP)])
+        c = self._cot_struct(cs)
         g = DeepGrad(gT.data_ptr(), gq.data_ptr(), gp.data_ptr())
         o = self._deep_struct(fwd)
-        check(L.conv_deep_backward(self.h, C.byref(st), C.byref(o), C.byref(c), C.byref(g),
-                                   C.c_void_p(wptr), nbytes, _stream(torch)), "conv_deep_backward")
+        check(lib().conv_deep_backward(self.h, C.byref(st), C.byref(o), C.byref(c), C.byref(g),
+                                       wptr, nbytes, _stream(self.torch)), "conv_deep_backward")
         return dict(g_T=gT, g_q=gq, g_tau=gp[0], g_eps=gp[1])
+
+    def shallow_backward(self, s: dict, fwd: dict, g_dTdt=None, g_dqdt=None, g_prec=None):
+        """Adjoint of shallow_forward at state `s` (with `fwd` its outputs): returns dict(g_T,
+        g_q, g_eps_sh, g_delta_sh) for the cotangents given (None = zero)."""
+        st = self._state(s)
+        ld = st.ld
+        cs = self._cotangents(ld, g_dTdt, g_dqdt, g_prec)
+        wptr, nbytes = self._backward_workspace(ld)
+        gT, gq, gp = self._f64(self.nlev, ld), self._f64(self.nlev, ld), self._f64(2)
+        c = self._cot_struct(cs)
+        g = ShallowGrad(gT.data_ptr(), gq.data_ptr(), gp.data_ptr())
+        o = self._shallow_struct(fwd)
+        check(lib().conv_shallow_backward(self.h, C.byref(st), C.byref(o), C.byref(c), C.byref(g),
+                                          wptr, nbytes, _stream(self.torch)),
+              "conv_shallow_backward")
+        return dict(g_T=gT, g_q=gq, g_eps_sh=gp[0], g_delta_sh=gp[1])
+
+    def step_backward(self, s: dict, deep: dict, shallow: dict, deep_cot=(None, None, None),
+                      shallow_cot=(None, None, None)):
+        """Adjoint of step at state `s` (with `deep`, `shallow` its outputs), for cotangents
+        (g_dTdt, g_dqdt, g_prec) of each scheme's outputs (None = zero): returns dict(g_T, g_q,
+        g_tau, g_eps, g_eps_sh, g_delta_sh)."""
+        st = self._state(s)
+        ld = st.ld
+        dc = self._cot_struct(self._cotangents(ld, *deep_cot))
+        sc = self._cot_struct(self._cotangents(ld, *shallow_cot))
+        wptr, nbytes = self._backward_workspace(ld)
+        gT, gq, gp = self._f64(self.nlev, ld), self._f64(self.nlev, ld), self._f64(4)
+        g = StepGrad(gT.data_ptr(), gq.data_ptr(), gp.data_ptr())
+        d, h = self._deep_struct(deep), self._shallow_struct(shallow)
+        check(lib().conv_step_backward(self.h, C.byref(st), C.byref(d), C.byref(h), C.byref(dc),
+                                       C.byref(sc), C.byref(g), wptr, nbytes, _stream(self.torch)),
+              "conv_step_backward")
+        return dict(g_T=gT, g_q=gq, g_tau=gp[0], g_eps=gp[1], g_eps_sh=gp[2], g_delta_sh=gp[3])
 
     def autotune(self, s: dict, deep: dict, shallow: dict, reps: int = 5, force: bool = False):
         """Pick the fastest persistent-grid shape for conv_step on these arrays (cached per
@@ -450,19 +506,56 @@ def _autograd():
             return (g["g_T"], g["g_q"], g["g_tau"].reshape(ctx.shapes[0]),
                     g["g_eps"].reshape(ctx.shapes[1]), None, None)
 
-    return DeepConv
+    class StepConv(torch.autograd.Function):
+        """(T, q, p) -> the deep and shallow (dTdt, dqdt, prec) of one step, p = (tau, eps_deep,
+        eps_sh, delta_sh) as a 4-vector, differentiable through conv_step_backward."""
+
+        @staticmethod
+        def forward(ctx, T, q, p4, conv, state):
+            import copy
+
+            p = copy.copy(conv.params)
+            p.tau, p.eps_deep, p.eps_sh, p.delta_sh = (float(v) for v in p4.detach().cpu())
+            conv.set_params(p)
+            s = dict(state)
+            s["T"], s["q"] = T.detach().contiguous(), q.detach().contiguous()
+            deep, shallow = conv.step(s)
+            ctx.conv, ctx.s, ctx.deep, ctx.shallow, ctx.params = conv, s, deep, shallow, p
+            ctx.pshape, ctx.pdevice = p4.shape, p4.device
+            return tuple(o[k].clone() for o in (deep, shallow) for k in ("dTdt", "dqdt", "prec"))
+
+        @staticmethod
+        def backward(ctx, gdT, gdq, gdP, gsT, gsq, gsP):
+            conv = ctx.conv
+            conv.set_params(ctx.params)
+            g = conv.step_backward(ctx.s, ctx.deep, ctx.shallow, (gdT, gdq, gdP), (gsT, gsq, gsP))
+            gp = torch.stack([g["g_tau"], g["g_eps"], g["g_eps_sh"], g["g_delta_sh"]])
+            return g["g_T"], g["g_q"], gp.reshape(ctx.pshape).to(ctx.pdevice), None, None
+
+    return DeepConv, StepConv
 
 
 _DeepConv = None
+_StepConv = None
 
 
 def deep_conv(conv: "Conv", state: dict, T, q, tau, eps_deep):
     """Differentiable deep convection: returns (dTdt, dqdt, prec); gradients flow to T, q and the
     0-d tensors tau, eps_deep through conv_deep_backward."""
-    global _DeepConv
+    global _DeepConv, _StepConv
     if _DeepConv is None:
-        _DeepConv = _autograd()
+        _DeepConv, _StepConv = _autograd()
     return _DeepConv.apply(T, q, tau, eps_deep, conv, state)
+
+
+def step_conv(conv: "Conv", state: dict, T, q, p4):
+    """Differentiable step (deep, state update, shallow): returns the deep (dTdt, dqdt, prec) and
+    the shallow (dTdt, dqdt, prec); gradients flow to T, q and the 4-vector p4 = (tau, eps_deep,
+    eps_sh, delta_sh) through conv_step_backward."""
+    global _DeepConv, _StepConv
+    if _StepConv is None:
+        _DeepConv, _StepConv = _autograd()
+    return _StepConv.apply(T, q, p4, conv, state)
 
 
 class Ensemble:

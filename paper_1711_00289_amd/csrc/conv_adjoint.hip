@@ -13,6 +13,12 @@
 //   (implicit derivative of the saturated inversion, dT/dH = 1/(cp + Lv qs')) -> flux-form
 //   tendencies -> downdraft strength alpha -> downdraft recurrence -> updraft recurrence -> h.
 // Outputs: dL/dT, dL/dq per level and dL/dtau, dL/deps_deep summed over columns in a fixed order.
+//
+// The shallow scheme (S1-S9, Algorithm 3) has an adjoint of the same shape (k_shallow_adjoint),
+// and the two compose into the adjoint of a whole step (Algorithm 1: deep, the state update
+// T' = T + dt dTdt, shallow on T'): the shallow adjoint runs first and yields dL/dT', which the
+// deep adjoint then carries through the update, as the identity plus dt times an extra cotangent
+// of the deep tendencies.
 #include "conv_internal.hpp"
 
 using namespace cvk;
@@ -38,6 +44,9 @@ struct AdjWork {
     int lmax;
     const double *cT, *cq, *cP;  // cotangents of dTdt, dqdt [nlev][ld] and prec [ld] (may be NULL)
     double *gT, *gq;             // [nlev][ld]
+    // Step mode: dL/dT', dL/dq' of the shallow scheme at the updated state (may alias gT, gq; NULL
+    // outside step mode).  They add dt*x to the tendencies' cotangents and x to the gradients.
+    const double *xT, *xq;
 };
 
 // Active (status 0) columns into a list; every other column gets zero gradients.
@@ -48,8 +57,8 @@ __global__ __launch_bounds__(BLOCK) void k_adj_compact(Member M, AdjWork w) {
     const bool act = live && M.dout.status[col] == 0;
     if (live && !act) {
         for (int k = 0; k < M.nlev; ++k) {
-            AT(w.gT, k) = 0.0;
-            AT(w.gq, k) = 0.0;
+            AT(w.gT, k) = w.xT ? AT(w.xT, k) : 0.0;
+            AT(w.gq, k) = w.xq ? AT(w.xq, k) : 0.0;
         }
         w.pgrad[col] = 0.0;
         w.pgrad[ld + col] = 0.0;
@@ -260,8 +269,8 @@ __global__ __launch_bounds__(BLOCK) void k_deep_adjoint(Member M, AdjWork w) {
         if (!(F > 0.0)) {
             // Not reachable for a status-0 column; no derivative there.
             for (int k = 0; k < L; ++k) {
-                AT(w.gT, k) = 0.0;
-                AT(w.gq, k) = 0.0;
+                AT(w.gT, k) = w.xT ? AT(w.xT, k) : 0.0;
+                AT(w.gq, k) = w.xq ? AT(w.xq, k) : 0.0;
             }
             w.pgrad[col] = 0.0;
             w.pgrad[ld + col] = 0.0;
@@ -277,8 +286,8 @@ __global__ __launch_bounds__(BLOCK) void k_deep_adjoint(Member M, AdjWork w) {
         // D10: outputs = M_b * unit profiles.
         double gMb = 0.0;
         for (int k = kt; k <= kb; ++k) {
-            const double cT = w.cT ? AT(w.cT, k) : 0.0;
-            const double cq = w.cq ? AT(w.cq, k) : 0.0;
+            const double cT = (w.cT ? AT(w.cT, k) : 0.0) + (w.xT ? dt * AT(w.xT, k) : 0.0);
+            const double cq = (w.cq ? AT(w.cq, k) : 0.0) + (w.xq ? dt * AT(w.xq, k) : 0.0);
             gMb += cT * S(X_DT1, k) + cq * S(X_DQ1, k);
             S(G_DT1, k) = cT * Mb;
             S(G_DQ1, k) = cq * Mb;
@@ -482,11 +491,379 @@ __global__ __launch_bounds__(BLOCK) void k_deep_adjoint(Member M, AdjWork w) {
 
         for (int k = 0; k < L; ++k) {
             const bool in = k >= kt && k <= kb;
-            AT(w.gT, k) = in ? S(G_T, k) : 0.0;
-            AT(w.gq, k) = in ? S(G_Q, k) : 0.0;
+            AT(w.gT, k) = (w.xT ? AT(w.xT, k) : 0.0) + (in ? S(G_T, k) : 0.0);
+            AT(w.gq, k) = (w.xq ? AT(w.xq, k) : 0.0) + (in ? S(G_Q, k) : 0.0);
         }
         w.pgrad[col] = gtau;
         w.pgrad[ld + col] = geps;
+    }
+#undef S
+}
+
+// ------------------------------------------------------------------ shallow scheme (S1-S9)
+// Per-level scratch of the shallow adjoint (index = level or interface).
+enum : int {
+    C_TP = 0, C_QP, C_Q1, C_FL,                            // S2-S5 scan levels: parcel, flags
+    W_ETA, W_HM, W_QM, W_QTU, W_TP, W_QP, W_Q1, W_FL,      // plume interfaces kt+1 .. ks
+    W_DT1, W_DQ1, W_GDT1, W_GDQ1,                          // unit tendencies and their adjoints
+    W_GT, W_GQ,                                            // dL/dT, dL/dq accumulators
+    N_SADJ
+};
+constexpr int FL_SAT = 1;   // the parcel is saturated
+constexpr int FL_AUX = 2;   // scan level: counted in CIN (B < 0); plume interface: rains out
+
+struct SAdjWork {
+    int *cnt;
+    int *list;
+    double *pgrad;  // [2][ld]: per-column dL/deps_sh, dL/ddelta_sh
+    double *scr;
+    int64_t stride;
+    int lmax;
+    const double *cT, *cq, *cP;  // cotangents of the shallow dTdt, dqdt, prec (may be NULL)
+    double *gT, *gq;             // dL/dT, dL/dq of the state the scheme saw [nlev][ld]
+    int upd;                     // the scheme saw T + dt*dTdt, q + dt*dqdt of M.dout (step)
+};
+
+// Shallow-active (status 0) columns into a list; every other column gets zero gradients.
+__global__ __launch_bounds__(BLOCK) void k_sadj_compact(Member M, SAdjWork w) {
+    const int64_t col = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    const bool live = col < M.ncol;
+    const int64_t ld = M.ld;
+    const bool act = live && M.sout.status[col] == 0;
+    if (live && !act) {
+        for (int k = 0; k < M.nlev; ++k) {
+            AT(w.gT, k) = 0.0;
+            AT(w.gq, k) = 0.0;
+        }
+        w.pgrad[col] = 0.0;
+        w.pgrad[ld + col] = 0.0;
+    }
+    const int slot = wave_append(act, &w.cnt[1]);
+    if (slot >= 0) w.list[slot] = (int)col;
+}
+
+// Adjoint of the parcel lift (C1) at a stored solution: with H the parcel's energy and qt its
+// water, a saturated parcel has cp T + Lv qs(T) = H (dT/dH = 1/(cp + Lv qs')), q_v = qs(T); an
+// unsaturated one T = (H - Lv qt)/cp, q_v = qt.  Adds to gH and gqt.
+__device__ __forceinline__ void lift_adjoint(bool sat, double Q1, double gTp, double gqv, double &gH,
+                                             double &gqt) {
+    if (sat) {
+        gH += (gTp + gqv * Q1) / (CP + LV * Q1);
+    } else {
+        gH += gTp * RCP_CP;
+        gqt += -LV * RCP_CP * gTp + gqv;
+    }
+}
+
+// Persistent over the shallow list.  Per column: recompute S1-S9 from the (possibly updated)
+// state with the forward run's source layer and plume top, storing what the reverse sweep needs;
+// then the reverse sweep: base flux (closure M_c or the humidity limiter) -> flux-form tendencies
+// -> plume recurrence (top interface first) -> the source's parcel -> M_c through rho_s and CIN ->
+// the source means.  The vertical-velocity equation only decides the plume top, which is held
+// fixed, so it carries no derivative.
+__global__ __launch_bounds__(BLOCK) void k_shallow_adjoint(Member M, SAdjWork w) {
+    const int n = w.cnt[1];
+    const int64_t gtid = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    const int64_t nthreads = (int64_t)gridDim.x * BLOCK;
+    const int L = M.nlev;
+    const int64_t ld = M.ld;
+    const conv_params_t &P = M.P;
+    const double dt = M.dt;
+    double *scr = w.scr;
+#define S(arr, lev) scr[((int64_t)(arr) * (w.lmax + 1) + (lev)) * w.stride + gtid]
+
+    for (int64_t slot = gtid; slot < n; slot += nthreads) {
+        const int64_t col = w.list[slot];
+        const int ks = M.sout.kbase[col], kt = M.sout.ktop[col];
+        const double phis = M.phis[col], tke = M.tke[col];
+        auto Tk = [&](int k) { return w.upd ? AT(M.T, k) + dt * AT(M.dout.dTdt, k) : AT(M.T, k); };
+        auto qk = [&](int k) { return w.upd ? AT(M.q, k) + dt * AT(M.dout.dqdt, k) : AT(M.q, k); };
+        auto sk = [&](int k) { return CP * Tk(k) + GRAV * AT(M.z, k) + phis; };
+        auto hk = [&](int k) { return (CP * Tk(k) + GRAV * AT(M.z, k) + phis) + LV * qk(k); };
+        auto zi = [&](int i) { return 0.5 * (AT(M.z, i - 1) + AT(M.z, i)); };
+        auto dpk = [&](int k) { return AT(M.pi, k + 1) - AT(M.pi, k); };
+        auto zero_column = [&]() {
+            for (int k = 0; k < L; ++k) {
+                AT(w.gT, k) = 0.0;
+                AT(w.gq, k) = 0.0;
+            }
+            w.pgrad[col] = 0.0;
+            w.pgrad[ld + col] = 0.0;
+        };
+        if (ks < 1 || kt < 0 || kt >= ks - 1) {  // not a status-0 column of this state
+            zero_column();
+            continue;
+        }
+
+        // ============================================ forward recomputation
+        // S1: pressure-weighted means over the source layers, summed bottom-up.
+        double hsum = 0.0, qsum = 0.0, wsum = 0.0;
+        for (int k = L - 1; k >= ks; --k) {
+            const double dp = dpk(k);
+            hsum += dp * hk(k);
+            qsum += dp * qk(k);
+            wsum += dp;
+        }
+        const double hs = hsum / wsum, qsrc = qsum / wsum;
+        // S2-S5: the undilute scan up to the level of free convection, and CIN.
+        double cin = 0.0;
+        int klcl = -1, klfc = -1;
+        {
+            Hint hint;
+            hint.clear();
+            for (int k = ks - 1; k >= 0; --k) {
+                const double pm = AT(M.pm, k);
+                if ((klcl < 0 && pm < P.p_lcl_min) || (klcl >= 0 && pm < P.p_sh_top_min)) break;
+                const Lifted r = lift(hs - GRAV * AT(M.z, k) - phis, qsrc, pm, hint);
+                const double B = tv(r.T, r.qv) - tv(Tk(k), qk(k));
+                if (klcl < 0 && r.sat) klcl = k;
+                S(C_TP, k) = r.T;
+                S(C_QP, k) = r.qv;
+                S(C_Q1, k) = r.sat ? sat_eval(r.T, pm).dqs : 0.0;
+                int fl = r.sat ? FL_SAT : 0;
+                if (klcl >= 0 && B > 0.0 && pm >= P.p_sh_top_min) {
+                    S(C_FL, k) = fl;
+                    klfc = k;
+                    break;
+                }
+                if (B < 0.0) {
+                    cin += RD * (-B) * log(AT(M.pi, k + 1) / AT(M.pi, k));
+                    fl |= FL_AUX;
+                }
+                S(C_FL, k) = fl;
+            }
+        }
+        if (klfc < 0) {  // not reachable for a status-0 column
+            zero_column();
+            continue;
+        }
+        // S6: closure.
+        const double sigw2 = P.c_tke * tke, sigw = sqrt(sigw2);
+        const double tvs = tv(Tk(ks), qk(ks));
+        const double rho_s = AT(M.pi, ks) / (RD * tvs);
+        const double Mclos = rho_s * sigw / SQRT_2PI * exp(-P.a_buoy * cin / sigw2);
+        // S7-S8: plume from interface ks up to kt+1, and the unit tendencies of layers ks .. kt.
+        double Mlim = __builtin_inf(), P1;
+        int klim = -1;
+        {
+            Hint hp;
+            hp.clear();
+            double eta = 1.0, hu = hs, qtu, Fs_lo, Fq_lo;
+            double zlo = zi(ks);
+            {
+                const Lifted r = lift(hs - GRAV * zlo - phis, qsrc, AT(M.pi, ks), hp);
+                const double ql = qsrc - r.qv;
+                const bool rain = ql - P.qlcrit_sh > 0.0;
+                const double rr = rain ? ql - P.qlcrit_sh : 0.0;
+                qtu = qsrc - rr;
+                const double slu = CP * r.T + GRAV * zlo + phis - LV * (ql - rr);
+                const double Fs = slu - sk(ks - 1), Fq = qtu - qk(ks - 1);
+                const double dp = dpk(ks);
+                const double dT1 = (0.0 - Fs + LV * rr) * GRAV / (CP * dp);
+                const double dq1 = (0.0 - Fq - rr) * GRAV / dp;
+                S(W_ETA, ks) = 1.0;
+                S(W_HM, ks) = hs;
+                S(W_QM, ks) = qsrc;
+                S(W_QTU, ks) = qtu;
+                S(W_TP, ks) = r.T;
+                S(W_QP, ks) = r.qv;
+                S(W_Q1, ks) = r.sat ? sat_eval(r.T, AT(M.pi, ks)).dqs : 0.0;
+                S(W_FL, ks) = (r.sat ? FL_SAT : 0) | (rain ? FL_AUX : 0);
+                S(W_DT1, ks) = dT1;
+                S(W_DQ1, ks) = dq1;
+                P1 = rr;
+                if (dq1 < 0.0) {
+                    const double m = qk(ks) / (-dt * dq1);
+                    if (m < Mlim) {
+                        Mlim = m;
+                        klim = ks;
+                    }
+                }
+                Fs_lo = Fs;
+                Fq_lo = Fq;
+            }
+            for (int k = ks - 1; k >= kt + 1; --k) {
+                const double zk = zi(k);
+                const double dz = zk - zlo;
+                const double E = P.eps_sh * eta * dz, D = P.delta_sh * eta * dz;
+                const double en = eta + E - D;
+                const double Tkk = Tk(k), qkk = qk(k);
+                const double hm =
+                    ((eta - D) * hu + E * ((CP * Tkk + GRAV * AT(M.z, k) + phis) + LV * qkk)) / en;
+                const double qm = ((eta - D) * qtu + E * qkk) / en;
+                const Lifted r = lift(hm - GRAV * zk - phis, qm, AT(M.pi, k), hp);
+                const double ql = qm - r.qv;
+                const bool rain = ql - P.qlcrit_sh > 0.0;
+                const double rr = rain ? ql - P.qlcrit_sh : 0.0;
+                const double qtn = qm - rr;
+                const double slu = CP * r.T + GRAV * zk + phis - LV * (ql - rr);
+                const double Fs = en * (slu - sk(k - 1)), Fq = en * (qtn - qk(k - 1));
+                const double pr = en * rr;
+                const double dp = dpk(k);
+                const double dT1 = (Fs_lo - Fs + LV * pr) * GRAV / (CP * dp);
+                const double dq1 = (Fq_lo - Fq - pr) * GRAV / dp;
+                S(W_ETA, k) = en;
+                S(W_HM, k) = hm;
+                S(W_QM, k) = qm;
+                S(W_QTU, k) = qtn;
+                S(W_TP, k) = r.T;
+                S(W_QP, k) = r.qv;
+                S(W_Q1, k) = r.sat ? sat_eval(r.T, AT(M.pi, k)).dqs : 0.0;
+                S(W_FL, k) = (r.sat ? FL_SAT : 0) | (rain ? FL_AUX : 0);
+                S(W_DT1, k) = dT1;
+                S(W_DQ1, k) = dq1;
+                P1 += pr;
+                if (dq1 < 0.0) {
+                    const double m = qkk / (-dt * dq1);
+                    if (m < Mlim) {
+                        Mlim = m;
+                        klim = k;
+                    }
+                }
+                eta = en;
+                hu = hm;
+                qtu = qtn;
+                zlo = zk;
+                Fs_lo = Fs;
+                Fq_lo = Fq;
+            }
+            // The top layer kt: only the flux through its bottom interface.
+            const double dp = dpk(kt);
+            const double dT1 = Fs_lo * GRAV / (CP * dp);
+            const double dq1 = Fq_lo * GRAV / dp;
+            S(W_DT1, kt) = dT1;
+            S(W_DQ1, kt) = dq1;
+            if (dq1 < 0.0) {
+                const double m = qk(kt) / (-dt * dq1);
+                if (m < Mlim) {
+                    Mlim = m;
+                    klim = kt;
+                }
+            }
+        }
+        const bool closure = Mclos <= Mlim || klim < 0;  // (klim < 0 only if M_c is not finite)
+        const double Mb = closure ? Mclos : Mlim;
+        // Highest level with a derivative: the plume top, or a CIN level above it when the
+        // entraining plume stops below the level of free convection.
+        const int kmin = min(kt, klfc + 1);
+
+        // ============================================ reverse sweep
+        for (int lev = kmin; lev < L; ++lev) {
+            S(W_GT, lev) = 0.0;
+            S(W_GQ, lev) = 0.0;
+        }
+        // S9 outputs = M_b * unit profiles.
+        double gMb = 0.0;
+        for (int k = kt; k <= ks; ++k) {
+            const double cT = w.cT ? AT(w.cT, k) : 0.0;
+            const double cq = w.cq ? AT(w.cq, k) : 0.0;
+            gMb += cT * S(W_DT1, k) + cq * S(W_DQ1, k);
+            S(W_GDT1, k) = cT * Mb;
+            S(W_GDQ1, k) = cq * Mb;
+        }
+        const double cPc = w.cP ? w.cP[col] : 0.0;
+        gMb += cPc * P1;
+        const double gP1 = cPc * Mb;
+        double gMclos = 0.0;
+        if (closure) {
+            gMclos = gMb;
+        } else {
+            const double dq1m = S(W_DQ1, klim);
+            S(W_GQ, klim) += gMb / (-dt * dq1m);
+            S(W_GDQ1, klim) += gMb * (-Mlim / dq1m);
+        }
+        // S8 and S7 in reverse, top interface first.  (ceta, chu, cqtu): what the step at
+        // interface k adds to the adjoints of the plume state at interface k+1.
+        double ceta = 0.0, chu = 0.0, cqtu = 0.0, geps = 0.0, gdel = 0.0, ghs = 0.0, gqs = 0.0;
+        for (int k = kt + 1; k <= ks; ++k) {
+            const double dpa = dpk(k - 1), dpb = dpk(k);
+            // Flux at interface k: the top of layer k, the bottom of layer k-1.
+            const double gFs = GRAV / (CP * dpa) * S(W_GDT1, k - 1) - GRAV / (CP * dpb) * S(W_GDT1, k);
+            const double gFq = GRAV / dpa * S(W_GDQ1, k - 1) - GRAV / dpb * S(W_GDQ1, k);
+            const double gpr = LV * GRAV / (CP * dpb) * S(W_GDT1, k) - GRAV / dpb * S(W_GDQ1, k) + gP1;
+            const double en = S(W_ETA, k), hm = S(W_HM, k), qm = S(W_QM, k), qtuk = S(W_QTU, k);
+            const double Tp = S(W_TP, k), qvp = S(W_QP, k), Q1 = S(W_Q1, k);
+            const int fl = (int)S(W_FL, k);
+            const double ql = qm - qvp;
+            const double rr = (fl & FL_AUX) ? ql - P.qlcrit_sh : 0.0;
+            const double zk = zi(k);
+            const double slu = CP * Tp + GRAV * zk + phis - LV * (ql - rr);
+            const double s_up = sk(k - 1), q_up = qk(k - 1);
+            double gen = gFs * (slu - s_up) + gFq * (qtuk - q_up) + ceta;
+            const double gslu = gFs * en;
+            const double gqtu = gFq * en + cqtu;
+            S(W_GT, k - 1) -= CP * gFs * en;
+            S(W_GQ, k - 1) -= gFq * en;
+            gen += rr * gpr;
+            double grr = en * gpr + LV * gslu - gqtu;
+            const double gTp = CP * gslu;
+            double gql = -LV * gslu;
+            double gqm = gqtu;
+            if (fl & FL_AUX) gql += grr;
+            gqm += gql;
+            const double gqv = -gql;
+            double gH = 0.0;
+            lift_adjoint((fl & FL_SAT) != 0, Q1, gTp, gqv, gH, gqm);
+            const double ghm = gH + chu;
+            if (k == ks) {  // the source interface: h_u = hs, q_m = q_src, eta = 1
+                ghs += ghm;
+                gqs += gqm;
+                break;
+            }
+            // The recurrence step from interface k+1 to k.
+            const double eta1 = S(W_ETA, k + 1), hu1 = S(W_HM, k + 1), qtu1 = S(W_QTU, k + 1);
+            const double dz = zk - zi(k + 1);
+            const double E = P.eps_sh * eta1 * dz, D = P.delta_sh * eta1 * dz;
+            const double a = eta1 - D;
+            const double ren = 1.0 / en;
+            const double ga = (ghm * hu1 + gqm * qtu1) * ren;
+            chu = ghm * a * ren;
+            cqtu = gqm * a * ren;
+            double gE = (ghm * hk(k) + gqm * qk(k)) * ren;
+            const double gh = ghm * E * ren;
+            S(W_GT, k) += CP * gh;
+            S(W_GQ, k) += LV * gh + gqm * E * ren;
+            gen -= (ghm * hm + gqm * qm) * ren;
+            double geta1 = gen + ga;
+            gE += gen;
+            const double gD = -gen - ga;
+            geta1 += gE * P.eps_sh * dz + gD * P.delta_sh * dz;
+            geps += gE * eta1 * dz;
+            gdel += gD * eta1 * dz;
+            ceta = geta1;
+        }
+        // S6: M_c = rho_s sigma_w / sqrt(2 pi) exp(-a CIN / sigma_w^2).
+        const double gcin = -gMclos * Mclos * P.a_buoy / sigw2;
+        {
+            const double grho = gMclos * Mclos / rho_s;
+            const double gtv = -grho * rho_s / tvs;
+            S(W_GT, ks) += gtv * (1.0 + CVIR * qk(ks));
+            S(W_GQ, ks) += gtv * CVIR * Tk(ks);
+        }
+        // S5: CIN over the scan levels with negative buoyancy.
+        for (int k = ks - 1; k > klfc; --k) {
+            const int fl = (int)S(C_FL, k);
+            if (!(fl & FL_AUX)) continue;
+            const double gB = -RD * log(AT(M.pi, k + 1) / AT(M.pi, k)) * gcin;
+            const double Tp = S(C_TP, k), qvp = S(C_QP, k);
+            S(W_GT, k) -= gB * (1.0 + CVIR * qk(k));
+            S(W_GQ, k) -= gB * CVIR * Tk(k);
+            lift_adjoint((fl & FL_SAT) != 0, S(C_Q1, k), gB * (1.0 + CVIR * qvp), gB * CVIR * Tp,
+                         ghs, gqs);
+        }
+        // S1: the source means.
+        for (int k = ks; k < L; ++k) {
+            const double f = dpk(k) / wsum;
+            S(W_GT, k) += CP * ghs * f;
+            S(W_GQ, k) += (LV * ghs + gqs) * f;
+        }
+        for (int k = 0; k < L; ++k) {
+            const bool in = k >= kmin;
+            AT(w.gT, k) = in ? S(W_GT, k) : 0.0;
+            AT(w.gq, k) = in ? S(W_GQ, k) : 0.0;
+        }
+        w.pgrad[col] = geps;
+        w.pgrad[ld + col] = gdel;
     }
 #undef S
 }
@@ -537,9 +914,10 @@ __global__ void k_adj_zero2(double *out) {
 }
 
 struct AdjLayout {
-    size_t cnt, part, list, pgrad, scr, total;
+    size_t cnt, part, list, slist, pgrad, scr, total;
     int64_t threads;
 };
+constexpr int NPGRAD = 4;  // per-column parameter-gradient rows: tau, eps_deep, eps_sh, delta_sh
 
 AdjLayout adj_layout(int64_t ncol, int nlev, int cus) {
     AdjLayout l{};
@@ -556,8 +934,10 @@ AdjLayout adj_layout(int64_t ncol, int nlev, int cus) {
     l.cnt = take(NCOUNTERS * sizeof(int));
     l.part = take(2 * NPART * sizeof(double));
     l.list = take(n * sizeof(int));
-    l.pgrad = 0;  // per-column values live in a [2][ld] region sized at call time
-    l.scr = take((size_t)N_ADJ * (nlev + 1) * l.threads * sizeof(double));
+    l.slist = take(n * sizeof(int));
+    l.pgrad = 0;  // per-column values live in a [NPGRAD][ld] region sized at call time
+    const int nscr = N_ADJ > N_SADJ ? N_ADJ : N_SADJ;  // the two adjoints run one after the other
+    l.scr = take((size_t)nscr * (nlev + 1) * l.threads * sizeof(double));
     l.total = off;
     return l;
 }
@@ -568,21 +948,75 @@ __global__ void k_adj_reset(int *cnt) {
 
 }  // namespace
 
+namespace {
+
+bool backward_state_ok(const conv_ctx_t *ctx, const conv_state_t *s, bool shallow) {
+    if (!s->T || !s->q || !s->p_mid || !s->z || !s->p_int || !s->phis || s->ld < ctx->ncol ||
+        !(s->dt > 0.0))
+        return false;
+    return !shallow || (s->pblh && s->tke);
+}
+
+// Sums rows r and r+1 of the per-column parameter gradients into out[0], out[1] (fixed order).
+void param_sums(const double *pgrad, int64_t ld, int64_t ncol, double *part, double *out,
+                hipStream_t st) {
+    hipLaunchKernelGGL(k_adj_partial, dim3(NPART), dim3(BLOCK), 0, st, pgrad, ld, ncol, part);
+    hipLaunchKernelGGL(k_adj_final, dim3(1), dim3(BLOCK), 0, st, (const double *)part, out);
+}
+
+AdjWork deep_work(char *b, const AdjLayout &l, const conv_ctx_t *ctx, const conv_deep_cot_t *cot,
+                  double *gT, double *gq, double *pgrad) {
+    AdjWork w;
+    w.cnt = (int *)(b + l.cnt);
+    w.list = (int *)(b + l.list);
+    w.scr = (double *)(b + l.scr);
+    w.pgrad = pgrad;
+    w.stride = l.threads;
+    w.lmax = ctx->nlev;
+    w.cT = cot ? cot->g_dTdt : nullptr;
+    w.cq = cot ? cot->g_dqdt : nullptr;
+    w.cP = cot ? cot->g_prec : nullptr;
+    w.gT = gT;
+    w.gq = gq;
+    w.xT = nullptr;
+    w.xq = nullptr;
+    return w;
+}
+
+SAdjWork shallow_work(char *b, const AdjLayout &l, const conv_ctx_t *ctx,
+                      const conv_shallow_cot_t *cot, double *gT, double *gq, double *pgrad,
+                      int upd) {
+    SAdjWork w;
+    w.cnt = (int *)(b + l.cnt);
+    w.list = (int *)(b + l.slist);
+    w.scr = (double *)(b + l.scr);
+    w.pgrad = pgrad;
+    w.stride = l.threads;
+    w.lmax = ctx->nlev;
+    w.cT = cot ? cot->g_dTdt : nullptr;
+    w.cq = cot ? cot->g_dqdt : nullptr;
+    w.cP = cot ? cot->g_prec : nullptr;
+    w.gT = gT;
+    w.gq = gq;
+    w.upd = upd;
+    return w;
+}
+
+}  // namespace
+
 extern "C" {
 
 size_t conv_backward_workspace_bytes(int64_t ncol, int32_t nlev, int64_t ld) {
     if (ncol < 0 || ncol > INT32_MAX || nlev < 2 || nlev > 256 || ld < ncol) return 0;
     const AdjLayout l = adj_layout(ncol, nlev, device_cus());
-    return l.total + (size_t)2 * (ld > 0 ? ld : 1) * sizeof(double) + 256;
+    return l.total + (size_t)NPGRAD * (ld > 0 ? ld : 1) * sizeof(double) + 256;
 }
 
 int conv_deep_backward(conv_ctx_t *ctx, const conv_state_t *state, const conv_deep_out_t *fwd,
                        const conv_deep_cot_t *cot, conv_deep_grad_t *grad, void *workspace,
                        size_t ws_bytes, void *stream) {
     if (!ctx || !state || !fwd || !cot || !grad || !workspace) return CONV_EINVAL;
-    if (!state->T || !state->q || !state->p_mid || !state->z || !state->p_int || !state->phis ||
-        state->ld < ctx->ncol || !(state->dt > 0.0))
-        return CONV_EINVAL;
+    if (!backward_state_ok(ctx, state, false)) return CONV_EINVAL;
     if (!fwd->status || !fwd->klaunch || !fwd->ktop || !grad->g_T || !grad->g_q || !grad->g_params)
         return CONV_EINVAL;
     if (((uintptr_t)workspace & 255u) != 0) return CONV_EINVAL;
@@ -595,28 +1029,85 @@ int conv_deep_backward(conv_ctx_t *ctx, const conv_state_t *state, const conv_de
         return check_launch();
     }
     char *b = (char *)workspace;
-    Member M = make_member(ctx->ncol, ctx->nlev, ctx->P, state, fwd, nullptr, 0);
-    AdjWork w;
-    w.cnt = (int *)(b + l.cnt);
-    w.list = (int *)(b + l.list);
-    w.scr = (double *)(b + l.scr);
-    w.pgrad = (double *)(b + l.total);
-    w.stride = l.threads;
-    w.lmax = ctx->nlev;
-    w.cT = cot->g_dTdt;
-    w.cq = cot->g_dqdt;
-    w.cP = cot->g_prec;
-    w.gT = grad->g_T;
-    w.gq = grad->g_q;
+    const Member M = make_member(ctx->ncol, ctx->nlev, ctx->P, state, fwd, nullptr, 0);
+    const AdjWork w = deep_work(b, l, ctx, cot, grad->g_T, grad->g_q, (double *)(b + l.total));
     const unsigned gcols = (unsigned)((ctx->ncol + BLOCK - 1) / BLOCK);
     hipLaunchKernelGGL(k_adj_reset, dim3(1), dim3(NCOUNTERS), 0, st, w.cnt);
     hipLaunchKernelGGL(k_adj_compact, dim3(gcols), dim3(BLOCK), 0, st, M, w);
     hipLaunchKernelGGL(k_deep_adjoint, dim3((unsigned)(l.threads / BLOCK)), dim3(BLOCK), 0, st, M, w);
+    param_sums(w.pgrad, ld, ctx->ncol, (double *)(b + l.part), grad->g_params, st);
+    return check_launch();
+}
+
+int conv_shallow_backward(conv_ctx_t *ctx, const conv_state_t *state,
+                          const conv_shallow_out_t *fwd, const conv_shallow_cot_t *cot,
+                          conv_shallow_grad_t *grad, void *workspace, size_t ws_bytes,
+                          void *stream) {
+    if (!ctx || !state || !fwd || !cot || !grad || !workspace) return CONV_EINVAL;
+    if (!backward_state_ok(ctx, state, true)) return CONV_EINVAL;
+    if (!fwd->status || !fwd->kbase || !fwd->ktop || !grad->g_T || !grad->g_q || !grad->g_params)
+        return CONV_EINVAL;
+    if (((uintptr_t)workspace & 255u) != 0) return CONV_EINVAL;
+    const AdjLayout l = adj_layout(ctx->ncol, ctx->nlev, ctx->cus);
+    const int64_t ld = state->ld;
+    if (ws_bytes < l.total + (size_t)2 * ld * sizeof(double)) return CONV_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    if (ctx->ncol == 0) {
+        hipLaunchKernelGGL(k_adj_zero2, dim3(1), dim3(64), 0, st, grad->g_params);
+        return check_launch();
+    }
+    char *b = (char *)workspace;
+    const Member M = make_member(ctx->ncol, ctx->nlev, ctx->P, state, nullptr, fwd, 0);
+    const SAdjWork w =
+        shallow_work(b, l, ctx, cot, grad->g_T, grad->g_q, (double *)(b + l.total), 0);
+    const unsigned gcols = (unsigned)((ctx->ncol + BLOCK - 1) / BLOCK);
+    hipLaunchKernelGGL(k_adj_reset, dim3(1), dim3(NCOUNTERS), 0, st, w.cnt);
+    hipLaunchKernelGGL(k_sadj_compact, dim3(gcols), dim3(BLOCK), 0, st, M, w);
+    hipLaunchKernelGGL(k_shallow_adjoint, dim3((unsigned)(l.threads / BLOCK)), dim3(BLOCK), 0, st,
+                       M, w);
+    param_sums(w.pgrad, ld, ctx->ncol, (double *)(b + l.part), grad->g_params, st);
+    return check_launch();
+}
+
+int conv_step_backward(conv_ctx_t *ctx, const conv_state_t *state, const conv_deep_out_t *dfwd,
+                       const conv_shallow_out_t *sfwd, const conv_deep_cot_t *dcot,
+                       const conv_shallow_cot_t *scot, conv_step_grad_t *grad, void *workspace,
+                       size_t ws_bytes, void *stream) {
+    if (!ctx || !state || !dfwd || !sfwd || !grad || !workspace) return CONV_EINVAL;
+    if (!backward_state_ok(ctx, state, true)) return CONV_EINVAL;
+    if (!dfwd->status || !dfwd->klaunch || !dfwd->ktop || !dfwd->dTdt || !dfwd->dqdt ||
+        !sfwd->status || !sfwd->kbase || !sfwd->ktop || !grad->g_T || !grad->g_q ||
+        !grad->g_params)
+        return CONV_EINVAL;
+    if (((uintptr_t)workspace & 255u) != 0) return CONV_EINVAL;
+    const AdjLayout l = adj_layout(ctx->ncol, ctx->nlev, ctx->cus);
+    const int64_t ld = state->ld;
+    if (ws_bytes < l.total + (size_t)NPGRAD * ld * sizeof(double)) return CONV_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    if (ctx->ncol == 0) {
+        hipLaunchKernelGGL(k_adj_zero2, dim3(1), dim3(64), 0, st, grad->g_params);
+        hipLaunchKernelGGL(k_adj_zero2, dim3(1), dim3(64), 0, st, grad->g_params + 2);
+        return check_launch();
+    }
+    char *b = (char *)workspace;
+    double *pgrad = (double *)(b + l.total);
+    const Member M = make_member(ctx->ncol, ctx->nlev, ctx->P, state, dfwd, sfwd, 0);
+    const unsigned gcols = (unsigned)((ctx->ncol + BLOCK - 1) / BLOCK);
+    const unsigned gpers = (unsigned)(l.threads / BLOCK);
+    // Shallow adjoint at the updated state: dL/dT', dL/dq' into g_T, g_q.
+    const SAdjWork sw = shallow_work(b, l, ctx, scot, grad->g_T, grad->g_q, pgrad + 2 * ld, 1);
+    hipLaunchKernelGGL(k_adj_reset, dim3(1), dim3(NCOUNTERS), 0, st, sw.cnt);
+    hipLaunchKernelGGL(k_sadj_compact, dim3(gcols), dim3(BLOCK), 0, st, M, sw);
+    hipLaunchKernelGGL(k_shallow_adjoint, dim3(gpers), dim3(BLOCK), 0, st, M, sw);
+    // Deep adjoint with the update's chain rule, in place on g_T, g_q.
+    AdjWork dw = deep_work(b, l, ctx, dcot, grad->g_T, grad->g_q, pgrad);
+    dw.xT = grad->g_T;
+    dw.xq = grad->g_q;
+    hipLaunchKernelGGL(k_adj_compact, dim3(gcols), dim3(BLOCK), 0, st, M, dw);
+    hipLaunchKernelGGL(k_deep_adjoint, dim3(gpers), dim3(BLOCK), 0, st, M, dw);
     double *part = (double *)(b + l.part);
-    hipLaunchKernelGGL(k_adj_partial, dim3(NPART), dim3(BLOCK), 0, st, (const double *)w.pgrad, ld,
-                       ctx->ncol, part);
-    hipLaunchKernelGGL(k_adj_final, dim3(1), dim3(BLOCK), 0, st, (const double *)part,
-                       grad->g_params);
+    param_sums(pgrad, ld, ctx->ncol, part, grad->g_params, st);
+    param_sums(pgrad + 2 * ld, ld, ctx->ncol, part, grad->g_params + 2, st);
     return check_launch();
 }
 
