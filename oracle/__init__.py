@@ -131,6 +131,9 @@ def lib():
         L.oracle_deep_column_jvp.argtypes = ([C.c_int, C.POINTER(Params)] + [dp] * 5 +
                                              [C.c_double, C.c_double, dp, dp, C.c_double,
                                               C.c_double, dp, dp, dp])
+        L.oracle_tracers.restype = C.c_int
+        L.oracle_tracers.argtypes = [C.c_int64, C.c_int, C.POINTER(Params), C.POINTER(State),
+                                     C.c_int, dp, dp, dp]
         L.oracle_shallow_column_jvp.restype = C.c_int
         L.oracle_shallow_column_jvp.argtypes = ([C.c_int, C.POINTER(Params)] + [dp] * 5 +
                                                 [C.c_double] * 4 + [dp, dp, C.c_double,
@@ -304,6 +307,23 @@ def deep_column_jvp(col: dict, dT, dq, dtau=0.0, deps=0.0, params: Params | None
                                       _ptr(dT), _ptr(dq), float(dtau), float(deps), _ptr(tT),
                                       _ptr(tq), C.byref(tp))
     return dict(dTdt=tT, dqdt=tq, prec=tp.value, status=st)
+
+
+def tracers(st: dict, tr, params: Params | None = None):
+    """Convective transport of passive tracers tr [ntr][nlev][ncol] by one step: returns
+    (tend, deep_tend), each [ntr][nlev][ncol]; tend = deep + shallow tendency."""
+    params = params or make_params()
+    L, n = _dims(st)
+    keep = []
+    s = _state(st, keep)
+    tr = np.ascontiguousarray(tr, dtype=np.float64)
+    ntr = tr.shape[0]
+    tend, deep = np.zeros_like(tr), np.zeros_like(tr)
+    rc = lib().oracle_tracers(n, L, C.byref(params), C.byref(s), ntr, _ptr(tr), _ptr(tend),
+                              _ptr(deep))
+    if rc != 0:
+        raise ValueError("oracle_tracers: bad arguments")
+    return tend, deep
 
 
 def shallow_column_jvp(col: dict, dT, dq, deps_sh=0.0, ddelta_sh=0.0,

@@ -404,7 +404,7 @@ void deep_column(int L, const oracle_params_t &P, const R &tau, const R &epsd, c
 
 /* ---------------------------------------------------------------- shallow scheme (S1-S9) */
 template <class R> struct ShallowRes {
-    std::vector<R> dTdt, dqdt, mu;
+    std::vector<R> dTdt, dqdt, mu, eta;
     R prec, cin, hs, qsrc, rho_s, sigw2, Mclos, Mlim, Mb, P1;
     int ks, klcl, klfc, kt, status;
 };
@@ -422,6 +422,7 @@ void shallow_column(int L, const oracle_params_t &P, const R &eps_sh, const R &d
     o.dTdt.assign(L, R(0.0));
     o.dqdt.assign(L, R(0.0));
     o.mu.assign(L + 1, R(0.0));
+    o.eta.assign(L + 1, R(0.0));
     o.prec = o.cin = o.hs = o.qsrc = o.rho_s = o.sigw2 = o.Mclos = o.Mb = o.P1 = R(0.0);
     o.Mlim = R(std::numeric_limits<double>::infinity());
     o.ks = o.klcl = o.klfc = o.kt = -1;
@@ -574,11 +575,81 @@ void shallow_column(int L, const oracle_params_t &P, const R &eps_sh, const R &d
         o.dqdt[k] = Mb * dq1[k];
     }
     for (int i = kt + 1; i <= ks; ++i) o.mu[i] = Mb * eta[i];
+    o.eta = eta;
     o.prec = Mb * P1;
     o.Mlim = Mlim;
     o.Mb = Mb;
     o.P1 = P1;
     o.status = 0;
+}
+
+/* ---------------------------------------------------------------- convective tracer transport
+ * A passive tracer C (mixing ratio per unit mass of air) is carried by the plumes exactly as the
+ * schemes carry moist static energy: each plume mixes in environmental air where it entrains, the
+ * updraft starts from the air of its source, the deep downdraft from layer k_d's air, and the
+ * tendencies are the flux divergences of the plume-minus-environment fluxes with the same upwind
+ * environmental values (D7, S8).  No sources or sinks: the column integral of the tendency,
+ * weighted by dp/g, is zero. */
+void deep_tracer(int L, const oracle_params_t &P, const DeepRes<double> &d, const Grid &g,
+                 const double *C, double *out) {
+    for (int k = 0; k < L; ++k) out[k] = 0.0;
+    if (d.status != 0) return;
+    const int kb = d.kb, kt = d.kt, kd = d.kd;
+    const std::vector<double> &eta = d.eta, &etad = d.etad;
+    // Updraft (D5's mixing): the launch layer's air at interface kb, entraining layer k's air
+    // between interfaces k+1 and k.
+    std::vector<double> Cu(L + 1, 0.0), Cd(L + 1, 0.0);
+    Cu[kb] = C[kb];
+    for (int k = kb - 1; k >= kt + 1; --k) {
+        const double E = P.eps_deep * eta[k + 1] * g.dz[k];
+        Cu[k] = (eta[k + 1] * Cu[k + 1] + E * C[k]) / eta[k];
+    }
+    // Downdraft (D6's mixing): layer k_d's air at interface k_d+1, entraining layer k's air
+    // between interfaces k and k+1.
+    if (kd >= 0) {
+        double ad = 1.0;
+        Cd[kd + 1] = C[kd];
+        for (int k = kd + 1; k <= kb - 1; ++k) {
+            const double Ed = P.eps_deep * ad * g.dz[k];
+            const double adn = ad + Ed;
+            Cd[k + 1] = (ad * Cd[k] + Ed * C[k]) / adn;
+            ad = adn;
+        }
+    }
+    // D7's fluxes and their divergence, scaled by the base mass flux.
+    std::vector<double> F(L + 1, 0.0);
+    for (int i = kt + 1; i <= kb; ++i) {
+        const double m = eta[i] + d.alpha * etad[i];
+        const int up = m >= 0.0 ? i - 1 : i;
+        F[i] = eta[i] * (Cu[i] - C[up]) + d.alpha * etad[i] * (Cd[i] - C[up]);
+    }
+    for (int k = kt; k <= kb; ++k) out[k] = d.Mb * (F[k + 1] - F[k]) * GRAV / g.dp[k];
+}
+
+void shallow_tracer(int L, const oracle_params_t &P, const ShallowRes<double> &o, const Grid &g,
+                    const double *C, double *out) {
+    for (int k = 0; k < L; ++k) out[k] = 0.0;
+    if (o.status != 0) return;
+    const int ks = o.ks, kt = o.kt;
+    const std::vector<double> &eta = o.eta;
+    // S1's source: the pressure-weighted mean over the source layers.
+    double csum = 0.0, wsum = 0.0;
+    for (int k = L - 1; k >= ks; --k) {
+        csum = csum + g.dp[k] * C[k];
+        wsum = wsum + g.dp[k];
+    }
+    // S7's mixing: entrainment of layer k's air and detrainment of plume air.
+    std::vector<double> Cu(L + 1, 0.0);
+    Cu[ks] = csum / wsum;
+    for (int k = ks - 1; k >= kt + 1; --k) {
+        const double E = P.eps_sh * eta[k + 1] * g.dz[k];
+        const double D = P.delta_sh * eta[k + 1] * g.dz[k];
+        Cu[k] = ((eta[k + 1] - D) * Cu[k + 1] + E * C[k]) / eta[k];
+    }
+    // S8's fluxes (environment from the layer above) and their divergence.
+    std::vector<double> F(L + 1, 0.0);
+    for (int i = kt + 1; i <= ks; ++i) F[i] = eta[i] * (Cu[i] - C[i - 1]);
+    for (int k = kt; k <= ks; ++k) out[k] = o.Mb * (F[k + 1] - F[k]) * GRAV / g.dp[k];
 }
 
 /* ---------------------------------------------------------------- level-major helpers */
@@ -710,6 +781,48 @@ int oracle_step(int64_t ncol, int nlev, const oracle_params_t *p, const oracle_s
                 oracle_deep_out_t *od, oracle_shallow_out_t *os) {
     if (!args_ok(ncol, nlev, p, s) || !od || !os) return -1;
     for (int64_t c = 0; c < ncol; ++c) step_one(nlev, p, s, c, od, os);
+    return 0;
+}
+
+int oracle_tracers(int64_t ncol, int nlev, const oracle_params_t *p, const oracle_state_t *s,
+                   int ntr, const double *tracers, double *tend, double *deep_tend) {
+    if (!args_ok(ncol, nlev, p, s) || ntr < 0 || (ntr > 0 && (!tracers || !tend))) return -1;
+    const int L = nlev;
+    const int64_t ld = s->ld, plane = (int64_t)L * ld;
+    ColIn col;
+    std::vector<double> C(L), Cd(L), Cs(L), C2(L), T2(L), q2(L);
+    for (int64_t c = 0; c < ncol; ++c) {
+        gather(s, L, c, col);
+        // The step (Algorithm 1): deep, the update, shallow on the updated state.
+        DeepRes<double> d;
+        deep_column<double>(L, *p, p->tau, p->eps_deep, col.T.data(), col.q.data(), col.pm.data(),
+                            col.pi.data(), col.z.data(), col.phis, s->dt, d);
+        for (int k = 0; k < L; ++k) {
+            T2[k] = col.T[k] + s->dt * d.dTdt[k];
+            q2[k] = col.q[k] + s->dt * d.dqdt[k];
+        }
+        ShallowRes<double> sh;
+        if (d.status == 3)
+            shallow_column<double>(L, *p, p->eps_sh, p->delta_sh, col.T.data(), col.q.data(),
+                                   col.pm.data(), col.pi.data(), col.z.data(), col.phis,
+                                   col.pblh, col.tke, s->dt, sh);
+        else
+            shallow_column<double>(L, *p, p->eps_sh, p->delta_sh, T2.data(), q2.data(),
+                                   col.pm.data(), col.pi.data(), col.z.data(), col.phis,
+                                   col.pblh, col.tke, s->dt, sh, true);
+        const Grid g = make_grid(L, col.pi.data(), col.z.data());
+        for (int t = 0; t < ntr; ++t) {
+            for (int k = 0; k < L; ++k) C[k] = tracers[t * plane + k * ld + c];
+            deep_tracer(L, *p, d, g, C.data(), Cd.data());
+            // The shallow scheme transports the tracer updated by the deep transport.
+            for (int k = 0; k < L; ++k) C2[k] = C[k] + s->dt * Cd[k];
+            shallow_tracer(L, *p, sh, g, C2.data(), Cs.data());
+            for (int k = 0; k < L; ++k) {
+                tend[t * plane + k * ld + c] = Cd[k] + Cs[k];
+                if (deep_tend) deep_tend[t * plane + k * ld + c] = Cd[k];
+            }
+        }
+    }
     return 0;
 }
 

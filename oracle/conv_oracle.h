@@ -97,6 +97,13 @@ int oracle_deep_column_jvp(int nlev, const oracle_params_t *p, const double *T, 
                            double dt, const double *dT, const double *dq, double dtau, double deps,
                            double *t_dTdt, double *t_dqdt, double *t_prec);
 
+/* Convective transport of ntr passive tracers by one step (deep, update, shallow on the updated
+ * state and on the tracer updated by the deep transport): tracers, tend, deep_tend are
+ * [ntr][nlev][ld] level-major like the state; tend = deep + shallow tendency; deep_tend (may be
+ * NULL) the deep part.  Returns 0, or -1 on bad arguments. */
+int oracle_tracers(int64_t ncol, int nlev, const oracle_params_t *p, const oracle_state_t *s,
+                   int ntr, const double *tracers, double *tend, double *deep_tend);
+
 /* Forward-mode derivative of the shallow scheme (S1-S9) of one column along (dT, dq, d eps_sh,
  * d delta_sh), with every integer decision of the run held fixed: source layers, lifting
  * condensation and free-convection levels, the levels counted in CIN, saturation and rain-out
