@@ -202,6 +202,24 @@ int conv_step_backward(conv_ctx_t *ctx, const conv_state_t *state, const conv_de
                        const conv_shallow_cot_t *scot, conv_step_grad_t *grad, void *workspace,
                        size_t ws_bytes, void *stream);
 
+/* ---------------------------------------------------------------- convective tracer transport
+ * Transport of ntr passive tracers (mixing ratios, no sources or sinks) by the plumes of one
+ * conv_step: each plume mixes a tracer exactly as it mixes moist static energy (deep updraft and
+ * downdraft of steps D5-D7, shallow updraft of S7-S8: the same entrainment, detrainment and upwind
+ * environment values), and the tendency is the flux divergence.  The shallow scheme transports the
+ * tracer updated by the deep transport, C + dt * deep tendency (Algorithm 1 order).  Extends the
+ * paper's convection, which moves heat and water, to every other constituent the same mass fluxes
+ * carry.
+ * `dfwd`, `sfwd`: the outputs of conv_step on `state` with the context's parameters (mu, md,
+ * status, klaunch, ktop of the deep scheme; mu, status, kbase, ktop of the shallow one); the
+ * plumes are not run again.  tracers, tend, deep_tend: device [ntr][nlev][ld] with the state's ld;
+ * tend receives the deep + shallow tendency (s-1), deep_tend (may be NULL) the deep part alone.
+ * Columns with neither scheme active get exact zeros.  ntr = 0 does nothing.  Returns CONV_EINVAL
+ * for missing arrays or ntr < 0. */
+int conv_tracer_transport(conv_ctx_t *ctx, const conv_state_t *state, const conv_deep_out_t *dfwd,
+                          const conv_shallow_out_t *sfwd, int32_t ntr, const double *tracers,
+                          double *tend, double *deep_tend, void *stream);
+
 /* ---------------------------------------------------------------- batched ensemble
  * Several grids ("members", e.g. ensemble members of a forecast) with their own column counts,
  * level counts (2..256), parameters and arrays, advanced by one conv_step each in the SAME kernel

@@ -30,7 +30,7 @@ EXPORTS = ("conv_workspace_bytes", "conv_create", "conv_set_params", "conv_destr
            "conv_get_launch", "conv_timing_start",
            "conv_timing_read", "conv_strerror", "conv_last_hip_error",
            "conv_backward_workspace_bytes", "conv_deep_backward", "conv_shallow_backward",
-           "conv_step_backward", "conv_autotune",
+           "conv_step_backward", "conv_tracer_transport", "conv_autotune",
            "conv_ensemble_workspace_bytes", "conv_ensemble_create", "conv_ensemble_destroy",
            "conv_ensemble_step", "conv_ensemble_set_launch", "conv_ensemble_get_launch",
            "conv_ensemble_autotune", "conv_ensemble_capture", "conv_ensemble_replay",
@@ -127,6 +127,10 @@ def lib():
                                          C.POINTER(ShallowOut), C.POINTER(DeepCot),
                                          C.POINTER(ShallowCot), C.POINTER(StepGrad), C.c_void_p,
                                          C.c_size_t, C.c_void_p]
+        L.conv_tracer_transport.restype = C.c_int
+        L.conv_tracer_transport.argtypes = [C.c_void_p, C.POINTER(State), C.POINTER(DeepOut),
+                                            C.POINTER(ShallowOut), C.c_int32, C.c_void_p,
+                                            C.c_void_p, C.c_void_p, C.c_void_p]
         L.conv_deep_backward.restype = C.c_int
         L.conv_deep_backward.argtypes = [C.c_void_p, C.POINTER(State), C.POINTER(DeepOut),
                                          C.POINTER(DeepCot), C.POINTER(DeepGrad), C.c_void_p,
@@ -241,8 +245,9 @@ def _stream(torch):
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-def to_device(st: dict, device="cuda", ld: int | None = None):
-    """Copy a level-major numpy state dict (from soundings.make_state) to device tensors."""
+def to_device(st: dict, device="cuda"):
+    """Copy a level-major numpy state dict (from soundings.make_state) to device tensors (the
+    arrays' width is the state's leading dimension)."""
     torch = _torch()
     out = {}
     for k in ("T", "q", "p_mid", "z", "p_int", "phis", "pblh", "tke"):
@@ -441,6 +446,26 @@ class Conv:
                                        C.byref(sc), C.byref(g), wptr, nbytes, _stream(self.torch)),
               "conv_step_backward")
         return dict(g_T=gT, g_q=gq, g_tau=gp[0], g_eps=gp[1], g_eps_sh=gp[2], g_delta_sh=gp[3])
+
+    def tracer_transport(self, s: dict, deep: dict, shallow: dict, tracers, deep_part=False,
+                         out=None):
+        """Convective transport of tracers [ntr][nlev][ld] (float64, device) by the plumes of the
+        step whose outputs are `deep`, `shallow`: returns the deep + shallow tendency, and with
+        deep_part also the deep part alone."""
+        torch = self.torch
+        st = self._state(s)
+        if tracers.dtype != torch.float64 or tracers.dim() != 3 or tuple(tracers.shape[1:]) != (
+                self.nlev, st.ld):
+            raise ValueError(f"tracers: expected float64 [ntr][{self.nlev}][{st.ld}]")
+        tr = tracers.contiguous()
+        tend = out if out is not None else torch.empty_like(tr)
+        dpart = torch.empty_like(tr) if deep_part else None
+        d, h = self._deep_struct(deep), self._shallow_struct(shallow)
+        check(lib().conv_tracer_transport(self.h, C.byref(st), C.byref(d), C.byref(h),
+                                          int(tr.shape[0]), tr.data_ptr(), tend.data_ptr(),
+                                          dpart.data_ptr() if dpart is not None else None,
+                                          _stream(torch)), "conv_tracer_transport")
+        return (tend, dpart) if deep_part else tend
 
     def autotune(self, s: dict, deep: dict, shallow: dict, reps: int = 5, force: bool = False):
         """Pick the fastest persistent-grid shape for conv_step on these arrays (cached per

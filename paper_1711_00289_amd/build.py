@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libconv.so")
-SOURCES = ["conv.hip", "conv_adjoint.hip", "mlp.hip", "surrogate.hip"]
+SOURCES = ["conv.hip", "conv_adjoint.hip", "conv_tracers.hip", "mlp.hip", "surrogate.hip"]
 HEADERS = ["conv_physics.hpp", "conv_internal.hpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -1,0 +1,207 @@
+"""Convective tracer transport on the GPU (conv_tracer_transport, through the C ABI) against the
+oracle's transport (written from the schemes' mixing rules in its own plume quantities; pinned on
+the CPU by the moist-static-energy identity, uniform tracers, burden conservation and linearity).
+
+* element-wise parity (1e-9 of each column's largest tendency) on columns of the 1-degree grid where
+  both schemes act, only the deep one, only the shallow one, and neither, with padded arrays;
+* the moist-static-energy identity on the GPU's own step: the tracer h gives cp dTdt + Lv dqdt of
+  each scheme;
+* the 884,736-column grid with the benchmark's tracers: sampled columns against the oracle, and at
+  every column the properties that hold at any size (zeros where nothing convects, the column
+  burden conserved);
+* the optional deep part, ntr = 0, argument errors.
+"""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1711_00289_amd import soundings as S
+
+pytestmark = pytest.mark.gpu
+
+CP, LV, GRAV = 1004.64, 2.501e6, 9.80616
+TOL = 1e-9
+# Absolute floor: a few status-0 shallow columns of the full grid have a subnormal base mass flux
+# (the closure's exp(-a CIN / sigma_w^2) close to underflow); the stored fluxes have lost mantissa
+# bits there, so their tendencies (~1e-314) match the oracle's only to that precision.
+FLOOR = 1e-290
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _B():
+    from paper_1711_00289_amd import binding
+
+    return binding
+
+
+def _np(x):
+    return x.detach().cpu().numpy()
+
+
+def _tracers(torch, ntr, L, n, ld, seed):
+    rng = np.random.default_rng(seed)
+    tr = np.exp(rng.standard_normal((ntr, L, n)))
+    dev = np.zeros((ntr, L, ld))
+    dev[:, :, :n] = tr
+    return tr, torch.as_tensor(dev, device="cuda")
+
+
+def _check(got, want):
+    scale = np.abs(want).max(axis=1, keepdims=True)  # per tracer and column
+    bad = ~(np.abs(got - want) <= TOL * scale + FLOOR)  # NaN counts as a mismatch
+    if bad.any():
+        t, k, j = np.argwhere(bad)[0]
+        raise AssertionError(f"{bad.sum()} elements; first at tracer {t} level {k} column {j}: "
+                             f"got {got[t, k, j]!r} want {want[t, k, j]!r} scale {scale[t, 0, j]!r}")
+
+
+def _pad(st, ld):
+    """The same state on arrays of leading dimension ld (padding columns copy column 0)."""
+    out = dict(st)
+    n = st["ncol"]
+    for k, v in st.items():
+        if isinstance(v, np.ndarray) and v.shape[-1] == n:
+            extra = np.repeat(v[..., :1], ld - n, axis=-1)
+            out[k] = np.ascontiguousarray(np.concatenate([v, extra], axis=-1))
+    return out
+
+
+@pytest.fixture(scope="module")
+def mixed(torch):
+    """Columns of the 1-degree grid with both schemes, the deep one only, and neither (plus the
+    shallow-only ones), on padded device arrays."""
+    B = _B()
+    st = S.grid_1deg()
+    od, osh = oracle.step(st, threads=8, chunk=16)
+    rng = np.random.default_rng(7)
+    deep = np.nonzero(od["status"] == 0)[0]
+    shallow = np.nonzero(osh["status"] == 0)[0]
+    quiet = np.nonzero((od["status"] != 0) & (osh["status"] != 0))[0]
+    cols = np.unique(np.concatenate([shallow, rng.choice(deep, 700, replace=False),
+                                     rng.choice(quiet, 300, replace=False)]))
+    sub = S.subset(st, cols)
+    n, L = sub["ncol"], sub["nlev"]
+    ld = n + 37
+    dev = B.to_device(_pad(sub, ld))
+    conv = B.Conv(n, L)
+    deep_o, sh_o = conv.step(dev)
+    return dict(st=sub, dev=dev, conv=conv, deep=deep_o, sh=sh_o, n=n, L=L, ld=ld)
+
+
+def test_parity_with_the_oracle(torch, mixed):
+    n, L, ld = mixed["n"], mixed["L"], mixed["ld"]
+    tr, trd = _tracers(torch, 3, L, n, ld, 8)
+    tend, dpart = mixed["conv"].tracer_transport(mixed["dev"], mixed["deep"], mixed["sh"], trd,
+                                                 deep_part=True)
+    torch.cuda.synchronize()
+    want, want_d = oracle.tracers(mixed["st"], tr)
+    _check(_np(tend)[:, :, :n], want)
+    _check(_np(dpart)[:, :, :n], want_d)
+    ds, ss = _np(mixed["deep"]["status"])[:n], _np(mixed["sh"]["status"])[:n]
+    assert (ds == 0).sum() > 500 and (ss == 0).sum() > 100 and ((ds != 0) & (ss != 0)).sum() > 100
+    quiet = (ds != 0) & (ss != 0)
+    assert np.all(_np(tend)[:, :, :n][:, :, quiet] == 0.0)
+
+
+def test_moist_static_energy_identity_on_the_gpu_step(torch, mixed):
+    n, L, ld = mixed["n"], mixed["L"], mixed["ld"]
+    st = mixed["st"]
+    h = CP * st["T"] + GRAV * st["z"] + st["phis"][None, :] + LV * st["q"]
+    hd = np.zeros((1, L, ld))
+    hd[0, :, :n] = h
+    tend, dpart = mixed["conv"].tracer_transport(mixed["dev"], mixed["deep"], mixed["sh"],
+                                                 torch.as_tensor(hd, device="cuda"),
+                                                 deep_part=True)
+    d = {k: _np(v)[..., :n] for k, v in mixed["deep"].items()}
+    s = {k: _np(v)[..., :n] for k, v in mixed["sh"].items()}
+    want_d = CP * d["dTdt"] + LV * d["dqdt"]
+    want_s = CP * s["dTdt"] + LV * s["dqdt"]
+    got_d = _np(dpart)[0, :, :n]
+    got_s = _np(tend)[0, :, :n] - got_d
+    sd = np.abs(want_d).max(axis=0)
+    ss = np.abs(want_s).max(axis=0)
+    assert np.all(np.abs(got_d - want_d).max(axis=0) <= TOL * sd)
+    assert np.all(np.abs(got_s - want_s).max(axis=0) <= TOL * ss + 1e-12 * sd)
+    # Status-0 shallow columns whose closure underflowed to a zero base mass flux are among them.
+    assert np.isfinite(_np(tend)).all()
+
+
+@pytest.fixture(scope="module")
+def big(torch):
+    """The 884,736 x 30 grid with 8 tracers (the benchmark's workload)."""
+    B = _B()
+    st = S.grid_quarter_deg()
+    n, L = st["ncol"], st["nlev"]
+    dev = B.to_device(st)
+    conv = B.Conv(n, L)
+    deep, sh = conv.step(dev)
+    g = torch.Generator(device="cuda").manual_seed(9)
+    tr = torch.exp(torch.randn((8, L, n), generator=g, dtype=torch.float64, device="cuda"))
+    tend = conv.tracer_transport(dev, deep, sh, tr)
+    torch.cuda.synchronize()
+    return dict(st=st, dev=dev, conv=conv, deep=deep, sh=sh, tr=tr, tend=tend)
+
+
+def test_full_grid_sampled_columns_against_the_oracle(torch, big):
+    st = big["st"]
+    ds, ss = _np(big["deep"]["status"]), _np(big["sh"]["status"])
+    rng = np.random.default_rng(10)
+    cols = np.unique(np.concatenate([rng.choice(np.nonzero(ds == 0)[0], 200, replace=False),
+                                     np.nonzero(ss == 0)[0][:100],
+                                     rng.choice(np.nonzero(ds != 0)[0], 50, replace=False)]))
+    sub = S.subset(st, cols)
+    tr = _np(big["tr"][:, :, torch.as_tensor(cols, device="cuda")])
+    want, _ = oracle.tracers(sub, tr)
+    got = _np(big["tend"][:, :, torch.as_tensor(cols, device="cuda")])
+    _check(got, want)
+
+
+def test_full_grid_properties(torch, big):
+    tend = big["tend"]
+    ds, ss = big["deep"]["status"], big["sh"]["status"]
+    quiet = (ds != 0) & (ss != 0)
+    assert bool((tend[:, :, quiet] == 0.0).all())
+    dp = (big["dev"]["p_int"][1:] - big["dev"]["p_int"][:-1])[None]
+    burden = (tend * dp).sum(dim=1)
+    scale = (tend * dp).abs().sum(dim=1)
+    assert bool(torch.isfinite(tend).all())
+    assert bool((burden.abs() <= 1e-12 * scale).all())
+
+
+def test_deep_part_is_optional_and_ntr_zero_is_a_no_op(torch, mixed):
+    n, L, ld = mixed["n"], mixed["L"], mixed["ld"]
+    _, trd = _tracers(torch, 2, L, n, ld, 11)
+    conv, dev = mixed["conv"], mixed["dev"]
+    a = conv.tracer_transport(dev, mixed["deep"], mixed["sh"], trd)
+    b, _ = conv.tracer_transport(dev, mixed["deep"], mixed["sh"], trd, deep_part=True)
+    assert torch.equal(a[:, :, :n], b[:, :, :n])  # padding columns are not written
+    empty = torch.empty((0, L, ld), dtype=torch.float64, device="cuda")
+    assert conv.tracer_transport(dev, mixed["deep"], mixed["sh"], empty).numel() == 0
+
+
+def test_argument_errors(torch, mixed):
+    B = _B()
+    L = B.lib()
+    conv, dev = mixed["conv"], mixed["dev"]
+    st = conv._state(dev)
+    d = B.Conv._deep_struct(mixed["deep"])
+    h = B.Conv._shallow_struct(mixed["sh"])
+    buf = torch.zeros((1, mixed["L"], mixed["ld"]), dtype=torch.float64, device="cuda")
+    s0 = B._stream(torch)
+    EINVAL = -1
+    assert L.conv_tracer_transport(conv.h, C.byref(st), C.byref(d), C.byref(h), -1,
+                                   buf.data_ptr(), buf.data_ptr(), None, s0) == EINVAL
+    assert L.conv_tracer_transport(conv.h, C.byref(st), C.byref(d), C.byref(h), 1, None,
+                                   buf.data_ptr(), None, s0) == EINVAL
+    assert L.conv_tracer_transport(conv.h, C.byref(st), None, C.byref(h), 1, buf.data_ptr(),
+                                   buf.data_ptr(), None, s0) == EINVAL
