@@ -153,6 +153,50 @@ def bench_adjoint(torch, B, S, reps):
                          float((shallow["status"] == 0).double().mean())}}
 
 
+NTRACERS = 8
+
+
+def tracer_bytes(L, ntr, deep, shallow):
+    """Algorithmic HBM bytes of one conv_tracer_transport call: the tendency written once for every
+    column, the tracers read over the active plumes' levels, the plumes' mass fluxes, interface
+    pressures and (shallow) heights, and the statuses of every column."""
+    import numpy as np
+
+    ds, ss = deep["status"], shallow["status"]
+    n = ds.size
+    total = ntr * L * 8 * n + 8 * n
+    a = ds == 0
+    kb, kt = deep["klaunch"][a].astype(np.int64), deep["ktop"][a].astype(np.int64)
+    nl = kb - kt + 1                                     # layers kt .. kb
+    total += int((ntr * nl * 8 + 2 * (nl - 1) * 8 + (nl + 1) * 8 + 8).sum())
+    b = ss == 0
+    ks, kts = shallow["kbase"][b].astype(np.int64), shallow["ktop"][b].astype(np.int64)
+    nl = L - kts                                         # layers kts .. L-1
+    total += int((ntr * nl * 8 + (ks - kts) * 8 + (nl + 1) * 8 + (ks - kts + 1) * 8 + 8).sum())
+    return total
+
+
+def bench_tracers(torch, B, conv, dev, deep, shallow, reps):
+    """Convective transport of 8 passive tracers (exp of N(0,1), seeded) by the headline grid's
+    step: time per call and the HBM roofline of k_tracers."""
+    L, n = conv.nlev, conv.ncol
+    g = torch.Generator(device="cuda").manual_seed(12)
+    tr = torch.exp(torch.randn((NTRACERS, L, n), generator=g, dtype=torch.float64, device="cuda"))
+    tend = torch.empty_like(tr)
+    for _ in range(3):
+        conv.tracer_transport(dev, deep, shallow, tr, out=tend)
+    ms = time_events(torch, lambda: conv.tracer_transport(dev, deep, shallow, tr, out=tend), reps)
+    host = lambda o: {k: o[k].cpu().numpy() for k in ("status", "klaunch", "ktop", "kbase")
+                      if k in o}
+    nbytes = tracer_bytes(L, NTRACERS, host(deep), host(shallow))
+    achieved = nbytes / (ms * 1e-3) / 1e9
+    return {"workload": f"{NTRACERS} passive tracers transported by the 884,736 x 30 step",
+            "ms": ms, "columns_per_s": n / (ms * 1e-3),
+            "roofline": {"bound": "hbm", "kernel": "k_tracers", "achieved": achieved,
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                         "algorithmic_bytes_per_launch": nbytes}}
+
+
 def bench_ensemble(torch, B, S, main_state, main_deep, main_shallow, reps, tune=True):
     """The 884,736-column grid plus 16 members of 55,296 columns (30/46/72 levels, tau 1800/3600/
     7200 s) as one ensemble: autotuned launch shape, captured HIP graph, timed replays; and the
@@ -343,6 +387,8 @@ def main():
     }
 
     if not args.no_extras:
+        out["tracers"] = bench_tracers(torch, B, conv, dev, deep, shallow, max(args.steps, 10))
+        print("[bench] tracers done", file=sys.stderr, flush=True)
         out["adjoint"] = bench_adjoint(torch, B, S, max(args.steps, 10))
         print("[bench] adjoint done", file=sys.stderr, flush=True)
         out["ensemble"] = bench_ensemble(torch, B, S, dev, deep, shallow, max(args.steps, 10),

@@ -215,7 +215,7 @@ int conv_step_backward(conv_ctx_t *ctx, const conv_state_t *state, const conv_de
  * plumes are not run again.  tracers, tend, deep_tend: device [ntr][nlev][ld] with the state's ld;
  * tend receives the deep + shallow tendency (s-1), deep_tend (may be NULL) the deep part alone.
  * Columns with neither scheme active get exact zeros.  ntr = 0 does nothing.  Returns CONV_EINVAL
- * for missing arrays or ntr < 0. */
+ * for missing arrays or ntr outside 0..65535. */
 int conv_tracer_transport(conv_ctx_t *ctx, const conv_state_t *state, const conv_deep_out_t *dfwd,
                           const conv_shallow_out_t *sfwd, int32_t ntr, const double *tracers,
                           double *tend, double *deep_tend, void *stream);

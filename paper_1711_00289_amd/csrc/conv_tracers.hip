@@ -12,13 +12,24 @@
 // mixing rates), the status and index outputs; the plumes are not run again.  The shallow scheme
 // transports the tracer already updated by the deep transport (Algorithm 1 order).
 //
-// One lane per column; tracers, then levels, innermost, so that a wavefront's stores of one level
-// are one contiguous 512-byte segment.  Quiet columns only store zeros.
+// One wavefront per block, one lane per column; block b takes tracer b % ntr of column block
+// b / ntr, so the tracers of one column block are dispatched together (they share its mass fluxes
+// in L2, and the slow convecting blocks spread over the run instead of piling up at its end).
+// A lane accumulates its
+// column's tendencies in LDS ([level][lane]); then the wavefront stores level by level with every
+// lane active, so each store covers whole 128-byte lines (stores that cover only part of a line,
+// as a wavefront mixing quiet and convecting columns would issue, run at a fraction of the
+// bandwidth on this part).  Quiet columns contribute zeros.
+#include <mutex>
+#include <set>
+
 #include "conv_internal.hpp"
 
 using namespace cvk;
 
 namespace {
+
+constexpr int TW = WAVE;  // threads per block
 
 struct TrArgs {
     Member M;          // state, both schemes' outputs and parameters of the step
@@ -28,100 +39,129 @@ struct TrArgs {
     double *dtend;     // deep tendency alone (may be NULL)
 };
 
-__global__ __launch_bounds__(BLOCK) void k_tracers(TrArgs a) {
+__global__ __launch_bounds__(TW) void k_tracers(TrArgs a) {
+    extern __shared__ double sh[];  // [nlev][TW]
     const Member &M = a.M;
-    const int64_t col = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    if (col >= M.ncol) return;
+    const int lane = threadIdx.x;
+    const int t = (int)(blockIdx.x % (unsigned)a.ntr);
+    const int64_t col = (int64_t)(blockIdx.x / (unsigned)a.ntr) * TW + lane;
+    const bool live = col < M.ncol;
     const int64_t ld = M.ld;
     const int L = M.nlev;
     const int64_t plane = (int64_t)L * ld;
     const conv_params_t &P = M.P;
+    const double *C = a.C + (int64_t)t * plane;
+    double *out = a.tend + (int64_t)t * plane;
+    double *dout = a.dtend ? a.dtend + (int64_t)t * plane : nullptr;
+#define SH(k) sh[(k) * TW + lane]
+
     // Active columns: status 0 with indices a status-0 column has, and a nonzero base mass flux
     // (the shallow closure's exp(-a CIN / sigma_w^2) can underflow to zero; such a plume moves
     // nothing).  Anything else moves nothing.
-    const int kb = M.dout.klaunch[col], kt = M.dout.ktop[col];
-    const int ks = M.sout.kbase[col], kts = M.sout.ktop[col];
-    const bool deep = M.dout.status[col] == 0 && kb >= 1 && kb < L && kt >= 0 && kt < kb &&
-                      AT(M.dout.mu, kb) > 0.0;
-    const bool shal = M.sout.status[col] == 0 && ks >= 1 && ks < L && kts >= 0 && kts < ks - 1 &&
-                      AT(M.sout.mu, ks) > 0.0;
+    bool deep = false, shal = false;
+    int kb = 0, kt = 0, ks = 0, kts = 0;
+    if (live) {
+        kb = M.dout.klaunch[col];
+        kt = M.dout.ktop[col];
+        ks = M.sout.kbase[col];
+        kts = M.sout.ktop[col];
+        deep = M.dout.status[col] == 0 && kb >= 1 && kb < L && kt >= 0 && kt < kb &&
+               AT(M.dout.mu, kb) > 0.0;
+        shal = M.sout.status[col] == 0 && ks >= 1 && ks < L && kts >= 0 && kts < ks - 1 &&
+               AT(M.sout.mu, ks) > 0.0;
+    }
     auto dp = [&](int k) { return AT(M.pi, k + 1) - AT(M.pi, k); };
     auto zi = [&](int i) { return 0.5 * (AT(M.z, i - 1) + AT(M.z, i)); };
-    // The downdraft starts at the first interface from the top where it carries mass.
-    int kd = -1;
-    if (deep)
-        for (int i = kt + 1; i <= kb; ++i)
-            if (AT(M.dout.md, i) != 0.0) {
-                kd = i - 1;
-                break;
-            }
 
-    for (int t = 0; t < a.ntr; ++t) {
-        const double *C = a.C + t * plane;
-        double *out = a.tend + t * plane;
-        double *dout = a.dtend ? a.dtend + t * plane : nullptr;
-        for (int k = 0; k < L; ++k) {
-            const bool in_d = deep && k >= kt && k <= kb;
-            const bool in_s = shal && k >= kts && k <= ks;
-            if (!in_d && !in_s) AT(out, k) = 0.0;
-            if (dout && !in_d) AT(dout, k) = 0.0;
+    // A wavefront with nothing convecting stores its zeros directly.
+    if (__ballot(deep || shal) == 0ull) {
+        if (live) {
+            for (int k = 0; k < L; ++k) {
+                AT(out, k) = 0.0;
+                if (dout) AT(dout, k) = 0.0;
+            }
         }
-        if (deep) {
-            // Updraft, bottom-up: C_u at interface i, its flux, and layer i's tendency from its
-            // bottom (Fb) and top fluxes.
-            double Cu = AT(C, kb), Fb = 0.0, mu1 = 0.0;
-            for (int i = kb; i >= kt + 1; --i) {
+        return;
+    }
+    for (int k = 0; k < L; ++k) SH(k) = 0.0;
+
+    if (deep) {
+        // Updraft, bottom-up: C_u at interface i, its flux, and layer i's tendency from its
+        // bottom (Fb) and top fluxes.  The next interface's loads are issued before the current
+        // one is computed (indices clamped: values loaded past the top are not used).  The
+        // downdraft's first interface (the highest one with md != 0) is noted on the way.
+        double Cu = AT(C, kb), Fb = 0.0, mu1 = 0.0;
+        double mu_n = AT(M.dout.mu, kb), md_n = AT(M.dout.md, kb), C_n = Cu, Cm_n = AT(C, kb - 1);
+        double pt_n = AT(M.pi, kb), pb_n = AT(M.pi, kb + 1);
+        int i0 = kb + 1;
+        for (int i = kb; i >= kt + 1; --i) {
+            const double mu = mu_n, md = md_n, Ci = C_n, Cim1 = Cm_n, ptop = pt_n, pbot = pb_n;
+            const int j = max(i - 1, 0), jj = max(i - 2, 0);
+            mu_n = AT(M.dout.mu, j);
+            md_n = AT(M.dout.md, j);
+            Cm_n = AT(C, jj);
+            pt_n = AT(M.pi, j);
+            C_n = Cim1;
+            pb_n = ptop;
+            if (md != 0.0) i0 = i;
+            if (i < kb) Cu = (mu1 * Cu + (mu - mu1) * Ci) / mu;
+            const double F = mu * (Cu - (mu + md >= 0.0 ? Cim1 : Ci));
+            SH(i) = (Fb - F) * GRAV / (pbot - ptop);
+            Fb = F;
+            mu1 = mu;
+        }
+        SH(kt) = Fb * GRAV / dp(kt);
+        // Downdraft, top-down from its first interface: C_d at interface i mixes layer i-1's air
+        // into C_d at i-1; its flux enters layer i-1 from below and leaves layer i at the top.
+        if (i0 <= kb) {
+            double Cd = AT(C, i0 - 1), ad1 = 0.0;
+            for (int i = i0; i <= kb; ++i) {
                 const double mu = AT(M.dout.mu, i), md = AT(M.dout.md, i);
-                if (i < kb) Cu = (mu1 * Cu + (mu - mu1) * AT(C, i)) / mu;
-                const double Cup = AT(C, mu + md >= 0.0 ? i - 1 : i);
-                const double F = mu * (Cu - Cup);
-                AT(out, i) = (Fb - F) * GRAV / dp(i);
-                Fb = F;
-                mu1 = mu;
+                const double ad = -md;
+                if (i > i0) Cd = (ad1 * Cd + (ad - ad1) * AT(C, i - 1)) / ad;
+                const double F = md * (Cd - AT(C, mu + md >= 0.0 ? i - 1 : i));
+                SH(i - 1) += F * GRAV / dp(i - 1);
+                SH(i) -= F * GRAV / dp(i);
+                ad1 = ad;
             }
-            AT(out, kt) = Fb * GRAV / dp(kt);
-            // Downdraft, top-down: C_d at interface i mixes layer i-1's air into C_d at i-1; its
-            // flux enters layer i-1 from below and leaves layer i at the top.
-            if (kd >= 0) {
-                double Cd = AT(C, kd), ad1 = 0.0;
-                for (int i = kd + 1; i <= kb; ++i) {
-                    const double mu = AT(M.dout.mu, i), md = AT(M.dout.md, i);
-                    const double ad = -md;
-                    if (i > kd + 1) Cd = (ad1 * Cd + (ad - ad1) * AT(C, i - 1)) / ad;
-                    const double F = md * (Cd - AT(C, mu + md >= 0.0 ? i - 1 : i));
-                    AT(out, i - 1) += F * GRAV / dp(i - 1);
-                    AT(out, i) -= F * GRAV / dp(i);
-                    ad1 = ad;
-                }
-            }
-            if (dout)
-                for (int k = kt; k <= kb; ++k) AT(dout, k) = AT(out, k);
-        }
-        if (shal) {
-            // The tracer the shallow scheme sees: updated by the deep transport.
-            auto in_d = [&](int k) { return deep && k >= kt && k <= kb; };
-            auto C2 = [&](int k) { return in_d(k) ? AT(C, k) + M.dt * AT(out, k) : AT(C, k); };
-            double csum = 0.0, wsum = 0.0;
-            for (int k = L - 1; k >= ks; --k) {
-                csum += dp(k) * C2(k);
-                wsum += dp(k);
-            }
-            double Cu = csum / wsum, Fb = 0.0, mu1 = 0.0;
-            for (int i = ks; i >= kts + 1; --i) {
-                const double mu = AT(M.sout.mu, i);
-                if (i < ks) {
-                    const double dz = zi(i) - zi(i + 1);
-                    const double E = P.eps_sh * mu1 * dz, D = P.delta_sh * mu1 * dz;
-                    Cu = ((mu1 - D) * Cu + E * C2(i)) / mu;
-                }
-                const double F = mu * (Cu - C2(i - 1));
-                AT(out, i) = (in_d(i) ? AT(out, i) : 0.0) + (Fb - F) * GRAV / dp(i);
-                Fb = F;
-                mu1 = mu;
-            }
-            AT(out, kts) = (in_d(kts) ? AT(out, kts) : 0.0) + Fb * GRAV / dp(kts);
         }
     }
+    if (dout) {
+        __builtin_amdgcn_wave_barrier();
+        if (live)
+            for (int k = 0; k < L; ++k) AT(dout, k) = SH(k);
+    }
+    if (shal) {
+        // The tracer the shallow scheme sees: updated by the deep transport (zero where the deep
+        // scheme left the column alone).
+        auto C2 = [&](int k) { return AT(C, k) + M.dt * SH(k); };
+        double csum = 0.0, wsum = 0.0;
+        for (int k = L - 1; k >= ks; --k) {
+            csum += dp(k) * C2(k);
+            wsum += dp(k);
+        }
+        // C2 reads the deep part of levels kts-1 .. L-1 before the shallow part is added to them:
+        // the recursion below adds to level i only after reading C2(i) and C2(i - 1) > level i.
+        double Cu = csum / wsum, Fb = 0.0, mu1 = 0.0;
+        for (int i = ks; i >= kts + 1; --i) {
+            const double mu = AT(M.sout.mu, i);
+            const double Cim1 = C2(i - 1);
+            if (i < ks) {
+                const double dz = zi(i) - zi(i + 1);
+                const double E = P.eps_sh * mu1 * dz, D = P.delta_sh * mu1 * dz;
+                Cu = ((mu1 - D) * Cu + E * C2(i)) / mu;
+            }
+            const double F = mu * (Cu - Cim1);
+            SH(i) += (Fb - F) * GRAV / dp(i);
+            Fb = F;
+            mu1 = mu;
+        }
+        SH(kts) += Fb * GRAV / dp(kts);
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (live)
+        for (int k = 0; k < L; ++k) AT(out, k) = SH(k);
+#undef SH
 }
 
 }  // namespace
@@ -131,7 +171,7 @@ extern "C" {
 int conv_tracer_transport(conv_ctx_t *ctx, const conv_state_t *state, const conv_deep_out_t *dfwd,
                           const conv_shallow_out_t *sfwd, int32_t ntr, const double *tracers,
                           double *tend, double *deep_tend, void *stream) {
-    if (!ctx || !state || !dfwd || !sfwd || ntr < 0) return CONV_EINVAL;
+    if (!ctx || !state || !dfwd || !sfwd || ntr < 0 || ntr > 65535) return CONV_EINVAL;
     if (!state->z || !state->p_int || state->ld < ctx->ncol || !(state->dt > 0.0)) return CONV_EINVAL;
     if (!dfwd->mu || !dfwd->md || !dfwd->status || !dfwd->klaunch || !dfwd->ktop || !sfwd->mu ||
         !sfwd->status || !sfwd->kbase || !sfwd->ktop)
@@ -144,8 +184,24 @@ int conv_tracer_transport(conv_ctx_t *ctx, const conv_state_t *state, const conv
     a.C = tracers;
     a.tend = tend;
     a.dtend = deep_tend;
-    const unsigned g = (unsigned)((ctx->ncol + BLOCK - 1) / BLOCK);
-    hipLaunchKernelGGL(k_tracers, dim3(g), dim3(BLOCK), 0, (hipStream_t)stream, a);
+    const size_t lds = (size_t)ctx->nlev * TW * sizeof(double);  // at most 128 KiB (nlev <= 256)
+    if (lds > 65536) {
+        static std::mutex mu;
+        static std::set<int> done;  // devices with the LDS limit of k_tracers raised
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess) return CONV_EHIP;
+        std::lock_guard<std::mutex> g(mu);
+        if (!done.count(dev)) {
+            if (hipFuncSetAttribute((const void *)k_tracers,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
+                hipSuccess)
+                return CONV_EHIP;
+            done.insert(dev);
+        }
+    }
+    const int64_t blocks = (ctx->ncol + TW - 1) / TW * ntr;
+    if (blocks > 0x7fffffff) return CONV_EINVAL;
+    hipLaunchKernelGGL(k_tracers, dim3((unsigned)blocks), dim3(TW), lds, (hipStream_t)stream, a);
     return check_launch();
 }
 
