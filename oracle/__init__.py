@@ -32,7 +32,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 PARAM_FIELDS = (
     "cape_threshold", "tau", "eps_deep", "alpha_dd", "evap_max_frac", "p_launch_min", "p_top_min",
     "eps_sh", "delta_sh", "qlcrit_sh", "cin_max", "a_buoy", "b_drag", "c_tke", "p_lcl_min",
-    "p_sh_top_min",
+    "p_sh_top_min", "eps_cape",
 )
 
 # Parameter defaults of the scheme reading (SI units).
@@ -40,6 +40,7 @@ DEFAULT_PARAMS = dict(
     cape_threshold=70.0, tau=3600.0, eps_deep=1.0e-4, alpha_dd=0.2, evap_max_frac=0.9,
     p_launch_min=60000.0, p_top_min=4000.0, eps_sh=1.0e-3, delta_sh=1.0e-3, qlcrit_sh=1.0e-3,
     cin_max=100.0, a_buoy=1.0, b_drag=1.0, c_tke=1.0, p_lcl_min=60000.0, p_sh_top_min=40000.0,
+    eps_cape=0.0,
 )
 
 

@@ -229,16 +229,26 @@ void deep_column(int L, const oracle_params_t &P, const R &tau, const R &epsd, c
         return;
     }
 
-    // D2: undilute pseudo-adiabatic parcel from layer kb, each layer independently.
+    // D2: pseudo-adiabatic parcel from layer kb, lifted layer by layer upward.  Undilute by
+    // default; with eps_cape > 0 it entrains environmental air on the way up (dilute CAPE): its
+    // mass grows by eps_cape per metre of mid-level height and h and the total water mix in as
+    // conserved quantities.  The condensate stays in the mixed water (not in the buoyancy), so
+    // eps_cape = 0 is exactly the undilute parcel of every layer lifted from kb's h and q.
     std::vector<R> Tp(L, R(0.0)), qp(L, R(0.0)), B(L, R(0.0));
     std::vector<char> sat(L, 0);
-    for (int k = klim; k < kb; ++k) {
-        R H = h[kb] - GRAV * z[k] - phis;
-        Lifted<R> pt = lift_(H, q[kb], pm[k]);
-        Tp[k] = pt.T;
-        qp[k] = pt.qv;
-        sat[k] = pt.sat;
-        B[k] = tv_(pt.T, pt.qv) - tv_(T[k], q[k]);
+    {
+        R hmix = h[kb], qmix = q[kb];
+        for (int k = kb - 1; k >= klim; --k) {
+            const double mix = P.eps_cape * (z[k] - z[k + 1]);
+            hmix = (hmix + mix * h[k]) / (1.0 + mix);
+            qmix = (qmix + mix * q[k]) / (1.0 + mix);
+            R H = hmix - GRAV * z[k] - phis;
+            Lifted<R> pt = lift_(H, qmix, pm[k]);
+            Tp[k] = pt.T;
+            qp[k] = pt.qv;
+            sat[k] = pt.sat;
+            B[k] = tv_(pt.T, pt.qv) - tv_(T[k], q[k]);
+        }
     }
     // D3: cloud top = highest layer in [klim, kb) with positive buoyancy.
     int kt = -1;
@@ -345,10 +355,31 @@ void deep_column(int L, const oracle_params_t &P, const R &tau, const R &epsd, c
     }
 
     // D8: closure.  F = -(d CAPE) along the unit tendencies with kb, kt and the saturation flags
-    // fixed (parcel perturbed through its launch-layer state), then M_c = CAPE / (tau * F).
+    // fixed, then M_c = CAPE / (tau * F).  The undilute parcel is perturbed through its
+    // launch-layer state; a dilute one also through the air it entrained on the way up.
     R dh = CP * dT1[kb] + LV * dq1[kb];
     R Fsum = R(0.0);
-    for (int k = kt; k <= kb - 1; ++k) {
+    if (P.eps_cape > 0.0) {
+        R dhm = dh, dqm = dq1[kb];
+        for (int k = kb - 1; k >= kt; --k) {
+            const double mix = P.eps_cape * (z[k] - z[k + 1]);
+            dhm = (dhm + mix * (CP * dT1[k] + LV * dq1[k])) / (1.0 + mix);
+            dqm = (dqm + mix * dq1[k]) / (1.0 + mix);
+            R dTp, dqp;
+            if (sat[k]) {
+                R qsp = dqsdT_(Tp[k], pm[k]);
+                dTp = dhm / (CP + LV * qsp);
+                dqp = qsp * dTp;
+            } else {
+                dTp = (dhm - LV * dqm) / CP;
+                dqp = dqm;
+            }
+            R dTvp = (1.0 + CVIR * qp[k]) * dTp + CVIR * Tp[k] * dqp;
+            R dTve = (1.0 + CVIR * q[k]) * dT1[k] + CVIR * T[k] * dq1[k];
+            Fsum = Fsum + g.lam[k] * (dTvp - dTve);
+        }
+    }
+    for (int k = kt; k <= kb - 1 && !(P.eps_cape > 0.0); ++k) {
         R dTp, dqp;
         if (sat[k]) {
             R qsp = dqsdT_(Tp[k], pm[k]);

@@ -24,6 +24,7 @@ extern "C" {
 typedef struct {
     double cape_threshold, tau, eps_deep, alpha_dd, evap_max_frac, p_launch_min, p_top_min;
     double eps_sh, delta_sh, qlcrit_sh, cin_max, a_buoy, b_drag, c_tke, p_lcl_min, p_sh_top_min;
+    double eps_cape; /* entrainment rate of the CAPE parcel, 1/m (0: undilute) */
 } oracle_params_t;
 
 typedef struct {
