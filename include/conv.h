@@ -70,6 +70,10 @@ typedef struct {
     double c_tke;          /* sigma_w^2 = c_tke * tke (1) */
     double p_lcl_min;      /* LCL must lie at p_mid >= this (60000 Pa) */
     double p_sh_top_min;   /* shallow LFC and plume top: p >= this (40000 Pa) */
+    double eps_cape;       /* entrainment rate of the CAPE parcel (0 1/m: undilute).  > 0: the
+                              parcel mixes in environmental air on its way up (dilute CAPE; h and
+                              total water mix in, eps_cape per metre of mid-level height) and the
+                              closure follows the entrained air too.  The adjoints support 0 only. */
 } conv_params_t;
 
 /* Input state (device pointers, read only). */
@@ -152,7 +156,9 @@ size_t conv_backward_workspace_bytes(int64_t ncol, int32_t nlev, int64_t ld);
  * Columns whose deep status is not 0 get zero gradients.  The parameter gradients are summed in a
  * fixed order (bit-reproducible).  `workspace`: caller-owned, 256-byte aligned, at least
  * conv_backward_workspace_bytes(ncol, nlev, ld) bytes; it may not be the context's forward
- * workspace.  The paper's deep convection (Algorithm 2) is the forward this differentiates. */
+ * workspace.  The paper's deep convection (Algorithm 2) is the forward this differentiates.
+ * Returns CONV_EUNSUPPORTED when the context's eps_cape is not 0 (the adjoint is of the undilute
+ * parcel). */
 int conv_deep_backward(conv_ctx_t *ctx, const conv_state_t *state, const conv_deep_out_t *fwd,
                        const conv_deep_cot_t *cot, conv_deep_grad_t *grad, void *workspace,
                        size_t ws_bytes, void *stream);
@@ -196,7 +202,8 @@ typedef struct {
  * through the update (identity plus dt times the deep tendencies' cotangent) into the deep
  * adjoint.  Branches are held fixed as for the two schemes' adjoints.  `dfwd` and `sfwd` must hold
  * the outputs of conv_step on the same state and parameters (status, klaunch, ktop, dTdt, dqdt of
- * the deep scheme; status, kbase, ktop of the shallow one).  Workspace as for conv_deep_backward. */
+ * the deep scheme; status, kbase, ktop of the shallow one).  Workspace as for conv_deep_backward.
+ * Returns CONV_EUNSUPPORTED when the context's eps_cape is not 0. */
 int conv_step_backward(conv_ctx_t *ctx, const conv_state_t *state, const conv_deep_out_t *dfwd,
                        const conv_shallow_out_t *sfwd, const conv_deep_cot_t *dcot,
                        const conv_shallow_cot_t *scot, conv_step_grad_t *grad, void *workspace,

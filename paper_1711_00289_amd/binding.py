@@ -17,12 +17,13 @@ CONV_OK, CONV_EINVAL, CONV_EUNSUPPORTED, CONV_EHIP = 0, -1, -2, -3
 PARAM_FIELDS = (
     "cape_threshold", "tau", "eps_deep", "alpha_dd", "evap_max_frac", "p_launch_min", "p_top_min",
     "eps_sh", "delta_sh", "qlcrit_sh", "cin_max", "a_buoy", "b_drag", "c_tke", "p_lcl_min",
-    "p_sh_top_min",
+    "p_sh_top_min", "eps_cape",
 )
 DEFAULTS = dict(
     cape_threshold=70.0, tau=3600.0, eps_deep=1.0e-4, alpha_dd=0.2, evap_max_frac=0.9,
     p_launch_min=60000.0, p_top_min=4000.0, eps_sh=1.0e-3, delta_sh=1.0e-3, qlcrit_sh=1.0e-3,
     cin_max=100.0, a_buoy=1.0, b_drag=1.0, c_tke=1.0, p_lcl_min=60000.0, p_sh_top_min=40000.0,
+    eps_cape=0.0,
 )
 
 EXPORTS = ("conv_workspace_bytes", "conv_create", "conv_set_params", "conv_destroy",

@@ -226,6 +226,8 @@ __global__ __launch_bounds__(BLOCK) void k_trigger(Src src, Work w) {
     double phis = 0.0, pblh = 0.0, tke = 0.0;
     int kb = -1;
     double hkb = 0.0, qkb = 0.0;
+    double hmix = 0.0, qmix = 0.0;  // the (dilute) parcel's h and total water
+    const bool dilute = P.eps_cape > 0.0;
     ShallowTrigger sh;
     sh.init(L);
     bool sstarted = false;
@@ -270,6 +272,8 @@ __global__ __launch_bounds__(BLOCK) void k_trigger(Src src, Work w) {
                     kb = k;  // a new launch layer: the parcel restarts above it
                     hkb = h;
                     qkb = v.q;
+                    hmix = h;
+                    qmix = v.q;
                     kt = -1;
                     S = SA = SB = Skt = SAkt = SBkt = 0.0;
                     hd.clear();
@@ -293,7 +297,12 @@ __global__ __launch_bounds__(BLOCK) void k_trigger(Src src, Work w) {
                 const double lam = log(pbot / v.pt);
                 const double tve = tv(v.T, v.q);
                 if (dd) {
-                    const Lifted r = lift(hkb - GRAV * v.z - phis, qkb, v.pm, hd);
+                    if (dilute) {  // entrain layer k's air over the rise from layer k+1
+                        const double mix = P.eps_cape * (v.z - zbelow);
+                        hmix = (hmix + mix * h) / (1.0 + mix);
+                        qmix = (qmix + mix * v.q) / (1.0 + mix);
+                    }
+                    const Lifted r = lift(hmix - GRAV * v.z - phis, qmix, v.pm, hd);
                     const double B = tv(r.T, r.qv) - tve;
                     S += RD * B * lam;
                     double ca, cb;
@@ -629,7 +638,41 @@ __global__ __launch_bounds__(BLOCK) void k_deep_plume(Src src, Work w) {
         }
 
         // D8: F from the launch-layer tendencies and the trigger's parcel sensitivities; D9, D10.
-        const double F = -RD * (dT1kb * SA + dq1kb * SB - Fenv);
+        // A dilute parcel is also moved by the air it entrained: its sensitivity is swept up from
+        // the launch layer along the unit tendencies, the parcel recomputed on the way.
+        double F = -RD * (dT1kb * SA + dq1kb * SB - Fenv);
+        if (P.eps_cape > 0.0) {
+            Hint hp;
+            hp.clear();
+            double hmix = (CP * AT(M.T, kb) + GRAV * AT(M.z, kb) + phis) + LV * AT(M.q, kb);
+            double qmix = AT(M.q, kb);
+            double dhm = CP * dT1kb + LV * dq1kb, dqm = dq1kb, Fsum = 0.0;
+            double zb = AT(M.z, kb);
+            for (int k = kb - 1; k >= kt; --k) {
+                const double Tk = AT(M.T, k), qk = AT(M.q, k), zk = AT(M.z, k), pm = AT(M.pm, k);
+                const double dT1 = SCR(X_DT1, k), dq1 = SCR(X_DQ1, k);
+                const double mix = P.eps_cape * (zk - zb);
+                hmix = (hmix + mix * ((CP * Tk + GRAV * zk + phis) + LV * qk)) / (1.0 + mix);
+                qmix = (qmix + mix * qk) / (1.0 + mix);
+                dhm = (dhm + mix * (CP * dT1 + LV * dq1)) / (1.0 + mix);
+                dqm = (dqm + mix * dq1) / (1.0 + mix);
+                const Lifted r = lift(hmix - GRAV * zk - phis, qmix, pm, hp);
+                double dTp, dqp;
+                if (r.sat) {
+                    const double Q1 = sat_eval(r.T, pm).dqs;  // qs' at the root itself
+                    dTp = dhm / (CP + LV * Q1);
+                    dqp = Q1 * dTp;
+                } else {
+                    dTp = (dhm - LV * dqm) * RCP_CP;
+                    dqp = dqm;
+                }
+                const double dTvp = (1.0 + CVIR * r.qv) * dTp + CVIR * r.T * dqp;
+                const double dTve = (1.0 + CVIR * qk) * dT1 + CVIR * Tk * dq1;
+                Fsum += log(AT(M.pi, k + 1) / AT(M.pi, k)) * (dTvp - dTve);
+                zb = zk;
+            }
+            F = -RD * Fsum;
+        }
         int st = 0;
         double Mb = 0.0;
         if (!(F > 0.0)) {

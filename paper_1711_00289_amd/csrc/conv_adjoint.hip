@@ -1020,6 +1020,7 @@ int conv_deep_backward(conv_ctx_t *ctx, const conv_state_t *state, const conv_de
     if (!fwd->status || !fwd->klaunch || !fwd->ktop || !grad->g_T || !grad->g_q || !grad->g_params)
         return CONV_EINVAL;
     if (((uintptr_t)workspace & 255u) != 0) return CONV_EINVAL;
+    if (ctx->P.eps_cape != 0.0) return CONV_EUNSUPPORTED;  // the adjoint is of the undilute parcel
     const AdjLayout l = adj_layout(ctx->ncol, ctx->nlev, ctx->cus);
     const int64_t ld = state->ld;
     if (ws_bytes < l.total + (size_t)2 * ld * sizeof(double)) return CONV_EINVAL;
@@ -1080,6 +1081,7 @@ int conv_step_backward(conv_ctx_t *ctx, const conv_state_t *state, const conv_de
         !grad->g_params)
         return CONV_EINVAL;
     if (((uintptr_t)workspace & 255u) != 0) return CONV_EINVAL;
+    if (ctx->P.eps_cape != 0.0) return CONV_EUNSUPPORTED;  // the deep adjoint is undilute
     const AdjLayout l = adj_layout(ctx->ncol, ctx->nlev, ctx->cus);
     const int64_t ld = state->ld;
     if (ws_bytes < l.total + (size_t)NPGRAD * ld * sizeof(double)) return CONV_EINVAL;
