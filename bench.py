@@ -35,12 +35,12 @@ NLON, NLAT = 1152, 768
 TRAFFIC_SOURCES = ("paper_1711_00289_amd/csrc/conv.hip", "paper_1711_00289_amd/csrc/conv_physics.hpp",
                    "paper_1711_00289_amd/csrc/conv_internal.hpp")
 MEASURED_TRAFFIC = {
-    "sources_sha256": "69a05461916b640012039103b9787d4d8be0945ba6e69834cbe63d643ca68253",
+    "sources_sha256": "f723bda93d0dd421c6cf1f00ed4694aa83602325a98d7019f8a817737bb79cf1",
     "fetch_factor": 2.0, "write_factor": 1.0,
-    "k_trigger": (533474, 1530023),
-    "k_deep_plume": (255215, 342386),
-    "k_shallow_retrigger": (120524, 9254),
-    "k_shallow_plume": (47699, 18146),
+    "k_trigger": (533438, 1530017),
+    "k_deep_plume": (253014, 343091),
+    "k_shallow_retrigger": (121214, 9254),
+    "k_shallow_plume": (48212, 18114),
 }
 
 
@@ -195,6 +195,19 @@ def bench_tracers(torch, B, conv, dev, deep, shallow, reps):
             "roofline": {"bound": "hbm", "kernel": "k_tracers", "achieved": achieved,
                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                          "algorithmic_bytes_per_launch": nbytes}}
+
+
+def bench_dilute(torch, B, dev, n, reps, eps_cape=1e-4):
+    """The step on the headline grid with the dilute (entraining) CAPE parcel."""
+    conv = B.Conv(n, NLEV, B.make_params(eps_cape=eps_cape))
+    deep, shallow = conv.step(dev)
+    for _ in range(3):
+        conv.step(dev, deep, shallow)
+    ms = time_events(torch, lambda: conv.step(dev, deep, shallow), reps)
+    return {"workload": f"conv_step on the 884,736 x 30 grid with eps_cape = {eps_cape} 1/m",
+            "ms_per_step": ms, "columns_per_s": n / (ms * 1e-3),
+            "deep_active_fraction": float((deep["status"] == 0).double().mean()),
+            "shallow_active_fraction": float((shallow["status"] == 0).double().mean())}
 
 
 def bench_ensemble(torch, B, S, main_state, main_deep, main_shallow, reps, tune=True):
@@ -389,6 +402,8 @@ def main():
     if not args.no_extras:
         out["tracers"] = bench_tracers(torch, B, conv, dev, deep, shallow, max(args.steps, 10))
         print("[bench] tracers done", file=sys.stderr, flush=True)
+        out["dilute"] = bench_dilute(torch, B, dev, n, max(args.steps, 10))
+        print("[bench] dilute done", file=sys.stderr, flush=True)
         out["adjoint"] = bench_adjoint(torch, B, S, max(args.steps, 10))
         print("[bench] adjoint done", file=sys.stderr, flush=True)
         out["ensemble"] = bench_ensemble(torch, B, S, dev, deep, shallow, max(args.steps, 10),
