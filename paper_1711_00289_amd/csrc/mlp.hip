@@ -1,7 +1,9 @@
 // mlp.hip -- the surrogate network's kernels for gfx950 (include/mlp.h): one tiled BF16 GEMM on
 // the matrix cores (v_mfma_f32_32x32x16_bf16, FP32 accumulation) with fused epilogues, used for the
-// forward layers (bias + GELU), the backward data gradient (times GELU') and, on transposed copies
-// with the batch split across blocks, the weight gradients; plus column sums, MSE and Adam.
+// forward layers (bias + GELU), the backward data gradient (times GELU') and, on batch-contiguous
+// (transposed) copies with the batch split across blocks, the weight gradients; plus the bias
+// gradients' row sums, MSE and Adam (which also refreshes the weights' BF16 copies).  In training
+// the forward and data-gradient products write the transposed copies from their epilogues.
 //
 // GEMM tiling: a block computes a BM x BN tile (128 x 128, 256 x 256 or 128 x 64, chosen by shape)
 // with its wavefronts in a WM x WN arrangement, each owning (BM/WM) x (BN/WN) as 32 x 32 MFMA
@@ -9,9 +11,11 @@
 // from global memory into registers while the current one feeds the MFMAs, and every row of a tile
 // is one full 128-byte line.  Block ids are mapped so that the N tiles of one M tile run on the
 // same XCD (the hardware deals consecutive blocks to the 8 XCDs in turn), so an activation tile is
-// fetched into one XCD's L2 once and reused there.  The epilogue stages each wavefront's
+// fetched into one XCD's L2 once and reused there; products with fewer M tiles than XCDs take
+// their tiles in plain order.  The epilogue stages each wavefront's
 // accumulators in LDS 32 rows at a time and finishes them in chunks of 8 consecutive columns of a
-// row, so that bias, pre-activation and outputs move in 16-byte loads and stores.
+// row, so that bias, pre-activation and outputs move in 16-byte loads and stores; a transposed
+// copy is gathered column by column from the same strips.
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -85,6 +89,7 @@ struct GemmArgs {
     int64_t M;
     int N, K;
     int tiles_m, tiles_n;
+    int xmap;    // XCD-grouped block order (at least NXCD tiles along M), else row-major tiles
     int ksplit;  // > 0: blockIdx.y covers K range [y*ksplit, (y+1)*ksplit)
     int mode;
     int vec;     // 16-byte epilogue accesses allowed (alignment of c, z, bias, ldc, split_stride)
@@ -93,6 +98,11 @@ struct GemmArgs {
     int64_t ldc;
     float *z;  // EPI_GELU output / EPI_DGELU input, leading dimension ldc
     int64_t split_stride;
+    // EPI_GELU / EPI_DGELU: optional transposed copy of the bf16 output, ct[n * ldt + m] for
+    // m < ldt (rows M <= m < ldt are zero), so that a later product can read it along the batch.
+    // Tiles with at most 64 columns per wavefront only; ldt % 8 == 0 and ct 16-byte aligned.
+    uint16_t *ct;
+    int64_t ldt;
 };
 
 // Global -> register -> LDS staging of one operand tile of ROWS x BK (element (r, k) at
@@ -144,11 +154,18 @@ __global__ __launch_bounds__(WM * WN * 64) void k_gemm(GemmArgs g) {
 
     const int t = threadIdx.x, lane = t & 63, w = t >> 6, wm = w / WN, wn = w % WN;
     const int64_t bid = blockIdx.x;
-    const int xcd = (int)(bid % NXCD);
-    const int64_t j = bid / NXCD;
-    const int tn = (int)(j % g.tiles_n);
-    const int64_t tm = (j / g.tiles_n) * NXCD + xcd;
-    if (tm >= g.tiles_m) return;
+    int tn;
+    int64_t tm;
+    if (g.xmap) {
+        const int xcd = (int)(bid % NXCD);
+        const int64_t j = bid / NXCD;
+        tn = (int)(j % g.tiles_n);
+        tm = (j / g.tiles_n) * NXCD + xcd;
+        if (tm >= g.tiles_m) return;
+    } else {
+        tn = (int)(bid % g.tiles_n);
+        tm = bid / g.tiles_n;
+    }
     const int64_t m0 = tm * BM;
     const int n0 = tn * BN;
     int k0 = 0, k1 = g.K;
@@ -214,6 +231,16 @@ __global__ __launch_bounds__(WM * WN * 64) void k_gemm(GemmArgs g) {
     constexpr int NCH = 32 * CPR / 64;   // chunks per lane per strip
     static_assert((32 * CPR) % 64 == 0, "strip chunks must divide among the lanes");
     const bool use_bias = g.bias && (g.mode == EPI_F32 || g.mode == EPI_GELU);
+    // Transposed copy: lane c of the wavefront owns column c of its strips and gathers the
+    // finished values of its TM * 32 rows, two BF16 per register.
+    constexpr bool CT_OK = SW <= 64;
+    constexpr int TLD = TM * 32 + 8;  // row stride (bf16) of the transposed tile T in LDS
+    static_assert(!CT_OK || WM * WN * (32 * SLD * sizeof(float) + SW * TLD * sizeof(uint16_t)) <=
+                                gemm_lds_bytes<BM, BN, WM, WN>(),
+                  "strips and transposed tiles must fit in the operand buffers");
+    const bool ct = CT_OK && g.ct != nullptr;
+    const int64_t mw = m0 + wm * (BM / WM);  // first row of this wavefront
+    uint32_t pk[CT_OK ? TM * 16 : 1];
 #pragma unroll
     for (int a = 0; a < TM; ++a) {
 #pragma unroll
@@ -284,6 +311,10 @@ __global__ __launch_bounds__(WM * WN * 64) void k_gemm(GemmArgs g) {
 #pragma unroll
                 for (int e = 0; e < 8; ++e) v[e] *= gelu_grad(x[e]);
             }
+            if (ct) {  // the finished values back into the strip for the column gather
+                *(float4 *)&strip[rr * SLD + cc] = *(float4 *)&v[0];
+                *(float4 *)&strip[rr * SLD + cc + 4] = *(float4 *)&v[4];
+            }
             uint16_t *c = (uint16_t *)g.c + o;
             if (full) {
                 uint32_t h[4];
@@ -297,8 +328,51 @@ __global__ __launch_bounds__(WM * WN * 64) void k_gemm(GemmArgs g) {
                     if (e < cnt) c[e] = f2bf(v[e]);
             }
         }
+        if constexpr (CT_OK) {
+            if (ct) {
+                __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): finished values are in the strip
+                __builtin_amdgcn_wave_barrier();
+                if (lane < SW) {
+#pragma unroll
+                    for (int rr = 0; rr < 32; rr += 2) {
+                        const int64_t m = mw + a * 32 + rr;
+                        const uint32_t lo = m < g.M ? f2bf(strip[rr * SLD + lane]) : 0u;
+                        const uint32_t hi = m + 1 < g.M ? f2bf(strip[(rr + 1) * SLD + lane]) : 0u;
+                        pk[a * 16 + rr / 2] = lo | (hi << 16);
+                    }
+                }
+            }
+        }
         __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): the strip is read before it is reused
         __builtin_amdgcn_wave_barrier();
+    }
+    if constexpr (CT_OK) {
+        // Through LDS once more so that each store instruction covers whole lines: lane c puts its
+        // column (TM * 32 rows, 16 bytes per 8 rows) in row c of T, then the wavefront stores
+        // 64 / PIECES columns per instruction, PIECES lanes per column.
+        constexpr int PIECES = TM * 4, CPI = 64 / PIECES;
+        static_assert(64 % PIECES == 0 && SW % CPI == 0, "column pieces must tile the wavefront");
+        if (ct) {
+            uint16_t *T = (uint16_t *)((float *)smem + WM * WN * 32 * SLD) + w * SW * TLD;
+            if (lane < SW) {
+#pragma unroll
+                for (int q = 0; q < PIECES; ++q)
+                    *(uint4 *)&T[lane * TLD + 8 * q] =
+                        make_uint4(pk[4 * q], pk[4 * q + 1], pk[4 * q + 2], pk[4 * q + 3]);
+            }
+            __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): T is written
+            __builtin_amdgcn_wave_barrier();
+            const int piece = lane % PIECES;
+            const int64_t m = mw + 8 * piece;  // ldt % 8 == 0: a piece below ldt is whole
+#pragma unroll
+            for (int i = 0; i < SW / CPI; ++i) {
+                const int col = i * CPI + lane / PIECES;
+                const int n = n0 + wn * (BN / WN) + col;
+                if (n < g.N && m < g.ldt)
+                    *(uint4 *)(g.ct + (int64_t)n * g.ldt + m) =
+                        *(const uint4 *)&T[col * TLD + 8 * piece];
+            }
+        }
     }
 }
 
@@ -306,8 +380,11 @@ template <int BM, int BN, int WM, int WN>
 int launch_tiles(GemmArgs g, int splits, hipStream_t st) {
     g.tiles_m = (int)((g.M + BM - 1) / BM);
     g.tiles_n = (g.N + BN - 1) / BN;
+    // With fewer M tiles than XCDs (the weight gradients' few tiles, split along K), grouping by
+    // XCD would leave XCDs idle: tiles then go in plain order and the splits spread them.
+    g.xmap = g.tiles_m >= NXCD;
     const int64_t mgroups = (g.tiles_m + NXCD - 1) / NXCD;
-    const int64_t blocks = mgroups * NXCD * g.tiles_n;
+    const int64_t blocks = g.xmap ? mgroups * NXCD * g.tiles_n : (int64_t)g.tiles_m * g.tiles_n;
     if (blocks <= 0 || blocks > 0x7fffffff || splits < 1) return MLP_EINVAL;
     constexpr size_t lds = gemm_lds_bytes<BM, BN, WM, WN>();
     // The LDS limit above 64 KiB is a per-device function attribute: set once per device.
@@ -333,6 +410,12 @@ int launch_gemm(const GemmArgs &in, int splits, hipStream_t st) {
     GemmArgs g = in;
     g.vec = al16(g.c) && (!g.z || al16(g.z)) && (!g.bias || al16(g.bias)) && g.ldc % 8 == 0 &&
             g.split_stride % 8 == 0;
+    if (g.ct) {  // the transposed copy needs at most 64 columns per wavefront
+        if (!al16(g.ct) || g.ldt % 8 != 0 || g.ldt < g.M || (g.mode != EPI_GELU && g.mode != EPI_DGELU))
+            return MLP_EINVAL;
+        if (g.N <= 64) return launch_tiles<128, 64, 2, 2>(g, splits, st);
+        return launch_tiles<128, 128, 2, 2>(g, splits, st);
+    }
     if (g.N <= 64) return launch_tiles<128, 64, 2, 2>(g, splits, st);
     const int64_t big = ((g.M + 255) / 256) * ((g.N + 255) / 256) * splits;
     if (g.N % 256 == 0 && big >= 1024) return launch_tiles<256, 256, 4, 2>(g, splits, st);
@@ -362,45 +445,50 @@ __global__ __launch_bounds__(THREADS) void k_transpose(const uint16_t *in, int64
 }
 
 // ------------------------------------------------------------------ reductions, loss, optimiser
-// part[s][n] = sum over rows [s*chunk, min((s+1)*chunk, rows)) of x[r][n] (bf16): four running
-// sums over rows r = 4j + {0,1,2,3} (independent, so the loads overlap), then added in order.
-__global__ __launch_bounds__(THREADS) void k_colsum_partial(const uint16_t *x, int64_t rows, int n,
-                                                            int64_t chunk, float *part) {
-    const int c = blockIdx.x * THREADS + threadIdx.x;
-    if (c >= n) return;
-    const int64_t r0 = (int64_t)blockIdx.y * chunk;
-    const int64_t r1 = r0 + chunk < rows ? r0 + chunk : rows;
-    float s[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll 4
-    for (int64_t r = r0; r < r1; ++r) s[(r - r0) & 3] += __uint_as_float((uint32_t)x[r * n + c] << 16);
-    part[(int64_t)blockIdx.y * n + c] = (s[0] + s[1]) + (s[2] + s[3]);
-}
-
-// out[i] = sum over s < S of part[s*len + i] for few outputs and many partials: one block per
-// output, a strided sum per thread and a fixed-shape tree.
-__global__ __launch_bounds__(THREADS) void k_sum_parts_tree(const float *part, int S, int64_t len,
-                                                            float *out) {
+// out[r] = sum over b < ld of x[r*ld + b] (bf16; ld % 8 == 0, the padding past the batch is zero):
+// one block per row, 16-byte loads, each thread's values summed in a fixed order, then a
+// fixed-shape tree.
+__global__ __launch_bounds__(THREADS) void k_rowsum(const uint16_t *x, int64_t ld, float *out) {
     __shared__ float sh[THREADS];
-    const int64_t i = blockIdx.x;
-    float v = 0.0f;
-    for (int k = threadIdx.x; k < S; k += THREADS) v += part[(int64_t)k * len + i];
-    sh[threadIdx.x] = v;
+    const uint16_t *row = x + (int64_t)blockIdx.x * ld;
+    float s[2] = {0.0f, 0.0f};
+    for (int64_t b = (int64_t)threadIdx.x * 8; b < ld; b += THREADS * 8) {
+        const uint4 v = *(const uint4 *)(row + b);
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            s[0] += __uint_as_float(w[e] << 16);
+            s[1] += __uint_as_float(w[e] & 0xFFFF0000u);
+        }
+    }
+    sh[threadIdx.x] = s[0] + s[1];
     __syncthreads();
     for (int h = THREADS / 2; h > 0; h /= 2) {
         if ((int)threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[i] = sh[0];
+    if (threadIdx.x == 0) out[blockIdx.x] = sh[0];
 }
 
-// out[i] = sum_{s < S} part[s*len + i], in order of s.
+// out[i] = sum over s < S of part[s*len + i]: a block takes 64 consecutive outputs, wavefront g
+// of its four sums partials g, g + 4, g + 8, ... in order, and the four sums are added in a fixed
+// order (so each output has four independent load chains instead of one).
+constexpr int SUM_COLS = 64;
+static_assert(THREADS == 4 * SUM_COLS, "k_sum_parts adds four wavefronts' sums");
 __global__ __launch_bounds__(THREADS) void k_sum_parts(const float *part, int S, int64_t len,
                                                        float *out) {
-    const int64_t i = (int64_t)blockIdx.x * THREADS + threadIdx.x;
-    if (i >= len) return;
+    __shared__ float sh[THREADS];
+    const int o = threadIdx.x % SUM_COLS, g = threadIdx.x / SUM_COLS;
+    const int64_t i = (int64_t)blockIdx.x * SUM_COLS + o;
     float s = 0.0f;
-    for (int k = 0; k < S; ++k) s += part[(int64_t)k * len + i];
-    out[i] = s;
+    if (i < len) {
+#pragma unroll 4
+        for (int k = g; k < S; k += THREADS / SUM_COLS) s += part[(int64_t)k * len + i];
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    if (g == 0 && i < len)
+        out[i] = (sh[o] + sh[SUM_COLS + o]) + (sh[2 * SUM_COLS + o] + sh[3 * SUM_COLS + o]);
 }
 
 __device__ float block_sum(float v) {  // fixed-shape tree over the block; result in thread 0
@@ -439,9 +527,19 @@ __global__ __launch_bounds__(THREADS) void k_mse_final(const float *part, int64_
     if (threadIdx.x == 0) loss[0] = tot * scale;
 }
 
+// Where each layer's weights sit in the parameter vector, and their BF16 copies.
+struct BfMap {
+    int n;
+    int64_t poff[MLP_MAX_LAYERS];
+    int no[MLP_MAX_LAYERS], ni[MLP_MAX_LAYERS];
+    uint16_t *wb[MLP_MAX_LAYERS], *wt[MLP_MAX_LAYERS];
+};
+
+// Adam on every parameter; a weight's new value also goes to its BF16 copies: wb (the layout of
+// W [no][ni]) and wt (transposed, [ni][no]).
 __global__ __launch_bounds__(THREADS) void k_adam(float *p, const float *g, float *m, float *v,
                                                   int64_t n, float lr, float b1, float b2, float eps,
-                                                  float bc1, float bc2) {
+                                                  float bc1, float bc2, BfMap bm) {
     const int64_t i = (int64_t)blockIdx.x * THREADS + threadIdx.x;
     if (i >= n) return;
     const float gi = g[i];
@@ -449,7 +547,26 @@ __global__ __launch_bounds__(THREADS) void k_adam(float *p, const float *g, floa
     const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
     m[i] = mi;
     v[i] = vi;
-    p[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+    const float pi = p[i] - lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+    p[i] = pi;
+    int64_t off = i;
+    int no = 0, ni = 0;
+    uint16_t *wb = nullptr, *wt = nullptr;
+#pragma unroll
+    for (int l = 0; l < MLP_MAX_LAYERS; ++l)  // the layer holding parameter i
+        if (l < bm.n && i >= bm.poff[l]) {
+            off = i - bm.poff[l];
+            no = bm.no[l];
+            ni = bm.ni[l];
+            wb = bm.wb[l];
+            wt = bm.wt[l];
+        }
+    if (off < (int64_t)no * ni) {  // a weight, not a bias
+        const uint16_t h = f2bf(pi);
+        const int r = (int)(off / ni), c = (int)(off % ni);
+        wb[off] = h;
+        wt[(int64_t)c * no + r] = h;
+    }
 }
 
 // BF16 copies of W [rows][cols]: wb (same layout) and wt (transposed [cols][rows]).
@@ -495,11 +612,14 @@ void wgrad_split(int64_t batch, int M, int N, int *S, int *chunk) {
 }
 
 constexpr int MAX_SPLIT = 64;
-constexpr int COLSUM_ROWS = 64;  // rows per partial of the bias-gradient column sums
 
 struct Layout {
     size_t params, grads, am, av, wb[MLP_MAX_LAYERS], wt[MLP_MAX_LAYERS];
-    size_t act[MLP_MAX_LAYERS], zf[MLP_MAX_LAYERS], dz[2], tr[2], part, lpart, total;
+    size_t act[MLP_MAX_LAYERS], zf[MLP_MAX_LAYERS], dz[2], part, lpart, total;
+    // Batch-contiguous (transposed) copies for the weight gradients, rows of ldt = max_batch
+    // rounded up to 8: actT[i] [w_i][ldt] written by the forward with keep, dzT [w][ldt] the
+    // current layer's output gradient, xT [w_0][ldt] the input.
+    size_t actT[MLP_MAX_LAYERS], dzT, xT;
     int64_t P;
     int64_t poff[MLP_MAX_LAYERS];  // offset of W_l in the parameter vector (b_l follows)
 };
@@ -527,8 +647,6 @@ Layout make_layout(const int32_t *w, int n, int64_t maxb) {
         P += (int64_t)w[i + 1] * w[i] + w[i + 1];
         size_t need = (size_t)MAX_SPLIT * w[i + 1] * w[i];
         if (need > pmax) pmax = need;
-        need = (size_t)((maxb + COLSUM_ROWS - 1) / COLSUM_ROWS) * w[i + 1];
-        if (need > pmax) pmax = need;
     }
     for (int i = 0; i <= n; ++i) wmax = w[i] > wmax ? w[i] : wmax;
     l.P = P;
@@ -540,14 +658,16 @@ Layout make_layout(const int32_t *w, int n, int64_t maxb) {
         l.wb[i] = take((size_t)w[i + 1] * w[i] * 2);
         l.wt[i] = take((size_t)w[i + 1] * w[i] * 2);
     }
+    const size_t ldt = (size_t)(maxb + 7) / 8 * 8;
     for (int i = 1; i < n; ++i) {
         l.act[i] = take((size_t)maxb * w[i] * 2);
         l.zf[i] = take((size_t)maxb * w[i] * 4);
+        l.actT[i] = take(ldt * w[i] * 2);
     }
     l.dz[0] = take((size_t)maxb * wmax * 2);
-    l.tr[0] = take((size_t)(maxb + TT) * wmax * 2);  // transposed copies for the weight gradient
-    l.tr[1] = take((size_t)(maxb + TT) * wmax * 2);
     l.dz[1] = take((size_t)maxb * wmax * 2);
+    l.dzT = take(ldt * wmax * 2);
+    l.xT = take(ldt * w[0] * 2);
     l.part = take(pmax * sizeof(float));
     l.lpart = take(((size_t)maxb * w[n] + THREADS - 1) / THREADS * sizeof(float));
     l.total = off;
@@ -667,7 +787,11 @@ int mlp_forward(mlp_t *m, const uint16_t *x, float *y, int64_t batch, int keep, 
         if (i + 1 < m->n) {
             g.mode = EPI_GELU;
             g.c = hp(m, m->lay.act[i + 1]);
-            g.z = keep ? fp(m, m->lay.zf[i + 1]) : nullptr;
+            if (keep) {
+                g.z = fp(m, m->lay.zf[i + 1]);
+                g.ct = hp(m, m->lay.actT[i + 1]);
+                g.ldt = (batch + 7) / 8 * 8;
+            }
         } else {
             g.mode = EPI_F32;
             g.c = y;
@@ -707,20 +831,25 @@ int mlp_backward(mlp_t *m, int64_t batch, void *stream) {
     hipStream_t st = (hipStream_t)stream;
     int cur = m->dz_top;
     float *part = fp(m, m->lay.part);
+    // Weight gradients dW_i[no][ni] = sum_b dz[b][no] ain[b][ni] read both factors along the batch:
+    // rows of ldt (the batch rounded up to 8, zero past it).  The hidden activations' copies come
+    // from the forward, the hidden gradients' from the data-gradient products; the input's and
+    // the output gradient's are transposed here.
+    const int64_t ldt = (batch + 7) / 8 * 8;
+    uint16_t *dzT = hp(m, m->lay.dzT), *xT = hp(m, m->lay.xT);
+    const int wo = m->w[m->n], w0 = m->w[0];
+    hipLaunchKernelGGL(k_transpose, dim3((wo + TT - 1) / TT, (unsigned)((ldt + TT - 1) / TT)),
+                       dim3(THREADS), 0, st, (const uint16_t *)hp(m, m->lay.dz[cur]), batch, wo,
+                       ldt, dzT);
+    hipLaunchKernelGGL(k_transpose, dim3((w0 + TT - 1) / TT, (unsigned)((ldt + TT - 1) / TT)),
+                       dim3(THREADS), 0, st, m->x, batch, w0, ldt, xT);
     for (int i = m->n - 1; i >= 0; --i) {
         const int no = m->w[i + 1], ni = m->w[i];
         const uint16_t *dz = hp(m, m->lay.dz[cur]);
-        const uint16_t *ain = i == 0 ? m->x : hp(m, m->lay.act[i]);
+        const uint16_t *aT = i == 0 ? xT : hp(m, m->lay.actT[i]);
         float *gW = fp(m, m->lay.grads) + m->lay.poff[i];
         float *gb = gW + (int64_t)no * ni;
-        // dW_i[no][ni] = sum_b dz[b][no] * ain[b][ni]: both factors transposed to batch-contiguous
-        // rows (zero-padded to a multiple of 8), then the NT kernel with the batch split.
-        const int64_t ldt = (batch + 7) / 8 * 8;
-        uint16_t *dzT = hp(m, m->lay.tr[0]), *aT = hp(m, m->lay.tr[1]);
-        hipLaunchKernelGGL(k_transpose, dim3((no + TT - 1) / TT, (unsigned)((ldt + TT - 1) / TT)),
-                           dim3(THREADS), 0, st, dz, batch, no, ldt, dzT);
-        hipLaunchKernelGGL(k_transpose, dim3((ni + TT - 1) / TT, (unsigned)((ldt + TT - 1) / TT)),
-                           dim3(THREADS), 0, st, ain, batch, ni, ldt, aT);
+        // dW: the NT kernel over the batch, split across blocks, partials summed in order.
         int S, chunk;
         wgrad_split(ldt, no, ni, &S, &chunk);
         GemmArgs g{};
@@ -738,17 +867,14 @@ int mlp_backward(mlp_t *m, int64_t batch, void *stream) {
         g.split_stride = (int64_t)no * ni;
         int rc = launch_gemm(g, S, st);
         if (rc != MLP_OK) return rc;
-        hipLaunchKernelGGL(k_sum_parts, dim3(nblocks((int64_t)no * ni)), dim3(THREADS), 0, st,
-                           (const float *)part, S, (int64_t)no * ni, gW);
-        // db_i[no] = sum_b dz[b][no], in chunks of COLSUM_ROWS rows, then over the chunks
-        const int64_t rchunk = COLSUM_ROWS;
-        const int RS = (int)((batch + rchunk - 1) / rchunk);
-        hipLaunchKernelGGL(k_colsum_partial, dim3(nblocks(no), RS), dim3(THREADS), 0, st, dz, batch,
-                           no, rchunk, part);
-        hipLaunchKernelGGL(k_sum_parts_tree, dim3(no), dim3(THREADS), 0, st, (const float *)part, RS,
-                           (int64_t)no, gb);
+        const unsigned sblocks = (unsigned)(((int64_t)no * ni + SUM_COLS - 1) / SUM_COLS);
+        hipLaunchKernelGGL(k_sum_parts, dim3(sblocks), dim3(THREADS), 0, st, (const float *)part, S,
+                           (int64_t)no * ni, gW);
+        // db_i[no] = sum_b dz[b][no]: row sums of the transposed gradient
+        hipLaunchKernelGGL(k_rowsum, dim3(no), dim3(THREADS), 0, st, (const uint16_t *)dzT, ldt, gb);
         if (i == 0) break;
-        // dz_prev[b][ni] = (sum_n dz[b][n] W_i[n][ni]) * gelu'(z_i[b][ni])
+        // dz_prev[b][ni] = (sum_n dz[b][n] W_i[n][ni]) * gelu'(z_i[b][ni]), and its transposed
+        // copy over dzT (whose last readers, the products above, come first on the stream).
         GemmArgs d{};
         d.a = dz;
         d.lda = no;
@@ -761,6 +887,8 @@ int mlp_backward(mlp_t *m, int64_t batch, void *stream) {
         d.c = hp(m, m->lay.dz[cur ^ 1]);
         d.ldc = ni;
         d.z = fp(m, m->lay.zf[i]);
+        d.ct = dzT;
+        d.ldt = ldt;
         rc = launch_gemm(d, 1, st);
         if (rc != MLP_OK) return rc;
         cur ^= 1;
@@ -777,10 +905,19 @@ int mlp_adam_step(mlp_t *m, float lr, float beta1, float beta2, float eps, void 
     const float bc1 = (float)(1.0 - pow((double)beta1, (double)m->t));
     const float bc2 = (float)(1.0 - pow((double)beta2, (double)m->t));
     const int64_t P = m->lay.P;
+    BfMap bm{};
+    bm.n = m->n;
+    for (int i = 0; i < m->n; ++i) {
+        bm.poff[i] = m->lay.poff[i];
+        bm.no[i] = m->w[i + 1];
+        bm.ni[i] = m->w[i];
+        bm.wb[i] = hp(m, m->lay.wb[i]);
+        bm.wt[i] = hp(m, m->lay.wt[i]);
+    }
     hipLaunchKernelGGL(k_adam, dim3(nblocks(P)), dim3(THREADS), 0, st, fp(m, m->lay.params),
                        (const float *)fp(m, m->lay.grads), fp(m, m->lay.am), fp(m, m->lay.av), P, lr,
-                       beta1, beta2, eps, bc1, bc2);
-    return refresh_bf16(m, st);
+                       beta1, beta2, eps, bc1, bc2, bm);
+    return check();
 }
 
 int mlp_train_step(mlp_t *m, const uint16_t *x, const float *target, int64_t batch, int n_valid,
