@@ -357,8 +357,9 @@ def test_ragged_sizes(torch, n):
         assert np.abs(g["g_T"][:, c] - gT).max() <= TOL * np.abs(gT).max()
 
 
-def test_other_level_count(torch):
-    st = S.make_state(300, 46, seed=404, warm=np.ones(300, dtype=bool))
+@pytest.mark.parametrize("nlev", [46, 256])
+def test_other_level_count(torch, nlev):
+    st = S.make_state(300, nlev, seed=404, warm=np.ones(300, dtype=bool))
     L, n = st["nlev"], st["ncol"]
     rng = np.random.default_rng(31)
     cT, cq, cP = _cotangents(rng, L, n)

@@ -134,13 +134,16 @@ def test_invalid_and_quiet_columns(torch):
     assert list(d["status"][1:5]) == [3, 3, 3, 3] and list(s["status"][1:6]) == [6] * 5
 
 
-@pytest.mark.parametrize("nlev", [46, 72])
+@pytest.mark.parametrize("nlev", [2, 3, 46, 72, 256])
 def test_other_level_counts(torch, nlev):
+    """From the fewest levels the context accepts (nothing can trigger) to the most (256)."""
     st = S.make_state(3000, nlev, seed=77, warm=np.arange(3000) < 1500)
     d, s = run_gpu(st, "step")
     od, osh = oracle.step(st)
     compare_deep(d, od, 3000)
     compare_shallow(s, osh, 3000)
+    if nlev >= 46:
+        assert (d["status"] == 0).sum() > 500 and (s["status"] == 0).sum() > 100
 
 
 @pytest.mark.parametrize("over", [dict(alpha_dd=0.0), dict(eps_deep=0.0), dict(eps_deep=5e-4),

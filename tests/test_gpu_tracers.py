@@ -9,6 +9,7 @@ the CPU by the moist-static-energy identity, uniform tracers, burden conservatio
 * the 884,736-column grid with the benchmark's tracers: sampled columns against the oracle, and at
   every column the properties that hold at any size (zeros where nothing convects, the column
   burden conserved);
+* 72 and 256 levels (the largest per-block LDS);
 * the optional deep part, ntr = 0, argument errors.
 """
 import ctypes as C
@@ -176,6 +177,27 @@ def test_full_grid_properties(torch, big):
     scale = (tend * dp).abs().sum(dim=1)
     assert bool(torch.isfinite(tend).all())
     assert bool((burden.abs() <= 1e-12 * scale).all())
+
+
+@pytest.mark.parametrize("nlev", [72, 256])
+def test_other_level_counts(torch, nlev):
+    """72 levels, and 256, the most a context takes (the kernel's per-block LDS, 128 KiB, is then
+    above the default limit and raised per device)."""
+    B = _B()
+    n, L = 3000, nlev
+    st = S.make_state(n, L, seed=78, warm=np.arange(n) < n // 2)
+    ld = n + 5
+    dev = B.to_device(_pad(st, ld))
+    conv = B.Conv(n, L)
+    deep, sh = conv.step(dev)
+    tr, trd = _tracers(torch, 2, L, n, ld, 12)
+    tend, dpart = conv.tracer_transport(dev, deep, sh, trd, deep_part=True)
+    torch.cuda.synchronize()
+    want, want_d = oracle.tracers(st, tr)
+    _check(_np(tend)[:, :, :n], want)
+    _check(_np(dpart)[:, :, :n], want_d)
+    ds, ss = _np(deep["status"])[:n], _np(sh["status"])[:n]
+    assert (ds == 0).sum() > 500 and (ss == 0).sum() > 100
 
 
 def test_deep_part_is_optional_and_ntr_zero_is_a_no_op(torch, mixed):
