@@ -35,12 +35,12 @@ NLON, NLAT = 1152, 768
 TRAFFIC_SOURCES = ("paper_1711_00289_amd/csrc/conv.hip", "paper_1711_00289_amd/csrc/conv_physics.hpp",
                    "paper_1711_00289_amd/csrc/conv_internal.hpp")
 MEASURED_TRAFFIC = {
-    "sources_sha256": "f723bda93d0dd421c6cf1f00ed4694aa83602325a98d7019f8a817737bb79cf1",
+    "sources_sha256": "3c0d476b0cc4cca47ce8a553379980fe5039eeeaf947375b0509c96251feafda",
     "fetch_factor": 2.0, "write_factor": 1.0,
-    "k_trigger": (533438, 1530017),
-    "k_deep_plume": (253014, 343091),
-    "k_shallow_retrigger": (121214, 9254),
-    "k_shallow_plume": (48212, 18114),
+    "k_trigger": (533468, 1530035),
+    "k_deep_plume": (268394, 352022),
+    "k_shallow_retrigger": (120859, 9254),
+    "k_shallow_plume": (47947, 18138),
 }
 
 

@@ -612,21 +612,46 @@ __global__ __launch_bounds__(BLOCK) void k_deep_plume(Src src, Work w) {
             if (P.alpha_dd * E1 > P.evap_max_frac * C1) alpha = P.evap_max_frac * C1 / E1;
             double Fs_t = Fs_kd, Fq_t = Fq_kd;
             double Tk = AT(M.T, kd), qk = AT(M.q, kd), zk = AT(M.z, kd), pt = AT(M.pi, kd);
+            // What layer k needs from memory: its bottom interface i = k+1 (environment below,
+            // both plumes there) and its own condensation and evaporation.  Loaded one layer
+            // ahead; levels are clamped so that every load is in range (values past kb unused).
+            struct DLev {
+                double Tb, qb, zb, pb, et, ed, su, sd, qu, qd, c, e1;
+            };
+            auto dload = [&](int k) {
+                DLev v;
+                const int i = min(k + 1, kb), kk = min(k, kb);
+                v.Tb = AT(M.T, i);
+                v.qb = AT(M.q, i);
+                v.zb = AT(M.z, i);
+                v.pb = AT(M.pi, min(k + 1, kb + 1));
+                v.et = SCR(U_ETA, i);
+                v.ed = SCR(D_ED, i);
+                v.su = SCR(U_SU, i);
+                v.sd = SCR(D_SD, i);
+                v.qu = SCR(U_QU, i);
+                v.qd = SCR(D_QD, i);
+                v.c = SCR(U_C, kk);
+                v.e1 = SCR(D_E1, kk);
+                return v;
+            };
+            DLev nx = dload(kd);
             for (int k = kd; k <= kb; ++k) {
                 const int i = k + 1;  // the layer's bottom interface
-                const int kn = min(i, kb);
-                const double Tb = AT(M.T, kn), qb = AT(M.q, kn), zbl = AT(M.z, kn), pb = AT(M.pi, i);
+                const DLev v = nx;
+                nx = dload(k + 1);
+                const double Tb = v.Tb, qb = v.qb, zbl = v.zb, pb = v.pb;
                 double Fs = 0.0, Fq = 0.0;
                 if (i <= kb) {
-                    const double et = SCR(U_ETA, i), ed = SCR(D_ED, i);
+                    const double et = v.et, ed = v.ed;
                     const bool upw = et + alpha * ed >= 0.0;
                     const double s_up = upw ? CP * Tk + GRAV * zk + phis : CP * Tb + GRAV * zbl + phis;
                     const double q_up = upw ? qk : qb;
-                    Fs = et * (SCR(U_SU, i) - s_up) + alpha * ed * (SCR(D_SD, i) - s_up);
-                    Fq = et * (SCR(U_QU, i) - q_up) + alpha * ed * (SCR(D_QD, i) - q_up);
+                    Fs = et * (v.su - s_up) + alpha * ed * (v.sd - s_up);
+                    Fq = et * (v.qu - q_up) + alpha * ed * (v.qd - q_up);
                 }
-                const double c = k == kd ? c_kd : SCR(U_C, k);
-                const double e1 = k <= kb - 1 ? SCR(D_E1, k) : 0.0;
+                const double c = k == kd ? c_kd : v.c;
+                const double e1 = k <= kb - 1 ? v.e1 : 0.0;
                 layer(k, Fs_t, Fq_t, Fs, Fq, c - alpha * e1, Tk, qk, pt, pb);
                 Fs_t = Fs;
                 Fq_t = Fq;
@@ -648,9 +673,30 @@ __global__ __launch_bounds__(BLOCK) void k_deep_plume(Src src, Work w) {
             double qmix = AT(M.q, kb);
             double dhm = CP * dT1kb + LV * dq1kb, dqm = dq1kb, Fsum = 0.0;
             double zb = AT(M.z, kb);
+            // Layer k's state, unit tendencies and interface pressures, loaded one layer ahead
+            // (levels clamped at kt: every load is in range, values past the top unused).
+            struct XLev {
+                double T, q, z, pm, dT1, dq1, pt, pb;
+            };
+            auto xload = [&](int k) {
+                XLev v;
+                const int kk = max(k, kt);
+                v.T = AT(M.T, kk);
+                v.q = AT(M.q, kk);
+                v.z = AT(M.z, kk);
+                v.pm = AT(M.pm, kk);
+                v.dT1 = SCR(X_DT1, kk);
+                v.dq1 = SCR(X_DQ1, kk);
+                v.pt = AT(M.pi, kk);
+                v.pb = AT(M.pi, kk + 1);
+                return v;
+            };
+            XLev nx = xload(kb - 1);
             for (int k = kb - 1; k >= kt; --k) {
-                const double Tk = AT(M.T, k), qk = AT(M.q, k), zk = AT(M.z, k), pm = AT(M.pm, k);
-                const double dT1 = SCR(X_DT1, k), dq1 = SCR(X_DQ1, k);
+                const XLev v = nx;
+                nx = xload(k - 1);
+                const double Tk = v.T, qk = v.q, zk = v.z, pm = v.pm;
+                const double dT1 = v.dT1, dq1 = v.dq1;
                 const double mix = P.eps_cape * (zk - zb);
                 hmix = (hmix + mix * ((CP * Tk + GRAV * zk + phis) + LV * qk)) / (1.0 + mix);
                 qmix = (qmix + mix * qk) / (1.0 + mix);
@@ -668,7 +714,7 @@ __global__ __launch_bounds__(BLOCK) void k_deep_plume(Src src, Work w) {
                 }
                 const double dTvp = (1.0 + CVIR * r.qv) * dTp + CVIR * r.T * dqp;
                 const double dTve = (1.0 + CVIR * qk) * dT1 + CVIR * Tk * dq1;
-                Fsum += log(AT(M.pi, k + 1) / AT(M.pi, k)) * (dTvp - dTve);
+                Fsum += log(v.pb / v.pt) * (dTvp - dTve);
                 zb = zk;
             }
             F = -RD * Fsum;
@@ -682,13 +728,30 @@ __global__ __launch_bounds__(BLOCK) void k_deep_plume(Src src, Work w) {
             Mb = Mc <= Mlim ? Mc : Mlim;
         }
         if (st == 0) {  // the trigger pass zeroed the whole column
-            for (int k = kt; k <= kb; ++k) {
-                AT(M.dout.dTdt, k) = Mb * SCR(X_DT1, k);
-                AT(M.dout.dqdt, k) = Mb * SCR(X_DQ1, k);
-            }
-            for (int i = kt + 1; i <= kb; ++i) {
-                AT(M.dout.mu, i) = Mb * SCR(U_ETA, i);
-                if (kd >= 0 && i >= kd + 1) AT(M.dout.md, i) = Mb * (alpha * SCR(D_ED, i));
+            // Layers kt..kb and interfaces kt+1..kb, OUTC levels at a time: the scratch loads of
+            // a batch are issued together (levels clamped to kb, so every load is in range), then
+            // the stores, instead of one load round trip per stored value.
+            constexpr int OUTC = 4;
+            const bool dd = kd >= 0;
+            for (int k0 = kt; k0 <= kb; k0 += OUTC) {
+                double a[OUTC], b[OUTC], e[OUTC], d[OUTC];
+#pragma unroll
+                for (int j = 0; j < OUTC; ++j) {
+                    const int k = min(k0 + j, kb);
+                    a[j] = SCR(X_DT1, k);
+                    b[j] = SCR(X_DQ1, k);
+                    e[j] = SCR(U_ETA, k);
+                    d[j] = SCR(D_ED, k);
+                }
+#pragma unroll
+                for (int j = 0; j < OUTC; ++j) {
+                    const int k = k0 + j;
+                    if (k > kb) break;
+                    AT(M.dout.dTdt, k) = Mb * a[j];
+                    AT(M.dout.dqdt, k) = Mb * b[j];
+                    if (k >= kt + 1) AT(M.dout.mu, k) = Mb * e[j];
+                    if (dd && k >= kd + 1) AT(M.dout.md, k) = Mb * (alpha * d[j]);
+                }
             }
         }
         M.dout.prec[col] = st == 0 ? Mb * P1 : 0.0;
