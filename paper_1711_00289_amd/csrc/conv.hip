@@ -423,9 +423,9 @@ enum DeepScr : int {
 // (D8), limiter (D9) and outputs (D10).  The updraft finishes an interface one level after
 // computing it, when the upwind layer's values (the next level up) have arrived.
 template <class Src>
-__global__ __launch_bounds__(BLOCK) void k_deep_plume(Src src, Work w) {
+__global__ __launch_bounds__(WAVE) void k_deep_plume(Src src, Work w) {
     const int n = w.cnt[CNT_DEEP];
-    const int64_t gtid = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    const int64_t gtid = (int64_t)blockIdx.x * WAVE + threadIdx.x;
     const int lane = threadIdx.x % WAVE;
     double *scr = w.dscr;
 #define SCR(arr, lev) scr[((int64_t)(arr) * (w.lmax + 1) + (lev)) * w.dstride + gtid]
@@ -434,7 +434,7 @@ __global__ __launch_bounds__(BLOCK) void k_deep_plume(Src src, Work w) {
     // slots past the grid's first round until the list runs out (list order keeps a wavefront's
     // columns close in memory).  Lane 0 holds the smallest slot, so it is active whenever any
     // lane is.
-    const int64_t first_round = (int64_t)gridDim.x * BLOCK;
+    const int64_t first_round = (int64_t)gridDim.x * WAVE;
     for (int64_t slot0 = gtid - lane;;) {
         const int64_t slot = slot0 + lane;
         if (slot >= n) break;
@@ -850,10 +850,10 @@ __global__ __launch_bounds__(BLOCK) void k_shallow_retrigger(Src src, Work w) {
 }
 
 template <class Src>
-__global__ __launch_bounds__(BLOCK) void k_shallow_plume(Src src, Work w) {
+__global__ __launch_bounds__(WAVE) void k_shallow_plume(Src src, Work w) {
     const int n = w.cnt[CNT_SHALLOW];
-    const int64_t gtid = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    const int64_t nthreads = (int64_t)gridDim.x * BLOCK;
+    const int64_t gtid = (int64_t)blockIdx.x * WAVE + threadIdx.x;
+    const int64_t nthreads = (int64_t)gridDim.x * WAVE;
     double *scr = w.sscr;
 #define SCR(arr, lev) scr[((int64_t)(arr) * (w.lmax + 1) + (lev)) * w.sstride + gtid]
 
@@ -1075,14 +1075,17 @@ int finish() { return check_launch(); }
 template <class Src, bool DEEP, bool SHALLOW>
 int launch_step(const Src &src, const Work &w, hipStream_t st, hipEvent_t *ev) {
     const unsigned gt = (unsigned)src.ntiles;
-    const unsigned gd = (unsigned)(w.dstride / BLOCK);
-    const unsigned gs = (unsigned)(w.sstride / BLOCK);
+    // The plume passes run one wavefront per block: a short list then spreads over as many
+    // compute units as it has wavefronts instead of filling a few (the wavefronts of one CU share
+    // its load pipeline and L1).
+    const unsigned gd = (unsigned)(w.dstride / WAVE);
+    const unsigned gs = (unsigned)(w.sstride / WAVE);
     if (ev) (void)hipEventRecord(ev[0], st);
     hipLaunchKernelGGL(k_reset, dim3(1), dim3(NCOUNTERS), 0, st, w.cnt);
     if (ev) (void)hipEventRecord(ev[1], st);
     hipLaunchKernelGGL((k_trigger<Src, DEEP, SHALLOW>), dim3(gt), dim3(BLOCK), 0, st, src, w);
     if (ev) (void)hipEventRecord(ev[2], st);
-    if (DEEP) hipLaunchKernelGGL((k_deep_plume<Src>), dim3(gd), dim3(BLOCK), 0, st, src, w);
+    if (DEEP) hipLaunchKernelGGL((k_deep_plume<Src>), dim3(gd), dim3(WAVE), 0, st, src, w);
     if (ev) (void)hipEventRecord(ev[3], st);
     if (DEEP && SHALLOW) {
         const int64_t cap = (int64_t)w.cus * RETRIGGER_BPC;
@@ -1090,7 +1093,7 @@ int launch_step(const Src &src, const Work &w, hipStream_t st, hipEvent_t *ev) {
         hipLaunchKernelGGL((k_shallow_retrigger<Src>), dim3(gr), dim3(BLOCK), 0, st, src, w);
     }
     if (ev) (void)hipEventRecord(ev[4], st);
-    if (SHALLOW) hipLaunchKernelGGL((k_shallow_plume<Src>), dim3(gs), dim3(BLOCK), 0, st, src, w);
+    if (SHALLOW) hipLaunchKernelGGL((k_shallow_plume<Src>), dim3(gs), dim3(WAVE), 0, st, src, w);
     if (ev) (void)hipEventRecord(ev[5], st);
     return finish();
 }

@@ -67,10 +67,10 @@ __global__ __launch_bounds__(BLOCK) void k_adj_compact(Member M, AdjWork w) {
     if (slot >= 0) w.list[slot] = (int)col;
 }
 
-__global__ __launch_bounds__(BLOCK) void k_deep_adjoint(Member M, AdjWork w) {
+__global__ __launch_bounds__(WAVE) void k_deep_adjoint(Member M, AdjWork w) {
     const int n = w.cnt[0];
-    const int64_t gtid = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    const int64_t nthreads = (int64_t)gridDim.x * BLOCK;
+    const int64_t gtid = (int64_t)blockIdx.x * WAVE + threadIdx.x;
+    const int64_t nthreads = (int64_t)gridDim.x * WAVE;
     const int L = M.nlev;
     const int64_t ld = M.ld;
     const conv_params_t &P = M.P;
@@ -561,10 +561,10 @@ __device__ __forceinline__ void lift_adjoint(bool sat, double Q1, double gTp, do
 // -> plume recurrence (top interface first) -> the source's parcel -> M_c through rho_s and CIN ->
 // the source means.  The vertical-velocity equation only decides the plume top, which is held
 // fixed, so it carries no derivative.
-__global__ __launch_bounds__(BLOCK) void k_shallow_adjoint(Member M, SAdjWork w) {
+__global__ __launch_bounds__(WAVE) void k_shallow_adjoint(Member M, SAdjWork w) {
     const int n = w.cnt[1];
-    const int64_t gtid = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    const int64_t nthreads = (int64_t)gridDim.x * BLOCK;
+    const int64_t gtid = (int64_t)blockIdx.x * WAVE + threadIdx.x;
+    const int64_t nthreads = (int64_t)gridDim.x * WAVE;
     const int L = M.nlev;
     const int64_t ld = M.ld;
     const conv_params_t &P = M.P;
@@ -1035,7 +1035,7 @@ int conv_deep_backward(conv_ctx_t *ctx, const conv_state_t *state, const conv_de
     const unsigned gcols = (unsigned)((ctx->ncol + BLOCK - 1) / BLOCK);
     hipLaunchKernelGGL(k_adj_reset, dim3(1), dim3(NCOUNTERS), 0, st, w.cnt);
     hipLaunchKernelGGL(k_adj_compact, dim3(gcols), dim3(BLOCK), 0, st, M, w);
-    hipLaunchKernelGGL(k_deep_adjoint, dim3((unsigned)(l.threads / BLOCK)), dim3(BLOCK), 0, st, M, w);
+    hipLaunchKernelGGL(k_deep_adjoint, dim3((unsigned)(l.threads / WAVE)), dim3(WAVE), 0, st, M, w);
     param_sums(w.pgrad, ld, ctx->ncol, (double *)(b + l.part), grad->g_params, st);
     return check_launch();
 }
@@ -1064,7 +1064,7 @@ int conv_shallow_backward(conv_ctx_t *ctx, const conv_state_t *state,
     const unsigned gcols = (unsigned)((ctx->ncol + BLOCK - 1) / BLOCK);
     hipLaunchKernelGGL(k_adj_reset, dim3(1), dim3(NCOUNTERS), 0, st, w.cnt);
     hipLaunchKernelGGL(k_sadj_compact, dim3(gcols), dim3(BLOCK), 0, st, M, w);
-    hipLaunchKernelGGL(k_shallow_adjoint, dim3((unsigned)(l.threads / BLOCK)), dim3(BLOCK), 0, st,
+    hipLaunchKernelGGL(k_shallow_adjoint, dim3((unsigned)(l.threads / WAVE)), dim3(WAVE), 0, st,
                        M, w);
     param_sums(w.pgrad, ld, ctx->ncol, (double *)(b + l.part), grad->g_params, st);
     return check_launch();
@@ -1095,18 +1095,18 @@ int conv_step_backward(conv_ctx_t *ctx, const conv_state_t *state, const conv_de
     double *pgrad = (double *)(b + l.total);
     const Member M = make_member(ctx->ncol, ctx->nlev, ctx->P, state, dfwd, sfwd, 0);
     const unsigned gcols = (unsigned)((ctx->ncol + BLOCK - 1) / BLOCK);
-    const unsigned gpers = (unsigned)(l.threads / BLOCK);
+    const unsigned gpers = (unsigned)(l.threads / WAVE);  // one wavefront per block
     // Shallow adjoint at the updated state: dL/dT', dL/dq' into g_T, g_q.
     const SAdjWork sw = shallow_work(b, l, ctx, scot, grad->g_T, grad->g_q, pgrad + 2 * ld, 1);
     hipLaunchKernelGGL(k_adj_reset, dim3(1), dim3(NCOUNTERS), 0, st, sw.cnt);
     hipLaunchKernelGGL(k_sadj_compact, dim3(gcols), dim3(BLOCK), 0, st, M, sw);
-    hipLaunchKernelGGL(k_shallow_adjoint, dim3(gpers), dim3(BLOCK), 0, st, M, sw);
+    hipLaunchKernelGGL(k_shallow_adjoint, dim3(gpers), dim3(WAVE), 0, st, M, sw);
     // Deep adjoint with the update's chain rule, in place on g_T, g_q.
     AdjWork dw = deep_work(b, l, ctx, dcot, grad->g_T, grad->g_q, pgrad);
     dw.xT = grad->g_T;
     dw.xq = grad->g_q;
     hipLaunchKernelGGL(k_adj_compact, dim3(gcols), dim3(BLOCK), 0, st, M, dw);
-    hipLaunchKernelGGL(k_deep_adjoint, dim3(gpers), dim3(BLOCK), 0, st, M, dw);
+    hipLaunchKernelGGL(k_deep_adjoint, dim3(gpers), dim3(WAVE), 0, st, M, dw);
     double *part = (double *)(b + l.part);
     param_sums(pgrad, ld, ctx->ncol, part, grad->g_params, st);
     param_sums(pgrad + 2 * ld, ld, ctx->ncol, part, grad->g_params + 2, st);
