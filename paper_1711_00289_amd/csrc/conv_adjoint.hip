@@ -67,6 +67,8 @@ __global__ __launch_bounds__(BLOCK) void k_adj_compact(Member M, AdjWork w) {
     if (slot >= 0) w.list[slot] = (int)col;
 }
 
+constexpr int AB = 4;  // levels per batch of loads in the reverse sweeps
+
 __global__ __launch_bounds__(WAVE) void k_deep_adjoint(Member M, AdjWork w) {
     const int n = w.cnt[0];
     const int64_t gtid = (int64_t)blockIdx.x * WAVE + threadIdx.x;
@@ -283,14 +285,30 @@ __global__ __launch_bounds__(WAVE) void k_deep_adjoint(Member M, AdjWork w) {
         // ============================================ reverse sweep
         for (int lev = kt; lev <= kb + 1; ++lev)
             for (int a = G_T; a < N_ADJ; ++a) S(a, lev) = 0.0;
+        // The reverse sweep's loops load AB levels at a time (levels clamped to the loop's range,
+        // so every load is in range; values past the end are not used), then compute those levels
+        // in order: one memory round trip per AB levels instead of one per level.  A loop that
+        // adds into a neighbouring level's accumulator keeps the batch's accumulators in registers.
         // D10: outputs = M_b * unit profiles.
         double gMb = 0.0;
-        for (int k = kt; k <= kb; ++k) {
-            const double cT = (w.cT ? AT(w.cT, k) : 0.0) + (w.xT ? dt * AT(w.xT, k) : 0.0);
-            const double cq = (w.cq ? AT(w.cq, k) : 0.0) + (w.xq ? dt * AT(w.xq, k) : 0.0);
-            gMb += cT * S(X_DT1, k) + cq * S(X_DQ1, k);
-            S(G_DT1, k) = cT * Mb;
-            S(G_DQ1, k) = cq * Mb;
+        for (int k0 = kt; k0 <= kb; k0 += AB) {
+            double cT[AB], cq[AB], d1[AB], q1[AB];
+#pragma unroll
+            for (int j = 0; j < AB; ++j) {
+                const int k = min(k0 + j, kb);
+                cT[j] = (w.cT ? AT(w.cT, k) : 0.0) + (w.xT ? dt * AT(w.xT, k) : 0.0);
+                cq[j] = (w.cq ? AT(w.cq, k) : 0.0) + (w.xq ? dt * AT(w.xq, k) : 0.0);
+                d1[j] = S(X_DT1, k);
+                q1[j] = S(X_DQ1, k);
+            }
+#pragma unroll
+            for (int j = 0; j < AB; ++j) {
+                const int k = k0 + j;
+                if (k > kb) break;
+                gMb += cT[j] * d1[j] + cq[j] * q1[j];
+                S(G_DT1, k) = cT[j] * Mb;
+                S(G_DQ1, k) = cq[j] * Mb;
+            }
         }
         const double cPc = w.cP ? w.cP[col] : 0.0;
         gMb += cPc * P1;
@@ -310,23 +328,49 @@ __global__ __launch_bounds__(WAVE) void k_deep_adjoint(Member M, AdjWork w) {
         double ghkb = 0.0, gqkb = 0.0;
         S(G_DT1, kb) += -RD * gF * SA;
         S(G_DQ1, kb) += -RD * gF * SB;
-        for (int k = kt; k <= kb - 1; ++k) {
-            const double lam = lamk(k), T = Tk(k), q = qk(k);
-            const double dT1 = S(X_DT1, k), dq1 = S(X_DQ1, k);
-            S(G_DT1, k) += RD * gF * lam * (1.0 + CVIR * q);
-            S(G_DQ1, k) += RD * gF * lam * CVIR * T;
+        for (int k0 = kt; k0 <= kb - 1; k0 += AB) {
+          struct V {
+              double pt, pb, T, q, dT1, dq1, Tp, qp, sat, Q1, Q2, gdt, gdq, gT, gq;
+          } v[AB];
+#pragma unroll
+          for (int j = 0; j < AB; ++j) {
+              const int k = min(k0 + j, kb - 1);
+              v[j].pt = AT(M.pi, k);
+              v[j].pb = AT(M.pi, k + 1);
+              v[j].T = Tk(k);
+              v[j].q = qk(k);
+              v[j].dT1 = S(X_DT1, k);
+              v[j].dq1 = S(X_DQ1, k);
+              v[j].Tp = S(P_TP, k);
+              v[j].qp = S(P_QP, k);
+              v[j].sat = S(P_SAT, k);
+              v[j].Q1 = S(P_Q1, k);
+              v[j].Q2 = S(P_Q2, k);
+              v[j].gdt = S(G_DT1, k);
+              v[j].gdq = S(G_DQ1, k);
+              v[j].gT = S(G_T, k);
+              v[j].gq = S(G_Q, k);
+          }
+#pragma unroll
+          for (int j = 0; j < AB; ++j) {
+            const int k = k0 + j;
+            if (k > kb - 1) break;
+            const double lam = log(v[j].pb / v[j].pt), T = v[j].T, q = v[j].q;
+            const double dT1 = v[j].dT1, dq1 = v[j].dq1;
+            S(G_DT1, k) = v[j].gdt + RD * gF * lam * (1.0 + CVIR * q);
+            S(G_DQ1, k) = v[j].gdq + RD * gF * lam * CVIR * T;
             double gTk = RD * gF * lam * CVIR * dq1;
             double gqk = RD * gF * lam * CVIR * dT1;
             const double ga = -RD * gF * lam * dT1b, gb = -RD * gF * lam * dq1b;
             const double gB = RD * lam * gcape;
-            const double Tp = S(P_TP, k), qp = S(P_QP, k);
+            const double Tp = v[j].Tp, qp = v[j].qp;
             double gTp = gB * (1.0 + CVIR * qp), gqp = gB * CVIR * Tp;
             gTk -= gB * (1.0 + CVIR * q);
             gqk -= gB * CVIR * T;
-            S(G_T, k) += gTk;
-            S(G_Q, k) += gqk;
-            if (S(P_SAT, k) != 0.0) {
-                const double Q1 = S(P_Q1, k), Q2 = S(P_Q2, k);
+            S(G_T, k) = v[j].gT + gTk;
+            S(G_Q, k) = v[j].gq + gqk;
+            if (v[j].sat != 0.0) {
+                const double Q1 = v[j].Q1, Q2 = v[j].Q2;
                 const double c = (1.0 + CVIR * qp) + CVIR * Tp * Q1;
                 const double den = CP + LV * Q1;
                 const double dc = CVIR * (2.0 * Q1 + Tp * Q2), dden = LV * Q2;
@@ -339,49 +383,143 @@ __global__ __launch_bounds__(WAVE) void k_deep_adjoint(Member M, AdjWork w) {
                 ghkb += gTp / CP;
                 gqkb += -LV * gTp / CP + gqp;
             }
+          }
         }
         // D7 tendencies: net sources per layer, fluxes per interface.
         double galpha = 0.0;
-        for (int k = kt; k <= kb; ++k) {
-            const double dp = dpk(k);
-            const double gnet = LV * GRAV / (CP * dp) * S(G_DT1, k) - GRAV / dp * S(G_DQ1, k) + gP1;
-            if (k >= kt + 1) S(G_C, k) += gnet;
-            if (kd >= 0 && k >= kd && k <= kb - 1) {
-                S(G_E1, k) += -alpha * gnet;
-                galpha -= gnet * S(D_E1, k);
+        for (int k0 = kt; k0 <= kb; k0 += AB) {
+            double pt[AB], pb[AB], gdt[AB], gdq[AB], gc[AB], ge[AB], e1[AB];
+#pragma unroll
+            for (int j = 0; j < AB; ++j) {
+                const int k = min(k0 + j, kb);
+                pt[j] = AT(M.pi, k);
+                pb[j] = AT(M.pi, k + 1);
+                gdt[j] = S(G_DT1, k);
+                gdq[j] = S(G_DQ1, k);
+                gc[j] = S(G_C, k);
+                ge[j] = S(G_E1, k);
+                e1[j] = S(D_E1, k);
+            }
+#pragma unroll
+            for (int j = 0; j < AB; ++j) {
+                const int k = k0 + j;
+                if (k > kb) break;
+                const double dp = pb[j] - pt[j];
+                const double gnet = LV * GRAV / (CP * dp) * gdt[j] - GRAV / dp * gdq[j] + gP1;
+                if (k >= kt + 1) S(G_C, k) = gc[j] + gnet;
+                if (kd >= 0 && k >= kd && k <= kb - 1) {
+                    S(G_E1, k) = ge[j] + -alpha * gnet;
+                    galpha -= gnet * e1[j];
+                }
             }
         }
-        for (int i = kt + 1; i <= kb; ++i) {
-            const double dpa = dpk(i - 1), dpb = dpk(i);
-            const double gPs = GRAV / (CP * dpa) * S(G_DT1, i - 1) - GRAV / (CP * dpb) * S(G_DT1, i);
-            const double gPq = GRAV / dpa * S(G_DQ1, i - 1) - GRAV / dpb * S(G_DQ1, i);
-            const double et = S(U_ETA, i);
-            const int up = S(X_UPW, i) != 0.0 ? i - 1 : i;
-            const double s_up = CP * Tk(up) + GRAV * AT(M.z, up) + phis;
-            const double q_up = qk(up);
-            const double zii = zi(i);
-            const double su = CP * S(U_TU, i) + GRAV * zii + phis, qu = S(U_QU, i);
-            const bool dn = kd >= 0 && i >= kd + 1;
-            const double ed = dn ? -S(D_AD, i) : 0.0;
-            const double m = et + alpha * ed;
-            S(G_ETA, i) += gPs * (su - s_up) + gPq * (qu - q_up);
-            S(G_TU, i) += CP * gPs * et;
-            S(G_QU, i) += gPq * et;
-            S(G_T, up) += -CP * gPs * m;
-            S(G_Q, up) += -gPq * m;
-            if (dn) {
-                const double sd = CP * S(D_TD, i) + GRAV * zii + phis, qd = S(D_QD, i);
-                galpha += gPs * ed * (sd - s_up) + gPq * ed * (qd - q_up);
-                S(G_AD, i) += -alpha * (gPs * (sd - s_up) + gPq * (qd - q_up));
-                S(G_TD, i) += CP * alpha * ed * gPs;
-                S(G_QD, i) += alpha * ed * gPq;
+        // Interfaces i0 .. i0+AB-1 touch the layer accumulators G_T, G_Q of layers i0-1 .. i0+AB-1
+        // (the upwind layer of interface i is i-1 or i): those are held in registers for the batch
+        // and stored once, each layer by the batch that last adds to it before the next loads it.
+        for (int i0 = kt + 1; i0 <= kb; i0 += AB) {
+            struct V {
+                double pa, pm, pb, gdta, gdtb, gdqa, gdqb, et, upw, Ta, za, qa, Tb, zb, qb, tu, qu, ad,
+                    td, qd, geta, gtu, gqu, gad, gtd, gqd;
+            } v[AB];
+            double gT[AB + 1], gq[AB + 1];
+#pragma unroll
+            for (int j = 0; j <= AB; ++j) {
+                const int k = min(i0 - 1 + j, kb);
+                gT[j] = S(G_T, k);
+                gq[j] = S(G_Q, k);
+            }
+#pragma unroll
+            for (int j = 0; j < AB; ++j) {
+                const int i = min(i0 + j, kb);
+                v[j].pa = AT(M.pi, i - 1);
+                v[j].pm = AT(M.pi, i);
+                v[j].pb = AT(M.pi, i + 1);
+                v[j].gdta = S(G_DT1, i - 1);
+                v[j].gdtb = S(G_DT1, i);
+                v[j].gdqa = S(G_DQ1, i - 1);
+                v[j].gdqb = S(G_DQ1, i);
+                v[j].et = S(U_ETA, i);
+                v[j].upw = S(X_UPW, i);
+                v[j].Ta = Tk(i - 1);
+                v[j].za = AT(M.z, i - 1);
+                v[j].qa = qk(i - 1);
+                v[j].Tb = Tk(i);
+                v[j].zb = AT(M.z, i);
+                v[j].qb = qk(i);
+                v[j].tu = S(U_TU, i);
+                v[j].qu = S(U_QU, i);
+                v[j].ad = S(D_AD, i);
+                v[j].td = S(D_TD, i);
+                v[j].qd = S(D_QD, i);
+                v[j].geta = S(G_ETA, i);
+                v[j].gtu = S(G_TU, i);
+                v[j].gqu = S(G_QU, i);
+                v[j].gad = S(G_AD, i);
+                v[j].gtd = S(G_TD, i);
+                v[j].gqd = S(G_QD, i);
+            }
+#pragma unroll
+            for (int j = 0; j < AB; ++j) {
+                const int i = i0 + j;
+                if (i > kb) break;
+                const double dpa = v[j].pm - v[j].pa, dpb = v[j].pb - v[j].pm;
+                const double gPs = GRAV / (CP * dpa) * v[j].gdta - GRAV / (CP * dpb) * v[j].gdtb;
+                const double gPq = GRAV / dpa * v[j].gdqa - GRAV / dpb * v[j].gdqb;
+                const double et = v[j].et;
+                const bool upw = v[j].upw != 0.0;  // upwind layer i-1, else i
+                const double s_up = upw ? CP * v[j].Ta + GRAV * v[j].za + phis
+                                        : CP * v[j].Tb + GRAV * v[j].zb + phis;
+                const double q_up = upw ? v[j].qa : v[j].qb;
+                const double zii = 0.5 * (v[j].za + v[j].zb);
+                const double su = CP * v[j].tu + GRAV * zii + phis, qu = v[j].qu;
+                const bool dn = kd >= 0 && i >= kd + 1;
+                const double ed = dn ? -v[j].ad : 0.0;
+                const double m = et + alpha * ed;
+                S(G_ETA, i) = v[j].geta + (gPs * (su - s_up) + gPq * (qu - q_up));
+                S(G_TU, i) = v[j].gtu + CP * gPs * et;
+                S(G_QU, i) = v[j].gqu + gPq * et;
+                if (upw) {
+                    gT[j] += -CP * gPs * m;
+                    gq[j] += -gPq * m;
+                } else {
+                    gT[j + 1] += -CP * gPs * m;
+                    gq[j + 1] += -gPq * m;
+                }
+                if (dn) {
+                    const double sd = CP * v[j].td + GRAV * zii + phis, qd = v[j].qd;
+                    galpha += gPs * ed * (sd - s_up) + gPq * ed * (qd - q_up);
+                    S(G_AD, i) = v[j].gad + -alpha * (gPs * (sd - s_up) + gPq * (qd - q_up));
+                    S(G_TD, i) = v[j].gtd + CP * alpha * ed * gPs;
+                    S(G_QD, i) = v[j].gqd + alpha * ed * gPq;
+                }
+            }
+#pragma unroll
+            for (int j = 0; j <= AB; ++j) {
+                const int k = i0 - 1 + j;
+                if (k > kb) break;
+                S(G_T, k) = gT[j];
+                S(G_Q, k) = gq[j];
             }
         }
         // D6 downdraft strength when capped by the evaporation limit.
         if (capped) {
             const double gC1 = galpha * beta / E1, gE1 = -galpha * alpha / E1;
-            for (int k = kt + 1; k <= kb; ++k) S(G_C, k) += gC1;
-            for (int k = kd; k <= kb - 1; ++k) S(G_E1, k) += gE1;
+            for (int k0 = kt + 1; k0 <= kb; k0 += AB) {
+                double g[AB];
+#pragma unroll
+                for (int j = 0; j < AB; ++j) g[j] = S(G_C, min(k0 + j, kb));
+#pragma unroll
+                for (int j = 0; j < AB; ++j)
+                    if (k0 + j <= kb) S(G_C, k0 + j) = g[j] + gC1;
+            }
+            for (int k0 = kd; k0 <= kb - 1; k0 += AB) {
+                double g[AB];
+#pragma unroll
+                for (int j = 0; j < AB; ++j) g[j] = S(G_E1, min(k0 + j, kb - 1));
+#pragma unroll
+                for (int j = 0; j < AB; ++j)
+                    if (k0 + j <= kb - 1) S(G_E1, k0 + j) = g[j] + gE1;
+            }
         }
         // D6 downdraft recurrence, in reverse (bottom layer first).  What an iteration adds to the
         // adjoints of the interface above it (ad, q_d, h_d) is carried in registers to the next
@@ -389,16 +527,41 @@ __global__ __launch_bounds__(WAVE) void k_deep_adjoint(Member M, AdjWork w) {
         if (kd >= 0) {
             double cad = 0.0, cqd = 0.0, chd = 0.0;  // recurrence parts at interface k+1
             double adk1 = S(D_AD, kb), hdk1 = S(D_HD, kb), qdk1 = S(D_QD, kb), zlo = zi(kb);
-            for (int k = kb - 1; k >= kd + 1; --k) {
-                const double adk = S(D_AD, k), hdk = S(D_HD, k), qdk = S(D_QD, k);
-                const double Ed = S(D_ED, k), Q1 = S(D_Q1, k + 1), q = qk(k), h = hk(k);
-                const double ge1 = S(G_E1, k), zk = zi(k);
-                double gad1 = S(G_AD, k + 1) + cad + ge1 * qdk1;
-                const double gqd1 = S(G_QD, k + 1) + cqd + ge1 * adk1;
+            for (int k0 = kb - 1; k0 >= kd + 1; k0 -= AB) {
+              struct V {
+                  double ad, hd, qd, Ed, Q1, q, h, ge1, zk, gad1, gqd1, gtd1, gT, gq;
+              } v[AB];
+#pragma unroll
+              for (int j = 0; j < AB; ++j) {
+                  const int k = max(k0 - j, kd + 1);
+                  v[j].ad = S(D_AD, k);
+                  v[j].hd = S(D_HD, k);
+                  v[j].qd = S(D_QD, k);
+                  v[j].Ed = S(D_ED, k);
+                  v[j].Q1 = S(D_Q1, k + 1);
+                  v[j].q = qk(k);
+                  v[j].h = hk(k);
+                  v[j].ge1 = S(G_E1, k);
+                  v[j].zk = zi(k);
+                  v[j].gad1 = S(G_AD, k + 1);
+                  v[j].gqd1 = S(G_QD, k + 1);
+                  v[j].gtd1 = S(G_TD, k + 1);
+                  v[j].gT = S(G_T, k);
+                  v[j].gq = S(G_Q, k);
+              }
+#pragma unroll
+              for (int j = 0; j < AB; ++j) {
+                const int k = k0 - j;
+                if (k < kd + 1) break;
+                const double adk = v[j].ad, hdk = v[j].hd, qdk = v[j].qd;
+                const double Ed = v[j].Ed, Q1 = v[j].Q1, q = v[j].q, h = v[j].h;
+                const double ge1 = v[j].ge1, zk = v[j].zk;
+                double gad1 = v[j].gad1 + cad + ge1 * qdk1;
+                const double gqd1 = v[j].gqd1 + cqd + ge1 * adk1;
                 double gad0 = -ge1 * qdk;
                 double gEd = -ge1 * q;
                 const double gq = -ge1 * Ed;
-                const double gTd1 = S(G_TD, k + 1) + gqd1 * Q1;
+                const double gTd1 = v[j].gtd1 + gqd1 * Q1;
                 const double ghd1 = chd + gTd1 / (CP + LV * Q1);
                 const double rad1 = 1.0 / adk1;
                 gad0 += ghd1 * hdk * rad1;
@@ -413,12 +576,13 @@ __global__ __launch_bounds__(WAVE) void k_deep_adjoint(Member M, AdjWork w) {
                 cad = gad0;
                 cqd = -ge1 * adk;
                 chd = ghd1 * adk * rad1;
-                S(G_T, k) += CP * gh;
-                S(G_Q, k) += LV * gh + gq;
+                S(G_T, k) = v[j].gT + CP * gh;
+                S(G_Q, k) = v[j].gq + (LV * gh + gq);
                 adk1 = adk;
                 hdk1 = hdk;
                 qdk1 = qdk;
                 zlo = zk;
+              }
             }
             // Start: h_d = h of layer kd at interface kd+1; e1_kd = q_d(kd+1) - q_kd.
             const double ge1 = S(G_E1, kd);
@@ -434,18 +598,48 @@ __global__ __launch_bounds__(WAVE) void k_deep_adjoint(Member M, AdjWork w) {
         double ceta = 0.0, chu = 0.0, cqu = 0.0;  // recurrence parts at interface k
         {
             double eta = S(U_ETA, kt + 1), zk = zi(kt + 1);
-            for (int k = kt + 1; k <= kb - 1; ++k) {
-                const double etan1 = S(U_ETA, k + 1);
-                const double hm = S(U_HM, k), hu1 = S(U_HM, k + 1);
-                const double qm = S(U_QM, k), qu = S(U_QU, k), qu1 = S(U_QU, k + 1);
-                const double E = S(U_E, k), Q1 = S(U_Q1, k), zlo = zi(k + 1);
-                const double gc = S(G_C, k);
-                double geta = S(G_ETA, k) + ceta + gc * (qm - qu);
+            for (int k0 = kt + 1; k0 <= kb - 1; k0 += AB) {
+              struct V {
+                  double etan1, hm, hu1, qm, qu, qu1, E, Q1, zlo, gc, geta, gqu, gTu, sat, h, q, gT,
+                      gq;
+              } v[AB];
+#pragma unroll
+              for (int j = 0; j < AB; ++j) {
+                  const int k = min(k0 + j, kb - 1);
+                  v[j].etan1 = S(U_ETA, k + 1);
+                  v[j].hm = S(U_HM, k);
+                  v[j].hu1 = S(U_HM, k + 1);
+                  v[j].qm = S(U_QM, k);
+                  v[j].qu = S(U_QU, k);
+                  v[j].qu1 = S(U_QU, k + 1);
+                  v[j].E = S(U_E, k);
+                  v[j].Q1 = S(U_Q1, k);
+                  v[j].zlo = zi(k + 1);
+                  v[j].gc = S(G_C, k);
+                  v[j].geta = S(G_ETA, k);
+                  v[j].gqu = S(G_QU, k);
+                  v[j].gTu = S(G_TU, k);
+                  v[j].sat = S(U_SAT, k);
+                  v[j].h = hk(k);
+                  v[j].q = qk(k);
+                  v[j].gT = S(G_T, k);
+                  v[j].gq = S(G_Q, k);
+              }
+#pragma unroll
+              for (int j = 0; j < AB; ++j) {
+                const int k = k0 + j;
+                if (k > kb - 1) break;
+                const double etan1 = v[j].etan1;
+                const double hm = v[j].hm, hu1 = v[j].hu1;
+                const double qm = v[j].qm, qu = v[j].qu, qu1 = v[j].qu1;
+                const double E = v[j].E, Q1 = v[j].Q1, zlo = v[j].zlo;
+                const double gc = v[j].gc;
+                double geta = v[j].geta + ceta + gc * (qm - qu);
                 double gqm = gc * eta;
-                const double gqu = S(G_QU, k) + cqu - gc * eta;
+                const double gqu = v[j].gqu + cqu - gc * eta;
                 double ghm = chu;
-                const double gTu = S(G_TU, k);
-                if (S(U_SAT, k) != 0.0) {
+                const double gTu = v[j].gTu;
+                if (v[j].sat != 0.0) {
                     ghm += (gTu + gqu * Q1) / (CP + LV * Q1);
                 } else {
                     ghm += gTu / CP;
@@ -455,10 +649,10 @@ __global__ __launch_bounds__(WAVE) void k_deep_adjoint(Member M, AdjWork w) {
                 double geta1 = (ghm * hu1 + gqm * qu1) * reta;
                 chu = ghm * etan1 * reta;
                 cqu = gqm * etan1 * reta;
-                double gE = (ghm * hk(k) + gqm * qk(k)) * reta;
+                double gE = (ghm * v[j].h + gqm * v[j].q) * reta;
                 const double gh = ghm * E * reta;
-                S(G_T, k) += CP * gh;
-                S(G_Q, k) += LV * gh + gqm * E * reta;
+                S(G_T, k) = v[j].gT + CP * gh;
+                S(G_Q, k) = v[j].gq + (LV * gh + gqm * E * reta);
                 geta += -(ghm * hm + gqm * qm) * reta;
                 geta1 += geta;
                 gE += geta;
@@ -468,6 +662,7 @@ __global__ __launch_bounds__(WAVE) void k_deep_adjoint(Member M, AdjWork w) {
                 ceta = geta1;
                 eta = etan1;
                 zk = zlo;
+              }
             }
         }
         {
@@ -489,10 +684,26 @@ __global__ __launch_bounds__(WAVE) void k_deep_adjoint(Member M, AdjWork w) {
         S(G_T, kb) += CP * ghkb;
         S(G_Q, kb) += LV * ghkb + gqkb;
 
-        for (int k = 0; k < L; ++k) {
-            const bool in = k >= kt && k <= kb;
-            AT(w.gT, k) = (w.xT ? AT(w.xT, k) : 0.0) + (in ? S(G_T, k) : 0.0);
-            AT(w.gq, k) = (w.xq ? AT(w.xq, k) : 0.0) + (in ? S(G_Q, k) : 0.0);
+        // All levels: the pass-through gradient (if any) plus the scheme's on the plume's levels.
+        // (x may be the output itself: a batch reads all its levels before it writes them.)
+        for (int k0 = 0; k0 < L; k0 += AB) {
+            double xt[AB], xq[AB], gt[AB], gq[AB];
+#pragma unroll
+            for (int j = 0; j < AB; ++j) {
+                const int k = min(k0 + j, L - 1);
+                xt[j] = w.xT ? AT(w.xT, k) : 0.0;
+                xq[j] = w.xq ? AT(w.xq, k) : 0.0;
+                gt[j] = S(G_T, k);
+                gq[j] = S(G_Q, k);
+            }
+#pragma unroll
+            for (int j = 0; j < AB; ++j) {
+                const int k = k0 + j;
+                if (k >= L) break;
+                const bool in = k >= kt && k <= kb;
+                AT(w.gT, k) = xt[j] + (in ? gt[j] : 0.0);
+                AT(w.gq, k) = xq[j] + (in ? gq[j] : 0.0);
+            }
         }
         w.pgrad[col] = gtau;
         w.pgrad[ld + col] = geps;
