@@ -98,18 +98,36 @@ __global__ __launch_bounds__(WAVE) void k_deep_adjoint(Member M, AdjWork w) {
         {
             Hint hp;
             hp.clear();
+            // The next layer's inputs are loaded one iteration ahead (clamped at kt).
+            struct PL {
+                double z, pm, T, q, pt, pb;
+            };
+            auto pload = [&](int k) {
+                PL v;
+                const int kk = max(k, kt);
+                v.z = AT(M.z, kk);
+                v.pm = AT(M.pm, kk);
+                v.T = Tk(kk);
+                v.q = qk(kk);
+                v.pt = AT(M.pi, kk);
+                v.pb = AT(M.pi, kk + 1);
+                return v;
+            };
+            PL nx = pload(kb - 1);
             for (int k = kb - 1; k >= kt; --k) {
-                const Lifted r = lift(hkb - GRAV * AT(M.z, k) - phis, qkb, AT(M.pm, k), hp);
+                const PL v = nx;
+                nx = pload(k - 1);
+                const Lifted r = lift(hkb - GRAV * v.z - phis, qkb, v.pm, hp);
                 // The closure's parcel sensitivity needs qs' and qs'' at the root itself (the
                 // solver carries qs'' only to zeroth order), so they are evaluated there.
-                const Sat sr = r.sat ? sat_eval(r.T, AT(M.pm, k)) : Sat{0.0, 0.0, 0.0, 0.0};
+                const Sat sr = r.sat ? sat_eval(r.T, v.pm) : Sat{0.0, 0.0, 0.0, 0.0};
                 S(P_TP, k) = r.T;
                 S(P_QP, k) = r.qv;
                 S(P_Q1, k) = sr.dqs;
                 S(P_Q2, k) = sr.d2qs;
                 S(P_SAT, k) = r.sat ? 1.0 : 0.0;
-                const double lam = lamk(k);
-                cape += RD * (tv(r.T, r.qv) - tv(Tk(k), qk(k))) * lam;
+                const double lam = log(v.pb / v.pt);
+                cape += RD * (tv(r.T, r.qv) - tv(v.T, v.q)) * lam;
                 double ca, cb;
                 if (r.sat) {
                     const double c = (1.0 + CVIR * r.qv) + CVIR * r.T * sr.dqs;
@@ -141,13 +159,29 @@ __global__ __launch_bounds__(WAVE) void k_deep_adjoint(Member M, AdjWork w) {
             C1 = qkb - r0.qv;
             S(U_C, kb) = C1;
             double eta = 1.0, hum = hkb, qup = r0.qv;
+            struct UL {
+                double za, z, T, q, p;  // heights of layers k-1 and k, T, q, top pressure of k
+            };
+            auto uload = [&](int k) {
+                UL v;
+                const int kk = max(k, kt + 1);
+                v.za = AT(M.z, kk - 1);
+                v.z = AT(M.z, kk);
+                v.T = Tk(kk);
+                v.q = qk(kk);
+                v.p = AT(M.pi, kk);
+                return v;
+            };
+            UL nx = uload(kb - 1);
             for (int k = kb - 1; k >= kt + 1; --k) {
-                const double zk = zi(k);
+                const UL v = nx;
+                nx = uload(k - 1);
+                const double zk = 0.5 * (v.za + v.z);
                 const double E = epsd * eta * (zk - zlo);
                 const double etan = eta + E;
-                const double hm = (eta * hum + E * hk(k)) / etan;
-                const double qm = (eta * qup + E * qk(k)) / etan;
-                const Lifted r = lift(hm - GRAV * zk - phis, qm, AT(M.pi, k), hu);
+                const double hm = (eta * hum + E * ((CP * v.T + GRAV * v.z + phis) + LV * v.q)) / etan;
+                const double qm = (eta * qup + E * v.q) / etan;
+                const Lifted r = lift(hm - GRAV * zk - phis, qm, v.p, hu);
                 const double c = etan * (qm - r.qv);
                 S(U_ETA, k) = etan;
                 S(U_HM, k) = hm;
@@ -193,14 +227,30 @@ __global__ __launch_bounds__(WAVE) void k_deep_adjoint(Member M, AdjWork w) {
             S(D_Q1, kd + 1) = s.dqs;
             E1 = qd - qk(kd);
             S(D_E1, kd) = E1;
+            struct DL {
+                double z, zb, T, q, pb;  // heights of layers k and k+1, T, q, bottom pressure of k
+            };
+            auto dload = [&](int k) {
+                DL v;
+                const int kk = min(k, kb - 1);
+                v.z = AT(M.z, kk);
+                v.zb = AT(M.z, kk + 1);
+                v.T = Tk(kk);
+                v.q = qk(kk);
+                v.pb = AT(M.pi, kk + 1);
+                return v;
+            };
+            DL nx = dload(kd + 1);
             for (int k = kd + 1; k <= kb - 1; ++k) {
-                const double zlow = zi(k + 1);
+                const DL v = nx;
+                nx = dload(k + 1);
+                const double zlow = 0.5 * (v.z + v.zb);
                 const double Ed = epsd * ad * (zii - zlow);
                 const double adn = ad + Ed;
-                hd = (ad * hd + Ed * hk(k)) / adn;
+                hd = (ad * hd + Ed * ((CP * v.T + GRAV * v.z + phis) + LV * v.q)) / adn;
                 H = hd - GRAV * zlow - phis;
-                Td = tsat_h(H, AT(M.pi, k + 1), (H - LV * qk(k)) * RCP_CP, s, hdn);
-                const double e1 = adn * s.qs - ad * qd - Ed * qk(k);
+                Td = tsat_h(H, v.pb, (H - LV * v.q) * RCP_CP, s, hdn);
+                const double e1 = adn * s.qs - ad * qd - Ed * v.q;
                 S(D_ED, k) = Ed;
                 S(D_E1, k) = e1;
                 S(D_AD, k + 1) = adn;
@@ -224,45 +274,77 @@ __global__ __launch_bounds__(WAVE) void k_deep_adjoint(Member M, AdjWork w) {
         int klim_at = -1;
         {
             double Fs_top = 0.0, Fq_top = 0.0;
-            for (int k = kt; k <= kb; ++k) {
-                double Fs = 0.0, Fq = 0.0;
-                const int i = k + 1;
-                if (i <= kb) {
-                    const double et = S(U_ETA, i);
-                    const bool dn = kd >= 0 && i >= kd + 1;
-                    const double ed = dn ? -S(D_AD, i) : 0.0;
-                    const bool upw = et + alpha * ed >= 0.0;
-                    const int up = upw ? i - 1 : i;
-                    const double s_up = CP * Tk(up) + GRAV * AT(M.z, up) + phis;
-                    const double q_up = qk(up);
-                    const double zii = zi(i);
-                    Fs = et * ((CP * S(U_TU, i) + GRAV * zii + phis) - s_up);
-                    Fq = et * (S(U_QU, i) - q_up);
-                    if (dn) {
-                        Fs += alpha * ed * ((CP * S(D_TD, i) + GRAV * zii + phis) - s_up);
-                        Fq += alpha * ed * (S(D_QD, i) - q_up);
-                    }
-                    S(X_UPW, i) = upw ? 1.0 : 0.0;
+            // Layers k0 .. k0+AB-1 and their bottom interfaces, loaded together (levels clamped
+            // to kb; the upwind candidates of both sides are loaded, the choice made after).
+            for (int k0 = kt; k0 <= kb; k0 += AB) {
+                struct V {
+                    double T, q, z, pt, pb, Tb, qb, zb, et, ad, tu, qu, td, qd, c, e1;
+                } v[AB];
+#pragma unroll
+                for (int j = 0; j < AB; ++j) {
+                    const int k = min(k0 + j, kb), i = min(k + 1, kb);
+                    v[j].T = Tk(k);
+                    v[j].q = qk(k);
+                    v[j].z = AT(M.z, k);
+                    v[j].pt = AT(M.pi, k);
+                    v[j].pb = AT(M.pi, k + 1);
+                    v[j].Tb = Tk(i);
+                    v[j].qb = qk(i);
+                    v[j].zb = AT(M.z, i);
+                    v[j].et = S(U_ETA, i);
+                    v[j].ad = S(D_AD, i);
+                    v[j].tu = S(U_TU, i);
+                    v[j].qu = S(U_QU, i);
+                    v[j].td = S(D_TD, i);
+                    v[j].qd = S(D_QD, i);
+                    v[j].c = S(U_C, k);
+                    v[j].e1 = S(D_E1, k);
                 }
-                const double c = (k >= kt + 1) ? S(U_C, k) : 0.0;
-                const double e1 = (kd >= 0 && k >= kd && k <= kb - 1) ? S(D_E1, k) : 0.0;
-                const double net = c - alpha * e1;
-                const double dp = dpk(k);
-                const double dT1 = (Fs - Fs_top + LV * net) * GRAV / (CP * dp);
-                const double dq1 = (Fq - Fq_top - net) * GRAV / dp;
-                S(X_DT1, k) = dT1;
-                S(X_DQ1, k) = dq1;
-                P1 += net;
-                if (k <= kb - 1) Fenv += lamk(k) * ((1.0 + CVIR * qk(k)) * dT1 + CVIR * Tk(k) * dq1);
-                if (dq1 < 0.0) {
-                    const double m = qk(k) / (-dt * dq1);
-                    if (m < Mlim) {
-                        Mlim = m;
-                        klim_at = k;
+#pragma unroll
+                for (int j = 0; j < AB; ++j) {
+                    const int k = k0 + j;
+                    if (k > kb) break;
+                    double Fs = 0.0, Fq = 0.0;
+                    const int i = k + 1;
+                    if (i <= kb) {
+                        const double et = v[j].et;
+                        const bool dn = kd >= 0 && i >= kd + 1;
+                        const double ed = dn ? -v[j].ad : 0.0;
+                        const bool upw = et + alpha * ed >= 0.0;  // upwind layer i-1 = k, else i
+                        const double s_up = upw ? CP * v[j].T + GRAV * v[j].z + phis
+                                                : CP * v[j].Tb + GRAV * v[j].zb + phis;
+                        const double q_up = upw ? v[j].q : v[j].qb;
+                        const double zii = 0.5 * (v[j].z + v[j].zb);
+                        Fs = et * ((CP * v[j].tu + GRAV * zii + phis) - s_up);
+                        Fq = et * (v[j].qu - q_up);
+                        if (dn) {
+                            Fs += alpha * ed * ((CP * v[j].td + GRAV * zii + phis) - s_up);
+                            Fq += alpha * ed * (v[j].qd - q_up);
+                        }
+                        S(X_UPW, i) = upw ? 1.0 : 0.0;
                     }
+                    const double c = (k >= kt + 1) ? v[j].c : 0.0;
+                    const double e1 = (kd >= 0 && k >= kd && k <= kb - 1) ? v[j].e1 : 0.0;
+                    const double net = c - alpha * e1;
+                    const double dp = v[j].pb - v[j].pt;
+                    const double dT1 = (Fs - Fs_top + LV * net) * GRAV / (CP * dp);
+                    const double dq1 = (Fq - Fq_top - net) * GRAV / dp;
+                    S(X_DT1, k) = dT1;
+                    S(X_DQ1, k) = dq1;
+                    P1 += net;
+                    if (k <= kb - 1)
+                        Fenv += log(v[j].pb / v[j].pt) *
+                                ((1.0 + CVIR * v[j].q) * dT1 + CVIR * v[j].T * dq1);
+                    if (dq1 < 0.0) {
+                        const double m = v[j].q / (-dt * dq1);
+                        if (m < Mlim) {
+                            Mlim = m;
+                            klim_at = k;
+                        }
+                    }
+                    Fs_top = Fs;
+                    Fq_top = Fq;
                 }
-                Fs_top = Fs;
-                Fq_top = Fq;
             }
         }
         const double dT1b = S(X_DT1, kb), dq1b = S(X_DQ1, kb);
@@ -963,14 +1045,26 @@ __global__ __launch_bounds__(WAVE) void k_shallow_adjoint(Member M, SAdjWork w) 
             S(W_GT, lev) = 0.0;
             S(W_GQ, lev) = 0.0;
         }
-        // S9 outputs = M_b * unit profiles.
+        // S9 outputs = M_b * unit profiles (AB levels loaded at a time, as in the deep adjoint).
         double gMb = 0.0;
-        for (int k = kt; k <= ks; ++k) {
-            const double cT = w.cT ? AT(w.cT, k) : 0.0;
-            const double cq = w.cq ? AT(w.cq, k) : 0.0;
-            gMb += cT * S(W_DT1, k) + cq * S(W_DQ1, k);
-            S(W_GDT1, k) = cT * Mb;
-            S(W_GDQ1, k) = cq * Mb;
+        for (int k0 = kt; k0 <= ks; k0 += AB) {
+            double cT[AB], cq[AB], d1[AB], q1[AB];
+#pragma unroll
+            for (int j = 0; j < AB; ++j) {
+                const int k = min(k0 + j, ks);
+                cT[j] = w.cT ? AT(w.cT, k) : 0.0;
+                cq[j] = w.cq ? AT(w.cq, k) : 0.0;
+                d1[j] = S(W_DT1, k);
+                q1[j] = S(W_DQ1, k);
+            }
+#pragma unroll
+            for (int j = 0; j < AB; ++j) {
+                const int k = k0 + j;
+                if (k > ks) break;
+                gMb += cT[j] * d1[j] + cq[j] * q1[j];
+                S(W_GDT1, k) = cT[j] * Mb;
+                S(W_GDQ1, k) = cq[j] * Mb;
+            }
         }
         const double cPc = w.cP ? w.cP[col] : 0.0;
         gMb += cPc * P1;
@@ -1063,15 +1157,41 @@ __global__ __launch_bounds__(WAVE) void k_shallow_adjoint(Member M, SAdjWork w) 
                          ghs, gqs);
         }
         // S1: the source means.
-        for (int k = ks; k < L; ++k) {
-            const double f = dpk(k) / wsum;
-            S(W_GT, k) += CP * ghs * f;
-            S(W_GQ, k) += (LV * ghs + gqs) * f;
+        for (int k0 = ks; k0 < L; k0 += AB) {
+            double pt[AB], pb[AB], gt[AB], gq[AB];
+#pragma unroll
+            for (int j = 0; j < AB; ++j) {
+                const int k = min(k0 + j, L - 1);
+                pt[j] = AT(M.pi, k);
+                pb[j] = AT(M.pi, k + 1);
+                gt[j] = S(W_GT, k);
+                gq[j] = S(W_GQ, k);
+            }
+#pragma unroll
+            for (int j = 0; j < AB; ++j) {
+                const int k = k0 + j;
+                if (k >= L) break;
+                const double f = (pb[j] - pt[j]) / wsum;
+                S(W_GT, k) = gt[j] + CP * ghs * f;
+                S(W_GQ, k) = gq[j] + (LV * ghs + gqs) * f;
+            }
         }
-        for (int k = 0; k < L; ++k) {
-            const bool in = k >= kmin;
-            AT(w.gT, k) = in ? S(W_GT, k) : 0.0;
-            AT(w.gq, k) = in ? S(W_GQ, k) : 0.0;
+        for (int k0 = 0; k0 < L; k0 += AB) {
+            double gt[AB], gq[AB];
+#pragma unroll
+            for (int j = 0; j < AB; ++j) {
+                const int k = min(k0 + j, L - 1);
+                gt[j] = S(W_GT, k);
+                gq[j] = S(W_GQ, k);
+            }
+#pragma unroll
+            for (int j = 0; j < AB; ++j) {
+                const int k = k0 + j;
+                if (k >= L) break;
+                const bool in = k >= kmin;
+                AT(w.gT, k) = in ? gt[j] : 0.0;
+                AT(w.gq, k) = in ? gq[j] : 0.0;
+            }
         }
         w.pgrad[col] = geps;
         w.pgrad[ld + col] = gdel;
