@@ -35,12 +35,12 @@ NLON, NLAT = 1152, 768
 TRAFFIC_SOURCES = ("paper_1711_00289_amd/csrc/conv.hip", "paper_1711_00289_amd/csrc/conv_physics.hpp",
                    "paper_1711_00289_amd/csrc/conv_internal.hpp")
 MEASURED_TRAFFIC = {
-    "sources_sha256": "3c0d476b0cc4cca47ce8a553379980fe5039eeeaf947375b0509c96251feafda",
+    "sources_sha256": "9bc1318af52f3be07157a9a7ec78567aadb9667afbe8f22b45a36cfdf929ac8e",
     "fetch_factor": 2.0, "write_factor": 1.0,
-    "k_trigger": (533468, 1530035),
-    "k_deep_plume": (268394, 352022),
-    "k_shallow_retrigger": (120859, 9254),
-    "k_shallow_plume": (47947, 18138),
+    "k_trigger": (533470, 1530023),
+    "k_deep_plume": (252366, 344880),
+    "k_shallow_retrigger": (120866, 9265),
+    "k_shallow_plume": (51539, 18167),
 }
 
 

@@ -260,8 +260,8 @@ void conv_ensemble_destroy(conv_ens_t *e); /* frees the host handle and any capt
  * memset nodes: capturable). */
 int conv_ensemble_step(conv_ens_t *e, void *stream);
 
-/* Persistent-grid shape (blocks per compute unit, 1..8) of the plume kernels.  Changing it drops a
- * captured graph. */
+/* Persistent-grid shape of the plume kernels (256-thread units per compute unit, 1..8, as for
+ * conv_set_launch).  Changing it drops a captured graph. */
 int conv_ensemble_set_launch(conv_ens_t *e, int fused_blocks_per_cu, int shallow_blocks_per_cu);
 int conv_ensemble_get_launch(conv_ens_t *e, int *fused_blocks_per_cu, int *shallow_blocks_per_cu);
 
@@ -283,9 +283,10 @@ int conv_autotune(conv_ctx_t *ctx, const conv_state_t *state, conv_deep_out_t *d
                   conv_shallow_out_t *shallow, void *stream, int reps, int force,
                   int *fused_blocks_per_cu, int *shallow_blocks_per_cu, float *ms);
 
-/* Launch shape of the persistent kernels: blocks of 256 threads per compute unit for the
- * deep-plume kernel and for the shallow-plume kernel (each 1..8; default 1 and 8).  The
- * workspace size does not depend on it.  Results do not depend on it (bit-identical). */
+/* Launch shape of the persistent kernels: 256-thread units per compute unit for the deep-plume
+ * kernel and for the shallow-plume kernel (each 1..8; default 1 and 8), launched as blocks of one
+ * 64-thread wavefront each (n units per CU = 4n such blocks per CU).  The workspace size does not
+ * depend on it.  Results do not depend on it (bit-identical). */
 int conv_set_launch(conv_ctx_t *ctx, int fused_blocks_per_cu, int shallow_blocks_per_cu);
 int conv_get_launch(conv_ctx_t *ctx, int *fused_blocks_per_cu, int *shallow_blocks_per_cu);
 
