@@ -30,6 +30,7 @@ using namespace cvk;
 namespace {
 
 constexpr int TW = WAVE;  // threads per block
+constexpr int TB = 8;     // levels whose loads are issued together in the plume sweeps
 
 struct TrArgs {
     Member M;          // state, both schemes' outputs and parameters of the step
@@ -87,42 +88,71 @@ __global__ __launch_bounds__(TW) void k_tracers(TrArgs a) {
 
     if (deep) {
         // Updraft, bottom-up: C_u at interface i, its flux, and layer i's tendency from its
-        // bottom (Fb) and top fluxes.  The next interface's loads are issued before the current
-        // one is computed (indices clamped: values loaded past the top are not used).  The
-        // downdraft's first interface (the highest one with md != 0) is noted on the way.
+        // bottom (Fb) and top fluxes.  The loads of TB interfaces are issued together, then those
+        // interfaces are computed (a level's arithmetic is far shorter than a load's latency);
+        // indices are clamped, so values loaded past the top are not used.  The downdraft's
+        // first interface (the highest one with md != 0) is noted on the way.
         double Cu = AT(C, kb), Fb = 0.0, mu1 = 0.0;
-        double mu_n = AT(M.dout.mu, kb), md_n = AT(M.dout.md, kb), C_n = Cu, Cm_n = AT(C, kb - 1);
-        double pt_n = AT(M.pi, kb), pb_n = AT(M.pi, kb + 1);
         int i0 = kb + 1;
-        for (int i = kb; i >= kt + 1; --i) {
-            const double mu = mu_n, md = md_n, Ci = C_n, Cim1 = Cm_n, ptop = pt_n, pbot = pb_n;
-            const int j = max(i - 1, 0), jj = max(i - 2, 0);
-            mu_n = AT(M.dout.mu, j);
-            md_n = AT(M.dout.md, j);
-            Cm_n = AT(C, jj);
-            pt_n = AT(M.pi, j);
-            C_n = Cim1;
-            pb_n = ptop;
-            if (md != 0.0) i0 = i;
-            if (i < kb) Cu = (mu1 * Cu + (mu - mu1) * Ci) / mu;
-            const double F = mu * (Cu - (mu + md >= 0.0 ? Cim1 : Ci));
-            SH(i) = (Fb - F) * GRAV / (pbot - ptop);
-            Fb = F;
-            mu1 = mu;
+        for (int b = kb; b >= kt + 1; b -= TB) {
+            double mu[TB], md[TB], Ci[TB + 1], pt[TB + 1];
+#pragma unroll
+            for (int j = 0; j <= TB; ++j) {
+                const int i = max(b - j, kt);
+                Ci[j] = AT(C, i);
+                pt[j] = AT(M.pi, i);
+            }
+            const double pbot0 = AT(M.pi, b + 1);
+#pragma unroll
+            for (int j = 0; j < TB; ++j) {
+                const int i = max(b - j, kt + 1);
+                mu[j] = AT(M.dout.mu, i);
+                md[j] = AT(M.dout.md, i);
+            }
+#pragma unroll
+            for (int j = 0; j < TB; ++j) {
+                const int i = b - j;
+                if (i < kt + 1) break;
+                // interface i: layer i below (C_i), layer i-1 above (C_{i-1}); layer i spans
+                // pressures pt[j] (top) .. its bottom interface (pt[j-1], or pbot0 for j = 0)
+                if (md[j] != 0.0) i0 = i;
+                if (i < kb) Cu = (mu1 * Cu + (mu[j] - mu1) * Ci[j]) / mu[j];
+                const double F = mu[j] * (Cu - (mu[j] + md[j] >= 0.0 ? Ci[j + 1] : Ci[j]));
+                const double pbot = j == 0 ? pbot0 : pt[j - 1];
+                SH(i) = (Fb - F) * GRAV / (pbot - pt[j]);
+                Fb = F;
+                mu1 = mu[j];
+            }
         }
         SH(kt) = Fb * GRAV / dp(kt);
         // Downdraft, top-down from its first interface: C_d at interface i mixes layer i-1's air
         // into C_d at i-1; its flux enters layer i-1 from below and leaves layer i at the top.
         if (i0 <= kb) {
             double Cd = AT(C, i0 - 1), ad1 = 0.0;
-            for (int i = i0; i <= kb; ++i) {
-                const double mu = AT(M.dout.mu, i), md = AT(M.dout.md, i);
-                const double ad = -md;
-                if (i > i0) Cd = (ad1 * Cd + (ad - ad1) * AT(C, i - 1)) / ad;
-                const double F = md * (Cd - AT(C, mu + md >= 0.0 ? i - 1 : i));
-                SH(i - 1) += F * GRAV / dp(i - 1);
-                SH(i) -= F * GRAV / dp(i);
-                ad1 = ad;
+            for (int b = i0; b <= kb; b += TB) {
+                // interfaces b .. b+TB-1: layers b-1 .. b+TB-1 and their interfaces b-1 .. b+TB
+                double mu[TB], md[TB], Cl[TB + 1], pl[TB + 2];
+#pragma unroll
+                for (int j = 0; j < TB; ++j) {
+                    const int i = min(b + j, kb);
+                    mu[j] = AT(M.dout.mu, i);
+                    md[j] = AT(M.dout.md, i);
+                }
+#pragma unroll
+                for (int j = 0; j <= TB; ++j) Cl[j] = AT(C, min(b - 1 + j, kb));
+#pragma unroll
+                for (int j = 0; j <= TB + 1; ++j) pl[j] = AT(M.pi, min(b - 1 + j, kb + 1));
+#pragma unroll
+                for (int j = 0; j < TB; ++j) {
+                    const int i = b + j;
+                    if (i > kb) break;
+                    const double ad = -md[j];
+                    if (i > i0) Cd = (ad1 * Cd + (ad - ad1) * Cl[j]) / ad;
+                    const double F = md[j] * (Cd - (mu[j] + md[j] >= 0.0 ? Cl[j] : Cl[j + 1]));
+                    SH(i - 1) += F * GRAV / (pl[j + 1] - pl[j]);
+                    SH(i) -= F * GRAV / (pl[j + 2] - pl[j + 1]);
+                    ad1 = ad;
+                }
             }
         }
     }
@@ -134,27 +164,56 @@ __global__ __launch_bounds__(TW) void k_tracers(TrArgs a) {
     if (shal) {
         // The tracer the shallow scheme sees: updated by the deep transport (zero where the deep
         // scheme left the column alone).
-        auto C2 = [&](int k) { return AT(C, k) + M.dt * SH(k); };
+        // C2(k) = C(k) + dt SH(k): the tracer after the deep transport.  The recursion below adds
+        // the shallow part to level i only after reading C2(i) and C2(i - 1), and level i is read
+        // by no later step, so SH holds the deep part wherever C2 is evaluated.
         double csum = 0.0, wsum = 0.0;
-        for (int k = L - 1; k >= ks; --k) {
-            csum += dp(k) * C2(k);
-            wsum += dp(k);
-        }
-        // C2 reads the deep part of levels kts-1 .. L-1 before the shallow part is added to them:
-        // the recursion below adds to level i only after reading C2(i) and C2(i - 1) > level i.
-        double Cu = csum / wsum, Fb = 0.0, mu1 = 0.0;
-        for (int i = ks; i >= kts + 1; --i) {
-            const double mu = AT(M.sout.mu, i);
-            const double Cim1 = C2(i - 1);
-            if (i < ks) {
-                const double dz = zi(i) - zi(i + 1);
-                const double E = P.eps_sh * mu1 * dz, D = P.delta_sh * mu1 * dz;
-                Cu = ((mu1 - D) * Cu + E * C2(i)) / mu;
+        for (int b = L - 1; b >= ks; b -= TB) {
+            double Ck[TB], pt[TB], pb[TB];
+#pragma unroll
+            for (int j = 0; j < TB; ++j) {
+                const int k = max(b - j, ks);
+                Ck[j] = AT(C, k);
+                pt[j] = AT(M.pi, k);
+                pb[j] = AT(M.pi, k + 1);
             }
-            const double F = mu * (Cu - Cim1);
-            SH(i) += (Fb - F) * GRAV / dp(i);
-            Fb = F;
-            mu1 = mu;
+#pragma unroll
+            for (int j = 0; j < TB; ++j) {
+                const int k = b - j;
+                if (k < ks) break;
+                const double dpk = pb[j] - pt[j];
+                csum += dpk * (Ck[j] + M.dt * SH(k));
+                wsum += dpk;
+            }
+        }
+        double Cu = csum / wsum, Fb = 0.0, mu1 = 0.0;
+        for (int b = ks; b >= kts + 1; b -= TB) {
+            // interfaces b .. b-TB+1: layers b .. b-TB, heights b+1 .. b-TB, pressures b+1 .. b-TB+1
+            double mu[TB], Cl[TB + 1], zl[TB + 2], pl[TB + 1];
+#pragma unroll
+            for (int j = 0; j < TB; ++j) mu[j] = AT(M.sout.mu, max(b - j, kts + 1));
+#pragma unroll
+            for (int j = 0; j <= TB; ++j) Cl[j] = AT(C, max(b - j, kts));
+#pragma unroll
+            for (int j = 0; j <= TB + 1; ++j) zl[j] = AT(M.z, min(max(b + 1 - j, 0), L - 1));
+#pragma unroll
+            for (int j = 0; j <= TB; ++j) pl[j] = AT(M.pi, max(b + 1 - j, 0));
+#pragma unroll
+            for (int j = 0; j < TB; ++j) {
+                const int i = b - j;
+                if (i < kts + 1) break;
+                const double Cim1 = Cl[j + 1] + M.dt * SH(i - 1);
+                if (i < ks) {
+                    // zi(i) - zi(i + 1), the interface heights as means of the layers around them
+                    const double dz = 0.5 * (zl[j + 2] + zl[j + 1]) - 0.5 * (zl[j + 1] + zl[j]);
+                    const double E = P.eps_sh * mu1 * dz, D = P.delta_sh * mu1 * dz;
+                    Cu = ((mu1 - D) * Cu + E * (Cl[j] + M.dt * SH(i))) / mu[j];
+                }
+                const double F = mu[j] * (Cu - Cim1);
+                SH(i) += (Fb - F) * GRAV / (pl[j] - pl[j + 1]);
+                Fb = F;
+                mu1 = mu[j];
+            }
         }
         SH(kts) += Fb * GRAV / dp(kts);
     }
