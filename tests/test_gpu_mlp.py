@@ -116,6 +116,28 @@ def test_forward_loss_backward_against_reference(torch, batch):
         assert _rel(gb, rb) <= 5e-3, (i, "b", _rel(gb, rb))
 
 
+@pytest.mark.parametrize("widths,batch", [((64, 32, 96, 32), 333), ((32, 64, 64, 32), 1),
+                                          ((96, 160, 32, 64), 777)])
+def test_other_widths_forward_backward(torch, widths, batch):
+    """Narrow layers (the 128 x 64 tile, also for the transposed copies of the training
+    products), a width that is not a multiple of the 128-column tile, ragged batches."""
+    widths = list(widths)
+    net, params, x, t = _net(torch, batch, 21, widths)
+    y = net.forward(bf16_dev(torch, x), keep=True)
+    loss = net.mse(y, torch.from_numpy(t).cuda(), widths[-1])
+    net.backward(batch)
+    grads = R.unflatten(net.get_grads().cpu().numpy(), widths)
+    torch.cuda.synchronize()
+    yr, acts, zs = R.forward(params, x, emulate=True)
+    assert _rel(y.cpu().numpy(), yr) <= 5e-3
+    lr, dy = R.mse(yr, t, widths[-1], emulate=True)
+    assert abs(float(loss.item()) - lr) <= 5e-3 * lr
+    gref = R.backward(params, acts, zs, dy, emulate=True)
+    for i, ((gW, gb), (rW, rb)) in enumerate(zip(grads, gref)):
+        assert _rel(gW, rW) <= 5e-3, (i, "W", _rel(gW, rW))
+        assert _rel(gb, rb) <= 5e-3, (i, "b", _rel(gb, rb))
+
+
 def test_gradients_reproducible_bit_for_bit(torch):
     net, params, x, t = _net(torch, 1500, 12)
     xd, td = bf16_dev(torch, x), torch.from_numpy(t).cuda()
