@@ -438,7 +438,7 @@ __global__ __launch_bounds__(WAVE) void k_deep_plume(Src src, Work w) {
     for (int64_t slot0 = gtid - lane;;) {
         const int64_t slot = slot0 + lane;
         if (slot >= n) break;
-        const Member &M = src.at(w.dmem[slot]);
+        const Member M = src.at(w.dmem[slot]);  // a copy: the fields stay in registers
         const int64_t ld = M.ld;
         const conv_params_t &P = M.P;
         const int64_t col = w.dlist[slot];
@@ -778,7 +778,7 @@ __global__ __launch_bounds__(BLOCK) void k_shallow_retrigger(Src src, Work w) {
         const int64_t slot = base + (threadIdx.x % WAVE);
         const bool act = slot < n;
         const int mi = act ? w.dmem[slot] : 0;
-        const Member &M = src.at(mi);
+        const Member M = src.at(mi);  // a copy: the fields stay in registers
         const int L = M.nlev;
         const int64_t ld = M.ld;
         const conv_params_t &P = M.P;
@@ -858,7 +858,7 @@ __global__ __launch_bounds__(WAVE) void k_shallow_plume(Src src, Work w) {
 #define SCR(arr, lev) scr[((int64_t)(arr) * (w.lmax + 1) + (lev)) * w.sstride + gtid]
 
     for (int64_t slot = gtid; slot < n; slot += nthreads) {
-        const Member &M = src.at(w.smem[slot]);
+        const Member M = src.at(w.smem[slot]);  // a copy: the fields stay in registers
         const int64_t ld = M.ld;
         const conv_params_t &P = M.P;
         const int64_t col = w.slist[slot];
