@@ -104,6 +104,34 @@ def test_dot_product_identity_per_column(torch):
     assert np.all(g["g_T"][:, quiet] == 0.0) and np.all(g["g_q"][:, quiet] == 0.0)
 
 
+@pytest.mark.parametrize("kw,branch", [(dict(tau=20.0), "limited"),
+                                       (dict(evap_max_frac=0.05), "capped")])
+def test_dot_product_identity_on_the_other_branches(torch, kw, branch):
+    """Every active column with the humidity limiter setting the base flux (D9), or with the
+    downdraft strength capped by the evaporation limit (D6): the state gradient through those
+    branches, per column."""
+    st = S.small_warm()
+    L, n = st["nlev"], st["ncol"]
+    rng = np.random.default_rng(26)
+    cT, cq, cP = _cotangents(rng, L, n)
+    op = oracle.make_params(**kw)
+    _, _, out, g = _run(torch, st, cT, cq, cP, _B().make_params(**kw))
+    act = np.nonzero(_np(out["status"]) == 0)[0]
+    assert len(act) > 100
+    hit = 0
+    for c in act:
+        col = oracle.column(st, int(c))
+        d = oracle.deep_column(col, op)["diag"]
+        hit += int(d["Mb"] < d["Mc"] if branch == "limited" else d["alpha"] < op.alpha_dd)
+        dT = rng.standard_normal(L)
+        dq = rng.standard_normal(L) * 1e-3 * col["q"]
+        j = oracle.deep_column_jvp(col, dT, dq, params=op)
+        rhs, rscale = _cot_dot(cT, cq, cP, c, j)
+        lterms = np.concatenate([g["g_T"][:, c] * dT, g["g_q"][:, c] * dq])
+        assert abs(lterms.sum() - rhs) <= TOL * max(rscale, np.abs(lterms).sum()), int(c)
+    assert hit > len(act) // 2
+
+
 def test_full_gradient_from_unit_tangents(torch):
     st = S.small_warm()
     L, n = st["nlev"], st["ncol"]
