@@ -35,12 +35,12 @@ NLON, NLAT = 1152, 768
 TRAFFIC_SOURCES = ("paper_1711_00289_amd/csrc/conv.hip", "paper_1711_00289_amd/csrc/conv_physics.hpp",
                    "paper_1711_00289_amd/csrc/conv_internal.hpp")
 MEASURED_TRAFFIC = {
-    "sources_sha256": "9bc1318af52f3be07157a9a7ec78567aadb9667afbe8f22b45a36cfdf929ac8e",
+    "sources_sha256": "2fbd7f7db2877bafc342439902eb249bfb2fcc0146e5a016f3a2d3caffd05bf6",
     "fetch_factor": 2.0, "write_factor": 1.0,
-    "k_trigger": (533470, 1530023),
-    "k_deep_plume": (252366, 344880),
-    "k_shallow_retrigger": (120866, 9265),
-    "k_shallow_plume": (51539, 18167),
+    "k_trigger": (533467, 1530031),
+    "k_deep_plume": (253324, 343845),
+    "k_shallow_retrigger": (120975, 9262),
+    "k_shallow_plume": (50857, 18172),
 }
 
 
