@@ -225,7 +225,7 @@ __global__ __launch_bounds__(BLOCK) void k_trigger(Src src, Work w) {
     bool valid = live;
     double phis = 0.0, pblh = 0.0, tke = 0.0;
     int kb = -1;
-    double hkb = 0.0, qkb = 0.0;
+    double hkb = 0.0;
     double hmix = 0.0, qmix = 0.0;  // the (dilute) parcel's h and total water
     const bool dilute = P.eps_cape > 0.0;
     ShallowTrigger sh;
@@ -271,7 +271,6 @@ __global__ __launch_bounds__(BLOCK) void k_trigger(Src src, Work w) {
                 if (v.pm >= P.p_launch_min && (kb < 0 || h > hkb)) {
                     kb = k;  // a new launch layer: the parcel restarts above it
                     hkb = h;
-                    qkb = v.q;
                     hmix = h;
                     qmix = v.q;
                     kt = -1;
@@ -957,11 +956,26 @@ __global__ __launch_bounds__(WAVE) void k_shallow_plume(Src src, Work w) {
         const int st = (kt == ks - 1) ? 5 : 0;
         const double Mb = Mclos <= Mlim ? Mclos : Mlim;
         if (st == 0) {  // the trigger pass zeroed the column; write the plume's levels
-            for (int k = kt; k <= ks; ++k) {
-                AT(M.sout.dTdt, k) = Mb * SCR(1, k);
-                AT(M.sout.dqdt, k) = Mb * SCR(2, k);
+            // OUTC levels at a time, loads first (levels clamped to ks), as in the deep plume.
+            constexpr int OUTC = 4;
+            for (int k0 = kt; k0 <= ks; k0 += OUTC) {
+                double a[OUTC], b[OUTC], e[OUTC];
+#pragma unroll
+                for (int j = 0; j < OUTC; ++j) {
+                    const int k = min(k0 + j, ks);
+                    a[j] = SCR(1, k);
+                    b[j] = SCR(2, k);
+                    e[j] = SCR(0, k);
+                }
+#pragma unroll
+                for (int j = 0; j < OUTC; ++j) {
+                    const int k = k0 + j;
+                    if (k > ks) break;
+                    AT(M.sout.dTdt, k) = Mb * a[j];
+                    AT(M.sout.dqdt, k) = Mb * b[j];
+                    if (k >= kt + 1) AT(M.sout.mu, k) = Mb * e[j];
+                }
             }
-            for (int i = kt + 1; i <= ks; ++i) AT(M.sout.mu, i) = Mb * SCR(0, i);
         }
         M.sout.prec[col] = st == 0 ? Mb * P1 : 0.0;
         M.sout.cin[col] = cin;

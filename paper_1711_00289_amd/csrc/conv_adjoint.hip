@@ -88,8 +88,6 @@ __global__ __launch_bounds__(WAVE) void k_deep_adjoint(Member M, AdjWork w) {
         auto qk = [&](int k) { return AT(M.q, k); };
         auto hk = [&](int k) { return (CP * AT(M.T, k) + GRAV * AT(M.z, k) + phis) + LV * AT(M.q, k); };
         auto zi = [&](int i) { return 0.5 * (AT(M.z, i - 1) + AT(M.z, i)); };
-        auto lamk = [&](int k) { return log(AT(M.pi, k + 1) / AT(M.pi, k)); };
-        auto dpk = [&](int k) { return AT(M.pi, k + 1) - AT(M.pi, k); };
 
         // ============================================ forward recomputation
         const double hkb = hk(kb), qkb = qk(kb);

@@ -72,7 +72,6 @@ __global__ __launch_bounds__(TW) void k_tracers(TrArgs a) {
                AT(M.sout.mu, ks) > 0.0;
     }
     auto dp = [&](int k) { return AT(M.pi, k + 1) - AT(M.pi, k); };
-    auto zi = [&](int i) { return 0.5 * (AT(M.z, i - 1) + AT(M.z, i)); };
 
     // A wavefront with nothing convecting stores its zeros directly.
     if (__ballot(deep || shal) == 0ull) {
