@@ -35,12 +35,12 @@ NLON, NLAT = 1152, 768
 TRAFFIC_SOURCES = ("paper_1711_00289_amd/csrc/conv.hip", "paper_1711_00289_amd/csrc/conv_physics.hpp",
                    "paper_1711_00289_amd/csrc/conv_internal.hpp")
 MEASURED_TRAFFIC = {
-    "sources_sha256": "2fbd7f7db2877bafc342439902eb249bfb2fcc0146e5a016f3a2d3caffd05bf6",
+    "sources_sha256": "e85862e6c39bfd5bd75d29bf989b3d1e386826380e3b454ce525e1411f474ce3",
     "fetch_factor": 2.0, "write_factor": 1.0,
-    "k_trigger": (533467, 1530031),
-    "k_deep_plume": (253324, 343845),
-    "k_shallow_retrigger": (120975, 9262),
-    "k_shallow_plume": (50857, 18172),
+    "k_trigger": (533465, 1530027),
+    "k_deep_plume": (257264, 343820),
+    "k_shallow_retrigger": (120921, 9256),
+    "k_shallow_plume": (51769, 18213),
 }
 
 
