@@ -254,7 +254,7 @@ def bench_surrogate(torch, B, main_state, truth_deep, truth_shallow, conv_step_m
 
     n = main_state["ncol"]
     sur, rep = SG.build_and_train(torch, n_train, epochs, batch=16384, lr=1e-3, seed=105,
-                                  max_cols=n, chunk=131_072,
+                                  max_cols=n, chunk=n,
                                   log=lambda m: print(f"[bench] surrogate {m}", file=sys.stderr,
                                                       flush=True))
     out = [torch.empty(NLEV, n, dtype=torch.float64, device="cuda") for _ in range(2)]

@@ -39,6 +39,19 @@ size_t mlp_workspace_bytes(const int32_t *widths, int n_layers, int64_t max_batc
 /* Handle over a 256-byte aligned workspace.  Weights are undefined until mlp_set_params. */
 int mlp_create(const int32_t *widths, int n_layers, int64_t max_batch, void *workspace,
                size_t ws_bytes, mlp_t **out);
+
+/* The same with a separate, smaller limit for training: inference forwards (keep = 0) and
+ * mlp_mse take up to max_batch rows, training forwards (keep != 0), mlp_backward and
+ * mlp_train_step up to max_train_batch (1 <= max_train_batch <= max_batch; a larger training
+ * batch is rejected with MLP_EINVAL).  Only the activations scale with max_batch; the
+ * pre-activations, transposed copies and hidden gradients that training keeps scale with
+ * max_train_batch, so a network that infers in large chunks and trains in small batches needs a
+ * fraction of mlp_workspace_bytes(widths, n_layers, max_batch).  mlp_create(.., b, ..) is
+ * mlp_create_ex(.., b, b, ..). */
+size_t mlp_workspace_bytes_ex(const int32_t *widths, int n_layers, int64_t max_batch,
+                              int64_t max_train_batch);
+int mlp_create_ex(const int32_t *widths, int n_layers, int64_t max_batch, int64_t max_train_batch,
+                  void *workspace, size_t ws_bytes, mlp_t **out);
 void mlp_destroy(mlp_t *m);
 
 /* Flat FP32 parameter vector layout: for l = 0..n_layers-1, W_l then b_l.  Its length: */
@@ -52,7 +65,8 @@ int mlp_get_params(const mlp_t *m, float *params, void *stream);
 int mlp_get_grads(const mlp_t *m, float *grads, void *stream);
 
 /* y[batch][widths[n]] = network(x[batch][widths[0]]).  `keep` != 0 stores the pre-activations and
- * activations for mlp_backward (training); 0 runs the lighter inference path.  batch <= max_batch. */
+ * activations for mlp_backward (training; batch <= max_train_batch); 0 runs the lighter inference
+ * path (batch <= max_batch). */
 int mlp_forward(mlp_t *m, const uint16_t *x, float *y, int64_t batch, int keep, void *stream);
 
 /* Mean squared error over the first n_valid outputs:

@@ -35,7 +35,8 @@ EXPORTS = ("conv_workspace_bytes", "conv_create", "conv_set_params", "conv_destr
            "conv_ensemble_workspace_bytes", "conv_ensemble_create", "conv_ensemble_destroy",
            "conv_ensemble_step", "conv_ensemble_set_launch", "conv_ensemble_get_launch",
            "conv_ensemble_autotune", "conv_ensemble_capture", "conv_ensemble_replay",
-           "mlp_workspace_bytes", "mlp_create", "mlp_destroy", "mlp_param_count", "mlp_set_params",
+           "mlp_workspace_bytes", "mlp_create", "mlp_workspace_bytes_ex", "mlp_create_ex",
+           "mlp_destroy", "mlp_param_count", "mlp_set_params",
            "mlp_get_params", "mlp_get_grads", "mlp_forward", "mlp_mse", "mlp_backward",
            "mlp_adam_step", "mlp_train_step", "mlp_gemm_nt", "mlp_strerror",
            "surr_pack_inputs_raw", "surr_pack_targets_raw", "surr_col_stats_scratch_bytes",
@@ -163,6 +164,11 @@ def lib():
         L.mlp_workspace_bytes.argtypes = [C.POINTER(C.c_int32), I, I64]
         L.mlp_create.restype = I
         L.mlp_create.argtypes = [C.POINTER(C.c_int32), I, I64, V, C.c_size_t, C.POINTER(V)]
+        L.mlp_workspace_bytes_ex.restype = C.c_size_t
+        L.mlp_workspace_bytes_ex.argtypes = [C.POINTER(C.c_int32), I, I64, I64]
+        L.mlp_create_ex.restype = I
+        L.mlp_create_ex.argtypes = [C.POINTER(C.c_int32), I, I64, I64, V, C.c_size_t,
+                                    C.POINTER(V)]
         L.mlp_destroy.restype = None
         L.mlp_destroy.argtypes = [V]
         L.mlp_param_count.restype = I64
@@ -673,26 +679,28 @@ def _ptr(t):
 
 class MLP:
     """The surrogate network (include/mlp.h) over a torch-allocated workspace.  Inputs are
-    torch.bfloat16 [batch][widths[0]]; outputs and targets float32 [batch][widths[-1]]."""
+    torch.bfloat16 [batch][widths[0]]; outputs and targets float32 [batch][widths[-1]].
+    `max_train_batch` (default max_batch) bounds the training forwards and backwards only."""
 
-    def __init__(self, widths, max_batch: int, device="cuda"):
+    def __init__(self, widths, max_batch: int, device="cuda", max_train_batch: int | None = None):
         torch = _torch()
         self.torch = torch
         self.widths = [int(w) for w in widths]
         self.n = len(self.widths) - 1
         self.max_batch = int(max_batch)
+        self.max_train_batch = int(max_train_batch or max_batch)
         self.device = device
         warr = (C.c_int32 * len(self.widths))(*self.widths)
         self._warr = warr
         L = lib()
-        nbytes = L.mlp_workspace_bytes(warr, self.n, self.max_batch)
+        nbytes = L.mlp_workspace_bytes_ex(warr, self.n, self.max_batch, self.max_train_batch)
         if nbytes == 0:
             raise ValueError("unsupported widths or batch")
         self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
         h = C.c_void_p()
-        mlp_check(L.mlp_create(warr, self.n, self.max_batch,
-                               C.c_void_p((self.ws.data_ptr() + 255) & ~255), nbytes, C.byref(h)),
-                  "mlp_create")
+        mlp_check(L.mlp_create_ex(warr, self.n, self.max_batch, self.max_train_batch,
+                                  C.c_void_p((self.ws.data_ptr() + 255) & ~255), nbytes,
+                                  C.byref(h)), "mlp_create_ex")
         self.h = h
         self.P = int(L.mlp_param_count(h))
         self.loss = torch.zeros(1, dtype=torch.float32, device=device)

@@ -631,7 +631,10 @@ bool widths_ok(const int32_t *w, int n) {
     return true;
 }
 
-Layout make_layout(const int32_t *w, int n, int64_t maxb) {
+// maxb: rows of an inference forward and of mlp_mse; maxt (<= maxb): rows of a training forward
+// (keep) and backward, the only users of the pre-activations, the transposed copies and the hidden
+// gradients.
+Layout make_layout(const int32_t *w, int n, int64_t maxb, int64_t maxt) {
     Layout l{};
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -658,14 +661,17 @@ Layout make_layout(const int32_t *w, int n, int64_t maxb) {
         l.wb[i] = take((size_t)w[i + 1] * w[i] * 2);
         l.wt[i] = take((size_t)w[i + 1] * w[i] * 2);
     }
-    const size_t ldt = (size_t)(maxb + 7) / 8 * 8;
+    const size_t ldt = (size_t)(maxt + 7) / 8 * 8;
     for (int i = 1; i < n; ++i) {
         l.act[i] = take((size_t)maxb * w[i] * 2);
-        l.zf[i] = take((size_t)maxb * w[i] * 4);
+        l.zf[i] = take((size_t)maxt * w[i] * 4);
         l.actT[i] = take(ldt * w[i] * 2);
     }
-    l.dz[0] = take((size_t)maxb * wmax * 2);
-    l.dz[1] = take((size_t)maxb * wmax * 2);
+    // dz[0]: the output gradient of mlp_mse (any batch) and a hidden gradient of mlp_backward
+    const size_t dz0 = (size_t)maxb * w[n] > (size_t)maxt * wmax ? (size_t)maxb * w[n]
+                                                                   : (size_t)maxt * wmax;
+    l.dz[0] = take(dz0 * 2);
+    l.dz[1] = take((size_t)maxt * wmax * 2);
     l.dzT = take(ldt * wmax * 2);
     l.xT = take(ldt * w[0] * 2);
     l.part = take(pmax * sizeof(float));
@@ -680,6 +686,7 @@ struct mlp {
     int n;
     int32_t w[MLP_MAX_LAYERS + 1];
     int64_t maxb;
+    int64_t maxt;          // rows of a training forward / backward (<= maxb)
     char *ws;
     Layout lay;
     int64_t t;             // Adam steps taken
@@ -707,23 +714,31 @@ int refresh_bf16(mlp *m, hipStream_t st) {
 
 extern "C" {
 
-size_t mlp_workspace_bytes(const int32_t *widths, int n_layers, int64_t max_batch) {
-    if (!widths_ok(widths, n_layers) || max_batch < 1 || max_batch > (1ll << 26)) return 0;
-    return make_layout(widths, n_layers, max_batch).total;
+size_t mlp_workspace_bytes_ex(const int32_t *widths, int n_layers, int64_t max_batch,
+                              int64_t max_train_batch) {
+    if (!widths_ok(widths, n_layers) || max_batch < 1 || max_batch > (1ll << 26) ||
+        max_train_batch < 1 || max_train_batch > max_batch)
+        return 0;
+    return make_layout(widths, n_layers, max_batch, max_train_batch).total;
 }
 
-int mlp_create(const int32_t *widths, int n_layers, int64_t max_batch, void *workspace,
-               size_t ws_bytes, mlp_t **out) {
+size_t mlp_workspace_bytes(const int32_t *widths, int n_layers, int64_t max_batch) {
+    return mlp_workspace_bytes_ex(widths, n_layers, max_batch, max_batch);
+}
+
+int mlp_create_ex(const int32_t *widths, int n_layers, int64_t max_batch, int64_t max_train_batch,
+                  void *workspace, size_t ws_bytes, mlp_t **out) {
     if (!out || !workspace || !widths_ok(widths, n_layers) || max_batch < 1 ||
-        max_batch > (1ll << 26))
+        max_batch > (1ll << 26) || max_train_batch < 1 || max_train_batch > max_batch)
         return MLP_EINVAL;
     if (((uintptr_t)workspace & 255u) != 0) return MLP_EINVAL;
-    const Layout l = make_layout(widths, n_layers, max_batch);
+    const Layout l = make_layout(widths, n_layers, max_batch, max_train_batch);
     if (ws_bytes < l.total) return MLP_EINVAL;
     mlp *m = new mlp;
     m->n = n_layers;
     for (int i = 0; i <= n_layers; ++i) m->w[i] = widths[i];
     m->maxb = max_batch;
+    m->maxt = max_train_batch;
     m->ws = (char *)workspace;
     m->lay = l;
     m->t = 0;
@@ -732,6 +747,11 @@ int mlp_create(const int32_t *widths, int n_layers, int64_t max_batch, void *wor
     m->dz_top = 0;
     *out = m;
     return MLP_OK;
+}
+
+int mlp_create(const int32_t *widths, int n_layers, int64_t max_batch, void *workspace,
+               size_t ws_bytes, mlp_t **out) {
+    return mlp_create_ex(widths, n_layers, max_batch, max_batch, workspace, ws_bytes, out);
 }
 
 void mlp_destroy(mlp_t *m) { delete m; }
@@ -771,7 +791,7 @@ int mlp_get_grads(const mlp_t *m, float *grads, void *stream) {
 }
 
 int mlp_forward(mlp_t *m, const uint16_t *x, float *y, int64_t batch, int keep, void *stream) {
-    if (!m || !x || !y || batch < 1 || batch > m->maxb) return MLP_EINVAL;
+    if (!m || !x || !y || batch < 1 || batch > (keep ? m->maxt : m->maxb)) return MLP_EINVAL;
     hipStream_t st = (hipStream_t)stream;
     const uint16_t *in = x;
     for (int i = 0; i < m->n; ++i) {

@@ -239,7 +239,7 @@ def build_and_train(torch, n_train: int, epochs: int, batch: int = 16384, lr: fl
     Xb = normalize(torch, X, in_mean, in_std, to_bf16=True)
     del X
     Yn = normalize(torch, Y, out_mean, out_std, to_bf16=False)
-    net = B.MLP(WIDTHS, max_batch=max(batch, chunk, hold))
+    net = B.MLP(WIDTHS, max_batch=max(batch, chunk, hold), max_train_batch=batch)
     net.set_params(init_params(torch, seed).cuda())
     curve, train_s, steps = train(torch, net, Xb[:n_train], Yn[:n_train], epochs, batch, lr,
                                   seed=seed, log=log)

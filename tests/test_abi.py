@@ -102,3 +102,22 @@ def test_ensemble_argument_checks_without_gpu():
     assert L.conv_ensemble_capture(None, None) == binding.CONV_EINVAL
     assert L.conv_ensemble_set_launch(None, 1, 1) == binding.CONV_EINVAL
     assert L.conv_autotune(None, None, None, None, None, 1, 0, None, None, None) == binding.CONV_EINVAL
+
+
+def test_mlp_training_batch_limit_sizes():
+    """A smaller training limit shrinks the MLP workspace; the plain call is the limit = max_batch
+    case; a limit above max_batch or below 1 is rejected."""
+    if not os.path.exists(binding.LIB_PATH):
+        pytest.skip("libconv.so not built")
+    L = binding.lib()
+    w = [96, 512, 512, 512, 512, 64]
+    wa = (C.c_int32 * len(w))(*w)
+    n = len(w) - 1
+    full = L.mlp_workspace_bytes(wa, n, 884736)
+    assert full > 0 and L.mlp_workspace_bytes_ex(wa, n, 884736, 884736) == full
+    small = L.mlp_workspace_bytes_ex(wa, n, 884736, 16384)
+    assert 0 < small < full / 3
+    assert L.mlp_workspace_bytes_ex(wa, n, 1000, 1001) == 0
+    assert L.mlp_workspace_bytes_ex(wa, n, 1000, 0) == 0
+    h = C.c_void_p()
+    assert L.mlp_create_ex(wa, n, 1000, 1001, C.c_void_p(256), 1 << 30, C.byref(h)) == -1

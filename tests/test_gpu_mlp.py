@@ -138,6 +138,30 @@ def test_other_widths_forward_backward(torch, widths, batch):
         assert _rel(gb, rb) <= 5e-3, (i, "b", _rel(gb, rb))
 
 
+def test_separate_training_batch_limit(torch):
+    """A context whose training limit is below its inference limit gives the same bits as one
+    sized for training at the full batch: inference over the full batch, a training forward,
+    loss and backward at the training limit; a training forward above the limit is rejected."""
+    B = _B()
+    net, params, x, t = _net(torch, 1000, 31)
+    small = B.MLP(WIDTHS, max_batch=3000, max_train_batch=1000)
+    small.set_params(torch.from_numpy(R.flatten(params)).cuda())
+    big = B.MLP(WIDTHS, max_batch=3000)
+    big.set_params(torch.from_numpy(R.flatten(params)).cuda())
+    rng = np.random.default_rng(32)
+    xi = bf16_dev(torch, rng.standard_normal((3000, WIDTHS[0])).astype(np.float32))
+    assert torch.equal(small.forward(xi), big.forward(xi))
+    xd, td = bf16_dev(torch, x), torch.from_numpy(t).cuda()
+    for m in (small, big):
+        y = m.forward(xd, keep=True)
+        m.mse(y, td, 61)
+        m.backward(1000)
+    torch.cuda.synchronize()
+    assert torch.equal(small.get_grads(), big.get_grads())
+    with pytest.raises(RuntimeError):
+        small.forward(xi[:1001], keep=True)
+
+
 def test_gradients_reproducible_bit_for_bit(torch):
     net, params, x, t = _net(torch, 1500, 12)
     xd, td = bf16_dev(torch, x), torch.from_numpy(t).cuda()
