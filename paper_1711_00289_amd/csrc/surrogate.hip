@@ -49,16 +49,30 @@ __global__ __launch_bounds__(TB) void k_pack_in(StateArgs s, int L, int64_t ncol
     const int lane = threadIdx.x % TC, grp = threadIdx.x / TC;
     const int64_t c = c0 + lane;
     const int64_t ld = s.ld;
-    for (int f = grp; f < w; f += TB / TC) {
-        float v = 0.0f;
-        if (c < ncol && f < 3 * L) {
-            double d;
-            if (f < L) d = s.T[(int64_t)f * ld + c];
-            else if (f < 2 * L) d = s.q[(int64_t)(f - L) * ld + c];
-            else d = s.pm[(int64_t)(f - 2 * L) * ld + c];
-            v = mode == 0 ? (float)d : ((float)d - mean[f]) / stdv[f];
+    // PU features per thread are loaded before any is converted, so that their loads are in
+    // flight together instead of one round trip each.
+    constexpr int PU = 8, G = TB / TC;
+    for (int f0 = grp; f0 < w; f0 += G * PU) {
+        double d[PU];
+#pragma unroll
+        for (int u = 0; u < PU; ++u) {
+            const int f = f0 + u * G;
+            d[u] = 0.0;
+            if (c < ncol && f < 3 * L) {
+                const double *src = f < L       ? s.T + (int64_t)f * ld
+                                    : f < 2 * L ? s.q + (int64_t)(f - L) * ld
+                                                : s.pm + (int64_t)(f - 2 * L) * ld;
+                d[u] = src[c];
+            }
         }
-        sh[f * SL + lane] = v;
+#pragma unroll
+        for (int u = 0; u < PU; ++u) {
+            const int f = f0 + u * G;
+            if (f >= w) break;
+            float v = 0.0f;
+            if (c < ncol && f < 3 * L) v = mode == 0 ? (float)d[u] : ((float)d[u] - mean[f]) / stdv[f];
+            sh[f * SL + lane] = v;
+        }
     }
     __syncthreads();
     const int nrows = (int)(ncol - c0 < TC ? ncol - c0 : TC);
@@ -192,13 +206,26 @@ __global__ __launch_bounds__(TB) void k_unpack(const float *y, int L, int64_t nc
     const int nf = 2 * L + 1;
     if (vec) {
         const int cpr = (nf + 3) / 4;  // f0 < nf <= w and w % 4 == 0, so f0 + 3 < w
-        for (int i = threadIdx.x; i < nrows * cpr; i += TB) {
-            const int r = i / cpr, f0 = (i % cpr) * 4;
-            const float4 v = *(const float4 *)&y[(c0 + r) * w + f0];
-            const float e[4] = {v.x, v.y, v.z, v.w};
+        constexpr int UU = 4;          // 16-byte loads per thread in flight together
+        for (int i0 = threadIdx.x; i0 < nrows * cpr; i0 += TB * UU) {
+            float4 v[UU];
 #pragma unroll
-            for (int k = 0; k < 4; ++k)
-                if (f0 + k < nf) sh[(f0 + k) * SL + r] = e[k] * stdv[f0 + k] + mean[f0 + k];
+            for (int u = 0; u < UU; ++u) {
+                const int i = i0 + u * TB;
+                v[u] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                if (i < nrows * cpr)
+                    v[u] = *(const float4 *)&y[(c0 + i / cpr) * w + (i % cpr) * 4];
+            }
+#pragma unroll
+            for (int u = 0; u < UU; ++u) {
+                const int i = i0 + u * TB;
+                if (i >= nrows * cpr) break;
+                const int r = i / cpr, f0 = (i % cpr) * 4;
+                const float e[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if (f0 + k < nf) sh[(f0 + k) * SL + r] = e[k] * stdv[f0 + k] + mean[f0 + k];
+            }
         }
     } else {
         for (int i = threadIdx.x; i < nrows * w; i += TB) {
