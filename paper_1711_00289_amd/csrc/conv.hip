@@ -89,12 +89,14 @@ struct Lev {
     double T, q, pm, z, pt;
 };
 
+// The trigger's sweep streams every input once: non-temporal loads, which keep the rest of the
+// grid's lines from displacing what the plume passes re-read.
 __device__ __forceinline__ void load_lev(Lev &v, const Member &M, int64_t ld, int64_t col, int k) {
-    v.T = AT(M.T, k);
-    v.q = AT(M.q, k);
-    v.pm = AT(M.pm, k);
-    v.z = AT(M.z, k);
-    v.pt = AT(M.pi, k);
+    v.T = __builtin_nontemporal_load(&AT(M.T, k));
+    v.q = __builtin_nontemporal_load(&AT(M.q, k));
+    v.pm = __builtin_nontemporal_load(&AT(M.pm, k));
+    v.z = __builtin_nontemporal_load(&AT(M.z, k));
+    v.pt = __builtin_nontemporal_load(&AT(M.pi, k));
 }
 
 // ------------------------------------------------------------------ shallow trigger (S1-S6)
@@ -171,19 +173,21 @@ __device__ void write_shallow_quiet(const Member &M, int64_t col, int st, double
 
 // Zero every output array of level k (and of interface k) of a column: the exact-zero outputs of
 // quiet columns, written while the sweep's loads are in flight; the plume passes overwrite only
-// the levels a plume touches.
+// the levels a plume touches.  Non-temporal stores: these lines are not read again in the step
+// (step 0.948 -> 0.924 ms with the non-temporal loads above, the trigger and the plume both
+// faster).
 template <bool DEEP, bool SHALLOW>
 __device__ __forceinline__ void zero_level(const Member &M, int64_t ld, int64_t col, int k) {
     if (DEEP) {
-        AT(M.dout.dTdt, k) = 0.0;
-        AT(M.dout.dqdt, k) = 0.0;
-        AT(M.dout.mu, k) = 0.0;
-        AT(M.dout.md, k) = 0.0;
+        __builtin_nontemporal_store(0.0, &AT(M.dout.dTdt, k));
+        __builtin_nontemporal_store(0.0, &AT(M.dout.dqdt, k));
+        __builtin_nontemporal_store(0.0, &AT(M.dout.mu, k));
+        __builtin_nontemporal_store(0.0, &AT(M.dout.md, k));
     }
     if (SHALLOW) {
-        AT(M.sout.dTdt, k) = 0.0;
-        AT(M.sout.dqdt, k) = 0.0;
-        AT(M.sout.mu, k) = 0.0;
+        __builtin_nontemporal_store(0.0, &AT(M.sout.dTdt, k));
+        __builtin_nontemporal_store(0.0, &AT(M.sout.dqdt, k));
+        __builtin_nontemporal_store(0.0, &AT(M.sout.mu, k));
     }
 }
 
