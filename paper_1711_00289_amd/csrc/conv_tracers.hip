@@ -15,6 +15,8 @@
 // One wavefront per block, one lane per column; block b takes tracer b % ntr of column block
 // b / ntr, so the tracers of one column block are dispatched together (they share its mass fluxes
 // in L2, and the slow convecting blocks spread over the run instead of piling up at its end).
+// The tendencies are written once and not read again here: non-temporal stores (0.58 -> 0.52 ms
+// for 8 tracers on the 884,736-column grid).
 // A lane accumulates its
 // column's tendencies in LDS ([level][lane]); then the wavefront stores level by level with every
 // lane active, so each store covers whole 128-byte lines (stores that cover only part of a line,
@@ -77,8 +79,8 @@ __global__ __launch_bounds__(TW) void k_tracers(TrArgs a) {
     if (__ballot(deep || shal) == 0ull) {
         if (live) {
             for (int k = 0; k < L; ++k) {
-                AT(out, k) = 0.0;
-                if (dout) AT(dout, k) = 0.0;
+                __builtin_nontemporal_store(0.0, &AT(out, k));
+                if (dout) __builtin_nontemporal_store(0.0, &AT(dout, k));
             }
         }
         return;
@@ -158,7 +160,7 @@ __global__ __launch_bounds__(TW) void k_tracers(TrArgs a) {
     if (dout) {
         __builtin_amdgcn_wave_barrier();
         if (live)
-            for (int k = 0; k < L; ++k) AT(dout, k) = SH(k);
+            for (int k = 0; k < L; ++k) __builtin_nontemporal_store(SH(k), &AT(dout, k));
     }
     if (shal) {
         // The tracer the shallow scheme sees: updated by the deep transport (zero where the deep
@@ -218,7 +220,7 @@ __global__ __launch_bounds__(TW) void k_tracers(TrArgs a) {
     }
     __builtin_amdgcn_wave_barrier();
     if (live)
-        for (int k = 0; k < L; ++k) AT(out, k) = SH(k);
+        for (int k = 0; k < L; ++k) __builtin_nontemporal_store(SH(k), &AT(out, k));
 #undef SH
 }
 

@@ -31,6 +31,7 @@ namespace {
 
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int THREADS = 256;  // block size of the elementwise and reduction kernels
 constexpr int BK = 64;
@@ -103,6 +104,7 @@ struct GemmArgs {
     // Tiles with at most 64 columns per wavefront only; ldt % 8 == 0 and ct 16-byte aligned.
     uint16_t *ct;
     int64_t ldt;
+    int nt;      // BF16 output not re-read soon (inference): non-temporal stores
 };
 
 // Global -> register -> LDS staging of one operand tile of ROWS x BK (element (r, k) at
@@ -321,7 +323,12 @@ __global__ __launch_bounds__(WM * WN * 64) void k_gemm(GemmArgs g) {
 #pragma unroll
                 for (int e = 0; e < 4; ++e)
                     h[e] = (uint32_t)f2bf(v[2 * e]) | ((uint32_t)f2bf(v[2 * e + 1]) << 16);
-                *(uint4 *)c = make_uint4(h[0], h[1], h[2], h[3]);
+                if (g.nt) {
+                    const u32x4 hv = {h[0], h[1], h[2], h[3]};
+                    __builtin_nontemporal_store(hv, (u32x4 *)c);
+                } else {
+                    *(uint4 *)c = make_uint4(h[0], h[1], h[2], h[3]);
+                }
             } else {
 #pragma unroll
                 for (int e = 0; e < 8; ++e)
@@ -811,6 +818,10 @@ int mlp_forward(mlp_t *m, const uint16_t *x, float *y, int64_t batch, int keep, 
                 g.z = fp(m, m->lay.zf[i + 1]);
                 g.ct = hp(m, m->lay.actT[i + 1]);
                 g.ldt = (batch + 7) / 8 * 8;
+            } else {
+                // inference: the activation is read once, by the next layer (3.94 -> 3.80 ms for
+                // the surrogate on the 884,736-column grid); training keeps its outputs cached
+                g.nt = 1;
             }
         } else {
             g.mode = EPI_F32;

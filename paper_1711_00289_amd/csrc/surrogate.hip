@@ -62,7 +62,7 @@ __global__ __launch_bounds__(TB) void k_pack_in(StateArgs s, int L, int64_t ncol
                 const double *src = f < L       ? s.T + (int64_t)f * ld
                                     : f < 2 * L ? s.q + (int64_t)(f - L) * ld
                                                 : s.pm + (int64_t)(f - 2 * L) * ld;
-                d[u] = src[c];
+                d[u] = __builtin_nontemporal_load(&src[c]);  // read once
             }
         }
 #pragma unroll
@@ -240,8 +240,8 @@ __global__ __launch_bounds__(TB) void k_unpack(const float *y, int L, int64_t nc
     for (int f = grp; f < 2 * L; f += TB / TC) {
         if (!live) continue;
         const double v = (double)sh[f * SL + lane];
-        if (f < L) dTdt[(int64_t)f * ld + col0 + c] = v;
-        else dqdt[(int64_t)(f - L) * ld + col0 + c] = v;
+        if (f < L) __builtin_nontemporal_store(v, &dTdt[(int64_t)f * ld + col0 + c]);  // written once
+        else __builtin_nontemporal_store(v, &dqdt[(int64_t)(f - L) * ld + col0 + c]);
     }
     if (grp == 0) {
         const double p = live ? (double)sh[2 * L * SL + lane] : 0.0;

@@ -134,7 +134,8 @@ def test_moist_static_energy_identity_on_the_gpu_step(torch, mixed):
     assert np.all(np.abs(got_d - want_d).max(axis=0) <= TOL * sd)
     assert np.all(np.abs(got_s - want_s).max(axis=0) <= TOL * ss + 1e-12 * sd)
     # Status-0 shallow columns whose closure underflowed to a zero base mass flux are among them.
-    assert np.isfinite(_np(tend)).all()
+    # (The padding columns past n are not written: they hold whatever the allocation held.)
+    assert np.isfinite(_np(tend)[..., :n]).all()
 
 
 @pytest.fixture(scope="module")
