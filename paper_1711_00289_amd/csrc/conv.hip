@@ -1460,11 +1460,19 @@ int conv_ensemble_create(int n_members, const conv_member_t *members, void *work
     const int cus = device_cus();
     const Layout l = make_layout(ncol, lmax, n_members, cus);
     if (ws_bytes < l.total) return CONV_EINVAL;
+    // Tiles go to the members with the most levels first: their columns then enter the active
+    // lists first, and the plume passes, which claim the lists in order, start on the longest
+    // plumes and end on short ones (largest jobs first) instead of finishing on a deep member.
+    // The table order is internal: every member's results go to its own arrays.
+    std::vector<int> order((size_t)n_members);
+    for (int i = 0; i < n_members; ++i) order[(size_t)i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return members[a].nlev > members[b].nlev; });
     std::vector<Member> tab((size_t)n_members);
     int64_t tile0 = 0;
-    for (int i = 0; i < n_members; ++i) {
-        const conv_member_t &m = members[i];
-        tab[(size_t)i] = make_member(m.ncol, m.nlev, m.params, &m.state, &m.deep, &m.shallow, tile0);
+    for (int j = 0; j < n_members; ++j) {
+        const conv_member_t &m = members[order[(size_t)j]];
+        tab[(size_t)j] = make_member(m.ncol, m.nlev, m.params, &m.state, &m.deep, &m.shallow, tile0);
         tile0 += (m.ncol + BLOCK - 1) / BLOCK;
     }
     if (hipMemcpy((char *)workspace + l.members, tab.data(), tab.size() * sizeof(Member),
