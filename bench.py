@@ -35,12 +35,12 @@ NLON, NLAT = 1152, 768
 TRAFFIC_SOURCES = ("paper_1711_00289_amd/csrc/conv.hip", "paper_1711_00289_amd/csrc/conv_physics.hpp",
                    "paper_1711_00289_amd/csrc/conv_internal.hpp")
 MEASURED_TRAFFIC = {
-    "sources_sha256": "e85862e6c39bfd5bd75d29bf989b3d1e386826380e3b454ce525e1411f474ce3",
+    "sources_sha256": "a50694032b90983d0a41a55fda83ecc6dd88ae7d40ca21898fe16ff6269db47a",
     "fetch_factor": 2.0, "write_factor": 1.0,
-    "k_trigger": (533465, 1530027),
-    "k_deep_plume": (257264, 343820),
-    "k_shallow_retrigger": (120921, 9256),
-    "k_shallow_plume": (51769, 18213),
+    "k_trigger": (542210, 1530036),
+    "k_deep_plume": (253758, 343415),
+    "k_shallow_retrigger": (132171, 9253),
+    "k_shallow_plume": (51217, 18222),
 }
 
 
