@@ -35,12 +35,12 @@ NLON, NLAT = 1152, 768
 TRAFFIC_SOURCES = ("paper_1711_00289_amd/csrc/conv.hip", "paper_1711_00289_amd/csrc/conv_physics.hpp",
                    "paper_1711_00289_amd/csrc/conv_internal.hpp")
 MEASURED_TRAFFIC = {
-    "sources_sha256": "a50694032b90983d0a41a55fda83ecc6dd88ae7d40ca21898fe16ff6269db47a",
+    "sources_sha256": "feac15df42f28d981fc2c032c38b72ab161b0f61b8a24b71f7ca262c6152b1b9",
     "fetch_factor": 2.0, "write_factor": 1.0,
-    "k_trigger": (542210, 1530036),
-    "k_deep_plume": (253758, 343415),
-    "k_shallow_retrigger": (132171, 9253),
-    "k_shallow_plume": (51217, 18222),
+    "k_trigger": (542631, 1529976),
+    "k_deep_plume": (252787, 343633),
+    "k_shallow_retrigger": (132077, 9253),
+    "k_shallow_plume": (51083, 18208),
 }
 
 

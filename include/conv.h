@@ -27,6 +27,9 @@
  *  - Return value: CONV_OK (0) or a negative CONV_E* code.  CONV_EINVAL: a NULL pointer, a bad
  *    size, ld < ncol, dt <= 0 or a workspace that is too small; nothing is enqueued.  CONV_EHIP: a
  *    kernel launch failed (conv_last_hip_error() returns the hipError_t value).
+ *  - A context over 0 columns reads and writes no array, so its calls accept NULL array pointers
+ *    (the argument structs themselves must be given); they enqueue nothing but the zeroing of the
+ *    backward calls' parameter gradients (g_params, which must be given).
  *  - A context is not thread-safe and its workspace is shared by its calls: calls on one context
  *    must be ordered on one stream.
  *  - Per-column physics outcomes are not errors; they are reported in `status`:

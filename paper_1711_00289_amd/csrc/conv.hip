@@ -1353,23 +1353,26 @@ void conv_destroy(conv_ctx_t *ctx) {
 
 int conv_deep_forward(conv_ctx_t *ctx, const conv_state_t *state, conv_deep_out_t *out,
                       void *stream) {
-    if (!ctx || !state_ok(ctx->ncol, state, false) || !deep_ok(out)) return CONV_EINVAL;
-    if (ctx->ncol == 0) return CONV_OK;
+    if (!ctx || !state || !out) return CONV_EINVAL;
+    if (ctx->ncol == 0) return CONV_OK;  // nothing to read or write: the arrays may be NULL
+    if (!state_ok(ctx->ncol, state, false) || !deep_ok(out)) return CONV_EINVAL;
     return run_one<true, false>(ctx, state, out, nullptr, (hipStream_t)stream);
 }
 
 int conv_shallow_forward(conv_ctx_t *ctx, const conv_state_t *state, conv_shallow_out_t *out,
                          void *stream) {
-    if (!ctx || !state_ok(ctx->ncol, state, true) || !shallow_ok(out)) return CONV_EINVAL;
+    if (!ctx || !state || !out) return CONV_EINVAL;
     if (ctx->ncol == 0) return CONV_OK;
+    if (!state_ok(ctx->ncol, state, true) || !shallow_ok(out)) return CONV_EINVAL;
     return run_one<false, true>(ctx, state, nullptr, out, (hipStream_t)stream);
 }
 
 int conv_step(conv_ctx_t *ctx, const conv_state_t *state, conv_deep_out_t *deep,
               conv_shallow_out_t *shallow, void *stream) {
-    if (!ctx || !state_ok(ctx->ncol, state, true) || !deep_ok(deep) || !shallow_ok(shallow))
-        return CONV_EINVAL;
+    if (!ctx || !state || !deep || !shallow) return CONV_EINVAL;
     if (ctx->ncol == 0) return CONV_OK;
+    if (!state_ok(ctx->ncol, state, true) || !deep_ok(deep) || !shallow_ok(shallow))
+        return CONV_EINVAL;
     return run_one<true, true>(ctx, state, deep, shallow, (hipStream_t)stream);
 }
 

@@ -1280,6 +1280,7 @@ __global__ void k_adj_reset(int *cnt) {
 namespace {
 
 bool backward_state_ok(const conv_ctx_t *ctx, const conv_state_t *s, bool shallow) {
+    if (ctx->ncol == 0) return true;  // nothing is read: the arrays may be NULL
     if (!s->T || !s->q || !s->p_mid || !s->z || !s->p_int || !s->phis || s->ld < ctx->ncol ||
         !(s->dt > 0.0))
         return false;
@@ -1346,7 +1347,8 @@ int conv_deep_backward(conv_ctx_t *ctx, const conv_state_t *state, const conv_de
                        size_t ws_bytes, void *stream) {
     if (!ctx || !state || !fwd || !cot || !grad || !workspace) return CONV_EINVAL;
     if (!backward_state_ok(ctx, state, false)) return CONV_EINVAL;
-    if (!fwd->status || !fwd->klaunch || !fwd->ktop || !grad->g_T || !grad->g_q || !grad->g_params)
+    if (!grad->g_params ||
+        (ctx->ncol > 0 && (!fwd->status || !fwd->klaunch || !fwd->ktop || !grad->g_T || !grad->g_q)))
         return CONV_EINVAL;
     if (((uintptr_t)workspace & 255u) != 0) return CONV_EINVAL;
     if (ctx->P.eps_cape != 0.0) return CONV_EUNSUPPORTED;  // the adjoint is of the undilute parcel
@@ -1375,7 +1377,8 @@ int conv_shallow_backward(conv_ctx_t *ctx, const conv_state_t *state,
                           void *stream) {
     if (!ctx || !state || !fwd || !cot || !grad || !workspace) return CONV_EINVAL;
     if (!backward_state_ok(ctx, state, true)) return CONV_EINVAL;
-    if (!fwd->status || !fwd->kbase || !fwd->ktop || !grad->g_T || !grad->g_q || !grad->g_params)
+    if (!grad->g_params ||
+        (ctx->ncol > 0 && (!fwd->status || !fwd->kbase || !fwd->ktop || !grad->g_T || !grad->g_q)))
         return CONV_EINVAL;
     if (((uintptr_t)workspace & 255u) != 0) return CONV_EINVAL;
     const AdjLayout l = adj_layout(ctx->ncol, ctx->nlev, ctx->cus);
@@ -1405,9 +1408,10 @@ int conv_step_backward(conv_ctx_t *ctx, const conv_state_t *state, const conv_de
                        size_t ws_bytes, void *stream) {
     if (!ctx || !state || !dfwd || !sfwd || !grad || !workspace) return CONV_EINVAL;
     if (!backward_state_ok(ctx, state, true)) return CONV_EINVAL;
-    if (!dfwd->status || !dfwd->klaunch || !dfwd->ktop || !dfwd->dTdt || !dfwd->dqdt ||
-        !sfwd->status || !sfwd->kbase || !sfwd->ktop || !grad->g_T || !grad->g_q ||
-        !grad->g_params)
+    if (!grad->g_params ||
+        (ctx->ncol > 0 && (!dfwd->status || !dfwd->klaunch || !dfwd->ktop || !dfwd->dTdt ||
+                           !dfwd->dqdt || !sfwd->status || !sfwd->kbase || !sfwd->ktop ||
+                           !grad->g_T || !grad->g_q)))
         return CONV_EINVAL;
     if (((uintptr_t)workspace & 255u) != 0) return CONV_EINVAL;
     if (ctx->P.eps_cape != 0.0) return CONV_EUNSUPPORTED;  // the deep adjoint is undilute

@@ -232,6 +232,7 @@ int conv_tracer_transport(conv_ctx_t *ctx, const conv_state_t *state, const conv
                           const conv_shallow_out_t *sfwd, int32_t ntr, const double *tracers,
                           double *tend, double *deep_tend, void *stream) {
     if (!ctx || !state || !dfwd || !sfwd || ntr < 0 || ntr > 65535) return CONV_EINVAL;
+    if (ctx->ncol == 0) return CONV_OK;  // nothing to read or write: the arrays may be NULL
     if (!state->z || !state->p_int || state->ld < ctx->ncol || !(state->dt > 0.0)) return CONV_EINVAL;
     if (!dfwd->mu || !dfwd->md || !dfwd->status || !dfwd->klaunch || !dfwd->ktop || !sfwd->mu ||
         !sfwd->status || !sfwd->kbase || !sfwd->ktop)
