@@ -241,7 +241,7 @@ def bench_ensemble(torch, B, S, main_state, main_deep, main_shallow, reps, tune=
     return {"workload": "884,736x30 grid + 16 members x 55,296 columns (nlev 30/46/72, "
                         "tau 1800/3600/7200 s), one captured graph per step",
             "columns": ncol, "ms_per_step": ms, "columns_per_s": ncol / (ms * 1e-3),
-            "launch_blocks_per_cu": list(ens.get_launch()), "separate_calls_ms": sep,
+            "launch_waves_per_cu": list(ens.get_launch()), "separate_calls_ms": sep,
             "batching_speedup": sep / ms}
 
 
@@ -288,7 +288,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--ncol", type=int, default=NLON * NLAT)
-    ap.add_argument("--launch", type=str, default="", help="deep,shallow plume blocks per CU")
+    ap.add_argument("--launch", type=str, default="", help="deep,shallow plume wavefronts per CU")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shape")
     ap.add_argument("--no-extras", action="store_true",
                     help="time only the headline step (no adjoint, ensemble)")
@@ -393,7 +393,7 @@ def main():
                           "achieved_GBs": step_bytes / (ms_step * 1e-3) / 1e9,
                           "frac": step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "kernels_ms": kavg,
-        "launch_blocks_per_cu": conv.get_launch(),
+        "launch_waves_per_cu": conv.get_launch(),
         "active_fraction": {"deep": float((dst == 0).mean()), "deep_triggered": float(trig.mean()),
                             "shallow": float((sst == 0).mean())},
         "wall_s_timed": wall,

@@ -263,17 +263,17 @@ void conv_ensemble_destroy(conv_ens_t *e); /* frees the host handle and any capt
  * memset nodes: capturable). */
 int conv_ensemble_step(conv_ens_t *e, void *stream);
 
-/* Persistent-grid shape of the plume kernels (256-thread units per compute unit, 1..8, as for
+/* Persistent-grid shape of the plume kernels (wavefronts per compute unit, 1..32, as for
  * conv_set_launch).  Changing it drops a captured graph. */
-int conv_ensemble_set_launch(conv_ens_t *e, int fused_blocks_per_cu, int shallow_blocks_per_cu);
-int conv_ensemble_get_launch(conv_ens_t *e, int *fused_blocks_per_cu, int *shallow_blocks_per_cu);
+int conv_ensemble_set_launch(conv_ens_t *e, int fused_waves_per_cu, int shallow_waves_per_cu);
+int conv_ensemble_get_launch(conv_ens_t *e, int *fused_waves_per_cu, int *shallow_waves_per_cu);
 
 /* Autotuner: times conv_ensemble_step (median of `reps` runs, 1..1000) for every candidate shape
- * in {1,2,3,4,6,8} x {1,2,4,8} and keeps the fastest.  Results are cached per process, keyed by
+ * in {4,5,6,8,12,16,24,32} x {4,8,16,32} wavefronts per CU and keeps the fastest.  Results are cached per process, keyed by
  * device and member shapes; `force` != 0 re-tunes.  Runs steps (the outputs are overwritten) and
  * waits on the host, so it may not be called during capture.  Outputs may be NULL. */
 int conv_ensemble_autotune(conv_ens_t *e, void *stream, int reps, int force,
-                           int *fused_blocks_per_cu, int *shallow_blocks_per_cu, float *ms);
+                           int *fused_waves_per_cu, int *shallow_waves_per_cu, float *ms);
 
 /* Captures one conv_ensemble_step on `stream` (not the null stream) into a HIP graph owned by the
  * handle, replacing any earlier one; conv_ensemble_replay launches it (CONV_EINVAL if there is
@@ -284,14 +284,14 @@ int conv_ensemble_replay(conv_ens_t *e, void *stream);
 /* The same autotuner for a single context's conv_step on (state, deep, shallow). */
 int conv_autotune(conv_ctx_t *ctx, const conv_state_t *state, conv_deep_out_t *deep,
                   conv_shallow_out_t *shallow, void *stream, int reps, int force,
-                  int *fused_blocks_per_cu, int *shallow_blocks_per_cu, float *ms);
+                  int *fused_waves_per_cu, int *shallow_waves_per_cu, float *ms);
 
-/* Launch shape of the persistent kernels: 256-thread units per compute unit for the deep-plume
- * kernel and for the shallow-plume kernel (each 1..8; default 1 and 8), launched as blocks of one
- * 64-thread wavefront each (n units per CU = 4n such blocks per CU).  The workspace size does not
- * depend on it.  Results do not depend on it (bit-identical). */
-int conv_set_launch(conv_ctx_t *ctx, int fused_blocks_per_cu, int shallow_blocks_per_cu);
-int conv_get_launch(conv_ctx_t *ctx, int *fused_blocks_per_cu, int *shallow_blocks_per_cu);
+/* Launch shape of the persistent kernels: wavefronts per compute unit for the deep-plume kernel
+ * and for the shallow-plume kernel (each 1..32; default 5 and 32), launched as blocks of one
+ * 64-thread wavefront each.  The workspace size does not depend on it.  Results do not depend on
+ * it (bit-identical). */
+int conv_set_launch(conv_ctx_t *ctx, int fused_waves_per_cu, int shallow_waves_per_cu);
+int conv_get_launch(conv_ctx_t *ctx, int *fused_waves_per_cu, int *shallow_waves_per_cu);
 
 /* Instrumentation: record HIP events on the call's stream around each kernel of the next
  * `max_calls` calls (0 turns recording off).  conv_timing_read() waits for the recorded calls and

@@ -476,7 +476,7 @@ class Conv:
 
     def autotune(self, s: dict, deep: dict, shallow: dict, reps: int = 5, force: bool = False):
         """Pick the fastest persistent-grid shape for conv_step on these arrays (cached per
-        process); returns (fused_blocks_per_cu, shallow_blocks_per_cu, median_ms)."""
+        process); returns (fused_waves_per_cu, shallow_waves_per_cu, median_ms)."""
         st = self._state(s)
         d, h = self._deep_struct(deep), self._shallow_struct(shallow)
         a, b, ms = C.c_int(0), C.c_int(0), C.c_float(0.0)
@@ -488,8 +488,8 @@ class Conv:
     # -- instrumentation -----------------------------------------------------------------
     STAGES = ("reset", "trigger", "deep_plume", "shallow_retrigger", "shallow_plume")
 
-    def set_launch(self, fused_blocks_per_cu: int, shallow_blocks_per_cu: int):
-        check(lib().conv_set_launch(self.h, int(fused_blocks_per_cu), int(shallow_blocks_per_cu)),
+    def set_launch(self, fused_waves_per_cu: int, shallow_waves_per_cu: int):
+        check(lib().conv_set_launch(self.h, int(fused_waves_per_cu), int(shallow_waves_per_cu)),
               "conv_set_launch")
 
     def get_launch(self):

@@ -1061,8 +1061,8 @@ Work make_work(char *b, const Layout &l, const Launch &launch, int cus) {
     w.ssig2 = (double *)(b + l.ssig2);
     w.dscr = (double *)(b + l.dscr);
     w.sscr = (double *)(b + l.sscr);
-    const int64_t fd = (int64_t)cus * launch.fused_bpc * BLOCK;
-    const int64_t sh = (int64_t)cus * launch.shallow_bpc * BLOCK;
+    const int64_t fd = (int64_t)cus * launch.fused_wpc * WAVE;
+    const int64_t sh = (int64_t)cus * launch.shallow_wpc * WAVE;
     w.dstride = fd < l.threads ? fd : l.threads;
     w.sstride = sh < l.threads ? sh : l.threads;
     w.lmax = l.lmax;
@@ -1131,10 +1131,13 @@ int run_one(conv_ctx *c, const conv_state_t *s, const conv_deep_out_t *d,
 }
 
 // ------------------------------------------------------------------ launch-shape autotuner
-// Candidate persistent-grid sizes (blocks per compute unit) for the deep-plume and shallow-plume
-// kernels; the trigger launch is one block per tile and has no shape to tune.
-constexpr int TUNE_FUSED[] = {1, 2, 3, 4, 6, 8};
-constexpr int TUNE_SHALLOW[] = {1, 2, 4, 8};
+// Candidate persistent-grid sizes (wavefronts per compute unit) for the deep-plume and
+// shallow-plume kernels; the trigger launch is one block per tile and has no shape to tune.  The
+// deep plume's candidates are fine around one and two wavefronts per SIMD: its end is set by how
+// many 64-column passes its busiest wavefronts take (on the 884,736-column grid, 5 per CU:
+// 0.255 -> 0.233 ms against 4).
+constexpr int TUNE_FUSED[] = {4, 5, 6, 8, 12, 16, 24, 32};
+constexpr int TUNE_SHALLOW[] = {4, 8, 16, 32};
 
 struct TuneResult {
     Launch launch;
@@ -1330,18 +1333,18 @@ int conv_set_params(conv_ctx_t *ctx, const conv_params_t *params) {
     return CONV_OK;
 }
 
-int conv_set_launch(conv_ctx_t *ctx, int fused_blocks_per_cu, int shallow_blocks_per_cu) {
-    if (!ctx || fused_blocks_per_cu < 1 || fused_blocks_per_cu > MAX_BPC ||
-        shallow_blocks_per_cu < 1 || shallow_blocks_per_cu > MAX_BPC)
+int conv_set_launch(conv_ctx_t *ctx, int fused_waves_per_cu, int shallow_waves_per_cu) {
+    if (!ctx || fused_waves_per_cu < 1 || fused_waves_per_cu > MAX_WPC ||
+        shallow_waves_per_cu < 1 || shallow_waves_per_cu > MAX_WPC)
         return CONV_EINVAL;
-    ctx->launch = Launch{fused_blocks_per_cu, shallow_blocks_per_cu};
+    ctx->launch = Launch{fused_waves_per_cu, shallow_waves_per_cu};
     return CONV_OK;
 }
 
-int conv_get_launch(conv_ctx_t *ctx, int *fused_blocks_per_cu, int *shallow_blocks_per_cu) {
-    if (!ctx || !fused_blocks_per_cu || !shallow_blocks_per_cu) return CONV_EINVAL;
-    *fused_blocks_per_cu = ctx->launch.fused_bpc;
-    *shallow_blocks_per_cu = ctx->launch.shallow_bpc;
+int conv_get_launch(conv_ctx_t *ctx, int *fused_waves_per_cu, int *shallow_waves_per_cu) {
+    if (!ctx || !fused_waves_per_cu || !shallow_waves_per_cu) return CONV_EINVAL;
+    *fused_waves_per_cu = ctx->launch.fused_wpc;
+    *shallow_waves_per_cu = ctx->launch.shallow_wpc;
     return CONV_OK;
 }
 
@@ -1424,7 +1427,7 @@ int conv_last_hip_error(void) { return g_last_hip; }
 
 int conv_autotune(conv_ctx_t *ctx, const conv_state_t *state, conv_deep_out_t *deep,
                   conv_shallow_out_t *shallow, void *stream, int reps, int force,
-                  int *fused_blocks_per_cu, int *shallow_blocks_per_cu, float *ms) {
+                  int *fused_waves_per_cu, int *shallow_waves_per_cu, float *ms) {
     if (!ctx || !state_ok(ctx->ncol, state, true) || !deep_ok(deep) || !shallow_ok(shallow) ||
         reps < 1 || reps > 1000)
         return CONV_EINVAL;
@@ -1442,8 +1445,8 @@ int conv_autotune(conv_ctx_t *ctx, const conv_state_t *state, conv_deep_out_t *d
                                run, &r);
     if (rc != CONV_OK) return rc;
     ctx->launch = r.launch;
-    if (fused_blocks_per_cu) *fused_blocks_per_cu = r.launch.fused_bpc;
-    if (shallow_blocks_per_cu) *shallow_blocks_per_cu = r.launch.shallow_bpc;
+    if (fused_waves_per_cu) *fused_waves_per_cu = r.launch.fused_wpc;
+    if (shallow_waves_per_cu) *shallow_waves_per_cu = r.launch.shallow_wpc;
     if (ms) *ms = r.ms;
     return CONV_OK;
 }
@@ -1511,35 +1514,35 @@ int conv_ensemble_step(conv_ens_t *e, void *stream) {
     return ens_launch(e, e->launch, (hipStream_t)stream);
 }
 
-int conv_ensemble_set_launch(conv_ens_t *e, int fused_blocks_per_cu, int shallow_blocks_per_cu) {
-    if (!e || fused_blocks_per_cu < 1 || fused_blocks_per_cu > MAX_BPC || shallow_blocks_per_cu < 1 ||
-        shallow_blocks_per_cu > MAX_BPC)
+int conv_ensemble_set_launch(conv_ens_t *e, int fused_waves_per_cu, int shallow_waves_per_cu) {
+    if (!e || fused_waves_per_cu < 1 || fused_waves_per_cu > MAX_WPC || shallow_waves_per_cu < 1 ||
+        shallow_waves_per_cu > MAX_WPC)
         return CONV_EINVAL;
-    e->launch = Launch{fused_blocks_per_cu, shallow_blocks_per_cu};
+    e->launch = Launch{fused_waves_per_cu, shallow_waves_per_cu};
     ens_drop_graph(e);
     return CONV_OK;
 }
 
-int conv_ensemble_get_launch(conv_ens_t *e, int *fused_blocks_per_cu, int *shallow_blocks_per_cu) {
-    if (!e || !fused_blocks_per_cu || !shallow_blocks_per_cu) return CONV_EINVAL;
-    *fused_blocks_per_cu = e->launch.fused_bpc;
-    *shallow_blocks_per_cu = e->launch.shallow_bpc;
+int conv_ensemble_get_launch(conv_ens_t *e, int *fused_waves_per_cu, int *shallow_waves_per_cu) {
+    if (!e || !fused_waves_per_cu || !shallow_waves_per_cu) return CONV_EINVAL;
+    *fused_waves_per_cu = e->launch.fused_wpc;
+    *shallow_waves_per_cu = e->launch.shallow_wpc;
     return CONV_OK;
 }
 
 int conv_ensemble_autotune(conv_ens_t *e, void *stream, int reps, int force,
-                           int *fused_blocks_per_cu, int *shallow_blocks_per_cu, float *ms) {
+                           int *fused_waves_per_cu, int *shallow_waves_per_cu, float *ms) {
     if (!e || reps < 1 || reps > 1000 || e->ntiles == 0) return CONV_EINVAL;
     hipStream_t st = (hipStream_t)stream;
     auto run = [&](const Launch &L) { return ens_launch(e, L, st); };
     TuneResult r;
     const int rc = tune_cached(tune_key("ensemble", e->cus, e->shapes), force, st, reps, run, &r);
     if (rc != CONV_OK) return rc;
-    if (r.launch.fused_bpc != e->launch.fused_bpc || r.launch.shallow_bpc != e->launch.shallow_bpc)
+    if (r.launch.fused_wpc != e->launch.fused_wpc || r.launch.shallow_wpc != e->launch.shallow_wpc)
         ens_drop_graph(e);
     e->launch = r.launch;
-    if (fused_blocks_per_cu) *fused_blocks_per_cu = r.launch.fused_bpc;
-    if (shallow_blocks_per_cu) *shallow_blocks_per_cu = r.launch.shallow_bpc;
+    if (fused_waves_per_cu) *fused_waves_per_cu = r.launch.fused_wpc;
+    if (shallow_waves_per_cu) *shallow_waves_per_cu = r.launch.shallow_wpc;
     if (ms) *ms = r.ms;
     return CONV_OK;
 }

@@ -71,12 +71,14 @@ __device__ __forceinline__ int wave_append(bool pred, int *counter) {
     return pred ? base + (int)__popcll(m & ((1ull << lane) - 1ull)) : -1;
 }
 
-// Launch shape: persistent blocks per compute unit for the fused and the shallow-plume kernels.
+// Launch shape: wavefronts per compute unit of the persistent deep-plume and shallow-plume
+// passes (launched as one-wavefront blocks).
 struct Launch {
-    int fused_bpc, shallow_bpc;
+    int fused_wpc, shallow_wpc;
 };
-constexpr int MAX_BPC = 8;
-constexpr Launch DEFAULT_LAUNCH = {1, 8};
+constexpr int MAX_BPC = 8;               // 256-thread units per CU the workspace is sized for
+constexpr int MAX_WPC = MAX_BPC * NWAVES;  // = 32 wavefronts per CU
+constexpr Launch DEFAULT_LAUNCH = {5, 32};
 
 struct Layout {
     size_t cnt, dlist, dmem, dkb, dkt, dkd, dcape, dSA, dSB;

@@ -160,7 +160,7 @@ def test_every_launch_shape_and_the_autotuner_give_the_same_bits(torch):
     ens.step()
     torch.cuda.synchronize()
     ref = [_snapshot(m) for m in ens.members]
-    for f, s in ((1, 1), (2, 4), (3, 8), (8, 1), (6, 2)):
+    for f, s in ((1, 1), (5, 16), (12, 32), (32, 4), (24, 8), (3, 7)):
         ens.set_launch(f, s)
         assert ens.get_launch() == (f, s)
         ens.step()
@@ -169,7 +169,7 @@ def test_every_launch_shape_and_the_autotuner_give_the_same_bits(torch):
             _equal(r[0], {k: m["deep"][k] for k in DEEP_F})
             _equal(r[1], {k: m["shallow"][k] for k in SHALLOW_F})
     f, s, ms = ens.autotune(reps=3, force=True)
-    assert f in (1, 2, 3, 4, 6, 8) and s in (1, 2, 4, 8) and ms > 0
+    assert f in (4, 5, 6, 8, 12, 16, 24, 32) and s in (4, 8, 16, 32) and ms > 0
     assert ens.get_launch() == (f, s)
     assert ens.autotune(reps=3) == (f, s, ms)  # cached
     ens.step()
@@ -179,6 +179,8 @@ def test_every_launch_shape_and_the_autotuner_give_the_same_bits(torch):
         _equal(r[1], {k: m["shallow"][k] for k in SHALLOW_F})
     with pytest.raises(RuntimeError):
         ens.set_launch(0, 1)
+    with pytest.raises(RuntimeError):
+        ens.set_launch(33, 4)
 
 
 def test_single_context_autotune_keeps_results(torch):
