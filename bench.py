@@ -35,12 +35,12 @@ NLON, NLAT = 1152, 768
 TRAFFIC_SOURCES = ("paper_1711_00289_amd/csrc/conv.hip", "paper_1711_00289_amd/csrc/conv_physics.hpp",
                    "paper_1711_00289_amd/csrc/conv_internal.hpp")
 MEASURED_TRAFFIC = {
-    "sources_sha256": "feac15df42f28d981fc2c032c38b72ab161b0f61b8a24b71f7ca262c6152b1b9",
+    "sources_sha256": "cdc5309005b61bdd05112c15b91fe105ad43fa1efc1fb8b77e84f8a53576f5a4",
     "fetch_factor": 2.0, "write_factor": 1.0,
-    "k_trigger": (542631, 1529976),
-    "k_deep_plume": (252787, 343633),
-    "k_shallow_retrigger": (132077, 9253),
-    "k_shallow_plume": (51083, 18208),
+    "k_trigger": (542299, 1530018),
+    "k_deep_plume": (275097, 355456),
+    "k_shallow_retrigger": (132062, 9251),
+    "k_shallow_plume": (51923, 18181),
 }
 
 
