@@ -102,6 +102,31 @@ def cpu_baseline(st, threads, min_cpu_s=15.0, max_steps=20):
     return steps * st["ncol"] / dt, dt, steps
 
 
+def cpu_one_thread(st, stride=32):
+    """The plain single-threaded oracle step over every `stride`-th column of the grid (the same
+    latitude mix, a bounded sample)."""
+    import oracle
+    from paper_1711_00289_amd import soundings as S
+
+    sub = S.subset(st, list(range(0, st["ncol"], stride)))
+    t0 = time.perf_counter()
+    oracle.step(sub)
+    dt = time.perf_counter() - t0
+    return sub["ncol"] / dt, dt, sub["ncol"]
+
+
+def copy_bandwidth(torch, mib=1024, reps=5):
+    """GB/s (bytes read + written) of a plain device-to-device copy of `mib` MiB: the practical
+    ceiling the step's HBM fraction is compared with."""
+    nb = mib * (1 << 20)
+    src = torch.ones(nb // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    ms = time_events(torch, lambda: dst.copy_(src), reps)
+    del src, dst
+    return 2 * nb / (ms * 1e-3) / 1e9
+
+
 def time_events(torch, fn, reps, stream=None):
     """Average ms of `fn()` over `reps` calls, bracketed by events on `stream` (default: current)."""
     stream = stream or torch.cuda.current_stream()
@@ -349,6 +374,17 @@ def main():
     conv.timing_start(0)
     kavg = {k: v / max(ncalls, 1) for k, v in kms.items()}
 
+    # Per-step spread: the same number of steps again, an event pair around each.
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    for a, b in evs:
+        a.record(stream)
+        conv.step(dev, deep, shallow)
+        b.record(stream)
+    torch.cuda.synchronize()
+    per_step = sorted(a.elapsed_time(b) for a, b in evs)
+    copy_gbs = copy_bandwidth(torch)
+
     if args.calibrate_copy:
         nb = args.calibrate_copy * (1 << 20)
         src = torch.ones(nb // 8, dtype=torch.float64, device="cuda")
@@ -375,6 +411,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_step,
+        "ms_per_step_median": per_step[len(per_step) // 2],
+        "ms_per_step_min": per_step[0],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -391,7 +429,9 @@ def main():
         "step_roofline": {"algorithmic_bytes": int(step_bytes),
                           "bytes_per_column": bytes_per_column(NLEV)["total"],
                           "achieved_GBs": step_bytes / (ms_step * 1e-3) / 1e9,
-                          "frac": step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS},
+                          "frac": step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                          "copy_GBs": copy_gbs,
+                          "frac_of_copy": step_bytes / (ms_step * 1e-3) / 1e9 / copy_gbs},
         "kernels_ms": kavg,
         "launch_waves_per_cu": conv.get_launch(),
         "active_fraction": {"deep": float((dst == 0).mean()), "deep_triggered": float(trig.mean()),
@@ -424,6 +464,11 @@ def main():
                                "sample": f"the full {n}-column grid, {nsteps} oracle steps "
                                          f"(OpenMP dynamic schedule, chunk 16), {secs:.1f} s wall "
                                          f"on {threads} threads"}
+        r1, s1, n1 = cpu_one_thread(st)
+        out["cpu_baseline"]["one_thread"] = {
+            "value": r1, "unit": "columns/s", "cores": 1,
+            "sample": f"every 32nd column of the grid ({n1} columns), one plain oracle step, "
+                      f"{s1:.2f} s"}
     print(json.dumps(out), flush=True)
 
 
