@@ -111,6 +111,31 @@ def test_quarter_degree_grid_sampled(torch):
     assert (d["mu"] >= 0).all() and (d["md"] <= 0).all() and (s["mu"] >= 0).all()
 
 
+def test_quarter_degree_grid_at_the_benchmarked_launch_shapes(torch):
+    """The 884,736-column step at the launch shape the benchmark's autotuner picks, and at the
+    extreme shapes it may pick, gives the same bits at every column as the default shape (whose
+    sampled columns the previous test checks against the oracle)."""
+    B = _bind()
+    st = S.grid_quarter_deg()
+    dev = B.to_device(st)
+    c = B.Conv(st["ncol"], st["nlev"])
+    d, s = c.step(dev)
+    torch.cuda.synchronize()
+    ref = [{k: v.clone() for k, v in o.items()} for o in (d, s)]
+    f, sh, _ = c.autotune(dev, d, s, reps=3, force=True)
+    shapes = [(f, sh), (1, 1), (4, 4), (32, 32)]
+    for shape in shapes:
+        c.set_launch(*shape)
+        for o in (d, s):
+            for v in o.values():
+                v.fill_(-7)
+        c.step(dev, d, s)
+        torch.cuda.synchronize()
+        for r, o in zip(ref, (d, s)):
+            for k in r:
+                assert torch.equal(r[k], o[k]), (shape, k)
+
+
 def test_padding_ld_greater_than_ncol(torch):
     base = S.make_state(777, 30, seed=31, warm=np.arange(777) % 3 != 0, ld=1024)
     d, s = run_gpu(base, "step")
