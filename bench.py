@@ -140,6 +140,15 @@ def time_events(torch, fn, reps, stream=None):
     return e0.elapsed_time(e1) / reps
 
 
+def adjoint_bytes(L: int, n: int, nact: int) -> int:
+    """Algorithmic HBM bytes of one conv_deep_backward call (cotangents of dTdt and dqdt, none of
+    prec): every column reads its status and writes g_T and g_q; an active column also reads its
+    inputs T, q, p_mid, z, p_int and phis, its launch and top levels and both cotangents."""
+    quiet = 4 + 2 * L * 8
+    active = (4 * L + (L + 1) + 1) * 8 + 2 * 4 + 2 * L * 8
+    return n * quiet + nact * active
+
+
 def bench_adjoint(torch, B, S, reps):
     """Deep forward and hand-written adjoint on the 288x192 = 55,296-column x 30-level grid with the
     loss sum(a*dTdt^2 + b*(Lv/cp*dqdt)^2), a, b ~ N(0,1)."""
@@ -169,9 +178,18 @@ def bench_adjoint(torch, B, S, reps):
         conv.step_backward(dev, deep, shallow, dcot, scot)
     sfwd = time_events(torch, lambda: conv.step(dev, deep, shallow), reps)
     sbwd = time_events(torch, lambda: conv.step_backward(dev, deep, shallow, dcot, scot), reps)
+    nact = int((out["status"] == 0).sum())
+    abytes = adjoint_bytes(NLEV, n, nact)
     return {"workload": "deep adjoint, 288x192 = 55,296 columns x 30 levels",
             "forward_ms": fwd, "backward_ms": bwd, "ratio": bwd / fwd,
-            "active_fraction": float((out["status"] == 0).double().mean()),
+            "active_fraction": nact / n,
+            "roofline": {"bound": "hbm", "achieved": abytes / (bwd * 1e-3) / 1e9,
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": abytes / (bwd * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                         "algorithmic_bytes_per_call": abytes,
+                         "adjoint_wavefronts": -(-nact // 64),
+                         "note": "one lane per active column: the call is as long as the longest "
+                                 "column's recompute-then-reverse chain"},
             "step": {"workload": "adjoint of the whole step (deep, update, shallow), same grid",
                      "forward_ms": sfwd, "backward_ms": sbwd, "ratio": sbwd / sfwd,
                      "shallow_active_fraction":
@@ -263,9 +281,14 @@ def bench_ensemble(torch, B, S, main_state, main_deep, main_shallow, reps, tune=
     separate()
     sep = time_events(torch, separate, max(2, reps // 4))
     ncol = sum(m["ncol"] for m in ens.members)
+    ebytes = sum(bytes_per_column(m["nlev"])["total"] * m["ncol"] for m in ens.members)
     return {"workload": "884,736x30 grid + 16 members x 55,296 columns (nlev 30/46/72, "
                         "tau 1800/3600/7200 s), one captured graph per step",
             "columns": ncol, "ms_per_step": ms, "columns_per_s": ncol / (ms * 1e-3),
+            "roofline": {"bound": "hbm", "achieved": ebytes / (ms * 1e-3) / 1e9,
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": ebytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                         "algorithmic_bytes_per_step": int(ebytes)},
             "launch_waves_per_cu": list(ens.get_launch()), "separate_calls_ms": sep,
             "batching_speedup": sep / ms}
 

@@ -74,3 +74,14 @@ def test_single_thread_oracle_sample():
     st = S.make_state(96, 30, seed=7, warm=np.ones(96, bool))
     rate, secs, n = bench.cpu_one_thread(st, stride=4)
     assert n == 24 and secs > 0 and rate == pytest.approx(n / secs)
+
+
+def test_adjoint_bytes():
+    """Quiet columns: status read, two gradient arrays written; an active column adds the deep
+    scheme's inputs (the step's inputs less pblh and tke), two level indices and two cotangent
+    arrays."""
+    L, n = 30, 1000
+    quiet = bench.adjoint_bytes(L, n, 0)
+    assert quiet == n * (4 + 2 * L * 8)
+    extra = (bench.adjoint_bytes(L, n, n) - quiet) / n
+    assert extra == bench.bytes_per_column(L)["inputs"] - 2 * 8 + 2 * 4 + 2 * L * 8
