@@ -7,9 +7,10 @@
 //
 // GEMM tiling: a block computes a BM x BN tile (128 x 128, 256 x 256 or 128 x 64, chosen by shape)
 // with its wavefronts in a WM x WN arrangement, each owning (BM/WM) x (BN/WN) as 32 x 32 MFMA
-// tiles.  K advances 64 at a time through double-buffered LDS tiles; the next K tile is fetched
-// from global memory into registers while the current one feeds the MFMAs, and every row of a tile
-// is one full 128-byte line.  Block ids are mapped so that the N tiles of one M tile run on the
+// tiles.  K advances 64 at a time through two LDS stages: the next K tile goes from global memory
+// straight into the other stage (global_load_lds_dwordx4, no register staging) while the current
+// one feeds the MFMAs; every row of a tile is one full 128-byte line, stored with its 16-byte
+// chunks XOR-swizzled by the row so that fragment reads are free of bank conflicts.  Block ids are mapped so that the N tiles of one M tile run on the
 // same XCD (the hardware deals consecutive blocks to the 8 XCDs in turn), so an activation tile is
 // fetched into one XCD's L2 once and reused there; products with fewer M tiles than XCDs take
 // their tiles in plain order.  The epilogue stages each wavefront's
@@ -35,7 +36,8 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int THREADS = 256;  // block size of the elementwise and reduction kernels
 constexpr int BK = 64;
-constexpr int LDK = BK + 8;  // LDS row stride in bf16 (144 bytes: 16-byte aligned, conflict-free)
+constexpr int LDS_ROW = BK + 8;  // bf16 per row when sizing a block's LDS (the epilogue's strips
+                                 // need more than the operand stages' unpadded rows)
 constexpr int NXCD = 8;
 
 thread_local int g_mlp_hip = 0;
@@ -107,40 +109,9 @@ struct GemmArgs {
     int nt;      // BF16 output not re-read soon (inference): non-temporal stores
 };
 
-// Global -> register -> LDS staging of one operand tile of ROWS x BK (element (r, k) at
-// p[r*ld + k]) as chunks of 8 consecutive k of one row: one 16-byte load per chunk, eight lanes per
-// 128-byte row.  Out-of-range chunks are zero (K limits are multiples of 8).
-template <int ROWS, int NT>
-struct Tile {
-    static constexpr int CHUNKS = ROWS * BK / 8;
-    static constexpr int PER = CHUNKS / NT;
-    static_assert(CHUNKS % NT == 0, "tile chunks must divide among the threads");
-    uint4 v[PER];
-
-    __device__ __forceinline__ void load(const uint16_t *p, int64_t ld, int64_t r0, int64_t rlim,
-                                         int k0, int klim, int t) {
-#pragma unroll
-        for (int i = 0; i < PER; ++i) {
-            const int idx = t + i * NT;
-            const int64_t r = r0 + (idx >> 3);
-            const int k = k0 + (idx & 7) * 8;
-            v[i] = make_uint4(0u, 0u, 0u, 0u);
-            if (r < rlim && k < klim) v[i] = *(const uint4 *)(p + r * ld + k);
-        }
-    }
-
-    __device__ __forceinline__ void store(uint16_t *s, int t) const {
-#pragma unroll
-        for (int i = 0; i < PER; ++i) {
-            const int idx = t + i * NT;
-            *(uint4 *)(s + (idx >> 3) * LDK + (idx & 7) * 8) = v[i];
-        }
-    }
-};
-
 template <int BM, int BN, int WM, int WN>
 constexpr size_t gemm_lds_bytes() {
-    return (size_t)2 * (BM + BN) * LDK * sizeof(uint16_t);
+    return (size_t)2 * (BM + BN) * LDS_ROW * sizeof(uint16_t);
 }
 
 template <int BM, int BN, int WM, int WN>
@@ -151,8 +122,6 @@ __global__ __launch_bounds__(WM * WN * 64) void k_gemm(GemmArgs g) {
     static_assert(WM * WN * 32 * SLD * sizeof(float) <= gemm_lds_bytes<BM, BN, WM, WN>(),
                   "epilogue strips must fit in the operand buffers");
     extern __shared__ __attribute__((aligned(16))) uint16_t smem[];
-    uint16_t *const A0 = smem, *const A1 = smem + BM * LDK;
-    uint16_t *const B0 = smem + 2 * BM * LDK, *const B1 = B0 + BN * LDK;
 
     const int t = threadIdx.x, lane = t & 63, w = t >> 6, wm = w / WN, wn = w % WN;
     const int64_t bid = blockIdx.x;
@@ -176,8 +145,6 @@ __global__ __launch_bounds__(WM * WN * 64) void k_gemm(GemmArgs g) {
         k1 = min(k0 + g.ksplit, g.K);
     }
 
-    Tile<BM, NT> ta;
-    Tile<BN, NT> tb;
     f32x16 acc[TM][TN];
 #pragma unroll
     for (int a = 0; a < TM; ++a)
@@ -186,42 +153,82 @@ __global__ __launch_bounds__(WM * WN * 64) void k_gemm(GemmArgs g) {
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
 
+    // Operand tiles in LDS without padding: row r of a stage is 64 BF16 (128 bytes, eight 16-byte
+    // chunks) and its k-chunk c sits at chunk position c ^ (r & 7), so the 32 rows a fragment read
+    // touches spread over every bank.  Whole K tiles go global -> LDS directly (one 16-byte chunk
+    // per lane, eight rows per wavefront instruction: lane i fills position i & 7 of row i >> 3 and
+    // so fetches chunk (i & 7) ^ (i >> 3)); rows past M or N read row M-1 or N-1 instead (their
+    // results are discarded).  A tile cut by the K limit goes through registers with zero fill.
+    constexpr int SROW = BK;                      // bf16 per LDS row
+    constexpr int STAGE_A = BM * SROW, STAGE_B = BN * SROW;
+    auto SA = [&](int buf) { return smem + buf * STAGE_A; };
+    auto SB = [&](int buf) { return smem + 2 * STAGE_A + buf * STAGE_B; };
+    constexpr int NWV = WM * WN;
+    static_assert(BM % (8 * NWV) == 0 && BN % (8 * NWV) == 0, "rows per wavefront instruction");
+    auto stage_direct = [&](const uint16_t *p, int64_t ld, int64_t r0, int64_t rlim, int kk,
+                            uint16_t *dst, int rows) {
+        const int lr = lane >> 3, pos = lane & 7;
+        for (int j = 0; j < rows / (8 * NWV); ++j) {
+            const int R0 = (j * NWV + w) * 8;
+            int64_t r = r0 + R0 + lr;
+            r = r < rlim ? r : rlim - 1;
+            const uint16_t *src = p + r * ld + kk + 8 * (pos ^ lr);
+            __builtin_amdgcn_global_load_lds((__attribute__((address_space(1))) void *)src,
+                                             (__attribute__((address_space(3))) void *)(dst + R0 * SROW),
+                                             16, 0, 0);
+        }
+    };
+    auto stage_regs = [&](const uint16_t *p, int64_t ld, int64_t r0, int64_t rlim, int kk, int klim,
+                          uint16_t *dst, int rows) {
+        for (int idx = t; idx < rows * 8; idx += NT) {
+            const int rr = idx >> 3, c = idx & 7;
+            const int64_t r = r0 + rr;
+            const int k = kk + 8 * c;
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (r < rlim && k < klim) v = *(const uint4 *)(p + r * ld + k);
+            *(uint4 *)(dst + rr * SROW + 8 * (c ^ (rr & 7))) = v;
+        }
+    };
+    auto stage = [&](int buf, int kk) {
+        if (kk + BK <= k1) {
+            stage_direct(g.a, g.lda, m0, g.M, kk, SA(buf), BM);
+            stage_direct(g.b, g.ldb, n0, g.N, kk, SB(buf), BN);
+        } else {
+            stage_regs(g.a, g.lda, m0, g.M, kk, k1, SA(buf), BM);
+            stage_regs(g.b, g.ldb, n0, g.N, kk, k1, SB(buf), BN);
+        }
+    };
+
     const int nk = k1 > k0 ? (k1 - k0 + BK - 1) / BK : 0;
-    if (nk > 0) {
-        ta.load(g.a, g.lda, m0, g.M, k0, k1, t);
-        tb.load(g.b, g.ldb, n0, g.N, k0, k1, t);
-        ta.store(A0, t);
-        tb.store(B0, t);
-    }
+    if (nk > 0) stage(0, k0);
+    __builtin_amdgcn_s_waitcnt(0x0f70);  // vmcnt(0): the direct loads have landed
     __syncthreads();
     const int lrow = lane & 31, lk = 8 * (lane >> 5);
     for (int kt = 0; kt < nk; ++kt) {
-        const bool odd = kt & 1;
-        const uint16_t *Ac = odd ? A1 : A0, *Bc = odd ? B1 : B0;
-        const bool more = kt + 1 < nk;
-        if (more) {
-            ta.load(g.a, g.lda, m0, g.M, k0 + (kt + 1) * BK, k1, t);
-            tb.load(g.b, g.ldb, n0, g.N, k0 + (kt + 1) * BK, k1, t);
-        }
+        const int cur = kt & 1;
+        if (kt + 1 < nk) stage(cur ^ 1, k0 + (kt + 1) * BK);
+        const uint16_t *Ac = SA(cur), *Bc = SB(cur);
 #pragma unroll
         for (int ks = 0; ks < BK; ks += 16) {
+            const int c = (ks + lk) >> 3;
             bf16x8 af[TM], bf[TN];
 #pragma unroll
-            for (int a = 0; a < TM; ++a)
-                af[a] = *(const bf16x8 *)&Ac[(wm * (BM / WM) + a * 32 + lrow) * LDK + ks + lk];
+            for (int a = 0; a < TM; ++a) {
+                const int r = wm * (BM / WM) + a * 32 + lrow;
+                af[a] = *(const bf16x8 *)&Ac[r * SROW + 8 * (c ^ (r & 7))];
+            }
 #pragma unroll
-            for (int b = 0; b < TN; ++b)
-                bf[b] = *(const bf16x8 *)&Bc[(wn * (BN / WN) + b * 32 + lrow) * LDK + ks + lk];
+            for (int b = 0; b < TN; ++b) {
+                const int r = wn * (BN / WN) + b * 32 + lrow;
+                bf[b] = *(const bf16x8 *)&Bc[r * SROW + 8 * (c ^ (r & 7))];
+            }
 #pragma unroll
             for (int a = 0; a < TM; ++a)
 #pragma unroll
                 for (int b = 0; b < TN; ++b)
                     acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[a], bf[b], acc[a][b], 0, 0, 0);
         }
-        if (more) {
-            ta.store(odd ? A0 : A1, t);
-            tb.store(odd ? B0 : B1, t);
-        }
+        __builtin_amdgcn_s_waitcnt(0x0f70);  // vmcnt(0): the next stage has landed
         __syncthreads();
     }
 
