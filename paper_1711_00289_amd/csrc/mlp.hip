@@ -10,7 +10,7 @@
 // tiles.  K advances 64 at a time through two LDS stages: the next K tile goes from global memory
 // straight into the other stage (global_load_lds_dwordx4, no register staging) while the current
 // one feeds the MFMAs; every row of a tile is one full 128-byte line, stored with its 16-byte
-// chunks XOR-swizzled by the row so that fragment reads are free of bank conflicts.  Block ids are mapped so that the N tiles of one M tile run on the
+// chunks XOR-swizzled by the row pair so that fragment reads are free of bank conflicts.  Block ids are mapped so that the N tiles of one M tile run on the
 // same XCD (the hardware deals consecutive blocks to the 8 XCDs in turn), so an activation tile is
 // fetched into one XCD's L2 once and reused there; products with fewer M tiles than XCDs take
 // their tiles in plain order.  The epilogue stages each wavefront's
@@ -154,11 +154,13 @@ __global__ __launch_bounds__(WM * WN * 64) void k_gemm(GemmArgs g) {
             for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
 
     // Operand tiles in LDS without padding: row r of a stage is 64 BF16 (128 bytes, eight 16-byte
-    // chunks) and its k-chunk c sits at chunk position c ^ (r & 7), so the 32 rows a fragment read
-    // touches spread over every bank.  Whole K tiles go global -> LDS directly (one 16-byte chunk
-    // per lane, eight rows per wavefront instruction: lane i fills position i & 7 of row i >> 3 and
-    // so fetches chunk (i & 7) ^ (i >> 3)); rows past M or N read row M-1 or N-1 instead (their
-    // results are discarded).  A tile cut by the K limit goes through registers with zero fill.
+    // chunks) and its k-chunk c sits at chunk position c ^ ((r >> 1) & 7).  With 64 four-byte
+    // banks, two 128-byte rows share one bank cycle; the swizzle gives the 16 consecutive rows that
+    // a fragment read serves together 16 distinct 16-byte bank groups.  Whole K tiles go global ->
+    // LDS directly (one 16-byte chunk per lane, eight rows per wavefront instruction: lane i fills
+    // position i & 7 of row i >> 3 and so fetches the chunk that belongs there); rows past M or N
+    // read row M-1 or N-1 instead (their results are discarded).  A tile cut by the K limit goes
+    // through registers with zero fill.
     constexpr int SROW = BK;                      // bf16 per LDS row
     constexpr int STAGE_A = BM * SROW, STAGE_B = BN * SROW;
     auto SA = [&](int buf) { return smem + buf * STAGE_A; };
@@ -172,7 +174,7 @@ __global__ __launch_bounds__(WM * WN * 64) void k_gemm(GemmArgs g) {
             const int R0 = (j * NWV + w) * 8;
             int64_t r = r0 + R0 + lr;
             r = r < rlim ? r : rlim - 1;
-            const uint16_t *src = p + r * ld + kk + 8 * (pos ^ lr);
+            const uint16_t *src = p + r * ld + kk + 8 * (pos ^ (((R0 + lr) >> 1) & 7));
             __builtin_amdgcn_global_load_lds((__attribute__((address_space(1))) void *)src,
                                              (__attribute__((address_space(3))) void *)(dst + R0 * SROW),
                                              16, 0, 0);
@@ -186,7 +188,7 @@ __global__ __launch_bounds__(WM * WN * 64) void k_gemm(GemmArgs g) {
             const int k = kk + 8 * c;
             uint4 v = make_uint4(0u, 0u, 0u, 0u);
             if (r < rlim && k < klim) v = *(const uint4 *)(p + r * ld + k);
-            *(uint4 *)(dst + rr * SROW + 8 * (c ^ (rr & 7))) = v;
+            *(uint4 *)(dst + rr * SROW + 8 * (c ^ ((rr >> 1) & 7))) = v;
         }
     };
     auto stage = [&](int buf, int kk) {
@@ -215,12 +217,12 @@ __global__ __launch_bounds__(WM * WN * 64) void k_gemm(GemmArgs g) {
 #pragma unroll
             for (int a = 0; a < TM; ++a) {
                 const int r = wm * (BM / WM) + a * 32 + lrow;
-                af[a] = *(const bf16x8 *)&Ac[r * SROW + 8 * (c ^ (r & 7))];
+                af[a] = *(const bf16x8 *)&Ac[r * SROW + 8 * (c ^ ((r >> 1) & 7))];
             }
 #pragma unroll
             for (int b = 0; b < TN; ++b) {
                 const int r = wn * (BN / WN) + b * 32 + lrow;
-                bf[b] = *(const bf16x8 *)&Bc[r * SROW + 8 * (c ^ (r & 7))];
+                bf[b] = *(const bf16x8 *)&Bc[r * SROW + 8 * (c ^ ((r >> 1) & 7))];
             }
 #pragma unroll
             for (int a = 0; a < TM; ++a)
