@@ -52,6 +52,10 @@ extern "C" {
 #define CONV_EINVAL (-1)
 #define CONV_EUNSUPPORTED (-2)
 #define CONV_EHIP (-3)
+#define CONV_ERANGE (-4) /* conv_step_static: the sizes need more than its static scratch */
+
+/* Size of the static device array conv_step_static uses as its workspace (one per GPU). */
+#define CONV_STATIC_SCRATCH_BYTES ((size_t)128 << 20)
 
 typedef struct conv_ctx conv_ctx_t; /* opaque host-side handle */
 
@@ -132,6 +136,23 @@ int conv_shallow_forward(conv_ctx_t *ctx, const conv_state_t *state, conv_shallo
  * T' = T + dt*dTdt, q' = q + dt*dqdt, then shallow on (T', q'). */
 int conv_step(conv_ctx_t *ctx, const conv_state_t *state, conv_deep_out_t *deep,
               conv_shallow_out_t *shallow, void *stream);
+
+/* conv_step with no context and no workspace argument, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that forbid allocation.  The
+ * kernels are conv_step's and the results bit-identical to it.  Their workspace (counters, active
+ * lists, plume scratch) is a static device array of CONV_STATIC_SCRATCH_BYTES that the library
+ * holds on every GPU it runs on until the process ends; its address is looked up once per device,
+ * on the first call there.  The plume kernels get the widest persistent grids (5 wavefronts per
+ * compute unit down to 1) whose workspace fits the array; sizes for which even one wavefront per
+ * compute unit does not fit (on 256 compute units: more than 813,920 columns of 30 levels, 541,312
+ * of 46 or 98,272 of 72) return CONV_ERANGE with nothing enqueued.  The call allocates no memory, host or
+ * device, and does not synchronise the host; `params` is a host pointer, read during the call.
+ * Every call on one GPU shares that GPU's array and leaves its contents behind (the counters are
+ * cleared by the call's own first kernel): calls that overlap on one GPU (different streams or
+ * threads) race, so the caller must order them. */
+int conv_step_static(int64_t ncol, int32_t nlev, const conv_params_t *params,
+                     const conv_state_t *state, conv_deep_out_t *deep,
+                     conv_shallow_out_t *shallow, void *stream);
 
 /* Cotangents of the deep outputs (device pointers; any may be NULL = zero). */
 typedef struct {

@@ -12,7 +12,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libconv.so")
 
-CONV_OK, CONV_EINVAL, CONV_EUNSUPPORTED, CONV_EHIP = 0, -1, -2, -3
+CONV_OK, CONV_EINVAL, CONV_EUNSUPPORTED, CONV_EHIP, CONV_ERANGE = 0, -1, -2, -3, -4
 
 PARAM_FIELDS = (
     "cape_threshold", "tau", "eps_deep", "alpha_dd", "evap_max_frac", "p_launch_min", "p_top_min",
@@ -28,7 +28,7 @@ DEFAULTS = dict(
 
 EXPORTS = ("conv_workspace_bytes", "conv_create", "conv_set_params", "conv_destroy",
            "conv_deep_forward", "conv_shallow_forward", "conv_step", "conv_set_launch",
-           "conv_get_launch", "conv_timing_start",
+           "conv_get_launch", "conv_step_static", "conv_timing_start",
            "conv_timing_read", "conv_strerror", "conv_last_hip_error",
            "conv_backward_workspace_bytes", "conv_deep_backward", "conv_shallow_backward",
            "conv_step_backward", "conv_tracer_transport", "conv_autotune",
@@ -110,6 +110,9 @@ def lib():
         L.conv_step.restype = C.c_int
         L.conv_step.argtypes = [C.c_void_p, C.POINTER(State), C.POINTER(DeepOut),
                                 C.POINTER(ShallowOut), C.c_void_p]
+        L.conv_step_static.restype = C.c_int
+        L.conv_step_static.argtypes = [C.c_int64, C.c_int32, C.POINTER(Params), C.POINTER(State),
+                                       C.POINTER(DeepOut), C.POINTER(ShallowOut), C.c_void_p]
         L.conv_set_launch.restype = C.c_int
         L.conv_set_launch.argtypes = [C.c_void_p, C.c_int, C.c_int]
         L.conv_get_launch.restype = C.c_int
@@ -298,6 +301,25 @@ def state_struct(torch, s: dict, nlev: int, ncol: int) -> State:
             raise ValueError(f"{k}: expected float64 [{ld}]")
     return State(*[s[k].data_ptr() for k in ("T", "q", "p_mid", "z", "p_int", "phis", "pblh",
                                               "tke")], ld, float(s["dt"]))
+
+
+def step_static(s: dict, ncol: int, nlev: int, deep: dict, shallow: dict,
+                params: Params | None = None, stream=None) -> int:
+    """conv_step_static: one step over columns 0..ncol-1 of the device state `s` into the
+    preallocated device outputs `deep` and `shallow`, with the library's static device scratch as
+    the workspace (nothing is allocated).  Returns the library's code (CONV_OK, or CONV_ERANGE for
+    sizes beyond the static scratch); raises on other errors."""
+    torch = _torch()
+    st = state_struct(torch, s, nlev, ncol)
+    params = params or make_params()
+    d = DeepOut(*[deep[f].data_ptr() for f, _ in DeepOut._fields_])
+    h = ShallowOut(*[shallow[f].data_ptr() for f, _ in ShallowOut._fields_])
+    strm = C.c_void_p(stream.cuda_stream) if stream is not None else _stream(torch)
+    rc = lib().conv_step_static(int(ncol), int(nlev), C.byref(params), C.byref(st), C.byref(d),
+                                C.byref(h), strm)
+    if rc != CONV_ERANGE:
+        check(rc, "conv_step_static")
+    return rc
 
 
 class Conv:

@@ -996,13 +996,14 @@ __global__ __launch_bounds__(WAVE) void k_shallow_plume(Src src, Work w) {
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Workspace layout for `ncol` columns (all members together) of at most `lmax` levels and `nmem`
-// ensemble members.
-Layout make_layout(int64_t ncol, int lmax, int nmem, int cus) {
+// ensemble members.  `thread_cap` > 0 limits the persistent grids the plume scratch is sized for.
+Layout make_layout(int64_t ncol, int lmax, int nmem, int cus, int64_t thread_cap = 0) {
     Layout l{};
     const int64_t n = ncol > 0 ? ncol : 1;
     const int64_t tiles = (n + BLOCK - 1) / BLOCK;
     const int64_t cap = (int64_t)cus * MAX_BPC;
     l.threads = (tiles < cap ? tiles : cap) * BLOCK;
+    if (thread_cap > 0 && thread_cap < l.threads) l.threads = thread_cap;
     l.lmax = lmax;
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -1379,6 +1380,65 @@ int conv_step(conv_ctx_t *ctx, const conv_state_t *state, conv_deep_out_t *deep,
     return run_one<true, true>(ctx, state, deep, shallow, (hipStream_t)stream);
 }
 
+// ------------------------------------------------------------------ conv_step_static
+// The workspace of conv_step_static: a static device array, one per GPU, held until the process
+// ends.  Host code never uses its name as an address (the name is a host-side stand-in): the
+// device address is looked up once per device with hipGetSymbolAddress and kept in g_scratch_ptr.
+static __device__ __align__(256) char scratch[CONV_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+char *g_scratch_ptr[MAX_DEVICES] = {};
+
+// Device address of the current device's `scratch` (looked up on the first call on a device).
+int static_scratch(char **out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return hip_fail();
+    if (dev < 0 || dev >= MAX_DEVICES) return CONV_EUNSUPPORTED;
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            g_last_hip = (int)(e != hipSuccess ? e : hipErrorInvalidSymbol);
+            (void)hipGetLastError();
+            return CONV_EHIP;
+        }
+        g_scratch_ptr[dev] = (char *)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return CONV_OK;
+}
+}  // namespace
+
+int conv_step_static(int64_t ncol, int32_t nlev, const conv_params_t *params,
+                     const conv_state_t *state, conv_deep_out_t *deep,
+                     conv_shallow_out_t *shallow, void *stream) {
+    if (!params || !state || !deep || !shallow || ncol < 0 || ncol > INT32_MAX || nlev < 2 ||
+        nlev > 256)
+        return CONV_EINVAL;
+    if (ncol == 0) return CONV_OK;
+    if (!state_ok(ncol, state, true) || !deep_ok(deep) || !shallow_ok(shallow)) return CONV_EINVAL;
+    // The widest plume grids (5, 4, ... 1 wavefronts per CU) whose workspace fits the array.
+    const int cus = device_cus();
+    Layout l{};
+    int wpc = DEFAULT_LAUNCH.fused_wpc;
+    for (; wpc >= 1; --wpc) {
+        l = make_layout(ncol, nlev, 1, cus, (int64_t)cus * wpc * WAVE);
+        if (l.total <= CONV_STATIC_SCRATCH_BYTES) break;
+    }
+    if (wpc < 1) return CONV_ERANGE;
+    char *ws = nullptr;
+    const int rc = static_scratch(&ws);
+    if (rc != CONV_OK) return rc;
+    One src;
+    src.m = make_member(ncol, nlev, *params, state, deep, shallow, 0);
+    src.ntiles = (ncol + BLOCK - 1) / BLOCK;
+    const Work w = make_work(ws, l, Launch{wpc, wpc}, cus);
+    return launch_step<One, true, true>(src, w, (hipStream_t)stream, nullptr);
+}
+
 int conv_timing_start(conv_ctx_t *ctx, int max_calls) {
     if (!ctx || max_calls < 0) return CONV_EINVAL;
     free_events(ctx);
@@ -1419,6 +1479,7 @@ const char *conv_strerror(int code) {
         case CONV_EINVAL: return "invalid argument";
         case CONV_EUNSUPPORTED: return "unsupported";
         case CONV_EHIP: return "HIP launch failure";
+        case CONV_ERANGE: return "size beyond the static scratch of conv_step_static";
         default: return "unknown error";
     }
 }

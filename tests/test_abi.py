@@ -121,3 +121,29 @@ def test_mlp_training_batch_limit_sizes():
     assert L.mlp_workspace_bytes_ex(wa, n, 1000, 0) == 0
     h = C.c_void_p()
     assert L.mlp_create_ex(wa, n, 1000, 1001, C.c_void_p(256), 1 << 30, C.byref(h)) == -1
+
+
+def test_static_step_rejects_sizes_beyond_its_scratch_without_gpu():
+    """conv_step_static checks its arguments and the size of the workspace its static device array
+    must hold before any HIP call that launches or allocates: bad arguments give CONV_EINVAL,
+    sizes beyond the array CONV_ERANGE (on 256 compute units the bound for 72 levels is 98,272
+    columns), nothing is enqueued."""
+    if not os.path.exists(binding.LIB_PATH):
+        pytest.skip("libconv.so not built")
+    L = binding.lib()
+    p = binding.make_params()
+    d = binding.DeepOut(*([256] * 10))
+    s = binding.ShallowOut(*([256] * 8))
+    st = binding.State(*([256] * 8), 3_000_000, 1800.0)  # never dereferenced
+    assert L.conv_step_static(2_000_000, 30, C.byref(p), C.byref(st), C.byref(d), C.byref(s),
+                              None) == binding.CONV_ERANGE
+    assert L.conv_step_static(2_000_000, 30, None, C.byref(st), C.byref(d), C.byref(s),
+                              None) == binding.CONV_EINVAL
+    assert L.conv_step_static(10, 1, C.byref(p), C.byref(st), C.byref(d), C.byref(s),
+                              None) == binding.CONV_EINVAL
+    assert L.conv_step_static(0, 30, C.byref(p), C.byref(st), C.byref(d), C.byref(s),
+                              None) == binding.CONV_OK
+    st.ld = 10  # ld < ncol
+    assert L.conv_step_static(200, 30, C.byref(p), C.byref(st), C.byref(d), C.byref(s),
+                              None) == binding.CONV_EINVAL
+    assert L.conv_strerror(binding.CONV_ERANGE).startswith(b"size beyond")
