@@ -118,6 +118,9 @@ def lib():
         L.oracle_step_omp.restype = C.c_int
         L.oracle_step_omp.argtypes = [C.c_int64, C.c_int, C.POINTER(Params), C.POINTER(State),
                                       C.POINTER(DeepOut), C.POINTER(ShallowOut), C.c_int, C.c_int]
+        L.oracle_step_ops.restype = C.c_int
+        L.oracle_step_ops.argtypes = [C.c_int64, C.c_int, C.POINTER(Params), C.POINTER(State),
+                                      C.c_void_p]
         L.oracle_deep_column.restype = C.c_int
         L.oracle_deep_column.argtypes = ([C.c_int, C.POINTER(Params)] + [dp] * 5 +
                                          [C.c_double, C.c_double] + [dp] * 5 +
@@ -239,6 +242,19 @@ def step(st: dict, params: Params | None = None, threads: int = 0, chunk: int = 
     if rc != 0:
         raise ValueError("oracle_step: bad arguments")
     return od, os_
+
+
+def step_ops(st: dict, params: Params | None = None):
+    """Algorithmic operation count of the step per column (float64 [ncol]): +, -, *, /, sqrt,
+    exp and log count 1 each (see oracle_step_ops)."""
+    params = params or make_params()
+    L, n = _dims(st)
+    keep = []
+    s = _state(st, keep)
+    ops = np.zeros(n)
+    if lib().oracle_step_ops(n, L, C.byref(params), C.byref(s), ops.ctypes.data) != 0:
+        raise ValueError("oracle_step_ops: bad arguments")
+    return ops
 
 
 def column(st: dict, c: int) -> dict:

@@ -48,6 +48,27 @@ inline Dual log(Dual a) { return Dual(std::log(a.v), a.d / a.v); }
 inline Dual sqrt(Dual a) { double r = std::sqrt(a.v); return Dual(r, a.d / (2.0 * r)); }
 inline double val(double x) { return x; }
 inline double val(const Dual &x) { return x.v; }
+
+/* Counted: a double that counts the arithmetic done on it (the algorithmic operation count of the
+ * scheme, for the roofline): +, -, *, / and sqrt count 1, exp and log count 1 (no fused
+ * multiply-add occurs: the oracle is built without contraction).  Only operations with a state- or
+ * parameter-dependent operand run in this type; the grid's own arithmetic (interface heights,
+ * layer thicknesses, log-pressure widths: 6 per layer) is added by the caller. */
+thread_local long long g_ops = 0;
+struct Counted {
+    double v;
+    Counted() : v(0.0) {}
+    Counted(double x) : v(x) {}  // NOLINT: implicit on purpose (constants)
+};
+inline Counted operator+(Counted a, Counted b) { ++g_ops; return Counted(a.v + b.v); }
+inline Counted operator-(Counted a, Counted b) { ++g_ops; return Counted(a.v - b.v); }
+inline Counted operator-(Counted a) { return Counted(-a.v); }
+inline Counted operator*(Counted a, Counted b) { ++g_ops; return Counted(a.v * b.v); }
+inline Counted operator/(Counted a, Counted b) { ++g_ops; return Counted(a.v / b.v); }
+inline Counted exp(Counted a) { ++g_ops; return Counted(std::exp(a.v)); }
+inline Counted log(Counted a) { ++g_ops; return Counted(std::log(a.v)); }
+inline Counted sqrt(Counted a) { ++g_ops; return Counted(std::sqrt(a.v)); }
+inline double val(const Counted &x) { return x.v; }
 using std::exp;
 using std::log;
 using std::sqrt;
@@ -774,6 +795,37 @@ void step_one(int L, const oracle_params_t *p, const oracle_state_t *s, int64_t 
     scatter_shallow(sh, L, s->ld, c, os);
 }
 
+// The step of one column (as step_one) with every state-dependent operation counted; returns the
+// count including the two grids' own arithmetic (6 operations per layer each).
+long long step_one_ops(int L, const oracle_params_t *p, const oracle_state_t *s, int64_t c) {
+    ColIn col;
+    gather(s, L, c, col);
+    std::vector<Counted> T(L), q(L);
+    for (int k = 0; k < L; ++k) {
+        T[k] = col.T[k];
+        q[k] = col.q[k];
+    }
+    g_ops = 0;
+    DeepRes<Counted> d;
+    deep_column<Counted>(L, *p, p->tau, p->eps_deep, T.data(), q.data(), col.pm.data(),
+                         col.pi.data(), col.z.data(), col.phis, s->dt, d);
+    std::vector<Counted> T2(L), q2(L);
+    for (int k = 0; k < L; ++k) {
+        T2[k] = T[k] + s->dt * d.dTdt[k];
+        q2[k] = q[k] + s->dt * d.dqdt[k];
+    }
+    ShallowRes<Counted> sh;
+    if (d.status == 3)
+        shallow_column<Counted>(L, *p, p->eps_sh, p->delta_sh, T.data(), q.data(), col.pm.data(),
+                                col.pi.data(), col.z.data(), col.phis, col.pblh, col.tke, s->dt,
+                                sh);
+    else
+        shallow_column<Counted>(L, *p, p->eps_sh, p->delta_sh, T2.data(), q2.data(),
+                                col.pm.data(), col.pi.data(), col.z.data(), col.phis, col.pblh,
+                                col.tke, s->dt, sh, true);
+    return g_ops + 2LL * 6 * L;
+}
+
 }  // namespace
 
 /* ---------------------------------------------------------------- C entry points */
@@ -854,6 +906,13 @@ int oracle_tracers(int64_t ncol, int nlev, const oracle_params_t *p, const oracl
             }
         }
     }
+    return 0;
+}
+
+int oracle_step_ops(int64_t ncol, int nlev, const oracle_params_t *p, const oracle_state_t *s,
+                    double *ops) {
+    if (!args_ok(ncol, nlev, p, s) || !ops) return -1;
+    for (int64_t c = 0; c < ncol; ++c) ops[c] = (double)step_one_ops(nlev, p, s, c);
     return 0;
 }
 

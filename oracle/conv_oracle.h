@@ -70,6 +70,13 @@ int oracle_shallow(int64_t ncol, int nlev, const oracle_params_t *p, const oracl
 int oracle_step(int64_t ncol, int nlev, const oracle_params_t *p, const oracle_state_t *s,
                 oracle_deep_out_t *od, oracle_shallow_out_t *os);
 
+/* Algorithmic operation count of oracle_step per column (ops[ncol]): +, -, *, /, sqrt, exp and
+ * log count 1 each, over every operation with a state- or parameter-dependent operand, plus the
+ * grid's own arithmetic (6 operations per layer for each scheme).  The count follows the oracle's
+ * own algorithm (its root finder's iterations included). */
+int oracle_step_ops(int64_t ncol, int nlev, const oracle_params_t *p, const oracle_state_t *s,
+                    double *ops);
+
 /* Same as oracle_step with OpenMP dynamic scheduling over columns (CPU baseline only). */
 int oracle_step_omp(int64_t ncol, int nlev, const oracle_params_t *p, const oracle_state_t *s,
                     oracle_deep_out_t *od, oracle_shallow_out_t *os, int chunk, int nthreads);

@@ -85,3 +85,25 @@ def test_adjoint_bytes():
     assert quiet == n * (4 + 2 * L * 8)
     extra = (bench.adjoint_bytes(L, n, n) - quiet) / n
     assert extra == bench.bytes_per_column(L)["inputs"] - 2 * 8 + 2 * 4 + 2 * L * 8
+
+
+def test_oracle_operation_count_and_cpu_sweep_helpers():
+    """The algorithmic operation count is per column, positive, and larger for convecting columns
+    (they run the plume passes); the chunk sweep's baseline runs at every chunk size; the CPU model
+    is read from lscpu when it exists."""
+    import oracle
+
+    st = S.make_state(64, 30, seed=7, warm=np.ones(64, bool))
+    ops = oracle.step_ops(st)
+    od, osh = oracle.step(st)
+    assert ops.shape == (64,) and (ops > 30 * 6).all()
+    act = od["status"] == 0
+    assert act.any() and (~act).any()
+    assert ops[act].mean() > 1.5 * ops[~act].mean()
+    mean, n = bench.oracle_ops(st, stride=4)
+    assert n == 16 and mean == pytest.approx(ops[::4].mean())
+    for c in bench.OMP_CHUNKS:
+        rate, secs, steps = bench.cpu_baseline(st, 2, chunk=c, min_cpu_s=0.0, max_steps=1)
+        assert steps == 1 and rate > 0
+    m = bench.cpu_model()
+    assert m is None or isinstance(m, str)
