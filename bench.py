@@ -268,6 +268,33 @@ def bench_tracers(torch, B, conv, dev, deep, shallow, reps):
                          "algorithmic_bytes_per_launch": nbytes}}
 
 
+def bench_momentum(torch, B, conv, dev, deep, shallow, reps, c_pgf=0.7):
+    """Convective momentum transport (u, v with the pressure-gradient term, coefficient c_pgf) by
+    the headline grid's step: time per call and the HBM roofline of the transport kernel (the
+    algorithmic bytes of two tracers)."""
+    L, n = conv.nlev, conv.ncol
+    g = torch.Generator(device="cuda").manual_seed(13)
+    base = torch.linspace(25.0, -8.0, L, dtype=torch.float64, device="cuda")[:, None]
+    w = torch.stack([base + 4.0 * torch.randn((L, n), generator=g, dtype=torch.float64,
+                                              device="cuda"),
+                     -0.4 * base + 4.0 * torch.randn((L, n), generator=g, dtype=torch.float64,
+                                                     device="cuda")])
+    tend = torch.empty_like(w)
+    for _ in range(3):
+        conv.momentum_transport(dev, deep, shallow, w, c_pgf=c_pgf, out=tend)
+    ms = time_events(torch, lambda: conv.momentum_transport(dev, deep, shallow, w, c_pgf=c_pgf,
+                                                            out=tend), reps)
+    host = lambda o: {k: o[k].cpu().numpy() for k in ("status", "klaunch", "ktop", "kbase")
+                      if k in o}
+    nbytes = tracer_bytes(L, 2, host(deep), host(shallow))
+    achieved = nbytes / (ms * 1e-3) / 1e9
+    return {"workload": f"momentum (u, v) transported by the 884,736 x 30 step, c_pgf = {c_pgf}",
+            "ms": ms, "columns_per_s": n / (ms * 1e-3),
+            "roofline": {"bound": "hbm", "kernel": "k_tracers", "achieved": achieved,
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                         "algorithmic_bytes_per_launch": nbytes}}
+
+
 def bench_dilute(torch, B, dev, n, reps, eps_cape=1e-4):
     """The step on the headline grid with the dilute (entraining) CAPE parcel."""
     conv = B.Conv(n, NLEV, B.make_params(eps_cape=eps_cape))
@@ -518,6 +545,8 @@ def main():
     if not args.no_extras:
         out["tracers"] = bench_tracers(torch, B, conv, dev, deep, shallow, max(args.steps, 10))
         print("[bench] tracers done", file=sys.stderr, flush=True)
+        out["momentum"] = bench_momentum(torch, B, conv, dev, deep, shallow, max(args.steps, 10))
+        print("[bench] momentum done", file=sys.stderr, flush=True)
         out["dilute"] = bench_dilute(torch, B, dev, n, max(args.steps, 10))
         print("[bench] dilute done", file=sys.stderr, flush=True)
         out["adjoint"] = bench_adjoint(torch, B, S, max(args.steps, 10))

@@ -251,6 +251,26 @@ int conv_tracer_transport(conv_ctx_t *ctx, const conv_state_t *state, const conv
                           const conv_shallow_out_t *sfwd, int32_t ntr, const double *tracers,
                           double *tend, double *deep_tend, void *stream);
 
+/* Convective momentum transport by the plumes of one conv_step: the two horizontal wind components
+ * carried as conv_tracer_transport carries a tracer, plus the convective pressure-gradient term of
+ * Gregory, Kershaw & Inness (1997, Q. J. R. Meteorol. Soc. 123): the cloud-scale pressure gradient
+ * pulls a plume's wind towards the environment's as the plume crosses environmental shear, so
+ * crossing a layer adds c_pgf times the plume's mass flux times the change of the environmental
+ * wind from the layer the plume comes from (below for an updraft, above for the downdraft) to the
+ * layer it crosses.  c_pgf = 0 is passive transport (the results are then bit-identical to
+ * conv_tracer_transport of the two components), 1 makes a plume follow the environment's shear;
+ * Gregory et al. use 0.7.  The tendencies are flux divergences, so column momentum is conserved.
+ * Extends the paper's convection, which moves heat and water, to the momentum the same mass fluxes
+ * carry.
+ * `dfwd`, `sfwd`: the outputs of conv_step on `state` with the context's parameters, as for
+ * conv_tracer_transport.  wind: device [2][nlev][ld] (u, then v; m/s) with the state's ld; tend
+ * (m s^-2) and deep_tend (may be NULL: the deep part alone) likewise.  Columns with neither scheme
+ * active get exact zeros.  Returns CONV_EINVAL for missing arrays or a non-finite c_pgf. */
+int conv_momentum_transport(conv_ctx_t *ctx, const conv_state_t *state,
+                            const conv_deep_out_t *dfwd, const conv_shallow_out_t *sfwd,
+                            const double *wind, double c_pgf, double *tend, double *deep_tend,
+                            void *stream);
+
 /* ---------------------------------------------------------------- batched ensemble
  * Several grids ("members", e.g. ensemble members of a forecast) with their own column counts,
  * level counts (2..256), parameters and arrays, advanced by one conv_step each in the SAME kernel

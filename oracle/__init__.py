@@ -138,6 +138,9 @@ def lib():
         L.oracle_tracers.restype = C.c_int
         L.oracle_tracers.argtypes = [C.c_int64, C.c_int, C.POINTER(Params), C.POINTER(State),
                                      C.c_int, dp, dp, dp]
+        L.oracle_momentum.restype = C.c_int
+        L.oracle_momentum.argtypes = [C.c_int64, C.c_int, C.POINTER(Params), C.POINTER(State),
+                                      dp, C.c_double, dp, dp]
         L.oracle_shallow_column_jvp.restype = C.c_int
         L.oracle_shallow_column_jvp.argtypes = ([C.c_int, C.POINTER(Params)] + [dp] * 5 +
                                                 [C.c_double] * 4 + [dp, dp, C.c_double,
@@ -340,6 +343,27 @@ def tracers(st: dict, tr, params: Params | None = None):
                               _ptr(deep))
     if rc != 0:
         raise ValueError("oracle_tracers: bad arguments")
+    return tend, deep
+
+
+CPGF_DEFAULT = 0.7  # Gregory, Kershaw & Inness (1997)
+
+
+def momentum(st: dict, wind, cpgf: float = CPGF_DEFAULT, params: Params | None = None):
+    """Convective momentum transport by one step: wind [2][nlev][ncol] (u, v) -> (tend,
+    deep_tend), each [2][nlev][ncol] in m s^-2; cpgf is the pressure-gradient coefficient."""
+    params = params or make_params()
+    L, n = _dims(st)
+    keep = []
+    s = _state(st, keep)
+    wind = np.ascontiguousarray(wind, dtype=np.float64)
+    if wind.shape != (2, L, n):
+        raise ValueError("wind must be [2][nlev][ncol]")
+    tend, deep = np.zeros_like(wind), np.zeros_like(wind)
+    rc = lib().oracle_momentum(n, L, C.byref(params), C.byref(s), _ptr(wind), float(cpgf),
+                               _ptr(tend), _ptr(deep))
+    if rc != 0:
+        raise ValueError("oracle_momentum: bad arguments")
     return tend, deep
 
 

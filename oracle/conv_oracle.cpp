@@ -641,9 +641,18 @@ void shallow_column(int L, const oracle_params_t &P, const R &eps_sh, const R &d
  * updraft starts from the air of its source, the deep downdraft from layer k_d's air, and the
  * tendencies are the flux divergences of the plume-minus-environment fluxes with the same upwind
  * environmental values (D7, S8).  No sources or sinks: the column integral of the tendency,
- * weighted by dp/g, is zero. */
+ * weighted by dp/g, is zero.
+ *
+ * Momentum (a wind component) is carried the same way plus the convective pressure-gradient term
+ * of Gregory, Kershaw & Inness (1997): the cloud-scale pressure gradient pulls the plume's wind
+ * towards the environment's as the plume crosses environmental shear, so crossing a layer adds
+ * cpgf times the plume's mass flux times the change of the environmental wind from the layer the
+ * plume comes from to the layer it crosses (the layer below for an updraft, the layer above for
+ * the downdraft).  cpgf = 0 is the passive tracer; cpgf = 1 makes the plume follow the
+ * environment's shear exactly.  The tendency stays a flux divergence, so column momentum is
+ * conserved. */
 void deep_tracer(int L, const oracle_params_t &P, const DeepRes<double> &d, const Grid &g,
-                 const double *C, double *out) {
+                 const double *C, double *out, double cpgf = 0.0) {
     for (int k = 0; k < L; ++k) out[k] = 0.0;
     if (d.status != 0) return;
     const int kb = d.kb, kt = d.kt, kd = d.kd;
@@ -654,7 +663,8 @@ void deep_tracer(int L, const oracle_params_t &P, const DeepRes<double> &d, cons
     Cu[kb] = C[kb];
     for (int k = kb - 1; k >= kt + 1; --k) {
         const double E = P.eps_deep * eta[k + 1] * g.dz[k];
-        Cu[k] = (eta[k + 1] * Cu[k + 1] + E * C[k]) / eta[k];
+        Cu[k] = (eta[k + 1] * Cu[k + 1] + E * C[k] + cpgf * eta[k + 1] * (C[k] - C[k + 1])) /
+                eta[k];
     }
     // Downdraft (D6's mixing): layer k_d's air at interface k_d+1, entraining layer k's air
     // between interfaces k and k+1.
@@ -664,7 +674,7 @@ void deep_tracer(int L, const oracle_params_t &P, const DeepRes<double> &d, cons
         for (int k = kd + 1; k <= kb - 1; ++k) {
             const double Ed = P.eps_deep * ad * g.dz[k];
             const double adn = ad + Ed;
-            Cd[k + 1] = (ad * Cd[k] + Ed * C[k]) / adn;
+            Cd[k + 1] = (ad * Cd[k] + Ed * C[k] + cpgf * ad * (C[k] - C[k - 1])) / adn;
             ad = adn;
         }
     }
@@ -679,7 +689,7 @@ void deep_tracer(int L, const oracle_params_t &P, const DeepRes<double> &d, cons
 }
 
 void shallow_tracer(int L, const oracle_params_t &P, const ShallowRes<double> &o, const Grid &g,
-                    const double *C, double *out) {
+                    const double *C, double *out, double cpgf = 0.0) {
     for (int k = 0; k < L; ++k) out[k] = 0.0;
     if (o.status != 0) return;
     const int ks = o.ks, kt = o.kt;
@@ -696,7 +706,8 @@ void shallow_tracer(int L, const oracle_params_t &P, const ShallowRes<double> &o
     for (int k = ks - 1; k >= kt + 1; --k) {
         const double E = P.eps_sh * eta[k + 1] * g.dz[k];
         const double D = P.delta_sh * eta[k + 1] * g.dz[k];
-        Cu[k] = ((eta[k + 1] - D) * Cu[k + 1] + E * C[k]) / eta[k];
+        Cu[k] = ((eta[k + 1] - D) * Cu[k + 1] + E * C[k] + cpgf * eta[k + 1] * (C[k] - C[k + 1])) /
+                eta[k];
     }
     // S8's fluxes (environment from the layer above) and their divergence.
     std::vector<double> F(L + 1, 0.0);
@@ -869,6 +880,17 @@ int oracle_step(int64_t ncol, int nlev, const oracle_params_t *p, const oracle_s
 
 int oracle_tracers(int64_t ncol, int nlev, const oracle_params_t *p, const oracle_state_t *s,
                    int ntr, const double *tracers, double *tend, double *deep_tend) {
+    return oracle_transport(ncol, nlev, p, s, ntr, tracers, 0.0, tend, deep_tend);
+}
+
+int oracle_momentum(int64_t ncol, int nlev, const oracle_params_t *p, const oracle_state_t *s,
+                    const double *wind, double cpgf, double *tend, double *deep_tend) {
+    if (!wind || !tend) return -1;
+    return oracle_transport(ncol, nlev, p, s, 2, wind, cpgf, tend, deep_tend);
+}
+
+int oracle_transport(int64_t ncol, int nlev, const oracle_params_t *p, const oracle_state_t *s,
+                     int ntr, const double *tracers, double cpgf, double *tend, double *deep_tend) {
     if (!args_ok(ncol, nlev, p, s) || ntr < 0 || (ntr > 0 && (!tracers || !tend))) return -1;
     const int L = nlev;
     const int64_t ld = s->ld, plane = (int64_t)L * ld;
@@ -896,10 +918,10 @@ int oracle_tracers(int64_t ncol, int nlev, const oracle_params_t *p, const oracl
         const Grid g = make_grid(L, col.pi.data(), col.z.data());
         for (int t = 0; t < ntr; ++t) {
             for (int k = 0; k < L; ++k) C[k] = tracers[t * plane + k * ld + c];
-            deep_tracer(L, *p, d, g, C.data(), Cd.data());
+            deep_tracer(L, *p, d, g, C.data(), Cd.data(), cpgf);
             // The shallow scheme transports the tracer updated by the deep transport.
             for (int k = 0; k < L; ++k) C2[k] = C[k] + s->dt * Cd[k];
-            shallow_tracer(L, *p, sh, g, C2.data(), Cs.data());
+            shallow_tracer(L, *p, sh, g, C2.data(), Cs.data(), cpgf);
             for (int k = 0; k < L; ++k) {
                 tend[t * plane + k * ld + c] = Cd[k] + Cs[k];
                 if (deep_tend) deep_tend[t * plane + k * ld + c] = Cd[k];

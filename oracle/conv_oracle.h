@@ -112,6 +112,16 @@ int oracle_deep_column_jvp(int nlev, const oracle_params_t *p, const double *T, 
 int oracle_tracers(int64_t ncol, int nlev, const oracle_params_t *p, const oracle_state_t *s,
                    int ntr, const double *tracers, double *tend, double *deep_tend);
 
+/* Convective momentum transport by one step: the two wind components wind[2][nlev][ld] (u, then v)
+ * carried by the plumes as tracers are, plus the pressure-gradient term of Gregory, Kershaw &
+ * Inness (1997) with coefficient cpgf (the plume's wind is pulled towards the environment's as it
+ * crosses shear; 0 = passive tracers).  tend, deep_tend (may be NULL): [2][nlev][ld], m s^-2. */
+int oracle_momentum(int64_t ncol, int nlev, const oracle_params_t *p, const oracle_state_t *s,
+                    const double *wind, double cpgf, double *tend, double *deep_tend);
+/* The common transport of ntr fields with pressure-gradient coefficient cpgf. */
+int oracle_transport(int64_t ncol, int nlev, const oracle_params_t *p, const oracle_state_t *s,
+                     int ntr, const double *tracers, double cpgf, double *tend, double *deep_tend);
+
 /* Forward-mode derivative of the shallow scheme (S1-S9) of one column along (dT, dq, d eps_sh,
  * d delta_sh), with every integer decision of the run held fixed: source layers, lifting
  * condensation and free-convection levels, the levels counted in CIN, saturation and rain-out

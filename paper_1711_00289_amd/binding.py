@@ -31,7 +31,8 @@ EXPORTS = ("conv_workspace_bytes", "conv_create", "conv_set_params", "conv_destr
            "conv_get_launch", "conv_step_static", "conv_timing_start",
            "conv_timing_read", "conv_strerror", "conv_last_hip_error",
            "conv_backward_workspace_bytes", "conv_deep_backward", "conv_shallow_backward",
-           "conv_step_backward", "conv_tracer_transport", "conv_autotune",
+           "conv_step_backward", "conv_tracer_transport", "conv_momentum_transport",
+           "conv_autotune",
            "conv_ensemble_workspace_bytes", "conv_ensemble_create", "conv_ensemble_destroy",
            "conv_ensemble_step", "conv_ensemble_set_launch", "conv_ensemble_get_launch",
            "conv_ensemble_autotune", "conv_ensemble_capture", "conv_ensemble_replay",
@@ -136,6 +137,10 @@ def lib():
         L.conv_tracer_transport.argtypes = [C.c_void_p, C.POINTER(State), C.POINTER(DeepOut),
                                             C.POINTER(ShallowOut), C.c_int32, C.c_void_p,
                                             C.c_void_p, C.c_void_p, C.c_void_p]
+        L.conv_momentum_transport.restype = C.c_int
+        L.conv_momentum_transport.argtypes = [C.c_void_p, C.POINTER(State), C.POINTER(DeepOut),
+                                              C.POINTER(ShallowOut), C.c_void_p, C.c_double,
+                                              C.c_void_p, C.c_void_p, C.c_void_p]
         L.conv_deep_backward.restype = C.c_int
         L.conv_deep_backward.argtypes = [C.c_void_p, C.POINTER(State), C.POINTER(DeepOut),
                                          C.POINTER(DeepCot), C.POINTER(DeepGrad), C.c_void_p,
@@ -494,6 +499,25 @@ class Conv:
                                           int(tr.shape[0]), tr.data_ptr(), tend.data_ptr(),
                                           dpart.data_ptr() if dpart is not None else None,
                                           _stream(torch)), "conv_tracer_transport")
+        return (tend, dpart) if deep_part else tend
+
+    def momentum_transport(self, s: dict, deep: dict, shallow: dict, wind, c_pgf: float = 0.7,
+                           deep_part=False, out=None):
+        """Convective momentum transport of wind [2][nlev][ld] (u, v; float64, device) by the
+        plumes of the step whose outputs are `deep`, `shallow`, with pressure-gradient coefficient
+        c_pgf: returns the deep + shallow tendency, and with deep_part also the deep part alone."""
+        torch = self.torch
+        st = self._state(s)
+        if wind.dtype != torch.float64 or tuple(wind.shape) != (2, self.nlev, st.ld):
+            raise ValueError(f"wind: expected float64 [2][{self.nlev}][{st.ld}]")
+        w = wind.contiguous()
+        tend = out if out is not None else torch.empty_like(w)
+        dpart = torch.empty_like(w) if deep_part else None
+        d, h = self._deep_struct(deep), self._shallow_struct(shallow)
+        check(lib().conv_momentum_transport(self.h, C.byref(st), C.byref(d), C.byref(h),
+                                            w.data_ptr(), float(c_pgf), tend.data_ptr(),
+                                            dpart.data_ptr() if dpart is not None else None,
+                                            _stream(torch)), "conv_momentum_transport")
         return (tend, dpart) if deep_part else tend
 
     def autotune(self, s: dict, deep: dict, shallow: dict, reps: int = 5, force: bool = False):

@@ -1,6 +1,8 @@
 // conv_tracers.hip -- convective transport of passive tracers by the plumes of one step (the
 // convection schemes the paper accelerates move heat and water; the same mass fluxes move every
-// other constituent).
+// other constituent), and convective momentum transport: the wind components carried the same way
+// plus the pressure-gradient term of Gregory, Kershaw & Inness (1997), which pulls a plume's wind
+// towards the environment's as it crosses shear (coefficient c_pgf; 0 = a passive tracer).
 //
 // A tracer is mixed by the plumes exactly as moist static energy is (D5-D7 deep, S7-S8 shallow):
 // the deep updraft starts from the launch layer's air and entrains layer k's air between
@@ -22,6 +24,7 @@
 // lane active, so each store covers whole 128-byte lines (stores that cover only part of a line,
 // as a wavefront mixing quiet and convecting columns would issue, run at a fraction of the
 // bandwidth on this part).  Quiet columns contribute zeros.
+#include <cmath>
 #include <mutex>
 #include <set>
 
@@ -36,6 +39,7 @@ constexpr int TB = 8;     // levels whose loads are issued together in the plume
 
 struct TrArgs {
     Member M;          // state, both schemes' outputs and parameters of the step
+    double pgf;        // pressure-gradient coefficient (0 for passive tracers)
     int ntr;
     const double *C;   // tracers [ntr][nlev][ld]
     double *tend;      // deep + shallow tendency [ntr][nlev][ld]
@@ -93,7 +97,10 @@ __global__ __launch_bounds__(TW) void k_tracers(TrArgs a) {
         // interfaces are computed (a level's arithmetic is far shorter than a load's latency);
         // indices are clamped, so values loaded past the top are not used.  The downdraft's
         // first interface (the highest one with md != 0) is noted on the way.
-        double Cu = AT(C, kb), Fb = 0.0, mu1 = 0.0;
+        // With a pressure-gradient term, crossing layer i adds pgf * mu[i+1] * (C_i - C_{i+1}):
+        // `Cbel` holds C of the layer below the interface being computed.
+        double Cu = AT(C, kb), Fb = 0.0, mu1 = 0.0, Cbel = 0.0;
+        const bool pgf = a.pgf != 0.0;
         int i0 = kb + 1;
         for (int b = kb; b >= kt + 1; b -= TB) {
             double mu[TB], md[TB], Ci[TB + 1], pt[TB + 1];
@@ -117,7 +124,12 @@ __global__ __launch_bounds__(TW) void k_tracers(TrArgs a) {
                 // interface i: layer i below (C_i), layer i-1 above (C_{i-1}); layer i spans
                 // pressures pt[j] (top) .. its bottom interface (pt[j-1], or pbot0 for j = 0)
                 if (md[j] != 0.0) i0 = i;
-                if (i < kb) Cu = (mu1 * Cu + (mu[j] - mu1) * Ci[j]) / mu[j];
+                if (i < kb) {
+                    double num = mu1 * Cu + (mu[j] - mu1) * Ci[j];
+                    if (pgf) num += a.pgf * mu1 * (Ci[j] - Cbel);
+                    Cu = num / mu[j];
+                }
+                Cbel = Ci[j];
                 const double F = mu[j] * (Cu - (mu[j] + md[j] >= 0.0 ? Ci[j + 1] : Ci[j]));
                 const double pbot = j == 0 ? pbot0 : pt[j - 1];
                 SH(i) = (Fb - F) * GRAV / (pbot - pt[j]);
@@ -129,7 +141,9 @@ __global__ __launch_bounds__(TW) void k_tracers(TrArgs a) {
         // Downdraft, top-down from its first interface: C_d at interface i mixes layer i-1's air
         // into C_d at i-1; its flux enters layer i-1 from below and leaves layer i at the top.
         if (i0 <= kb) {
-            double Cd = AT(C, i0 - 1), ad1 = 0.0;
+            // Crossing layer i-1 downward adds pgf * |md[i-1]| * (C_{i-1} - C_{i-2}): `Cabv` holds
+            // C of the layer above the one crossed.
+            double Cd = AT(C, i0 - 1), ad1 = 0.0, Cabv = 0.0;
             for (int b = i0; b <= kb; b += TB) {
                 // interfaces b .. b+TB-1: layers b-1 .. b+TB-1 and their interfaces b-1 .. b+TB
                 double mu[TB], md[TB], Cl[TB + 1], pl[TB + 2];
@@ -148,7 +162,12 @@ __global__ __launch_bounds__(TW) void k_tracers(TrArgs a) {
                     const int i = b + j;
                     if (i > kb) break;
                     const double ad = -md[j];
-                    if (i > i0) Cd = (ad1 * Cd + (ad - ad1) * Cl[j]) / ad;
+                    if (i > i0) {
+                        double num = ad1 * Cd + (ad - ad1) * Cl[j];
+                        if (pgf) num += a.pgf * ad1 * (Cl[j] - Cabv);
+                        Cd = num / ad;
+                    }
+                    Cabv = Cl[j];
                     const double F = md[j] * (Cd - (mu[j] + md[j] >= 0.0 ? Cl[j] : Cl[j + 1]));
                     SH(i - 1) += F * GRAV / (pl[j + 1] - pl[j]);
                     SH(i) -= F * GRAV / (pl[j + 2] - pl[j + 1]);
@@ -187,7 +206,8 @@ __global__ __launch_bounds__(TW) void k_tracers(TrArgs a) {
                 wsum += dpk;
             }
         }
-        double Cu = csum / wsum, Fb = 0.0, mu1 = 0.0;
+        double Cu = csum / wsum, Fb = 0.0, mu1 = 0.0, C2bel = 0.0;
+        const bool pgf = a.pgf != 0.0;
         for (int b = ks; b >= kts + 1; b -= TB) {
             // interfaces b .. b-TB+1: layers b .. b-TB, heights b+1 .. b-TB, pressures b+1 .. b-TB+1
             double mu[TB], Cl[TB + 1], zl[TB + 2], pl[TB + 1];
@@ -204,12 +224,16 @@ __global__ __launch_bounds__(TW) void k_tracers(TrArgs a) {
                 const int i = b - j;
                 if (i < kts + 1) break;
                 const double Cim1 = Cl[j + 1] + M.dt * SH(i - 1);
+                const double C2i = Cl[j] + M.dt * SH(i);  // before SH(i) takes its shallow part
                 if (i < ks) {
                     // zi(i) - zi(i + 1), the interface heights as means of the layers around them
                     const double dz = 0.5 * (zl[j + 2] + zl[j + 1]) - 0.5 * (zl[j + 1] + zl[j]);
                     const double E = P.eps_sh * mu1 * dz, D = P.delta_sh * mu1 * dz;
-                    Cu = ((mu1 - D) * Cu + E * (Cl[j] + M.dt * SH(i))) / mu[j];
+                    double num = (mu1 - D) * Cu + E * C2i;
+                    if (pgf) num += a.pgf * mu1 * (C2i - C2bel);
+                    Cu = num / mu[j];
                 }
+                C2bel = C2i;
                 const double F = mu[j] * (Cu - Cim1);
                 SH(i) += (Fb - F) * GRAV / (pl[j] - pl[j + 1]);
                 Fb = F;
@@ -228,9 +252,33 @@ __global__ __launch_bounds__(TW) void k_tracers(TrArgs a) {
 
 extern "C" {
 
+namespace {
+int transport(conv_ctx_t *ctx, const conv_state_t *state, const conv_deep_out_t *dfwd,
+              const conv_shallow_out_t *sfwd, int32_t ntr, const double *tracers, double pgf,
+              double *tend, double *deep_tend, void *stream);
+}  // namespace
+
 int conv_tracer_transport(conv_ctx_t *ctx, const conv_state_t *state, const conv_deep_out_t *dfwd,
                           const conv_shallow_out_t *sfwd, int32_t ntr, const double *tracers,
                           double *tend, double *deep_tend, void *stream) {
+    return transport(ctx, state, dfwd, sfwd, ntr, tracers, 0.0, tend, deep_tend, stream);
+}
+
+int conv_momentum_transport(conv_ctx_t *ctx, const conv_state_t *state,
+                            const conv_deep_out_t *dfwd, const conv_shallow_out_t *sfwd,
+                            const double *wind, double c_pgf, double *tend, double *deep_tend,
+                            void *stream) {
+    if (!std::isfinite(c_pgf)) return CONV_EINVAL;
+    if (ctx && ctx->ncol > 0 && (!wind || !tend)) return CONV_EINVAL;
+    return transport(ctx, state, dfwd, sfwd, 2, wind, c_pgf, tend, deep_tend, stream);
+}
+
+}  // extern "C"
+
+namespace {
+int transport(conv_ctx_t *ctx, const conv_state_t *state, const conv_deep_out_t *dfwd,
+              const conv_shallow_out_t *sfwd, int32_t ntr, const double *tracers, double pgf,
+              double *tend, double *deep_tend, void *stream) {
     if (!ctx || !state || !dfwd || !sfwd || ntr < 0 || ntr > 65535) return CONV_EINVAL;
     if (ctx->ncol == 0) return CONV_OK;  // nothing to read or write: the arrays may be NULL
     if (!state->z || !state->p_int || state->ld < ctx->ncol || !(state->dt > 0.0)) return CONV_EINVAL;
@@ -241,6 +289,7 @@ int conv_tracer_transport(conv_ctx_t *ctx, const conv_state_t *state, const conv
     if (ctx->ncol == 0 || ntr == 0) return CONV_OK;
     TrArgs a;
     a.M = make_member(ctx->ncol, ctx->nlev, ctx->P, state, dfwd, sfwd, 0);
+    a.pgf = pgf;
     a.ntr = ntr;
     a.C = tracers;
     a.tend = tend;
@@ -265,5 +314,4 @@ int conv_tracer_transport(conv_ctx_t *ctx, const conv_state_t *state, const conv
     hipLaunchKernelGGL(k_tracers, dim3((unsigned)blocks), dim3(TW), lds, (hipStream_t)stream, a);
     return check_launch();
 }
-
-}  // extern "C"
+}  // namespace

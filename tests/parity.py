@@ -8,11 +8,13 @@ import numpy as np
 
 RTOL = 1e-9
 FLOOR = 1e-300
-# Absolute floor (on top of RTOL) for the CAPE of columns that do not trigger: CAPE (D4) is a
-# signed sum of buoyancy terms of up to ~1e3 J/kg, so a CAPE near zero carries the terms' absolute
-# rounding (different summation and contraction orders give ~1e-12 J/kg), not a relative one.
-# Triggered columns (CAPE above the threshold, tens of J/kg at least) keep the pure relative bar.
-ABS_FLOOR = {"cape": 1e-9}
+# Absolute floors (on top of RTOL) for scalars that are sums of buoyancy terms: each term carries
+# the absolute rounding of a difference of two virtual temperatures near 300 K (the saturated
+# parcel's root is exact only to its last bit), about 1e-12 J/kg per layer whatever the sum's
+# size, so a sum near zero cannot meet a relative bar.  CAPE (D4) gets the floor only where the
+# column does not trigger (triggered columns, CAPE above the threshold, keep the pure relative
+# bar); CIN (S5) gets it everywhere (its decision is made at cin_max = 100 J/kg, far above).
+ABS_FLOOR = {"cape": 1e-9, "cin": 1e-9}
 ABS_FLOOR_ONLY_UNTRIGGERED = ("cape",)
 
 DEEP_INT = ("klaunch", "ktop", "trig", "status")

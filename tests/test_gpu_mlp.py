@@ -81,6 +81,48 @@ def test_gemm_gelu_epilogue(torch, M, N, K):
     assert np.all(np.abs(ag - aref) <= 2.0 ** -7 * np.abs(aref) + 1e-30)
 
 
+@pytest.fixture(scope="module", params=[96, 512])
+def full_size_product(request):
+    """Operands of the full-size product on the 256 x 256 tile (M = 131,137, N = 512, K = 96 or
+    512) with its float64 reference and FP32-accumulation bound (computed once per K)."""
+    K = request.param
+    M, N = 131_137, 512
+    rng = np.random.default_rng(K + 5)
+    A = R.bf16(rng.standard_normal((M, K)).astype(np.float32)).astype(np.float64)
+    Bm = R.bf16((rng.standard_normal((N, K)) / np.sqrt(K)).astype(np.float32)).astype(np.float64)
+    bias = (0.1 * rng.standard_normal(N)).astype(np.float32)
+    ref = A @ Bm.T + bias
+    bound = 3e-5 * (np.abs(A) @ np.abs(Bm).T + np.abs(bias)) + 1e-30
+    return A, Bm, bias, ref, bound
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_gemm_full_size_on_the_large_tile(torch, full_size_product, mode):
+    """The 256 x 256 tile (eight wavefronts, operands loaded straight into swizzled LDS rows) runs
+    every hidden layer of the one-chunk inference: it is chosen when the product has at least
+    1,024 tiles (M >= 131,072 at N = 512).  M = 131,137 adds a ragged 65-row tail; K = 96 is the
+    input layer (one direct K tile and a zero-filled K tail), K = 512 a hidden layer.  Every
+    element against the float64 product: mode 0 (FP32 + bias) and mode 1's FP32 pre-activation at
+    the accumulation bound, mode 1's BF16 GELU output bit-equal on >= 99.9 % of the elements and
+    within one BF16 unit everywhere."""
+    A, Bm, bias, ref, bound = full_size_product
+    print(f"gemm {A.shape[0]} x {Bm.shape[0]} x {A.shape[1]} mode {mode}", flush=True)
+    a, b, bb = bf16_dev(torch, A), bf16_dev(torch, Bm), torch.from_numpy(bias).cuda()
+    if mode == 0:
+        c = _B().gemm_nt(a, b, bb, mode=0)
+        err = np.abs(c.cpu().numpy().astype(np.float64) - ref)
+        assert np.all(err <= bound), float((err / bound).max())
+        return
+    act, z = _B().gemm_nt(a, b, bb, mode=1, z=True)
+    zg = z.cpu().numpy().astype(np.float64)
+    err = np.abs(zg - ref)
+    assert np.all(err <= bound), float((err / bound).max())
+    ag = host_bf16(act)
+    aref = R.bf16(R.gelu(zg.astype(np.float32)).astype(np.float32)).astype(np.float64)
+    assert (ag == aref).mean() >= 0.999
+    assert np.all(np.abs(ag - aref) <= 2.0 ** -7 * np.abs(aref) + 1e-30)
+
+
 def _net(torch, batch, seed, widths=WIDTHS):
     B = _B()
     net = B.MLP(widths, max_batch=max(batch, 64))

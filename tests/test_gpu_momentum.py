@@ -1,0 +1,177 @@
+"""Convective momentum transport on the GPU (conv_momentum_transport, through the C ABI) against the
+oracle's transport (pinned on the CPU: passive transport at c_pgf = 0, uniform-wind and Galilean
+invariance, column momentum conservation, closed forms without entrainment).
+
+* element-wise parity (1e-9 of each column's largest tendency) at c_pgf = 0.7 (Gregory, Kershaw &
+  Inness 1997) and 1.0 on columns of the 1-degree grid where both schemes act, only one, and
+  neither, with padded arrays; the deep part alone too;
+* c_pgf = 0 gives conv_tracer_transport's bits for the two components;
+* the whole 1-degree grid against the oracle, and at every column of the 884,736-column grid the
+  properties that hold at any size (a uniform wind moves nothing, column momentum conserved, zeros
+  where nothing convects);
+* argument errors.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1711_00289_amd import soundings as S
+
+pytestmark = pytest.mark.gpu
+
+GRAV = 9.80616
+TOL = 1e-9
+FLOOR = 1e-290  # subnormal shallow base mass fluxes (see the tracer tests)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _B():
+    from paper_1711_00289_amd import binding
+
+    return binding
+
+
+def _np(x):
+    return x.detach().cpu().numpy()
+
+
+def _wind(L, n, seed):
+    rng = np.random.default_rng(seed)
+    base = np.linspace(25.0, -8.0, L)[:, None]
+    return np.stack([base + rng.normal(0.0, 4.0, (L, n)), -0.4 * base + rng.normal(0.0, 4.0, (L, n))])
+
+
+def _dev(torch, w, ld):
+    d = np.zeros((2, w.shape[1], ld))
+    d[:, :, :w.shape[2]] = w
+    return torch.as_tensor(d, device="cuda")
+
+
+def _check(got, want):
+    scale = np.abs(want).max(axis=1, keepdims=True)  # per component and column
+    bad = ~(np.abs(got - want) <= TOL * scale + FLOOR)
+    if bad.any():
+        t, k, j = np.argwhere(bad)[0]
+        raise AssertionError(f"{bad.sum()} elements; first at component {t} level {k} column {j}: "
+                             f"got {got[t, k, j]!r} want {want[t, k, j]!r}")
+
+
+@pytest.fixture(scope="module")
+def mixed(torch):
+    B = _B()
+    st = S.grid_1deg()
+    od, osh = oracle.step(st, threads=8, chunk=16)
+    rng = np.random.default_rng(17)
+    deep = np.nonzero(od["status"] == 0)[0]
+    shallow = np.nonzero(osh["status"] == 0)[0]
+    quiet = np.nonzero((od["status"] != 0) & (osh["status"] != 0))[0]
+    cols = np.unique(np.concatenate([shallow, rng.choice(deep, 700, replace=False),
+                                     rng.choice(quiet, 300, replace=False)]))
+    sub = S.subset(st, cols)
+    n, L = sub["ncol"], sub["nlev"]
+    ld = n + 29
+    pad = {}
+    for k, v in sub.items():
+        if isinstance(v, np.ndarray) and v.shape[-1] == n:
+            pad[k] = np.ascontiguousarray(np.concatenate([v, np.repeat(v[..., :1], ld - n, -1)], -1))
+        else:
+            pad[k] = v
+    dev = B.to_device(pad)
+    conv = B.Conv(n, L)
+    d, s = conv.step(dev)
+    return dict(st=sub, dev=dev, conv=conv, deep=d, sh=s, n=n, L=L, ld=ld)
+
+
+@pytest.mark.parametrize("cpgf", [0.7, 1.0])
+def test_parity_with_the_oracle(torch, mixed, cpgf):
+    n, L, ld = mixed["n"], mixed["L"], mixed["ld"]
+    print(f"momentum parity, {n} columns, c_pgf {cpgf}", flush=True)
+    w = _wind(L, n, 5)
+    tend, dpart = mixed["conv"].momentum_transport(mixed["dev"], mixed["deep"], mixed["sh"],
+                                                   _dev(torch, w, ld), c_pgf=cpgf, deep_part=True)
+    torch.cuda.synchronize()
+    want, want_d = oracle.momentum(mixed["st"], w, cpgf=cpgf)
+    _check(_np(tend)[:, :, :n], want)
+    _check(_np(dpart)[:, :, :n], want_d)
+    ds, ss = _np(mixed["deep"]["status"])[:n], _np(mixed["sh"]["status"])[:n]
+    quiet = (ds != 0) & (ss != 0)
+    assert (ds == 0).sum() > 500 and (ss == 0).sum() > 100 and quiet.sum() > 100
+    assert np.all(_np(tend)[:, :, :n][:, :, quiet] == 0.0)
+
+
+def test_zero_coefficient_gives_the_tracer_bits(torch, mixed):
+    n, L, ld = mixed["n"], mixed["L"], mixed["ld"]
+    wd = _dev(torch, _wind(L, n, 6), ld)
+    args = (mixed["dev"], mixed["deep"], mixed["sh"], wd)
+    tm, dm = mixed["conv"].momentum_transport(*args, c_pgf=0.0, deep_part=True)
+    tt, dt = mixed["conv"].tracer_transport(*args, deep_part=True)
+    torch.cuda.synchronize()
+    assert torch.equal(tm[:, :, :n], tt[:, :, :n]) and torch.equal(dm[:, :, :n], dt[:, :, :n])
+
+
+def test_whole_one_degree_grid(torch):
+    B = _B()
+    st = S.grid_1deg()
+    n, L = st["ncol"], st["nlev"]
+    dev = B.to_device(st)
+    conv = B.Conv(n, L)
+    d, s = conv.step(dev)
+    w = _wind(L, n, 7)
+    tend = conv.momentum_transport(dev, d, s, _dev(torch, w, n), c_pgf=0.7)
+    torch.cuda.synchronize()
+    want, _ = oracle.momentum(st, w, cpgf=0.7)
+    _check(_np(tend), want)
+
+
+def test_quarter_degree_grid_properties(torch):
+    """The 884,736-column grid: a uniform wind moves nothing; a sheared one conserves every
+    column's momentum; quiet columns get zeros."""
+    B = _B()
+    st = S.grid_quarter_deg()
+    n, L = st["ncol"], st["nlev"]
+    dev = B.to_device(st)
+    conv = B.Conv(n, L)
+    d, s = conv.step(dev)
+    base = torch.linspace(25.0, -8.0, L, dtype=torch.float64, device="cuda")[:, None]
+    g = torch.Generator(device="cuda").manual_seed(8)
+    w = torch.stack([base + 4.0 * torch.randn(L, n, generator=g, dtype=torch.float64, device="cuda"),
+                     -0.4 * base + 4.0 * torch.randn(L, n, generator=g, dtype=torch.float64,
+                                                     device="cuda")])
+    tend = conv.momentum_transport(dev, d, s, w, c_pgf=0.7)
+    uni = torch.empty_like(w)
+    uni[0].fill_(7.0)
+    uni[1].fill_(-3.0)
+    t0 = conv.momentum_transport(dev, d, s, uni, c_pgf=0.7)
+    dp = torch.diff(torch.as_tensor(st["p_int"], device="cuda"), dim=0)
+    col = (tend * dp / GRAV).sum(1)
+    mag = (tend.abs() * dp / GRAV).sum(1) + 1e-300
+    torch.cuda.synchronize()
+    scale = float(tend.abs().max())
+    assert float(t0.abs().max()) <= 1e-12 * scale
+    assert float((col.abs() / mag).max()) < 1e-12
+    act = (d["status"] == 0) | (s["status"] == 0)
+    assert bool((tend[:, :, ~act] == 0).all())
+
+
+def test_argument_errors(torch, mixed):
+    import ctypes as C
+
+    B = _B()
+    L = B.lib()
+    conv = mixed["conv"]
+    st = conv._state(mixed["dev"])
+    dd, hh = conv._deep_struct(mixed["deep"]), conv._shallow_struct(mixed["sh"])
+    out = torch.empty(2, mixed["L"], mixed["ld"], dtype=torch.float64, device="cuda")
+    assert L.conv_momentum_transport(conv.h, C.byref(st), C.byref(dd), C.byref(hh), None, 0.7,
+                                     out.data_ptr(), None, None) == B.CONV_EINVAL
+    assert L.conv_momentum_transport(conv.h, C.byref(st), C.byref(dd), C.byref(hh),
+                                     out.data_ptr(), float("nan"), out.data_ptr(), None,
+                                     None) == B.CONV_EINVAL
