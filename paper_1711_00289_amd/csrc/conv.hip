@@ -491,15 +491,24 @@ __global__ __launch_bounds__(WAVE) void k_deep_plume(Src src, Work w) {
             SCR(D_QD, kd + 1) = qd;
             E1 = qd - qkd;
             SCR(D_E1, kd) = E1;
-            // Loads are unconditional (indices clamped) so the wait counts stay exact.
-            int k = kd + 1;
-            double Tn = AT(M.T, k), qn = AT(M.q, k), zn = AT(M.z, min(k + 1, kb)), pn = AT(M.pi, k + 1);
-            for (; k <= kb - 1; ++k) {
-                const double Tk = Tn, qk = qn, zk = zb, zbelow = zn, pbel = pn;
-                Tn = AT(M.T, min(k + 1, kb));
-                qn = AT(M.q, min(k + 1, kb));
-                zn = AT(M.z, min(k + 2, kb));
-                pn = AT(M.pi, min(k + 2, kb + 1));
+            // Layer k needs T, q of layer k, the height of layer k+1 and the pressure of its
+            // bottom interface.  Two level buffers: the loads of layer k+2 are issued while layer
+            // k is worked on (indices clamped, so every load is in range and the wait counts stay
+            // exact; values past the base are not used).
+            struct DdLev {
+                double T, q, zbel, pbel;
+            };
+            auto ddload = [&](int k) {
+                DdLev v;
+                const int kk = min(k, kb);
+                v.T = AT(M.T, kk);
+                v.q = AT(M.q, kk);
+                v.zbel = AT(M.z, min(k + 1, kb));
+                v.pbel = AT(M.pi, min(k + 1, kb + 1));
+                return v;
+            };
+            auto ddlevel = [&](const DdLev &v, int k) {
+                const double Tk = v.T, qk = v.q, zk = zb, zbelow = v.zbel, pbel = v.pbel;
                 zb = zbelow;
                 const double hk = (CP * Tk + GRAV * zk + phis) + LV * qk;
                 const double zlow = 0.5 * (zk + zbelow);
@@ -517,6 +526,14 @@ __global__ __launch_bounds__(WAVE) void k_deep_plume(Src src, Work w) {
                 ad = adn;
                 qd = s.qs;
                 zii = zlow;
+            };
+            DdLev d0 = ddload(kd + 1), d1 = ddload(kd + 2);
+            for (int k = kd + 1; k <= kb - 1; k += 2) {
+                ddlevel(d0, k);
+                d0 = ddload(k + 2);
+                if (k + 1 > kb - 1) break;
+                ddlevel(d1, k + 1);
+                d1 = ddload(k + 3);
             }
         }
 
@@ -566,16 +583,25 @@ __global__ __launch_bounds__(WAVE) void k_deep_plume(Src src, Work w) {
                 Fs_b = Fs;
                 Fq_b = Fq;
             };
-            int k = kb - 1;
-            double Tn = AT(M.T, k), qn = AT(M.q, k), zn = zup, zn2 = AT(M.z, max(k - 1, 0)),
-                   pn = AT(M.pi, k);
-            for (; k >= kt + 1; --k) {
-                const double Tk = Tn, qk = qn, zkk = zn, zabove = zn2, pik = pn;
-                Tn = AT(M.T, k - 1);
-                qn = AT(M.q, k - 1);
-                zn = zabove;
-                zn2 = AT(M.z, max(k - 2, 0));
-                pn = AT(M.pi, k - 1);
+            // Layer k needs T, q and the top-interface pressure of layer k and the height of the
+            // layer above.  Two level buffers: the loads of layer k-2 are issued while layer k is
+            // worked on (indices clamped at 0; values past the top are not used).
+            struct UpLev {
+                double T, q, zab, p;
+            };
+            auto upload = [&](int k) {
+                UpLev v;
+                const int kk = max(k, 0);
+                v.T = AT(M.T, kk);
+                v.q = AT(M.q, kk);
+                v.zab = AT(M.z, max(k - 1, 0));
+                v.p = AT(M.pi, kk);
+                return v;
+            };
+            double zcur = zup;  // height of the layer being worked on
+            auto uplevel = [&](const UpLev &v, int k) {
+                const double Tk = v.T, qk = v.q, zkk = zcur, zabove = v.zab, pik = v.p;
+                zcur = zabove;
                 finish(k, Tk, qk, zkk);
                 const double zk = 0.5 * (zabove + zkk);
                 const double hkk = (CP * Tk + GRAV * zkk + phis) + LV * qk;
@@ -601,11 +627,25 @@ __global__ __launch_bounds__(WAVE) void k_deep_plume(Src src, Work w) {
                 e_q = qk;
                 p_bot = p_top;
                 p_top = pik;
+            };
+            UpLev u0 = upload(kb - 1), u1 = upload(kb - 2);
+            bool top_in_u1 = false;  // which buffer holds layer kt when the sweep ends
+            for (int k = kb - 1; k >= kt + 1; k -= 2) {
+                uplevel(u0, k);
+                u0 = upload(k - 2);
+                if (k - 1 < kt + 1) {
+                    top_in_u1 = true;
+                    break;
+                }
+                uplevel(u1, k - 1);
+                u1 = upload(k - 3);
             }
+            const double tT = top_in_u1 ? u1.T : u0.T, tq = top_in_u1 ? u1.q : u0.q,
+                         tp = top_in_u1 ? u1.p : u0.p;
             // Interface kt+1 and layer kt+1 with layer kt's environment (loaded ahead), then the
             // top layer kt, whose upper flux is zero and which has no source.
-            finish(kt, Tn, qn, zn);
-            layer(kt, 0.0, 0.0, Fs_b, Fq_b, 0.0, Tn, qn, pn, p_top);
+            finish(kt, tT, tq, zcur);
+            layer(kt, 0.0, 0.0, Fs_b, Fq_b, 0.0, tT, tq, tp, p_top);
         }
 
         // D6 strength, then D7 for the downdraft region: layers kd .. kb.
@@ -638,11 +678,9 @@ __global__ __launch_bounds__(WAVE) void k_deep_plume(Src src, Work w) {
                 v.e1 = SCR(D_E1, kk);
                 return v;
             };
-            DLev nx = dload(kd);
-            for (int k = kd; k <= kb; ++k) {
+            // Two level buffers: the loads of layer k+2 are in flight while layer k is computed.
+            auto dlevel = [&](const DLev &v, int k) {
                 const int i = k + 1;  // the layer's bottom interface
-                const DLev v = nx;
-                nx = dload(k + 1);
                 const double Tb = v.Tb, qb = v.qb, zbl = v.zb, pb = v.pb;
                 double Fs = 0.0, Fq = 0.0;
                 if (i <= kb) {
@@ -662,6 +700,14 @@ __global__ __launch_bounds__(WAVE) void k_deep_plume(Src src, Work w) {
                 qk = qb;
                 zk = zbl;
                 pt = pb;
+            };
+            DLev v0 = dload(kd), v1 = dload(kd + 1);
+            for (int k = kd; k <= kb; k += 2) {
+                dlevel(v0, k);
+                v0 = dload(k + 2);
+                if (k + 1 > kb) break;
+                dlevel(v1, k + 1);
+                v1 = dload(k + 3);
             }
         }
 
