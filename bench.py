@@ -402,6 +402,38 @@ def bench_gemm(torch, B, reps, warmup):
     return res
 
 
+def bench_infer_only(torch, B, reps, warmup):
+    """Surrogate inference alone on the 884,736-column grid with a randomly initialised network
+    (no training): time per call and the rate against the BF16 MFMA peak."""
+    from paper_1711_00289_amd import soundings as S
+    from paper_1711_00289_amd import surrogate as SG
+
+    st = S.grid_quarter_deg(NLEV)
+    n = st["ncol"]
+    dev = B.to_device(st)
+    net = B.MLP(SG.WIDTHS, max_batch=n, max_train_batch=4096)
+    net.set_params(SG.init_params(torch, 1).cuda())
+    f32 = lambda v: torch.tensor(v, dtype=torch.float32, device="cuda")
+    norms = (f32(np.r_[np.full(NLEV, 250.0), np.full(NLEV, 5e-3), np.full(NLEV, 5e4),
+                       np.zeros(SG.WIDTHS[0] - 3 * NLEV)]),
+             f32(np.r_[np.full(NLEV, 20.0), np.full(NLEV, 5e-3), np.full(NLEV, 3e4),
+                       np.ones(SG.WIDTHS[0] - 3 * NLEV)]),
+             f32(np.zeros(SG.WIDTHS[-1])),
+             f32(np.r_[np.full(NLEV, 1e-4), np.full(NLEV, 1e-7), [1e-4],
+                       np.ones(SG.WIDTHS[-1] - 2 * NLEV - 1)]))
+    sur = SG.Surrogate(net, norms, (-1.0, 1.0), n, n)
+    out = tuple([torch.empty(NLEV, n, dtype=torch.float64, device="cuda") for _ in range(2)] +
+                [torch.empty(n, dtype=torch.float64, device="cuda")])
+    for _ in range(max(1, warmup)):
+        sur.infer(dev, n, fallback=False, out=out)
+    ms = time_events(torch, lambda: sur.infer(dev, n, fallback=False, out=out), reps)
+    flop = 2 * sum(SG.WIDTHS[i] * SG.WIDTHS[i + 1] for i in range(len(SG.WIDTHS) - 1)) * n
+    tf = flop / (ms * 1e-3) / 1e12
+    return {"workload": f"surrogate inference, MLP {SG.WIDTHS} (random weights), 884,736 "
+                        f"columns in one call", "ms": ms, "TFLOPs": tf,
+            "mfma_frac": tf / 2500.0}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -419,6 +451,9 @@ def main():
     ap.add_argument("--gemm-only", action="store_true",
                     help="time only the surrogate's GEMM kernel (mlp_gemm_nt, bias + GELU) on "
                          "131,072 and 884,736 x 512 x 512 and exit")
+    ap.add_argument("--infer-only", action="store_true",
+                    help="time only the surrogate's inference (random network, no training) on "
+                         "the 884,736-column grid and exit")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after timing, copy a MIB-MiB device buffer once (a plain copy kernel of "
                          "known size for scaling hardware byte counters)")
@@ -435,6 +470,9 @@ def main():
 
     if args.gemm_only:
         print(json.dumps(bench_gemm(torch, B, args.steps, args.warmup)), flush=True)
+        return
+    if args.infer_only:
+        print(json.dumps(bench_infer_only(torch, B, args.steps, args.warmup)), flush=True)
         return
 
     t0 = time.perf_counter()

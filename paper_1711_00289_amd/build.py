@@ -9,7 +9,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libconv.so")
 SOURCES = ["conv.hip", "conv_adjoint.hip", "conv_tracers.hip", "mlp.hip", "surrogate.hip"]
-HEADERS = ["conv_physics.hpp", "conv_internal.hpp"]
+HEADERS = ["conv_physics.hpp", "conv_internal.hpp", "mlp_internal.hpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -27,6 +27,7 @@
 #include <vector>
 
 #include "mlp.h"
+#include "mlp_internal.hpp"
 
 namespace {
 
@@ -727,6 +728,22 @@ int refresh_bf16(mlp *m, hipStream_t st) {
 }
 
 }  // namespace
+
+namespace mlpk {
+
+NetView net_view(const mlp_t *mc) {
+    mlp *m = const_cast<mlp *>(mc);
+    NetView v{};
+    v.n = m->n;
+    for (int i = 0; i <= m->n; ++i) v.w[i] = m->w[i];
+    for (int i = 0; i < m->n; ++i) {
+        v.wb[i] = hp(m, m->lay.wb[i]);
+        v.bias[i] = fp(m, m->lay.params) + m->lay.poff[i] + (int64_t)m->w[i + 1] * m->w[i];
+    }
+    return v;
+}
+
+}  // namespace mlpk
 
 extern "C" {
 

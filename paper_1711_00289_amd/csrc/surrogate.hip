@@ -15,6 +15,7 @@
 #include "conv.h"
 #include "conv_internal.hpp"
 #include "mlp.h"
+#include "mlp_internal.hpp"
 #include "surrogate.h"
 
 using namespace cvk;
@@ -252,6 +253,263 @@ __global__ __launch_bounds__(TB) void k_unpack(const float *y, int L, int64_t nc
     }
 }
 
+// ------------------------------------------------------------------ fused inference
+// The whole network for a tile of FR columns in one persistent block: the columns' features are
+// packed (normalised, BF16) into an LDS activation tile [FR][FROW], every layer's product runs on
+// the matrix cores (v_mfma_f32_32x32x16_bf16, FP32 accumulation) with its activations read from
+// and written back to that tile, and the output layer is un-normalised and stored level-major with
+// the fallback test.  No activation leaves the chip (the layer-by-layer path moves about 7 GB of
+// them through HBM for the 884,736-column grid).  Hidden layers: wavefront w computes all FR rows
+// of output columns [64 w, 64 w + 64), reading its weight rows straight from global memory (the
+// network's 1.7 MB of BF16 weights stay in every XCD's L2); the output layer gives each wavefront
+// one 32 x 32 tile.  Products accumulate K in steps of 16 in increasing order from zero, the bias
+// is added in FP32, GELU and the BF16 rounding are those of the layer-by-layer kernels, so the
+// results are the same bits.
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
+
+constexpr int FR = 128;           // columns (network rows) per tile
+constexpr int FH = 512;           // hidden width
+constexpr int FROW = FH + 8;      // BF16 per LDS row: the 16-byte pad puts the 32 rows a fragment
+                                  // read serves on distinct 16-byte bank groups
+constexpr int FWAVES = 8;
+constexpr int FT = FWAVES * 64;
+constexpr int FOUT = 64;          // output width
+constexpr int RING = 2;           // k-steps of weight fragments in flight
+constexpr int YS = FOUT + 1;      // floats per row of the output staging tile
+constexpr size_t FUSED_LDS = (size_t)FR * FROW * sizeof(uint16_t);
+
+struct FusedArgs {
+    const double *T, *q, *pm;
+    int64_t ld;
+    int L;
+    int64_t ncol, ntiles;
+    int nl, w_in;                 // layers, input width
+    const uint16_t *W[MLP_MAX_LAYERS];  // fragment-major BF16 weights (k_frag_pack)
+    const float *B[MLP_MAX_LAYERS];
+    const float *in_mean, *in_std, *out_mean, *out_std;
+    double lo, hi;
+    double *dTdt, *dqdt, *prec;   // level-major outputs with leading dimension ld
+    int *list, *cnt;
+};
+
+// Layer l's weights and bias (a wavefront-uniform selection among the kernel argument's entries,
+// so the argument block is not copied to private memory for indexing).
+__device__ __forceinline__ const uint16_t *layer_w(const FusedArgs &a, int l) {
+    const uint16_t *p = a.W[0];
+#pragma unroll
+    for (int i = 1; i < MLP_MAX_LAYERS; ++i) p = l == i ? a.W[i] : p;
+    return p;
+}
+__device__ __forceinline__ const float *layer_b(const FusedArgs &a, int l) {
+    const float *p = a.B[0];
+#pragma unroll
+    for (int i = 1; i < MLP_MAX_LAYERS; ++i) p = l == i ? a.B[i] : p;
+    return p;
+}
+
+// erfc by the Chebyshev-fitted form of Press et al., Numerical Recipes (erfcc) and GELU from it:
+// the same FP32 operations as the layer-by-layer kernels' epilogue.
+__device__ __forceinline__ float f_erfc(float x) {
+    const float ax = fabsf(x);
+    const float t = __builtin_amdgcn_rcpf(1.0f + 0.5f * ax);
+    float p = 0.17087277f;
+    p = fmaf(p, t, -0.82215223f);
+    p = fmaf(p, t, 1.48851587f);
+    p = fmaf(p, t, -1.13520398f);
+    p = fmaf(p, t, 0.27886807f);
+    p = fmaf(p, t, -0.18628806f);
+    p = fmaf(p, t, 0.09678418f);
+    p = fmaf(p, t, 0.37409196f);
+    p = fmaf(p, t, 1.00002368f);
+    p = fmaf(p, t, -1.26551223f);
+    const float r = t * __expf(fmaf(-ax, ax, p));
+    return x >= 0.0f ? r : 2.0f - r;
+}
+__device__ __forceinline__ float f_gelu(float z) {
+    return 0.5f * z * f_erfc(-z * 0.70710678118654752f);
+}
+
+__global__ __launch_bounds__(FT, 1) void k_surr_fused(FusedArgs a) {
+    extern __shared__ uint16_t act[];  // [FR][FROW]; the output staging reuses it as float [FR][YS]
+    const int tid = threadIdx.x;
+    const int w = tid / 64, lane = tid % 64;
+    const int lrow = lane & 31, lk = 8 * (lane >> 5);
+    const int L = a.L;
+    const int64_t ld = a.ld;
+    for (int64_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+        const int64_t c0 = tile * FR;
+        const int nrows = (int)(a.ncol - c0 < FR ? a.ncol - c0 : FR);
+
+        // Pack: feature f of column c0 + r at act[r][f]; loads along the columns are contiguous;
+        // 8 in flight per thread.  Features past 3L (padding) and rows past the grid are zero.
+        constexpr int PU = 8;
+        const int nf = a.w_in * FR;
+        for (int i0 = tid; i0 < nf; i0 += FT * PU) {
+            double d[PU];
+#pragma unroll
+            for (int u = 0; u < PU; ++u) {
+                const int i = i0 + u * FT;
+                const int f = i / FR, r = i % FR;
+                d[u] = 0.0;
+                if (i < nf && r < nrows && f < 3 * L) {
+                    const double *src = f < L       ? a.T + (int64_t)f * ld
+                                        : f < 2 * L ? a.q + (int64_t)(f - L) * ld
+                                                    : a.pm + (int64_t)(f - 2 * L) * ld;
+                    d[u] = __builtin_nontemporal_load(&src[c0 + r]);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < PU; ++u) {
+                const int i = i0 + u * FT;
+                if (i >= nf) break;
+                const int f = i / FR, r = i % FR;
+                float v = 0.0f;
+                if (r < nrows && f < 3 * L) v = ((float)d[u] - a.in_mean[f]) / a.in_std[f];
+                act[r * FROW + f] = f2bf(v);
+            }
+        }
+        __syncthreads();
+
+        // Hidden layers: act (K wide) -> GELU(act . W^T + b) (512 wide), in place.
+        for (int l = 0; l + 1 < a.nl; ++l) {
+            const int K = l == 0 ? a.w_in : FH;
+            const uint16_t *Wl = layer_w(a, l);
+            const int n0 = 64 * w;
+            f32x16 acc[4][2];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+            // Fragment-major weights: the fragment of n-tile t at k-step s is 64 lanes x 16
+            // contiguous bytes, so each load is one contiguous 1 KB read.  Fragments of RING
+            // k-steps are in flight while one is multiplied: the loads for step s + RING go out
+            // right after step s's products, into the slot step s used.
+            const int nst = K / 16;
+            const uint16_t *wrow0 = Wl + ((int64_t)(2 * w) * nst * 64 + lane) * 8;
+            const uint16_t *wrow1 = Wl + ((int64_t)(2 * w + 1) * nst * 64 + lane) * 8;
+            bf16x8 bq0[RING], bq1[RING];
+#pragma unroll
+            for (int j = 0; j < RING; ++j) {
+                if (j < nst) {
+                    bq0[j] = *(const bf16x8 *)(wrow0 + 512 * j);
+                    bq1[j] = *(const bf16x8 *)(wrow1 + 512 * j);
+                }
+            }
+#pragma unroll 1
+            for (int s0 = 0; s0 < nst; s0 += RING) {
+#pragma unroll
+                for (int j = 0; j < RING; ++j) {
+                    const int st = s0 + j;
+                    if (st >= nst) break;
+                    const int ks = 16 * st;
+                    bf16x8 af[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        af[i] = *(const bf16x8 *)&act[(32 * i + lrow) * FROW + ks + lk];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        acc[i][0] =
+                            __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[i], bq0[j], acc[i][0], 0, 0, 0);
+                        acc[i][1] =
+                            __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[i], bq1[j], acc[i][1], 0, 0, 0);
+                    }
+                    if (st + RING < nst) {
+                        bq0[j] = *(const bf16x8 *)(wrow0 + 512 * (st + RING));
+                        bq1[j] = *(const bf16x8 *)(wrow1 + 512 * (st + RING));
+                    }
+                }
+            }
+            __syncthreads();  // every wavefront has read its inputs
+            // Accumulator layout of a 32x32 tile: register r of lane l holds row
+            // 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32.
+            const float *Bl = layer_b(a, l);
+            const float bias0 = Bl[n0 + lrow], bias1 = Bl[n0 + 32 + lrow];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int row = 32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                    act[row * FROW + n0 + lrow] = f2bf(f_gelu(acc[i][0][r] + bias0));
+                    act[row * FROW + n0 + 32 + lrow] = f2bf(f_gelu(acc[i][1][r] + bias1));
+                }
+            __syncthreads();
+        }
+
+        // Output layer: wavefront w computes rows 32 (w % 4) .., columns 32 (w / 4) ..; then
+        // y * scale + mean per output, staged as float [FR][YS].
+        {
+            const int l = a.nl - 1;
+            const int mt = w % 4, nt = w / 4;
+            constexpr int NST = FH / 16;
+            const uint16_t *wrow = layer_w(a, l) + ((int64_t)nt * NST * 64 + lane) * 8;
+            f32x16 acc;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+            bf16x8 bq[RING];
+#pragma unroll
+            for (int j = 0; j < RING; ++j) bq[j] = *(const bf16x8 *)(wrow + 512 * j);
+#pragma unroll 1
+            for (int s0 = 0; s0 < NST; s0 += RING) {
+#pragma unroll
+                for (int j = 0; j < RING; ++j) {
+                    const int st = s0 + j;
+                    if (st >= NST) break;
+                    const int ks = 16 * st;
+                    const bf16x8 af = *(const bf16x8 *)&act[(32 * mt + lrow) * FROW + ks + lk];
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af, bq[j], acc, 0, 0, 0);
+                    if (st + RING < NST) bq[j] = *(const bf16x8 *)(wrow + 512 * (st + RING));
+                }
+            }
+            __syncthreads();
+            float *ys = (float *)act;
+            const int col = 32 * nt + lrow;
+            const float bias = layer_b(a, l)[col], sd = a.out_std[col], mn = a.out_mean[col];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int row = 32 * mt + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                const float y = acc[r] + bias;
+                ys[row * YS + col] = y * sd + mn;
+            }
+            __syncthreads();
+            // Level-major stores: 2L profiles of FR consecutive columns (written once).
+            for (int i = tid; i < 2 * L * FR; i += FT) {
+                const int f = i / FR, r = i % FR;
+                if (r >= nrows) continue;
+                const double v = (double)ys[r * YS + f];
+                if (f < L) __builtin_nontemporal_store(v, &a.dTdt[(int64_t)f * ld + c0 + r]);
+                else __builtin_nontemporal_store(v, &a.dqdt[(int64_t)(f - L) * ld + c0 + r]);
+            }
+            if (tid < FR) {
+                const bool live = tid < nrows;
+                const double p = live ? (double)ys[tid * YS + 2 * L] : 0.0;
+                if (live) a.prec[c0 + tid] = p > 0.0 ? p : 0.0;
+                const bool fb = live && (p < a.lo || p > a.hi);
+                const int slot = wave_append(fb, a.cnt);
+                if (slot >= 0) a.list[slot] = (int)(c0 + tid);
+            }
+            __syncthreads();  // the staging tile is read before the next tile's packing
+        }
+    }
+}
+
+// Fragment-major copy of one layer's BF16 weights W [N][K] for the fused kernel: the fragment of
+// n-tile t (32 output columns) at k-step s (16 inputs) is the MFMA operand as the 64 lanes hold it
+// (lane i: row 32 t + i % 32, inputs 16 s + 8 (i / 32) .. + 7), stored as 64 consecutive 16-byte
+// pieces at ((t * K / 16 + s) * 64 + i) * 8.
+__global__ __launch_bounds__(TB) void k_frag_pack(const uint16_t *W, int N, int K, uint16_t *dst) {
+    const int64_t g = (int64_t)blockIdx.x * TB + threadIdx.x;
+    const int S = K / 16;
+    if (g >= (int64_t)(N / 32) * S * 64) return;
+    const int i = (int)(g % 64);
+    const int64_t ts = g / 64;
+    const int t = (int)(ts / S), st = (int)(ts % S);
+    const uint16_t *src = W + (int64_t)(32 * t + i % 32) * K + 16 * st + 8 * (i / 32);
+    *(uint4 *)(dst + g * 8) = *(const uint4 *)src;
+}
+
 struct Compact {
     double *T, *q, *pm, *z, *pi, *phis, *pblh, *tke;
     int64_t ld;
@@ -315,8 +573,18 @@ int lds_limit(const void *fn, size_t bytes) {
 }
 size_t al(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Networks the fused inference kernel handles: hidden layers of width FH, an input of at most FH
+// features (a multiple of 16) holding the 3L packed features, an output of FOUT holding 2L + 1.
+bool fused_ok(const mlpk::NetView &v, int L) {
+    if (v.n < 2 || v.w[0] % 16 != 0 || v.w[0] > FH || v.w[0] < 3 * L) return false;
+    if (v.w[v.n] != FOUT || 2 * L + 1 > FOUT) return false;
+    for (int i = 1; i < v.n; ++i)
+        if (v.w[i] != FH) return false;
+    return true;
+}
+
 struct SLayout {
-    size_t x, y, norm, list, cnt, cst, dout, sout, cws, total;
+    size_t x, y, norm, list, cnt, wfrag, cst, dout, sout, cws, total;
     size_t cws_bytes;
 };
 
@@ -334,6 +602,7 @@ SLayout surr_layout(int L, int w_in, int w_out, int64_t maxc, int64_t chunk, int
     l.norm = take((size_t)2 * (w_in + w_out) * 4);
     l.list = take(m * 4);
     l.cnt = take(256);
+    l.wfrag = take((size_t)MLP_MAX_LAYERS * FH * FH * sizeof(uint16_t));
     l.cst = take(((size_t)4 * L + (L + 1) + 3) * m * 8);
     l.dout = take(((size_t)2 * L + 2 * (L + 1) + 2) * m * 8 + 4 * m * 4);
     l.sout = take(((size_t)2 * L + (L + 1) + 2) * m * 8 + 3 * m * 4);
@@ -525,7 +794,44 @@ int surr_infer(surr_t *s, const conv_state_t *state, int64_t ncol, double *dTdt,
         lds_limit((const void *)k_unpack, unpack_lds(L)) != CONV_OK)
         return CONV_EHIP;
     hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, cnt);
-    for (int64_t c0 = 0; c0 < ncol; c0 += s->chunk) {
+    const mlpk::NetView nv = mlpk::net_view(s->net);
+    if (fused_ok(nv, L)) {
+        // The whole network per tile on the chip: one launch for every column, no chunks.
+        if (lds_limit((const void *)k_surr_fused, FUSED_LDS) != CONV_OK) return CONV_EHIP;
+        FusedArgs fa{};
+        fa.T = state->T;
+        fa.q = state->q;
+        fa.pm = state->p_mid;
+        fa.ld = ld;
+        fa.L = L;
+        fa.ncol = ncol;
+        fa.ntiles = (ncol + FR - 1) / FR;
+        fa.nl = nv.n;
+        fa.w_in = nv.w[0];
+        uint16_t *wf = (uint16_t *)(s->ws + s->lay.wfrag);
+        for (int i = 0; i < nv.n; ++i) {
+            const int64_t cnt_i = (int64_t)nv.w[i + 1] * nv.w[i];
+            hipLaunchKernelGGL(k_frag_pack, dim3((unsigned)nb(cnt_i / 8, TB)), dim3(TB), 0, st,
+                               nv.wb[i], nv.w[i + 1], nv.w[i], wf);
+            fa.W[i] = wf;
+            fa.B[i] = nv.bias[i];
+            wf += cnt_i;
+        }
+        fa.in_mean = nrm(s, 0);
+        fa.in_std = nrm(s, 1);
+        fa.out_mean = nrm(s, 2);
+        fa.out_std = nrm(s, 3);
+        fa.lo = s->lo;
+        fa.hi = s->hi;
+        fa.dTdt = dTdt;
+        fa.dqdt = dqdt;
+        fa.prec = prec;
+        fa.list = list;
+        fa.cnt = cnt;
+        const int64_t grid = fa.ntiles < device_cus() ? fa.ntiles : device_cus();
+        hipLaunchKernelGGL(k_surr_fused, dim3((unsigned)grid), dim3(FT), FUSED_LDS, st, fa);
+    }
+    for (int64_t c0 = 0; c0 < ncol && !fused_ok(nv, L); c0 += s->chunk) {
         const int64_t n = ncol - c0 < s->chunk ? ncol - c0 : s->chunk;
         StateArgs a{state->T + c0, state->q + c0, state->p_mid + c0, ld};
         hipLaunchKernelGGL(k_pack_in, dim3(nb(n, TC)), dim3(TB), pack_lds(s->w_in), st, a, L, n,
