@@ -429,9 +429,14 @@ def bench_infer_only(torch, B, reps, warmup):
     ms = time_events(torch, lambda: sur.infer(dev, n, fallback=False, out=out), reps)
     flop = 2 * sum(SG.WIDTHS[i] * SG.WIDTHS[i + 1] for i in range(len(SG.WIDTHS) - 1)) * n
     tf = flop / (ms * 1e-3) / 1e12
+    # the layer-by-layer path (mlp_forward on the whole grid as one batch) for comparison
+    sur.set_fused(False)
+    sur.infer(dev, n, fallback=False, out=out)
+    ms_lay = time_events(torch, lambda: sur.infer(dev, n, fallback=False, out=out), reps)
+    sur.set_fused(True)
     return {"workload": f"surrogate inference, MLP {SG.WIDTHS} (random weights), 884,736 "
                         f"columns in one call", "ms": ms, "TFLOPs": tf,
-            "mfma_frac": tf / 2500.0}
+            "mfma_frac": tf / 2500.0, "layer_by_layer_ms": ms_lay}
 
 
 def main():

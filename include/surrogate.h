@@ -71,6 +71,14 @@ void surr_destroy(surr_t *s);
 int surr_set_norm(surr_t *s, const float *in_mean, const float *in_std, const float *out_mean,
                   const float *out_std, double prec_lo, double prec_hi, void *stream);
 
+/* Inference path.  With enable != 0 (the default) a network of hidden width 512, an input width
+ * from 64 to 512 that is a multiple of 32 and an output width of 64 runs as one fused kernel (every
+ * layer of a 64-column tile on the chip, activations in LDS, no chunks); with enable == 0, and for
+ * other networks, inference goes layer by layer through mlp_forward in batches of `chunk` columns.
+ * Both give the same bits.  Returns 1 when the next surr_infer takes the fused kernel, 0 when not,
+ * CONV_EINVAL for a NULL handle. */
+int surr_set_fused(surr_t *s, int enable);
+
 /* Total tendencies of one step for columns 0..ncol-1 (ncol <= max_cols): dTdt, dqdt [L][ld],
  * prec [ld] (FP64).  Predicted precipitation below zero is set to zero.  With fallback != 0 the
  * flagged columns are gathered, stepped by conv_step and scattered back, which waits once on the

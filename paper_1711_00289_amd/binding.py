@@ -42,7 +42,7 @@ EXPORTS = ("conv_workspace_bytes", "conv_create", "conv_set_params", "conv_destr
            "mlp_adam_step", "mlp_train_step", "mlp_gemm_nt", "mlp_strerror",
            "surr_pack_inputs_raw", "surr_pack_targets_raw", "surr_col_stats_scratch_bytes",
            "surr_col_stats", "surr_normalize", "surr_pack_inputs", "surr_workspace_bytes",
-           "surr_create", "surr_destroy", "surr_set_norm", "surr_infer")
+           "surr_create", "surr_destroy", "surr_set_norm", "surr_set_fused", "surr_infer")
 
 
 class Params(C.Structure):
@@ -221,6 +221,8 @@ def lib():
         L.surr_destroy.argtypes = [V]
         L.surr_set_norm.restype = I
         L.surr_set_norm.argtypes = [V, V, V, V, V, C.c_double, C.c_double, V]
+        L.surr_set_fused.restype = I
+        L.surr_set_fused.argtypes = [V, I]
         L.surr_infer.restype = I
         L.surr_infer.argtypes = [V, C.POINTER(State), I64, V, V, V, I, C.POINTER(I64), V]
         L.conv_strerror.restype = C.c_char_p

@@ -49,36 +49,8 @@ __device__ __forceinline__ uint16_t f2bf(float f) {  // round to nearest even
     return (uint16_t)(u >> 16);
 }
 
-// erfc(x) by the Chebyshev-fitted form of Press et al., Numerical Recipes (erfcc, fractional error
-// below 1.2e-7 everywhere): erfc(x) = t exp(-x^2 + P(t)) with t = 1/(1 + |x|/2), reflected as
-// 2 - erfc(-x) for x < 0.  Branch-free: one reciprocal and one exponential.
-__device__ __forceinline__ float erfc_cheb(float x) {
-    const float ax = fabsf(x);
-    const float t = __builtin_amdgcn_rcpf(1.0f + 0.5f * ax);
-    float p = 0.17087277f;
-    p = fmaf(p, t, -0.82215223f);
-    p = fmaf(p, t, 1.48851587f);
-    p = fmaf(p, t, -1.13520398f);
-    p = fmaf(p, t, 0.27886807f);
-    p = fmaf(p, t, -0.18628806f);
-    p = fmaf(p, t, 0.09678418f);
-    p = fmaf(p, t, 0.37409196f);
-    p = fmaf(p, t, 1.00002368f);
-    p = fmaf(p, t, -1.26551223f);
-    const float r = t * __expf(fmaf(-ax, ax, p));
-    return x >= 0.0f ? r : 2.0f - r;
-}
-
-// GELU(z) = z Phi(z) with Phi(z) = erfc(-z/sqrt 2)/2 (the erfc form keeps full relative accuracy
-// in the negative tail, where 1 + erf(z/sqrt 2) would cancel).
-__device__ __forceinline__ float gelu(float z) {
-    return 0.5f * z * erfc_cheb(-z * 0.70710678118654752f);
-}
-
-__device__ __forceinline__ float gelu_grad(float z) {
-    return 0.5f * erfc_cheb(-z * 0.70710678118654752f) +
-           z * 0.39894228040143268f * __expf(-0.5f * z * z);
-}
+using mlpk::gelu;
+using mlpk::gelu_grad;
 
 enum Mode : int {
     EPI_F32 = 0,      // c (float) = acc + bias
@@ -332,7 +304,7 @@ __global__ __launch_bounds__(WM * WN * 64) void k_gemm(GemmArgs g) {
                 uint32_t h[4];
 #pragma unroll
                 for (int e = 0; e < 4; ++e)
-                    h[e] = (uint32_t)f2bf(v[2 * e]) | ((uint32_t)f2bf(v[2 * e + 1]) << 16);
+                    h[e] = mlpk::bf16x2(v[2 * e], v[2 * e + 1]);
                 if (g.nt) {
                     const u32x4 hv = {h[0], h[1], h[2], h[3]};
                     __builtin_nontemporal_store(hv, (u32x4 *)c);
@@ -353,9 +325,9 @@ __global__ __launch_bounds__(WM * WN * 64) void k_gemm(GemmArgs g) {
 #pragma unroll
                     for (int rr = 0; rr < 32; rr += 2) {
                         const int64_t m = mw + a * 32 + rr;
-                        const uint32_t lo = m < g.M ? f2bf(strip[rr * SLD + lane]) : 0u;
-                        const uint32_t hi = m + 1 < g.M ? f2bf(strip[(rr + 1) * SLD + lane]) : 0u;
-                        pk[a * 16 + rr / 2] = lo | (hi << 16);
+                        pk[a * 16 + rr / 2] =
+                            mlpk::bf16x2(m < g.M ? strip[rr * SLD + lane] : 0.0f,
+                                         m + 1 < g.M ? strip[(rr + 1) * SLD + lane] : 0.0f);
                     }
                 }
             }

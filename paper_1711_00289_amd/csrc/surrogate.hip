@@ -254,37 +254,61 @@ __global__ __launch_bounds__(TB) void k_unpack(const float *y, int L, int64_t nc
 }
 
 // ------------------------------------------------------------------ fused inference
-// The whole network for a tile of FR columns in one persistent block: the columns' features are
-// packed (normalised, BF16) into an LDS activation tile [FR][FROW], every layer's product runs on
-// the matrix cores (v_mfma_f32_32x32x16_bf16, FP32 accumulation) with its activations read from
-// and written back to that tile, and the output layer is un-normalised and stored level-major with
-// the fallback test.  No activation leaves the chip (the layer-by-layer path moves about 7 GB of
-// them through HBM for the 884,736-column grid).  Hidden layers: wavefront w computes all FR rows
-// of output columns [64 w, 64 w + 64), reading its weight rows straight from global memory (the
-// network's 1.7 MB of BF16 weights stay in every XCD's L2); the output layer gives each wavefront
-// one 32 x 32 tile.  Products accumulate K in steps of 16 in increasing order from zero, the bias
-// is added in FP32, GELU and the BF16 rounding are those of the layer-by-layer kernels, so the
-// results are the same bits.
+// The whole network for a tile of FR = 64 columns in one persistent block: the columns' features
+// are packed (normalised, BF16) into an LDS activation tile [FR][FROW], every layer's product runs
+// on the matrix cores (v_mfma_f32_32x32x16_bf16, FP32 accumulation) with its activations read
+// from and written back to that tile, and the output layer is un-normalised and stored
+// level-major, with the fallback test, straight from the accumulators.  No activation leaves the
+// chip (the layer-by-layer path moves about 7 GB of them through HBM for the 884,736-column grid).
+//
+// Two blocks of four wavefronts share a CU (one wavefront of each on every SIMD) and run apart, so
+// one block's epilogues (bias, GELU, BF16 rounding: vector ALU work) overlap the other's products
+// on the matrix cores.  Hidden layers: wavefront w computes output columns [128 w, 128 w + 128) of
+// all FR rows as the transposed product (weights as the first operand), so each lane ends with 4
+// consecutive output columns of one row per accumulator group, written as one 8-byte LDS store.
+// The output layer gives each wavefront one 32 x 32 tile.  Weight operands come straight from
+// global memory (the network's 1.7 MB of BF16 weights stay in every XCD's L2) in a fragment-major
+// copy (k_frag_pack), RING k-steps in flight; the next product's first RING steps are loaded
+// before each epilogue, so they arrive while it runs.  Biases and normalisation statistics are
+// kept in LDS.  Products accumulate K in steps of 16 in increasing order from zero, the bias is
+// added in FP32, and GELU and the BF16 rounding are the layer-by-layer kernels', so the results
+// are the same bits.
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
 
-constexpr int FR = 128;           // columns (network rows) per tile
+constexpr int FR = 64;            // columns (network rows) per tile
 constexpr int FH = 512;           // hidden width
+constexpr int FIN = 96;           // input width
 constexpr int FROW = FH + 8;      // BF16 per LDS row: the 16-byte pad puts the 32 rows a fragment
                                   // read serves on distinct 16-byte bank groups
-constexpr int FWAVES = 8;
+constexpr int FWAVES = 4;
 constexpr int FT = FWAVES * 64;
+constexpr int FBLOCKS = 2;        // resident blocks per CU
+constexpr int FN = FH / FWAVES;   // hidden output columns per wavefront
+constexpr int FJ = FN / 32;       // 32-column weight tiles per wavefront
 constexpr int FOUT = 64;          // output width
-constexpr int RING = 2;           // k-steps of weight fragments in flight
-constexpr int YS = FOUT + 1;      // floats per row of the output staging tile
-constexpr size_t FUSED_LDS = (size_t)FR * FROW * sizeof(uint16_t);
+constexpr int RING = 3;           // k-steps of weight fragments in flight
+constexpr int NSTH = FH / 16;     // k-steps of a 512-wide product
+constexpr int NST0 = FIN / 16;    // k-steps of the input layer
+constexpr size_t FACT = (size_t)FR * FROW * sizeof(uint16_t);  // activation tile bytes
+constexpr size_t LDS_PER_CU = 160 * 1024;
+static_assert(FR == 64 && FOUT == 64 && FWAVES == 4, "the output layer maps 2 x 2 tiles of 32 x 32 "
+                                                      "onto the four wavefronts");
+static_assert(RING <= NST0 && RING <= NSTH, "the weight ring fits every k-loop");
+
+// LDS bytes of a block for a network of nl layers: the activation tile, then (float) the hidden
+// layers' biases [nl - 1][FH], the output bias, scale and mean [FOUT] each, the input mean and
+// scale [FIN] each.
+size_t fused_lds(int nl) {
+    return FACT + sizeof(float) * ((size_t)(nl - 1) * FH + 3 * FOUT + 2 * FIN);
+}
 
 struct FusedArgs {
     const double *T, *q, *pm;
     int64_t ld;
     int L;
     int64_t ncol, ntiles;
-    int nl, w_in;                 // layers, input width
+    int nl;                       // layers (hidden + output)
     const uint16_t *W[MLP_MAX_LAYERS];  // fragment-major BF16 weights (k_frag_pack)
     const float *B[MLP_MAX_LAYERS];
     const float *in_mean, *in_std, *out_mean, *out_std;
@@ -293,8 +317,8 @@ struct FusedArgs {
     int *list, *cnt;
 };
 
-// Layer l's weights and bias (a wavefront-uniform selection among the kernel argument's entries,
-// so the argument block is not copied to private memory for indexing).
+// Layer l's weights (a wavefront-uniform selection among the kernel argument's entries, so the
+// argument block is not copied to private memory for indexing).
 __device__ __forceinline__ const uint16_t *layer_w(const FusedArgs &a, int l) {
     const uint16_t *p = a.W[0];
 #pragma unroll
@@ -308,190 +332,261 @@ __device__ __forceinline__ const float *layer_b(const FusedArgs &a, int l) {
     return p;
 }
 
-// erfc by the Chebyshev-fitted form of Press et al., Numerical Recipes (erfcc) and GELU from it:
-// the same FP32 operations as the layer-by-layer kernels' epilogue.
-__device__ __forceinline__ float f_erfc(float x) {
-    const float ax = fabsf(x);
-    const float t = __builtin_amdgcn_rcpf(1.0f + 0.5f * ax);
-    float p = 0.17087277f;
-    p = fmaf(p, t, -0.82215223f);
-    p = fmaf(p, t, 1.48851587f);
-    p = fmaf(p, t, -1.13520398f);
-    p = fmaf(p, t, 0.27886807f);
-    p = fmaf(p, t, -0.18628806f);
-    p = fmaf(p, t, 0.09678418f);
-    p = fmaf(p, t, 0.37409196f);
-    p = fmaf(p, t, 1.00002368f);
-    p = fmaf(p, t, -1.26551223f);
-    const float r = t * __expf(fmaf(-ax, ax, p));
-    return x >= 0.0f ? r : 2.0f - r;
+// Weight fragments are read through a buffer resource (base and size in scalar registers): the
+// per-step offsets are then constants in scalar registers next to one lane offset, not a 64-bit
+// address per step and tile held in vector registers.  Reads past `bytes` return zeros.
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t frag_rsrc(const uint16_t *w, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc((void *)w, 0, (int)bytes, 0x00020000);
 }
-__device__ __forceinline__ float f_gelu(float z) {
-    return 0.5f * z * f_erfc(-z * 0.70710678118654752f);
+__device__ __forceinline__ bf16x8 frag_load(__amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                            uint32_t soff) {
+    return __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff,
+                                                                             (int)soff, 0));
 }
 
-__global__ __launch_bounds__(FT, 1) void k_surr_fused(FusedArgs a) {
-    extern __shared__ uint16_t act[];  // [FR][FROW]; the output staging reuses it as float [FR][YS]
+// Loads of the weight ring: slot q takes the fragments of k-step `st` of the wavefront's NJ tiles
+// (TS bytes apart).  `sb` is an opaque zero: the offsets derived from it are formed where they are
+// used instead of being hoisted, all of them, into registers for the whole kernel.
+template <int NJ, uint32_t TS>
+__device__ __forceinline__ void ring_load(bf16x8 (&bq)[RING][FJ], int q, __amdgpu_buffer_rsrc_t r,
+                                          uint32_t woff, uint32_t sb, int st) {
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) bq[q][j] = frag_load(r, woff, sb + j * TS + 1024u * st);
+}
+__device__ __forceinline__ uint32_t opaque_zero() {
+    uint32_t z = 0;
+    asm volatile("" : "+s"(z));
+    return z;
+}
+template <int NJ, uint32_t TS>
+__device__ __forceinline__ void ring_fill(bf16x8 (&bq)[RING][FJ], __amdgpu_buffer_rsrc_t r,
+                                          uint32_t woff) {
+    const uint32_t sb = opaque_zero();
+#pragma unroll
+    for (int q = 0; q < RING; ++q) ring_load<NJ, TS>(bq, q, r, woff, sb, q);
+}
+
+// The k-loop of a hidden product, fully unrolled: NS steps of 16 inputs, 2 row blocks x FJ
+// weight tiles per wavefront.  The ring holds steps 0 .. RING - 1 on entry; the first step reads
+// its activation fragments from LDS, each step reads the next step's before its products and
+// loads the weight fragments RING steps ahead after them (the scheduler is kept from moving
+// those loads).
+template <int NS, int S = 0>
+__device__ __forceinline__ void hidden_k(__amdgpu_buffer_rsrc_t r, uint32_t woff, uint32_t sb,
+                                         const uint16_t *actK, f32x16 (&acc)[2][FJ],
+                                         bf16x8 (&bq)[RING][FJ], bf16x8 (&af)[2][2]) {
+    if constexpr (S < NS) {
+        constexpr int slot = S % RING, cur = S % 2;
+        if constexpr (S == 0) {
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb) af[0][rb] = *(const bf16x8 *)(actK + 32 * rb * FROW);
+        }
+        if constexpr (S + 1 < NS) {
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb)
+                af[cur ^ 1][rb] = *(const bf16x8 *)(actK + 32 * rb * FROW + 16 * (S + 1));
+        }
+#pragma unroll
+        for (int j = 0; j < FJ; ++j)
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb)
+                acc[rb][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                    bq[slot][j], af[cur][rb], S == 0 ? f32x16{} : acc[rb][j], 0, 0, 0);
+        if constexpr (S + RING < NS) ring_load<FJ, NS * 1024u>(bq, slot, r, woff, sb, S + RING);
+        __builtin_amdgcn_sched_barrier(0);
+        hidden_k<NS, S + 1>(r, woff, sb, actK, acc, bq, af);
+    }
+}
+
+// The output layer's k-loop for the wavefront's 32 x 32 tile (ring slot column 0).
+template <int S = 0>
+__device__ __forceinline__ void out_k(__amdgpu_buffer_rsrc_t r, uint32_t woff, uint32_t sb,
+                                      const uint16_t *actK, f32x16 &acc, bf16x8 (&bq)[RING][FJ],
+                                      bf16x8 (&af)[2][2]) {
+    if constexpr (S < NSTH) {
+        constexpr int slot = S % RING, cur = S % 2;
+        if constexpr (S == 0) af[0][0] = *(const bf16x8 *)actK;
+        if constexpr (S + 1 < NSTH) af[cur ^ 1][0] = *(const bf16x8 *)(actK + 16 * (S + 1));
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bq[slot][0], af[cur][0],
+                                                      S == 0 ? f32x16{} : acc, 0, 0, 0);
+        if constexpr (S + RING < NSTH) ring_load<1, 0>(bq, slot, r, woff, sb, S + RING);
+        __builtin_amdgcn_sched_barrier(0);
+        out_k<S + 1>(r, woff, sb, actK, acc, bq, af);
+    }
+}
+
+// The epilogue of a hidden product as groups of 4 elements: group gi is row block gi / 16,
+// weight tile (gi / 4) % 4, accumulator registers 4 (gi % 4) .. + 3 (4 consecutive columns of one
+// row in the transposed layout).  `bias` (LDS) and `dst` point at the lane's first column.  Each
+// group reads the next group's biases before its own arithmetic, and the scheduler is kept from
+// pulling every group's reads to the front (which would hold them all in registers).
+template <int GI>
+__device__ __forceinline__ float4 epi_bias(const float *bias) {
+    return *(const float4 *)(bias + 32 * ((GI / 4) % FJ) + 8 * (GI % 4));
+}
+template <int GI, int GN>
+__device__ __forceinline__ void epi_groups(const f32x16 (&acc)[2][FJ], const float *bias,
+                                           uint16_t *dst, float4 b) {
+    if constexpr (GI < GN) {
+        constexpr int rb = GI / 16, j = (GI / 4) % FJ, g = GI % 4;
+        float4 bn = b;
+        if constexpr (GI + 1 < GN) bn = epi_bias<GI + 1>(bias);
+        const float y0 = mlpk::gelu(acc[rb][j][4 * g + 0] + b.x);
+        const float y1 = mlpk::gelu(acc[rb][j][4 * g + 1] + b.y);
+        const float y2 = mlpk::gelu(acc[rb][j][4 * g + 2] + b.z);
+        const float y3 = mlpk::gelu(acc[rb][j][4 * g + 3] + b.w);
+        *(uint2 *)(dst + 32 * rb * FROW + 32 * j + 8 * g) =
+            make_uint2(mlpk::bf16x2(y0, y1), mlpk::bf16x2(y2, y3));
+        __builtin_amdgcn_sched_barrier(0);
+        epi_groups<GI + 1, GN>(acc, bias, dst, bn);
+    }
+}
+
+__global__ __launch_bounds__(FT, FBLOCKS) void k_surr_fused(FusedArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint16_t *act = (uint16_t *)smem;  // [FR][FROW]
+    float *pb = (float *)(smem + FACT);
+    float *p_hb = pb;                              // hidden biases [nl - 1][FH]
+    float *p_ob = p_hb + (a.nl - 1) * FH;          // output bias, scale, mean [FOUT] each
+    float *p_os = p_ob + FOUT, *p_om = p_os + FOUT;
+    float *p_im = p_om + FOUT, *p_is = p_im + FIN; // input mean, scale [FIN] each
     const int tid = threadIdx.x;
-    const int w = tid / 64, lane = tid % 64;
+    const int lane = tid % 64;
+    const int wu = __builtin_amdgcn_readfirstlane(tid / 64);  // the wavefront index, uniform
     const int lrow = lane & 31, lk = 8 * (lane >> 5);
     const int L = a.L;
-    const int64_t ld = a.ld;
-    for (int64_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
-        const int64_t c0 = tile * FR;
-        const int nrows = (int)(a.ncol - c0 < FR ? a.ncol - c0 : FR);
+    for (int i = tid; i < (a.nl - 1) * FH; i += FT) p_hb[i] = layer_b(a, i / FH)[i % FH];
+    for (int i = tid; i < FOUT; i += FT) {
+        p_ob[i] = layer_b(a, a.nl - 1)[i];
+        p_os[i] = a.out_std[i];
+        p_om[i] = a.out_mean[i];
+    }
+    for (int i = tid; i < FIN; i += FT) {
+        p_im[i] = a.in_mean[i];
+        p_is[i] = a.in_std[i];
+    }
+    // Lane-fixed LDS positions and weight offsets.
+    const uint16_t *actK = act + lrow * FROW + lk;
+    uint16_t *dst = act + lrow * FROW + FN * wu + 4 * (lane >> 5);
+    const uint32_t woff0 = (uint32_t)(FJ * wu) * (NST0 * 1024u) + 16u * lane;
+    const uint32_t woffH = (uint32_t)(FJ * wu) * (NSTH * 1024u) + 16u * lane;
+    const int orb = wu % 2, ont = wu / 2;  // the output tile
+    const uint32_t woffO = (uint32_t)ont * (NSTH * 1024u) + 16u * lane;
+    // Buffer resources of the layers' fragment-major weights.
+    auto rsrc = [&](int l) {
+        const uint32_t bytes = l == 0 ? FIN * FH * 2u : l + 1 < a.nl ? FH * FH * 2u : FH * FOUT * 2u;
+        return frag_rsrc(layer_w(a, l), bytes);
+    };
+    const __amdgpu_buffer_rsrc_t r0 = rsrc(0), rO = rsrc(a.nl - 1);
+    bf16x8 bq[RING][FJ], af[2][2];
+    f32x16 acc[2][FJ], accO;
+    double d[3][8];
 
-        // Pack: feature f of column c0 + r at act[r][f]; loads along the columns are contiguous;
-        // 8 in flight per thread.  Features past 3L (padding) and rows past the grid are zero.
-        constexpr int PU = 8;
-        const int nf = a.w_in * FR;
-        for (int i0 = tid; i0 < nf; i0 += FT * PU) {
-            double d[PU];
+    // Pack, in two halves: `pack_load` puts tile t's features in registers (task k of wavefront
+    // w is feature group w + 4 k, 8 levels of the lane's column, contiguous across the wavefront
+    // and in flight together); `pack_store` normalises them, rounds to BF16 and writes one
+    // 16-byte row piece per group.  Features past 3L and rows past the grid are zero.
+    auto pack_load = [&](int64_t t) {
+        int64_t ld = a.ld;
+        int pl = lane, pw = wu;
+        asm volatile("" : "+s"(ld), "+v"(pl), "+s"(pw));  // recomputed per tile, not hoisted
+        const int64_t col = t * FR + pl;
+        const bool rok = col < a.ncol;
+        static_assert(FIN / 8 == 3 * FWAVES, "three feature groups per wavefront");
 #pragma unroll
-            for (int u = 0; u < PU; ++u) {
-                const int i = i0 + u * FT;
-                const int f = i / FR, r = i % FR;
-                d[u] = 0.0;
-                if (i < nf && r < nrows && f < 3 * L) {
-                    const double *src = f < L       ? a.T + (int64_t)f * ld
-                                        : f < 2 * L ? a.q + (int64_t)(f - L) * ld
-                                                    : a.pm + (int64_t)(f - 2 * L) * ld;
-                    d[u] = __builtin_nontemporal_load(&src[c0 + r]);
-                }
-            }
+        for (int k = 0; k < 3; ++k) {
 #pragma unroll
-            for (int u = 0; u < PU; ++u) {
-                const int i = i0 + u * FT;
-                if (i >= nf) break;
-                const int f = i / FR, r = i % FR;
-                float v = 0.0f;
-                if (r < nrows && f < 3 * L) v = ((float)d[u] - a.in_mean[f]) / a.in_std[f];
-                act[r * FROW + f] = f2bf(v);
+            for (int e = 0; e < 8; ++e) {
+                const int f = 8 * (pw + FWAVES * k) + e;  // wavefront-uniform
+                const double *src = f < L       ? a.T + (int64_t)f * ld
+                                    : f < 2 * L ? a.q + (int64_t)(f - L) * ld
+                                                : a.pm + (int64_t)(f - 2 * L) * ld;
+                d[k][e] = f < 3 * L && rok ? __builtin_nontemporal_load(&src[col]) : 0.0;
             }
         }
+    };
+    auto pack_store = [&]() {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int g = wu + FWAVES * k;
+            float v[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int f = 8 * g + e;
+                v[e] = ((float)d[k][e] - p_im[f]) / p_is[f];
+                v[e] = f < 3 * L ? v[e] : 0.0f;  // d is 0 past the grid: (0 - mean) / scale
+            }
+            *(uint4 *)&act[lane * FROW + 8 * g] =
+                make_uint4(mlpk::bf16x2(v[0], v[1]), mlpk::bf16x2(v[2], v[3]),
+                           mlpk::bf16x2(v[4], v[5]), mlpk::bf16x2(v[6], v[7]));
+        }
+    };
+
+    int64_t tile = blockIdx.x;  // the grid is at most the number of tiles
+    ring_fill<FJ, NST0 * 1024u>(bq, r0, woff0);
+    pack_load(tile);
+    __syncthreads();  // parameters in LDS
+    pack_store();
+    for (;;) {
+        const int64_t c0 = tile * FR;  // rows past the grid are computed and not stored
         __syncthreads();
-
-        // Hidden layers: act (K wide) -> GELU(act . W^T + b) (512 wide), in place.
+        // Hidden layers.  The ring holds the first steps of layer l's fragments on entry.
         for (int l = 0; l + 1 < a.nl; ++l) {
-            const int K = l == 0 ? a.w_in : FH;
-            const uint16_t *Wl = layer_w(a, l);
-            const int n0 = 64 * w;
-            f32x16 acc[4][2];
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 2; ++j)
-#pragma unroll
-                    for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
-            // Fragment-major weights: the fragment of n-tile t at k-step s is 64 lanes x 16
-            // contiguous bytes, so each load is one contiguous 1 KB read.  Fragments of RING
-            // k-steps are in flight while one is multiplied: the loads for step s + RING go out
-            // right after step s's products, into the slot step s used.
-            const int nst = K / 16;
-            const uint16_t *wrow0 = Wl + ((int64_t)(2 * w) * nst * 64 + lane) * 8;
-            const uint16_t *wrow1 = Wl + ((int64_t)(2 * w + 1) * nst * 64 + lane) * 8;
-            bf16x8 bq0[RING], bq1[RING];
-#pragma unroll
-            for (int j = 0; j < RING; ++j) {
-                if (j < nst) {
-                    bq0[j] = *(const bf16x8 *)(wrow0 + 512 * j);
-                    bq1[j] = *(const bf16x8 *)(wrow1 + 512 * j);
-                }
+            if (l == 0) {
+                hidden_k<NST0>(r0, woff0, opaque_zero(), actK, acc, bq, af);
+            } else {
+                hidden_k<NSTH>(rsrc(l), woffH, opaque_zero(), actK, acc, bq, af);
             }
-#pragma unroll 1
-            for (int s0 = 0; s0 < nst; s0 += RING) {
-#pragma unroll
-                for (int j = 0; j < RING; ++j) {
-                    const int st = s0 + j;
-                    if (st >= nst) break;
-                    const int ks = 16 * st;
-                    bf16x8 af[4];
-#pragma unroll
-                    for (int i = 0; i < 4; ++i)
-                        af[i] = *(const bf16x8 *)&act[(32 * i + lrow) * FROW + ks + lk];
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        acc[i][0] =
-                            __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[i], bq0[j], acc[i][0], 0, 0, 0);
-                        acc[i][1] =
-                            __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[i], bq1[j], acc[i][1], 0, 0, 0);
-                    }
-                    if (st + RING < nst) {
-                        bq0[j] = *(const bf16x8 *)(wrow0 + 512 * (st + RING));
-                        bq1[j] = *(const bf16x8 *)(wrow1 + 512 * (st + RING));
-                    }
-                }
+            // The next product's first steps, in flight during the epilogue.
+            if (l + 2 < a.nl) {
+                ring_fill<FJ, NSTH * 1024u>(bq, rsrc(l + 1), woffH);
+            } else {
+                ring_fill<1, 0>(bq, rO, woffO);
             }
-            __syncthreads();  // every wavefront has read its inputs
-            // Accumulator layout of a 32x32 tile: register r of lane l holds row
-            // 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32.
-            const float *Bl = layer_b(a, l);
-            const float bias0 = Bl[n0 + lrow], bias1 = Bl[n0 + 32 + lrow];
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const int row = 32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                    act[row * FROW + n0 + lrow] = f2bf(f_gelu(acc[i][0][r] + bias0));
-                    act[row * FROW + n0 + 32 + lrow] = f2bf(f_gelu(acc[i][1][r] + bias1));
-                }
+            __syncthreads();  // every wavefront has read the layer's inputs
+            const float *bias = p_hb + l * FH + FN * wu + 4 * (lane >> 5);
+            epi_groups<0, 8 * FJ>(acc, bias, dst, epi_bias<0>(bias));
             __syncthreads();
         }
-
-        // Output layer: wavefront w computes rows 32 (w % 4) .., columns 32 (w / 4) ..; then
-        // y * scale + mean per output, staged as float [FR][YS].
+        // Output layer: wavefront w's tile is rows 32 (w % 2) .., outputs 32 (w / 2) ...
+        out_k(rO, woffO, opaque_zero(), actK + 32 * orb * FROW, accO, bq, af);
+        ring_fill<FJ, NST0 * 1024u>(bq, r0, woff0);  // the next tile's first product
+        const int64_t next = tile + gridDim.x;
+        const bool have = next < a.ntiles;
+        pack_load(next);  // in flight while the outputs are stored (nothing past the grid)
         {
-            const int l = a.nl - 1;
-            const int mt = w % 4, nt = w / 4;
-            constexpr int NST = FH / 16;
-            const uint16_t *wrow = layer_w(a, l) + ((int64_t)nt * NST * 64 + lane) * 8;
-            f32x16 acc;
-#pragma unroll
-            for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
-            bf16x8 bq[RING];
-#pragma unroll
-            for (int j = 0; j < RING; ++j) bq[j] = *(const bf16x8 *)(wrow + 512 * j);
-#pragma unroll 1
-            for (int s0 = 0; s0 < NST; s0 += RING) {
-#pragma unroll
-                for (int j = 0; j < RING; ++j) {
-                    const int st = s0 + j;
-                    if (st >= NST) break;
-                    const int ks = 16 * st;
-                    const bf16x8 af = *(const bf16x8 *)&act[(32 * mt + lrow) * FROW + ks + lk];
-                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af, bq[j], acc, 0, 0, 0);
-                    if (st + RING < NST) bq[j] = *(const bf16x8 *)(wrow + 512 * (st + RING));
-                }
-            }
-            __syncthreads();
-            float *ys = (float *)act;
-            const int col = 32 * nt + lrow;
-            const float bias = layer_b(a, l)[col], sd = a.out_std[col], mn = a.out_mean[col];
+            // Un-normalise and store (transposed layout: register r of lane l is output
+            // 32 nt + 8 (r / 4) + 4 (l / 32) + r % 4 of column c0 + 32 rb + l % 32); tendencies
+            // level-major, precipitation clipped at zero, and the fallback test on it.
+            int64_t ld = a.ld;
+            int pl = lane;
+            asm volatile("" : "+s"(ld), "+v"(pl));  // recomputed per tile, not hoisted
+            const int64_t col = c0 + 32 * orb + (pl & 31);
+            const bool live = col < a.ncol;
+            bool fb = false;
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                const int row = 32 * mt + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                const float y = acc[r] + bias;
-                ys[row * YS + col] = y * sd + mn;
+                const int f = 32 * ont + 8 * (r >> 2) + 4 * (pl >> 5) + (r & 3);
+                if (f > 2 * L) continue;
+                const float y = accO[r] + p_ob[f];
+                const double v = (double)(y * p_os[f] + p_om[f]);
+                if (f < L) {
+                    if (live) __builtin_nontemporal_store(v, &a.dTdt[(int64_t)f * ld + col]);
+                } else if (f < 2 * L) {
+                    if (live) __builtin_nontemporal_store(v, &a.dqdt[(int64_t)(f - L) * ld + col]);
+                } else {
+                    if (live) a.prec[col] = v > 0.0 ? v : 0.0;
+                    fb = live && (v < a.lo || v > a.hi);
+                }
             }
-            __syncthreads();
-            // Level-major stores: 2L profiles of FR consecutive columns (written once).
-            for (int i = tid; i < 2 * L * FR; i += FT) {
-                const int f = i / FR, r = i % FR;
-                if (r >= nrows) continue;
-                const double v = (double)ys[r * YS + f];
-                if (f < L) __builtin_nontemporal_store(v, &a.dTdt[(int64_t)f * ld + c0 + r]);
-                else __builtin_nontemporal_store(v, &a.dqdt[(int64_t)(f - L) * ld + c0 + r]);
-            }
-            if (tid < FR) {
-                const bool live = tid < nrows;
-                const double p = live ? (double)ys[tid * YS + 2 * L] : 0.0;
-                if (live) a.prec[c0 + tid] = p > 0.0 ? p : 0.0;
-                const bool fb = live && (p < a.lo || p > a.hi);
-                const int slot = wave_append(fb, a.cnt);
-                if (slot >= 0) a.list[slot] = (int)(c0 + tid);
-            }
-            __syncthreads();  // the staging tile is read before the next tile's packing
+            const int slot = wave_append(fb, a.cnt);
+            if (slot >= 0) a.list[slot] = (int)col;
         }
+        if (!have) break;
+        __syncthreads();  // every wavefront has read the tile before it is repacked
+        pack_store();
+        tile = next;
     }
 }
 
@@ -573,14 +668,15 @@ int lds_limit(const void *fn, size_t bytes) {
 }
 size_t al(size_t x) { return (x + 255) & ~size_t(255); }
 
-// Networks the fused inference kernel handles: hidden layers of width FH, an input of at most FH
-// features (a multiple of 16) holding the 3L packed features, an output of FOUT holding 2L + 1.
+// Networks the fused inference kernel handles: an input of FIN features holding the 3L packed
+// features, hidden layers of width FH, an output of FOUT holding 2L + 1, and few enough layers
+// that two blocks' LDS (activation tile and parameters) fit a CU.
 bool fused_ok(const mlpk::NetView &v, int L) {
-    if (v.n < 2 || v.w[0] % 16 != 0 || v.w[0] > FH || v.w[0] < 3 * L) return false;
+    if (v.n < 2 || v.w[0] != FIN || 3 * L > FIN) return false;
     if (v.w[v.n] != FOUT || 2 * L + 1 > FOUT) return false;
     for (int i = 1; i < v.n; ++i)
         if (v.w[i] != FH) return false;
-    return true;
+    return FBLOCKS * fused_lds(v.n) <= LDS_PER_CU;
 }
 
 struct SLayout {
@@ -628,6 +724,7 @@ struct surr {
     char *ws;
     SLayout lay;
     double lo, hi;
+    int fused = 1;  // surr_set_fused
 };
 
 namespace {
@@ -757,6 +854,12 @@ int surr_create(mlp_t *net, int32_t nlev, int32_t w_in, int32_t w_out, int64_t m
 
 void surr_destroy(surr_t *s) { delete s; }
 
+int surr_set_fused(surr_t *s, int enable) {
+    if (!s) return CONV_EINVAL;
+    s->fused = enable != 0;
+    return s->fused && fused_ok(mlpk::net_view(s->net), s->L) ? 1 : 0;
+}
+
 int surr_set_norm(surr_t *s, const float *in_mean, const float *in_std, const float *out_mean,
                   const float *out_std, double prec_lo, double prec_hi, void *stream) {
     if (!s || !in_mean || !in_std || !out_mean || !out_std || !(prec_lo <= prec_hi)) return CONV_EINVAL;
@@ -795,9 +898,10 @@ int surr_infer(surr_t *s, const conv_state_t *state, int64_t ncol, double *dTdt,
         return CONV_EHIP;
     hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, cnt);
     const mlpk::NetView nv = mlpk::net_view(s->net);
-    if (fused_ok(nv, L)) {
+    const bool fused = s->fused && fused_ok(nv, L);
+    if (fused) {
         // The whole network per tile on the chip: one launch for every column, no chunks.
-        if (lds_limit((const void *)k_surr_fused, FUSED_LDS) != CONV_OK) return CONV_EHIP;
+        if (lds_limit((const void *)k_surr_fused, fused_lds(nv.n)) != CONV_OK) return CONV_EHIP;
         FusedArgs fa{};
         fa.T = state->T;
         fa.q = state->q;
@@ -807,7 +911,6 @@ int surr_infer(surr_t *s, const conv_state_t *state, int64_t ncol, double *dTdt,
         fa.ncol = ncol;
         fa.ntiles = (ncol + FR - 1) / FR;
         fa.nl = nv.n;
-        fa.w_in = nv.w[0];
         uint16_t *wf = (uint16_t *)(s->ws + s->lay.wfrag);
         for (int i = 0; i < nv.n; ++i) {
             const int64_t cnt_i = (int64_t)nv.w[i + 1] * nv.w[i];
@@ -828,10 +931,11 @@ int surr_infer(surr_t *s, const conv_state_t *state, int64_t ncol, double *dTdt,
         fa.prec = prec;
         fa.list = list;
         fa.cnt = cnt;
-        const int64_t grid = fa.ntiles < device_cus() ? fa.ntiles : device_cus();
-        hipLaunchKernelGGL(k_surr_fused, dim3((unsigned)grid), dim3(FT), FUSED_LDS, st, fa);
+        const int64_t slots = (int64_t)FBLOCKS * device_cus();
+        const int64_t grid = fa.ntiles < slots ? fa.ntiles : slots;
+        hipLaunchKernelGGL(k_surr_fused, dim3((unsigned)grid), dim3(FT), fused_lds(nv.n), st, fa);
     }
-    for (int64_t c0 = 0; c0 < ncol && !fused_ok(nv, L); c0 += s->chunk) {
+    for (int64_t c0 = 0; c0 < ncol && !fused; c0 += s->chunk) {
         const int64_t n = ncol - c0 < s->chunk ? ncol - c0 : s->chunk;
         StateArgs a{state->T + c0, state->q + c0, state->p_mid + c0, ld};
         hipLaunchKernelGGL(k_pack_in, dim3(nb(n, TC)), dim3(TB), pack_lds(s->w_in), st, a, L, n,

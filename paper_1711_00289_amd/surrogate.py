@@ -189,6 +189,13 @@ class Surrogate:
         except Exception:
             pass
 
+    def set_fused(self, enable: bool) -> bool:
+        """Choose the fused inference kernel (default) or the layer-by-layer path; returns whether
+        the next inference takes the fused kernel."""
+        rc = B.lib().surr_set_fused(self.h, int(enable))
+        _check(min(rc, 0), "surr_set_fused")
+        return rc == 1
+
     def infer(self, dev, ncol: int, fallback: bool = True, out=None):
         """Returns (dTdt [L][ld], dqdt [L][ld], prec [ld], n_fallback or None)."""
         torch = self.torch

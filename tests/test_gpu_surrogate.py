@@ -142,9 +142,36 @@ def test_inference_matches_the_network_and_unpacks(torch, stepped):
     assert np.array_equal(x.view(torch.int16).cpu().numpy().view(np.uint16), wx)
 
 
+@pytest.mark.parametrize("ncol", [1, 63, 64, 65, 6_001])
+def test_fused_kernel_gives_the_layer_by_layer_bits(torch, stepped, ncol):
+    """The fused inference kernel (whole network per 64-column tile, activations in LDS) against the
+    layer-by-layer path (surr_pack_inputs, mlp_forward, unpack) on the same network: identical
+    tendencies, precipitation and fallback decisions, on ragged column counts with the leading
+    dimension of the 6,001-column state."""
+    st, dev, d, s = stepped
+    print(f"fused vs layer by layer, {ncol} columns", flush=True)
+    probe, _ = _tiny_surrogate(torch, prec_range=(-1e30, 1e30))
+    raw = probe.infer(dev, st["ncol"], fallback=False)[2].cpu().numpy()
+    hi = float(np.quantile(raw, 0.7))
+    sur, _ = _tiny_surrogate(torch, prec_range=(-1e30, hi))
+    assert sur.set_fused(True)
+    *a, nf_a = sur.infer(dev, ncol, fallback=True)
+    a = [t.cpu().numpy() for t in a]
+    assert not sur.set_fused(False)
+    *b, nf_b = sur.infer(dev, ncol, fallback=True)
+    b = [t.cpu().numpy() for t in b]
+    sur.set_fused(True)
+    assert nf_a == nf_b
+    if ncol == 6_001:
+        assert 0 < nf_a < ncol
+    for x, y in zip(a, b):
+        assert np.array_equal(x[..., :ncol], y[..., :ncol])
+
+
 def test_one_chunk_inference_on_the_full_grid(torch):
-    """Inference of the whole 1152 x 768 = 884,736-column grid in one chunk, the benchmarked shape
-    (every hidden layer on the 256 x 256 GEMM tile), against the numpy network with BF16 rounding
+    """Inference of the whole 1152 x 768 = 884,736-column grid in one call, the benchmarked shape
+    (the fused kernel; layer by layer every hidden layer runs on the 256 x 256 GEMM tile, and the
+    two give the same bits), against the numpy network with BF16 rounding
     emulated (oracle/mlp_ref.py) on 3,000 sampled rows: the unpacked tendencies, normalised by the
     output scales, normwise over the sample within 5e-3 (a few BF16 flips, the whole-network bar of
     the MLP tests), and the median row within 1e-5 of its own largest output (a row whose
@@ -157,6 +184,12 @@ def test_one_chunk_inference_on_the_full_grid(torch):
     dev = B.to_device(st)
     sur, net = _tiny_surrogate(torch, max_cols=n, chunk=n)
     dT, dq, pr, _ = sur.infer(dev, n, fallback=False)
+    # the layer-by-layer path on the whole grid gives the fused kernel's bits
+    sur.set_fused(False)
+    lay = [t.clone() for t in sur.infer(dev, n, fallback=False)[:3]]
+    sur.set_fused(True)
+    assert all(torch.equal(u, v) for u, v in zip((dT, dq, pr), lay))
+    del lay
     in_mean, in_std, out_mean, out_std = sur.norms
     x = torch.empty(n, 96, dtype=torch.bfloat16, device="cuda")
     sst = B.state_struct(torch, dev, L, n)
