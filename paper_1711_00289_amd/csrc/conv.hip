@@ -219,7 +219,8 @@ template <class Src, bool DEEP, bool SHALLOW>
 __global__ __launch_bounds__(BLOCK) void k_trigger(Src src, Work w) {
     const int64_t tile = blockIdx.x;
     const int mi = src.find(tile);
-    const Member &M = src.at(mi);
+    const Member M = src.at(mi);  // a copy: loaded once (through a reference into the member
+                                  // table every use would be reloaded after each store)
     const int L = M.nlev;
     const int64_t ld = M.ld;
     const conv_params_t &P = M.P;

@@ -29,10 +29,21 @@ struct Member {
     conv_shallow_out_t sout;
 };
 
+// Pointers read from device memory (the ensemble's member table) are generic to the compiler:
+// loads and stores through them become FLAT instructions, which cannot take a scalar base and
+// also count against the LDS/scalar-load wait counter.  Rebuilding each pointer as a global one
+// from its address lets the compiler use global accesses (the kernels' arrays are all in global
+// memory).
+template <class T>
+__device__ __forceinline__ T *glb(T *p) {
+    typedef __attribute__((address_space(1))) T gT;
+    return (T *)(gT *)(uintptr_t)p;
+}
+
 struct One {
     Member m;
     int64_t ntiles;
-    __device__ const Member &at(int) const { return m; }
+    __device__ Member at(int) const { return m; }
     __device__ int find(int64_t) const { return 0; }
 };
 
@@ -40,7 +51,38 @@ struct Many {
     const Member *ms;  // device table, ascending tile0
     int nm;
     int64_t ntiles;
-    __device__ const Member &at(int i) const { return ms[i]; }
+    __device__ Member at(int i) const {
+        Member m = ms[i];
+        m.T = glb(m.T);
+        m.q = glb(m.q);
+        m.pm = glb(m.pm);
+        m.pi = glb(m.pi);
+        m.z = glb(m.z);
+        m.phis = glb(m.phis);
+        m.pblh = glb(m.pblh);
+        m.tke = glb(m.tke);
+        conv_deep_out_t &d = m.dout;
+        d.dTdt = glb(d.dTdt);
+        d.dqdt = glb(d.dqdt);
+        d.mu = glb(d.mu);
+        d.md = glb(d.md);
+        d.prec = glb(d.prec);
+        d.cape = glb(d.cape);
+        d.klaunch = glb(d.klaunch);
+        d.ktop = glb(d.ktop);
+        d.trig = glb(d.trig);
+        d.status = glb(d.status);
+        conv_shallow_out_t &h = m.sout;
+        h.dTdt = glb(h.dTdt);
+        h.dqdt = glb(h.dqdt);
+        h.mu = glb(h.mu);
+        h.prec = glb(h.prec);
+        h.cin = glb(h.cin);
+        h.kbase = glb(h.kbase);
+        h.ktop = glb(h.ktop);
+        h.status = glb(h.status);
+        return m;
+    }
     // The member holding `tile`: the last entry with tile0 <= tile (members without columns share
     // their successor's tile0 and are skipped).
     __device__ int find(int64_t tile) const {
