@@ -35,12 +35,12 @@ NLON, NLAT = 1152, 768
 TRAFFIC_SOURCES = ("paper_1711_00289_amd/csrc/conv.hip", "paper_1711_00289_amd/csrc/conv_physics.hpp",
                    "paper_1711_00289_amd/csrc/conv_internal.hpp")
 MEASURED_TRAFFIC = {
-    "sources_sha256": "cdc5309005b61bdd05112c15b91fe105ad43fa1efc1fb8b77e84f8a53576f5a4",
+    "sources_sha256": "14152a26ed1ef463399721cb6ac61349f10495a926efad6e63823f8b5f39f018",
     "fetch_factor": 2.0, "write_factor": 1.0,
-    "k_trigger": (542299, 1530018),
-    "k_deep_plume": (275097, 355456),
-    "k_shallow_retrigger": (132062, 9251),
-    "k_shallow_plume": (51923, 18181),
+    "k_trigger": (542188, 1530034),
+    "k_deep_plume": (268826, 350720),
+    "k_shallow_retrigger": (132261, 9254),
+    "k_shallow_plume": (51660, 18171),
 }
 
 
@@ -215,9 +215,10 @@ def bench_adjoint(torch, B, S, reps):
                          "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": abytes / (bwd * 1e-3) / 1e9 / HBM_PEAK_GBS,
                          "algorithmic_bytes_per_call": abytes,
-                         "adjoint_wavefronts": -(-nact // 64),
-                         "note": "one lane per active column: the call is as long as the longest "
-                                 "column's recompute-then-reverse chain"},
+                         "adjoint_wavefronts": 4 * -(-nact // 64),
+                         "note": "four wavefronts per 64 active columns (updraft, two parcel halves, "
+                                 "downdraft chains in parallel): the call is as long as the "
+                                 "updraft's recompute-then-reverse chain"},
             "step": {"workload": "adjoint of the whole step (deep, update, shallow), same grid",
                      "forward_ms": sfwd, "backward_ms": sbwd, "ratio": sbwd / sfwd,
                      "shallow_active_fraction":
