@@ -144,8 +144,8 @@ int conv_step(conv_ctx_t *ctx, const conv_state_t *state, conv_deep_out_t *deep,
  * holds on every GPU it runs on until the process ends; its address is looked up once per device,
  * on the first call there.  The plume kernels get the widest persistent grids (5 wavefronts per
  * compute unit down to 1) whose workspace fits the array; sizes for which even one wavefront per
- * compute unit does not fit (on 256 compute units: more than 813,920 columns of 30 levels, 541,312
- * of 46 or 98,272 of 72) return CONV_ERANGE with nothing enqueued.  The call allocates no memory, host or
+ * compute unit does not fit (on 256 compute units: more than 1,017,088 columns of 30 levels,
+ * 726,112 of 46 or 385,344 of 72) return CONV_ERANGE with nothing enqueued.  The call allocates no memory, host or
  * device, and does not synchronise the host; `params` is a host pointer, read during the call.
  * Every call on one GPU shares that GPU's array and leaves its contents behind (the counters are
  * cleared by the call's own first kernel): calls that overlap on one GPU (different streams or

@@ -14,10 +14,13 @@
 //   k_deep_plume     persistent; wavefronts claim 64 consecutive slots of the deep list at a time:
 //                    updraft (D5), downdraft (D6), flux-form tendencies (D7), closure (D8),
 //                    limiter (D9), outputs (D10).
-//   k_shallow_retrigger  the shallow trigger (S1-S6) of the deep columns on the deep-updated state.
-//   k_shallow_plume  persistent over the shallow list: plume, tendencies, limiter (S7-S9).
+//   k_shallow_retrigger  the shallow trigger (S1-S6) of the deep columns on the deep-updated
+//                    state, with the plume, tendencies and limiter (S7-S9) of those that pass in
+//                    the same lane; then the plumes of the columns the trigger listed.
+//   k_shallow_plume  persistent over the shallow list: S7-S9 (the shallow scheme alone).
 // Per-level plume profiles live in a per-thread scratch region of the caller's workspace laid out
-// [array][level][thread], so a wavefront's accesses to one level are contiguous.  Level loops load
+// [array][level][thread], so a wavefront's accesses to one level are contiguous; the deep plume
+// keeps its unit tendencies in LDS when the grid has at most 31 levels.  Level loops load
 // the next level's inputs before working on the current level.  Kernels are generic over a member
 // source: one grid (kernel argument) or an ensemble table of grids with their own level counts,
 // parameters and arrays (device memory) covered by the same launches.
@@ -63,7 +66,7 @@ int check_launch() {
 
 namespace {
 
-constexpr int DEEP_SCR = 10;    // deep plume profiles (enum DeepScr)
+constexpr int DEEP_SCR = 7;     // deep plume profiles (enum DeepScr)
 constexpr int SHALLOW_SCR = 3;  // eta, dT1, dq1
 constexpr int CNT_DEEP = 0;
 constexpr int CNT_SHALLOW = 1;
@@ -77,11 +80,19 @@ struct Work {
     double *shs, *sqs, *scin, *sMc, *ssig2;
     double *dscr, *sscr;
     int64_t dstride, sstride;  // threads of the deep-plume / shallow-plume persistent grids
+    int64_t rstride;           // threads of the shallow re-trigger grid
     int lmax;                  // level capacity of the scratch
     int cus;                   // compute units of the device
 };
 
 constexpr int RETRIGGER_BPC = 3;  // 256-thread units per compute unit of the shallow re-trigger
+
+// The deep plume keeps its unit tendencies (the last two of its DEEP_SCR profiles) in LDS when
+// they take at most a fifth of a CU's 160 KB, so that its default five wavefronts per CU stay
+// resident: up to 31 levels.  The workspace then holds only the other profiles.
+inline size_t deep_xl_bytes(int lmax) { return (size_t)2 * (lmax + 1) * WAVE * sizeof(double); }
+inline bool deep_xl(int lmax) { return deep_xl_bytes(lmax) <= 32768; }
+inline int deep_scr_global(int lmax) { return deep_xl(lmax) ? DEEP_SCR - 2 : DEEP_SCR; }
 
 
 // The inputs of one level of one column (pt = p_int at the level's top interface).
@@ -191,11 +202,17 @@ __device__ __forceinline__ void zero_level(const Member &M, int64_t ld, int64_t 
     }
 }
 
+// M_c of S8 from the closure inputs of a column that passed S1-S6.
+__device__ __forceinline__ double shallow_closure(const Member &M, const ShallowTrigger &s,
+                                                  double rho_s, double sigw2) {
+    const double sigw = sqrt(sigw2);
+    return rho_s * sigw / SQRT_2PI * exp(-M.P.a_buoy * s.cin / sigw2);
+}
+
 // Stores the closure inputs of a shallow column that passed S1-S6 in list slot `slot`.
 __device__ void shallow_enqueue(const Member &M, const Work &w, int slot, int mi, int64_t col,
                                 const ShallowTrigger &s, double rho_s, double tke, int updated) {
     const double sigw2 = M.P.c_tke * tke;
-    const double sigw = sqrt(sigw2);
     w.slist[slot] = (int)col;
     w.smem[slot] = mi;
     w.sks[slot] = s.ks;
@@ -204,7 +221,7 @@ __device__ void shallow_enqueue(const Member &M, const Work &w, int slot, int mi
     w.sqs[slot] = s.qs;
     w.scin[slot] = s.cin;
     w.ssig2[slot] = sigw2;
-    w.sMc[slot] = rho_s * sigw / SQRT_2PI * exp(-M.P.a_buoy * s.cin / sigw2);
+    w.sMc[slot] = shallow_closure(M, s, rho_s, sigw2);
 }
 
 // ------------------------------------------------------------------ kernels
@@ -414,25 +431,35 @@ __global__ __launch_bounds__(BLOCK) void k_trigger(Src src, Work w) {
 // kept for every level of the plume; the others only for the downdraft region kd .. kb.
 enum DeepScr : int {
     U_SU = 0, U_QU, U_C,   // updraft s, q_v and condensation at interfaces kd+1 .. kb
-    D_ED, D_SD, D_QD,      // downdraft eta_d (< 0), s, q at interfaces kd+1 .. kb
-    D_E1,                  // downdraft evaporation in layers kd .. kb-1
+    D_ED,                  // downdraft eta_d (< 0) at interfaces kd+1 .. kb
     U_ETA,                 // updraft mass flux at interfaces kt+1 .. kb
-    X_DT1, X_DQ1,          // unit tendencies in layers kt .. kb
+    X_DT1, X_DQ1,          // unit tendencies in layers kt .. kb (last: in LDS when they fit)
 };
 
-// Deep plume pass, persistent over the deep list.  Per column: the saturated downdraft (D6) from
-// the trigger's k_d down to the base; the entraining updraft (D5) from the base to the top, which
-// also completes the fluxes and tendencies (D7) of the layers above the downdraft, where the
-// downdraft strength alpha does not enter; then alpha and the layers k_d .. kb; then the closure
-// (D8), limiter (D9) and outputs (D10).  The updraft finishes an interface one level after
-// computing it, when the upwind layer's values (the next level up) have arrived.
-template <class Src>
+// Deep plume pass, persistent over the deep list.  Per column: the entraining updraft (D5) from
+// the base to the top, which also completes the fluxes and tendencies (D7) of the layers above the
+// downdraft, where the downdraft strength alpha does not enter; then one top-down sweep from the
+// trigger's k_d to the base that carries the saturated downdraft (D6) and, at each of its
+// interfaces, the fluxes and tendencies of the layer above; then the closure (D8), limiter (D9)
+// and outputs (D10).  The updraft finishes an interface one level after computing it, when the
+// upwind layer's values (the next level up) have arrived.  The downdraft sweep takes alpha at its
+// uncapped value; alpha is capped by the updraft's condensation only when the downdraft's total
+// evaporation, known at the end of the sweep, exceeds the allowed fraction of it, and then the
+// sweep runs again with the capped alpha (its contributions are accumulated apart for this).
+// With XL the unit tendencies live in the block's LDS (one wavefront per block, [array][level]
+// [lane]) instead of the global scratch: they are written once per layer and read back by the
+// closure and the output stores, and in LDS they leave the caches to the inputs and the other
+// profiles.
+template <class Src, bool XL>
 __global__ __launch_bounds__(WAVE) void k_deep_plume(Src src, Work w) {
     const int n = w.cnt[CNT_DEEP];
     const int64_t gtid = (int64_t)blockIdx.x * WAVE + threadIdx.x;
     const int lane = threadIdx.x % WAVE;
     double *scr = w.dscr;
 #define SCR(arr, lev) scr[((int64_t)(arr) * (w.lmax + 1) + (lev)) * w.dstride + gtid]
+    extern __shared__ double xlds[];
+#define XS(arr, lev) \
+    (*(XL ? &xlds[(((arr) - X_DT1) * (w.lmax + 1) + (lev)) * WAVE + lane] : &SCR(arr, lev)))
 
     // Wavefront g takes slots 64g .. 64g+63 of the deep list, then claims the next 64 unclaimed
     // slots past the grid's first round until the list runs out (list order keeps a wavefront's
@@ -453,90 +480,30 @@ __global__ __launch_bounds__(WAVE) void k_deep_plume(Src src, Work w) {
         const double epsd = P.eps_deep;
         const double dt = M.dt;
 
-        // Accumulations of D7-D9.
-        double P1 = 0.0, Fenv = 0.0, Mlim = __builtin_inf(), dT1kb = 0.0, dq1kb = 0.0;
+        // Accumulations of D7-D9: the layers the updraft sweep completes, and the downdraft
+        // region (kept apart, since it is recomputed when alpha is capped).
+        struct Acc {
+            double P1, Fenv, Mlim;
+        };
+        Acc up = {0.0, 0.0, __builtin_inf()}, dn = {0.0, 0.0, __builtin_inf()};
+        double dT1kb = 0.0, dq1kb = 0.0;
         // One layer's unit tendencies from the fluxes at its top and bottom interfaces.
-        auto layer = [&](int k, double Fs_top, double Fq_top, double Fs_bot, double Fq_bot,
+        auto layer = [&](Acc &a, int k, double Fs_top, double Fq_top, double Fs_bot, double Fq_bot,
                          double net, double T, double q, double p_top, double p_bot) {
             const double dp = p_bot - p_top;
             const double dT1 = (Fs_bot - Fs_top + LV * net) * GRAV / (CP * dp);
             const double dq1 = (Fq_bot - Fq_top - net) * GRAV / dp;
-            SCR(X_DT1, k) = dT1;
-            SCR(X_DQ1, k) = dq1;
-            P1 += net;
+            XS(X_DT1, k) = dT1;
+            XS(X_DQ1, k) = dq1;
+            a.P1 += net;
             if (k <= kb - 1) {
-                Fenv += log(p_bot / p_top) * ((1.0 + CVIR * q) * dT1 + CVIR * T * dq1);
+                a.Fenv += log(p_bot / p_top) * ((1.0 + CVIR * q) * dT1 + CVIR * T * dq1);
             } else {
                 dT1kb = dT1;
                 dq1kb = dq1;
             }
-            if (dq1 < 0.0) Mlim = fmin(Mlim, q / (-dt * dq1));
+            if (dq1 < 0.0) a.Mlim = fmin(a.Mlim, q / (-dt * dq1));
         };
-
-        // D6: saturated downdraft from interface kd+1 down to the base.
-        double E1 = 0.0;
-        if (kd >= 0) {
-            Hint hdn;
-            hdn.clear();
-            Sat s;
-            const double qkd = AT(M.q, kd);
-            const double zkd = AT(M.z, kd);
-            double hd = (CP * AT(M.T, kd) + GRAV * zkd + phis) + LV * qkd;
-            double zb = AT(M.z, kd + 1);
-            double zii = 0.5 * (zkd + zb);
-            double H = hd - GRAV * zii - phis;
-            double Td = tsat_h(H, AT(M.pi, kd + 1), (H - LV * qkd) * RCP_CP, s, hdn);
-            double ad = 1.0, qd = s.qs;
-            SCR(D_ED, kd + 1) = -1.0;
-            SCR(D_SD, kd + 1) = CP * Td + GRAV * zii + phis;
-            SCR(D_QD, kd + 1) = qd;
-            E1 = qd - qkd;
-            SCR(D_E1, kd) = E1;
-            // Layer k needs T, q of layer k, the height of layer k+1 and the pressure of its
-            // bottom interface.  Two level buffers: the loads of layer k+2 are issued while layer
-            // k is worked on (indices clamped, so every load is in range and the wait counts stay
-            // exact; values past the base are not used).
-            struct DdLev {
-                double T, q, zbel, pbel;
-            };
-            auto ddload = [&](int k) {
-                DdLev v;
-                const int kk = min(k, kb);
-                v.T = AT(M.T, kk);
-                v.q = AT(M.q, kk);
-                v.zbel = AT(M.z, min(k + 1, kb));
-                v.pbel = AT(M.pi, min(k + 1, kb + 1));
-                return v;
-            };
-            auto ddlevel = [&](const DdLev &v, int k) {
-                const double Tk = v.T, qk = v.q, zk = zb, zbelow = v.zbel, pbel = v.pbel;
-                zb = zbelow;
-                const double hk = (CP * Tk + GRAV * zk + phis) + LV * qk;
-                const double zlow = 0.5 * (zk + zbelow);
-                const double Ed = epsd * ad * (zii - zlow);
-                const double adn = ad + Ed;
-                hd = (ad * hd + Ed * hk) / adn;
-                H = hd - GRAV * zlow - phis;
-                Td = tsat_h(H, pbel, (H - LV * qk) * RCP_CP, s, hdn);
-                const double e1 = adn * s.qs - ad * qd - Ed * qk;
-                SCR(D_E1, k) = e1;
-                SCR(D_ED, k + 1) = -adn;
-                SCR(D_SD, k + 1) = CP * Td + GRAV * zlow + phis;
-                SCR(D_QD, k + 1) = s.qs;
-                E1 += e1;
-                ad = adn;
-                qd = s.qs;
-                zii = zlow;
-            };
-            DdLev d0 = ddload(kd + 1), d1 = ddload(kd + 2);
-            for (int k = kd + 1; k <= kb - 1; k += 2) {
-                ddlevel(d0, k);
-                d0 = ddload(k + 2);
-                if (k + 1 > kb - 1) break;
-                ddlevel(d1, k + 1);
-                d1 = ddload(k + 3);
-            }
-        }
 
         // D5 + the alpha-free part of D7: updraft from the base (interface kb) to interface kt+1.
         // `u_*` hold the updraft at interface i+1, `e_*` the environment of layer i+1, `p_top` and
@@ -575,7 +542,7 @@ __global__ __launch_bounds__(WAVE) void k_deep_plume(Src src, Work w) {
                 const double Fs = u_eta * (u_su - s_up);
                 const double Fq = u_eta * (u_qu - qi);
                 if (kd < 0 || j <= kd - 1) {
-                    layer(j, Fs, Fq, Fs_b, Fq_b, u_c, e_T, e_q, p_top, p_bot);
+                    layer(up, j, Fs, Fq, Fs_b, Fq_b, u_c, e_T, e_q, p_top, p_bot);
                 } else {  // j == kd
                     Fs_kd = Fs;
                     Fq_kd = Fq;
@@ -646,71 +613,108 @@ __global__ __launch_bounds__(WAVE) void k_deep_plume(Src src, Work w) {
             // Interface kt+1 and layer kt+1 with layer kt's environment (loaded ahead), then the
             // top layer kt, whose upper flux is zero and which has no source.
             finish(kt, tT, tq, zcur);
-            layer(kt, 0.0, 0.0, Fs_b, Fq_b, 0.0, tT, tq, tp, p_top);
+            layer(up, kt, 0.0, 0.0, Fs_b, Fq_b, 0.0, tT, tq, tp, p_top);
         }
 
-        // D6 strength, then D7 for the downdraft region: layers kd .. kb.
+        // D6 with the downdraft region's part of D7: layers kd .. kb, top down.
         double alpha = 0.0;
         if (kd >= 0) {
-            alpha = P.alpha_dd;
-            if (P.alpha_dd * E1 > P.evap_max_frac * C1) alpha = P.evap_max_frac * C1 / E1;
-            double Fs_t = Fs_kd, Fq_t = Fq_kd;
-            double Tk = AT(M.T, kd), qk = AT(M.q, kd), zk = AT(M.z, kd), pt = AT(M.pi, kd);
-            // What layer k needs from memory: its bottom interface i = k+1 (environment below,
-            // both plumes there) and its own condensation and evaporation.  Loaded one layer
-            // ahead; levels are clamped so that every load is in range (values past kb unused).
-            struct DLev {
-                double Tb, qb, zb, pb, et, ed, su, sd, qu, qd, c, e1;
+            // What layer k needs from memory: the environment of layer k+1 and the pressure of
+            // the interface between them (which the downdraft reaches next), and the updraft at
+            // that interface and its condensation in layer k.  Two level buffers: the loads of
+            // layer k+2 are issued while layer k is worked on (levels clamped, so every load is in
+            // range; values past the base are not used).
+            struct FLev {
+                double Tb, qb, zb, pb, et, su, qu, c;
             };
-            auto dload = [&](int k) {
-                DLev v;
+            auto fload = [&](int k) {
+                FLev v;
                 const int i = min(k + 1, kb), kk = min(k, kb);
                 v.Tb = AT(M.T, i);
                 v.qb = AT(M.q, i);
                 v.zb = AT(M.z, i);
                 v.pb = AT(M.pi, min(k + 1, kb + 1));
                 v.et = SCR(U_ETA, i);
-                v.ed = SCR(D_ED, i);
                 v.su = SCR(U_SU, i);
-                v.sd = SCR(D_SD, i);
                 v.qu = SCR(U_QU, i);
-                v.qd = SCR(D_QD, i);
                 v.c = SCR(U_C, kk);
-                v.e1 = SCR(D_E1, kk);
                 return v;
             };
-            // Two level buffers: the loads of layer k+2 are in flight while layer k is computed.
-            auto dlevel = [&](const DLev &v, int k) {
-                const int i = k + 1;  // the layer's bottom interface
-                const double Tb = v.Tb, qb = v.qb, zbl = v.zb, pb = v.pb;
-                double Fs = 0.0, Fq = 0.0;
-                if (i <= kb) {
-                    const double et = v.et, ed = v.ed;
-                    const bool upw = et + alpha * ed >= 0.0;
-                    const double s_up = upw ? CP * Tk + GRAV * zk + phis : CP * Tb + GRAV * zbl + phis;
-                    const double q_up = upw ? qk : qb;
-                    Fs = et * (v.su - s_up) + alpha * ed * (v.sd - s_up);
-                    Fq = et * (v.qu - q_up) + alpha * ed * (v.qd - q_up);
+            const double T_kd = AT(M.T, kd), q_kd = AT(M.q, kd), z_kd = AT(M.z, kd),
+                         p_kd = AT(M.pi, kd);
+            alpha = P.alpha_dd;
+            for (int pass = 0;; ++pass) {
+                Hint hdn;
+                hdn.clear();
+                Sat s;
+                dn = {0.0, 0.0, __builtin_inf()};
+                double E1 = 0.0, hd = 0.0, ad = 1.0, qd = 0.0, zii = 0.0;
+                double Fs_t = Fs_kd, Fq_t = Fq_kd;
+                double Tk = T_kd, qk = q_kd, zk = z_kd, pt = p_kd;
+                auto flevel = [&](const FLev &v, int k) {
+                    const int i = k + 1;  // the layer's bottom interface
+                    double Fs = 0.0, Fq = 0.0, e1 = 0.0;
+                    if (i <= kb) {
+                        // The downdraft from interface k down to i: it starts saturated at the
+                        // interface below k_d with layer k_d's h; below, it entrains each layer's
+                        // air in proportion to its mass flux and the distance.
+                        const double zlow = 0.5 * (zk + v.zb);
+                        double adn, Ed = 0.0;
+                        if (k == kd) {
+                            hd = (CP * Tk + GRAV * zk + phis) + LV * qk;
+                            adn = 1.0;
+                        } else {
+                            const double hk = (CP * Tk + GRAV * zk + phis) + LV * qk;
+                            Ed = epsd * ad * (zii - zlow);
+                            adn = ad + Ed;
+                            hd = (ad * hd + Ed * hk) / adn;
+                        }
+                        const double H = hd - GRAV * zlow - phis;
+                        const double Td = tsat_h(H, v.pb, (H - LV * qk) * RCP_CP, s, hdn);
+                        if (k == kd) {
+                            e1 = s.qs - qk;
+                        } else {
+                            e1 = adn * s.qs - ad * qd - Ed * qk;
+                        }
+                        const double sd = CP * Td + GRAV * zlow + phis;
+                        ad = adn;
+                        qd = s.qs;
+                        zii = zlow;
+                        // The fluxes at interface i, upwind in the net environmental flow.
+                        const double et = v.et, ed = -adn;
+                        SCR(D_ED, i) = ed;
+                        const bool upw = et + alpha * ed >= 0.0;
+                        const double s_up = upw ? CP * Tk + GRAV * zk + phis
+                                                : CP * v.Tb + GRAV * v.zb + phis;
+                        const double q_up = upw ? qk : v.qb;
+                        Fs = et * (v.su - s_up) + alpha * ed * (sd - s_up);
+                        Fq = et * (v.qu - q_up) + alpha * ed * (qd - q_up);
+                        E1 += e1;
+                    }
+                    const double c = k == kd ? c_kd : v.c;
+                    layer(dn, k, Fs_t, Fq_t, Fs, Fq, c - alpha * e1, Tk, qk, pt, v.pb);
+                    Fs_t = Fs;
+                    Fq_t = Fq;
+                    Tk = v.Tb;
+                    qk = v.qb;
+                    zk = v.zb;
+                    pt = v.pb;
+                };
+                FLev v0 = fload(kd), v1 = fload(kd + 1);
+                for (int k = kd; k <= kb; k += 2) {
+                    flevel(v0, k);
+                    v0 = fload(k + 2);
+                    if (k + 1 > kb) break;
+                    flevel(v1, k + 1);
+                    v1 = fload(k + 3);
                 }
-                const double c = k == kd ? c_kd : v.c;
-                const double e1 = k <= kb - 1 ? v.e1 : 0.0;
-                layer(k, Fs_t, Fq_t, Fs, Fq, c - alpha * e1, Tk, qk, pt, pb);
-                Fs_t = Fs;
-                Fq_t = Fq;
-                Tk = Tb;
-                qk = qb;
-                zk = zbl;
-                pt = pb;
-            };
-            DLev v0 = dload(kd), v1 = dload(kd + 1);
-            for (int k = kd; k <= kb; k += 2) {
-                dlevel(v0, k);
-                v0 = dload(k + 2);
-                if (k + 1 > kb) break;
-                dlevel(v1, k + 1);
-                v1 = dload(k + 3);
+                // D6's strength: capped so that the downdraft evaporates at most the allowed
+                // fraction of the updraft's condensation.
+                if (pass > 0 || !(P.alpha_dd * E1 > P.evap_max_frac * C1)) break;
+                alpha = P.evap_max_frac * C1 / E1;
             }
         }
+        const double P1 = up.P1 + dn.P1, Fenv = up.Fenv + dn.Fenv, Mlim = fmin(up.Mlim, dn.Mlim);
 
         // D8: F from the launch-layer tendencies and the trigger's parcel sensitivities; D9, D10.
         // A dilute parcel is also moved by the air it entrained: its sensitivity is swept up from
@@ -735,8 +739,8 @@ __global__ __launch_bounds__(WAVE) void k_deep_plume(Src src, Work w) {
                 v.q = AT(M.q, kk);
                 v.z = AT(M.z, kk);
                 v.pm = AT(M.pm, kk);
-                v.dT1 = SCR(X_DT1, kk);
-                v.dq1 = SCR(X_DQ1, kk);
+                v.dT1 = XS(X_DT1, kk);
+                v.dq1 = XS(X_DQ1, kk);
                 v.pt = AT(M.pi, kk);
                 v.pb = AT(M.pi, kk + 1);
                 return v;
@@ -788,10 +792,10 @@ __global__ __launch_bounds__(WAVE) void k_deep_plume(Src src, Work w) {
 #pragma unroll
                 for (int j = 0; j < OUTC; ++j) {
                     const int k = min(k0 + j, kb);
-                    a[j] = SCR(X_DT1, k);
-                    b[j] = SCR(X_DQ1, k);
-                    e[j] = SCR(U_ETA, k);
-                    d[j] = SCR(D_ED, k);
+                    a[j] = XS(X_DT1, k);
+                    b[j] = XS(X_DQ1, k);
+                    e[j] = SCR(U_ETA, max(k, kt + 1));
+                    d[j] = SCR(D_ED, dd ? max(k, kd + 1) : k);
                 }
 #pragma unroll
                 for (int j = 0; j < OUTC; ++j) {
@@ -811,15 +815,166 @@ __global__ __launch_bounds__(WAVE) void k_deep_plume(Src src, Work w) {
         if (lane == 0) claim = atomicAdd(&w.cnt[CNT_DGRAB], WAVE);
         slot0 = first_round + __builtin_amdgcn_readfirstlane(claim);
     }
+#undef XS
 #undef SCR
 }
 
-// Shallow trigger (S1-S6) on the deep-updated state T' = T + dt*dTdt, q' = q + dt*dqdt of every
-// column of the deep list; persistent, wavefront-uniform loop so the shallow list's ballot is
-// convergent.  Its own kernel (not the tail of the deep plume pass) so that it runs at the
-// occupancy its few registers allow.
+// S7-S9 of one shallow column that passed S1-S6: the plume from the source interface ks with
+// its closure inputs (from the trigger or the re-trigger), the tendencies and the limiter; writes
+// the column's shallow outputs.  `upd`: the plume sees the deep-updated state T + dt*dTdt,
+// q + dt*dqdt.  The per-level profiles go to the thread's scratch column `tid` of `stride`.
+__device__ void shallow_plume_column(const Member &M, int64_t col, int ks, bool upd, double hs,
+                                     double qsrc, double cin, double Mclos, double sigw2,
+                                     double *scr, int64_t stride, int64_t tid, int lmax) {
+    const int64_t ld = M.ld;
+    const conv_params_t &P = M.P;
+#define SCR(arr, lev) scr[((int64_t)(arr) * (lmax + 1) + (lev)) * stride + tid]
+    const double phis = M.phis[col];
+    auto Tn = [&](int k) { return upd ? AT(M.T, k) + M.dt * AT(M.dout.dTdt, k) : AT(M.T, k); };
+    auto qn = [&](int k) { return upd ? AT(M.q, k) + M.dt * AT(M.dout.dqdt, k) : AT(M.q, k); };
+    auto zi = [&](int i) { return 0.5 * (AT(M.z, i - 1) + AT(M.z, i)); };
+
+    Hint hp;
+    hp.clear();
+    double Mlim = __builtin_inf();
+    double P1;
+    double Fs_lo, Fq_lo;  // fluxes at the interface below the current layer
+    double eta = 1.0, hu = hs, qtu;
+    // S7 start: thermodynamics at the source interface ks.
+    {
+        const double zs = zi(ks);
+        const Lifted r = lift(hs - GRAV * zs - phis, qsrc, AT(M.pi, ks), hp);
+        const double ql = qsrc - r.qv;
+        const double rr = ql - P.qlcrit_sh > 0.0 ? ql - P.qlcrit_sh : 0.0;
+        qtu = qsrc - rr;
+        const double slu = CP * r.T + GRAV * zs + phis - LV * (ql - rr);
+        const double s_up = CP * Tn(ks - 1) + GRAV * AT(M.z, ks - 1) + phis;
+        const double Fs = slu - s_up, Fq = qtu - qn(ks - 1);
+        const double dp = AT(M.pi, ks + 1) - AT(M.pi, ks);
+        const double dT1 = (0.0 - Fs + LV * rr) * GRAV / (CP * dp);
+        const double dq1 = (0.0 - Fq - rr) * GRAV / dp;
+        SCR(0, ks) = 1.0;
+        SCR(1, ks) = dT1;
+        SCR(2, ks) = dq1;
+        P1 = rr;
+        if (dq1 < 0.0) Mlim = fmin(Mlim, qn(ks) / (-M.dt * dq1));
+        Fs_lo = Fs;
+        Fq_lo = Fq;
+    }
+    double w2 = sigw2 + 2.0 * P.a_buoy * cin;
+    int kt = -1;
+    double zlo = zi(ks);
+    for (int k = ks - 1; k >= 0; --k) {
+        bool stop = AT(M.pi, k) < P.p_sh_top_min || k == 0;
+        double zk = 0.0, E = 0.0, D = 0.0, en = 0.0;
+        if (!stop) {
+            zk = zi(k);
+            const double dz = zk - zlo;
+            E = P.eps_sh * eta * dz;
+            D = P.delta_sh * eta * dz;
+            en = eta + E - D;
+            stop = !(en > 0.0);
+        }
+        double Fs = 0.0, Fq = 0.0, rr = 0.0, w2n = 0.0, hm = 0.0, qtn = 0.0;
+        if (!stop) {
+            const double Tk = Tn(k), qk = qn(k);
+            hm = ((eta - D) * hu + E * ((CP * Tk + GRAV * AT(M.z, k) + phis) + LV * qk)) / en;
+            const double qm = ((eta - D) * qtu + E * qk) / en;
+            const Lifted r = lift(hm - GRAV * zk - phis, qm, AT(M.pi, k), hp);
+            const double ql = qm - r.qv;
+            rr = ql - P.qlcrit_sh > 0.0 ? ql - P.qlcrit_sh : 0.0;
+            const double Trho = r.T * (1.0 + CVIR * r.qv - (ql - rr));
+            const double Tve = tv(Tk, qk);
+            const double B = GRAV * (Trho - Tve) / Tve;
+            w2n = w2 + 2.0 * (zk - zlo) * (P.a_buoy * B - P.b_drag * P.eps_sh * w2);
+            stop = !(w2n > 0.0);
+            if (!stop) {
+                qtn = qm - rr;
+                const double slu = CP * r.T + GRAV * zk + phis - LV * (ql - rr);
+                const double s_up = CP * Tn(k - 1) + GRAV * AT(M.z, k - 1) + phis;
+                Fs = en * (slu - s_up);
+                Fq = en * (qtn - qn(k - 1));
+            }
+        }
+        const double pr = stop ? 0.0 : en * rr;
+        const double dp = AT(M.pi, k + 1) - AT(M.pi, k);
+        const double dT1 = (Fs_lo - Fs + LV * pr) * GRAV / (CP * dp);
+        const double dq1 = (Fq_lo - Fq - pr) * GRAV / dp;
+        SCR(1, k) = dT1;
+        SCR(2, k) = dq1;
+        P1 += pr;
+        if (dq1 < 0.0) Mlim = fmin(Mlim, qn(k) / (-M.dt * dq1));
+        if (stop) {
+            kt = k;
+            break;
+        }
+        SCR(0, k) = en;
+        eta = en;
+        hu = hm;
+        qtu = qtn;
+        w2 = w2n;
+        zlo = zk;
+        Fs_lo = Fs;
+        Fq_lo = Fq;
+    }
+    const int st = (kt == ks - 1) ? 5 : 0;
+    const double Mb = Mclos <= Mlim ? Mclos : Mlim;
+    if (st == 0) {  // the trigger pass zeroed the column; write the plume's levels
+        // OUTC levels at a time, loads first (levels clamped to ks), as in the deep plume.
+        constexpr int OUTC = 4;
+        for (int k0 = kt; k0 <= ks; k0 += OUTC) {
+            double a[OUTC], b[OUTC], e[OUTC];
+#pragma unroll
+            for (int j = 0; j < OUTC; ++j) {
+                const int k = min(k0 + j, ks);
+                a[j] = SCR(1, k);
+                b[j] = SCR(2, k);
+                e[j] = SCR(0, k);
+            }
+#pragma unroll
+            for (int j = 0; j < OUTC; ++j) {
+                const int k = k0 + j;
+                if (k > ks) break;
+                AT(M.sout.dTdt, k) = Mb * a[j];
+                AT(M.sout.dqdt, k) = Mb * b[j];
+                if (k >= kt + 1) AT(M.sout.mu, k) = Mb * e[j];
+            }
+        }
+    }
+    M.sout.prec[col] = st == 0 ? Mb * P1 : 0.0;
+    M.sout.cin[col] = cin;
+    M.sout.kbase[col] = ks;
+    M.sout.ktop[col] = kt;
+    M.sout.status[col] = st;
+#undef SCR
+}
+
+// The shallow plume pass over the list the trigger filled (columns without deep convection).
 template <class Src>
-__global__ __launch_bounds__(BLOCK) void k_shallow_retrigger(Src src, Work w) {
+__global__ __launch_bounds__(WAVE) void k_shallow_plume(Src src, Work w) {
+    const int n = w.cnt[CNT_SHALLOW];
+    const int64_t gtid = (int64_t)blockIdx.x * WAVE + threadIdx.x;
+    const int64_t nthreads = (int64_t)gridDim.x * WAVE;
+    for (int64_t slot = gtid; slot < n; slot += nthreads) {
+        const Member M = src.at(w.smem[slot]);  // a copy: the fields stay in registers
+        shallow_plume_column(M, w.slist[slot], w.sks[slot], w.sflag[slot] != 0, w.shs[slot],
+                             w.sqs[slot], w.scin[slot], w.sMc[slot], w.ssig2[slot], w.sscr,
+                             w.sstride, gtid, w.lmax);
+    }
+}
+
+// The shallow scheme after the deep one: the shallow trigger (S1-S6) on the deep-updated state
+// T' = T + dt*dTdt, q' = q + dt*dqdt of every column of the deep list, and the plume (S7-S9) of
+// each column that passes it, in the same lane; then the plumes of the columns the trigger listed
+// (no deep convection there).  Persistent over the deep list.  Its own kernel (not the tail of
+// the deep plume pass) so that it runs at the occupancy its registers allow; the plumes run
+// inline because most of the columns that pass S1-S6 after deep convection stop at their first
+// level, which a separate pass would pay a list round trip and a launch for.  Held to three
+// wavefronts per SIMD (at most 168 registers; the inline plume wants more): the occupancy its
+// launch of 12 wavefronts per CU needs.
+template <class Src>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3)))
+void k_shallow_retrigger(Src src, Work w) {
     const int n = w.cnt[CNT_DEEP];
     const int64_t gtid = (int64_t)blockIdx.x * WAVE + threadIdx.x;  // one wavefront per block
     const int64_t nthreads = (int64_t)gridDim.x * WAVE;
@@ -889,153 +1044,26 @@ __global__ __launch_bounds__(BLOCK) void k_shallow_retrigger(Src src, Work w) {
             } else {
                 sst = 6;
             }
-            if (sst < 0)
+            if (sst < 0) {
                 rho_s = AT(M.pi, sh.ks) / (RD * tv(Tn(sh.ks), qn(sh.ks)));
-            else
+                const double sigw2 = P.c_tke * tke;
+                shallow_plume_column(M, col, sh.ks, true, sh.hs, sh.qs, sh.cin,
+                                     shallow_closure(M, sh, rho_s, sigw2), sigw2, w.sscr, nthreads,
+                                     gtid, w.lmax);
+            } else {
                 write_shallow_quiet(M, col, sst, sh.cin, sh.ks);
+            }
         }
-        const int sslot = wave_append(act && sst < 0, &w.cnt[CNT_SHALLOW]);
-        if (sslot >= 0) shallow_enqueue(M, w, sslot, mi, col, sh, rho_s, tke, 1);
+    }
+    const int ns = w.cnt[CNT_SHALLOW];
+    for (int64_t slot = gtid; slot < ns; slot += nthreads) {
+        const Member M = src.at(w.smem[slot]);
+        shallow_plume_column(M, w.slist[slot], w.sks[slot], w.sflag[slot] != 0, w.shs[slot],
+                             w.sqs[slot], w.scin[slot], w.sMc[slot], w.ssig2[slot], w.sscr,
+                             nthreads, gtid, w.lmax);
     }
 }
 
-template <class Src>
-__global__ __launch_bounds__(WAVE) void k_shallow_plume(Src src, Work w) {
-    const int n = w.cnt[CNT_SHALLOW];
-    const int64_t gtid = (int64_t)blockIdx.x * WAVE + threadIdx.x;
-    const int64_t nthreads = (int64_t)gridDim.x * WAVE;
-    double *scr = w.sscr;
-#define SCR(arr, lev) scr[((int64_t)(arr) * (w.lmax + 1) + (lev)) * w.sstride + gtid]
-
-    for (int64_t slot = gtid; slot < n; slot += nthreads) {
-        const Member M = src.at(w.smem[slot]);  // a copy: the fields stay in registers
-        const int64_t ld = M.ld;
-        const conv_params_t &P = M.P;
-        const int64_t col = w.slist[slot];
-        const int ks = w.sks[slot];
-        const bool upd = w.sflag[slot] != 0;
-        const double hs = w.shs[slot], qsrc = w.sqs[slot], cin = w.scin[slot];
-        const double Mclos = w.sMc[slot], sigw2 = w.ssig2[slot];
-        const double phis = M.phis[col];
-        auto Tn = [&](int k) { return upd ? AT(M.T, k) + M.dt * AT(M.dout.dTdt, k) : AT(M.T, k); };
-        auto qn = [&](int k) { return upd ? AT(M.q, k) + M.dt * AT(M.dout.dqdt, k) : AT(M.q, k); };
-        auto zi = [&](int i) { return 0.5 * (AT(M.z, i - 1) + AT(M.z, i)); };
-
-        Hint hp;
-        hp.clear();
-        double Mlim = __builtin_inf();
-        double P1;
-        double Fs_lo, Fq_lo;  // fluxes at the interface below the current layer
-        double eta = 1.0, hu = hs, qtu;
-        // S7 start: thermodynamics at the source interface ks.
-        {
-            const double zs = zi(ks);
-            const Lifted r = lift(hs - GRAV * zs - phis, qsrc, AT(M.pi, ks), hp);
-            const double ql = qsrc - r.qv;
-            const double rr = ql - P.qlcrit_sh > 0.0 ? ql - P.qlcrit_sh : 0.0;
-            qtu = qsrc - rr;
-            const double slu = CP * r.T + GRAV * zs + phis - LV * (ql - rr);
-            const double s_up = CP * Tn(ks - 1) + GRAV * AT(M.z, ks - 1) + phis;
-            const double Fs = slu - s_up, Fq = qtu - qn(ks - 1);
-            const double dp = AT(M.pi, ks + 1) - AT(M.pi, ks);
-            const double dT1 = (0.0 - Fs + LV * rr) * GRAV / (CP * dp);
-            const double dq1 = (0.0 - Fq - rr) * GRAV / dp;
-            SCR(0, ks) = 1.0;
-            SCR(1, ks) = dT1;
-            SCR(2, ks) = dq1;
-            P1 = rr;
-            if (dq1 < 0.0) Mlim = fmin(Mlim, qn(ks) / (-M.dt * dq1));
-            Fs_lo = Fs;
-            Fq_lo = Fq;
-        }
-        double w2 = sigw2 + 2.0 * P.a_buoy * cin;
-        int kt = -1;
-        double zlo = zi(ks);
-        for (int k = ks - 1; k >= 0; --k) {
-            bool stop = AT(M.pi, k) < P.p_sh_top_min || k == 0;
-            double zk = 0.0, E = 0.0, D = 0.0, en = 0.0;
-            if (!stop) {
-                zk = zi(k);
-                const double dz = zk - zlo;
-                E = P.eps_sh * eta * dz;
-                D = P.delta_sh * eta * dz;
-                en = eta + E - D;
-                stop = !(en > 0.0);
-            }
-            double Fs = 0.0, Fq = 0.0, rr = 0.0, w2n = 0.0, hm = 0.0, qtn = 0.0;
-            if (!stop) {
-                const double Tk = Tn(k), qk = qn(k);
-                hm = ((eta - D) * hu + E * ((CP * Tk + GRAV * AT(M.z, k) + phis) + LV * qk)) / en;
-                const double qm = ((eta - D) * qtu + E * qk) / en;
-                const Lifted r = lift(hm - GRAV * zk - phis, qm, AT(M.pi, k), hp);
-                const double ql = qm - r.qv;
-                rr = ql - P.qlcrit_sh > 0.0 ? ql - P.qlcrit_sh : 0.0;
-                const double Trho = r.T * (1.0 + CVIR * r.qv - (ql - rr));
-                const double Tve = tv(Tk, qk);
-                const double B = GRAV * (Trho - Tve) / Tve;
-                w2n = w2 + 2.0 * (zk - zlo) * (P.a_buoy * B - P.b_drag * P.eps_sh * w2);
-                stop = !(w2n > 0.0);
-                if (!stop) {
-                    qtn = qm - rr;
-                    const double slu = CP * r.T + GRAV * zk + phis - LV * (ql - rr);
-                    const double s_up = CP * Tn(k - 1) + GRAV * AT(M.z, k - 1) + phis;
-                    Fs = en * (slu - s_up);
-                    Fq = en * (qtn - qn(k - 1));
-                }
-            }
-            const double pr = stop ? 0.0 : en * rr;
-            const double dp = AT(M.pi, k + 1) - AT(M.pi, k);
-            const double dT1 = (Fs_lo - Fs + LV * pr) * GRAV / (CP * dp);
-            const double dq1 = (Fq_lo - Fq - pr) * GRAV / dp;
-            SCR(1, k) = dT1;
-            SCR(2, k) = dq1;
-            P1 += pr;
-            if (dq1 < 0.0) Mlim = fmin(Mlim, qn(k) / (-M.dt * dq1));
-            if (stop) {
-                kt = k;
-                break;
-            }
-            SCR(0, k) = en;
-            eta = en;
-            hu = hm;
-            qtu = qtn;
-            w2 = w2n;
-            zlo = zk;
-            Fs_lo = Fs;
-            Fq_lo = Fq;
-        }
-        const int st = (kt == ks - 1) ? 5 : 0;
-        const double Mb = Mclos <= Mlim ? Mclos : Mlim;
-        if (st == 0) {  // the trigger pass zeroed the column; write the plume's levels
-            // OUTC levels at a time, loads first (levels clamped to ks), as in the deep plume.
-            constexpr int OUTC = 4;
-            for (int k0 = kt; k0 <= ks; k0 += OUTC) {
-                double a[OUTC], b[OUTC], e[OUTC];
-#pragma unroll
-                for (int j = 0; j < OUTC; ++j) {
-                    const int k = min(k0 + j, ks);
-                    a[j] = SCR(1, k);
-                    b[j] = SCR(2, k);
-                    e[j] = SCR(0, k);
-                }
-#pragma unroll
-                for (int j = 0; j < OUTC; ++j) {
-                    const int k = k0 + j;
-                    if (k > ks) break;
-                    AT(M.sout.dTdt, k) = Mb * a[j];
-                    AT(M.sout.dqdt, k) = Mb * b[j];
-                    if (k >= kt + 1) AT(M.sout.mu, k) = Mb * e[j];
-                }
-            }
-        }
-        M.sout.prec[col] = st == 0 ? Mb * P1 : 0.0;
-        M.sout.cin[col] = cin;
-        M.sout.kbase[col] = ks;
-        M.sout.ktop[col] = kt;
-        M.sout.status[col] = st;
-    }
-#undef SCR
-}
 
 #undef AT
 
@@ -1077,7 +1105,7 @@ Layout make_layout(int64_t ncol, int lmax, int nmem, int cus, int64_t thread_cap
     l.sMc = take(n * sizeof(double));
     l.ssig2 = take(n * sizeof(double));
     l.members = take((size_t)(nmem > 0 ? nmem : 1) * sizeof(Member));
-    l.dscr = take((size_t)DEEP_SCR * (lmax + 1) * l.threads * sizeof(double));
+    l.dscr = take((size_t)deep_scr_global(lmax) * (lmax + 1) * l.threads * sizeof(double));
     l.sscr = take((size_t)SHALLOW_SCR * (lmax + 1) * l.threads * sizeof(double));
     l.total = off;
     return l;
@@ -1113,6 +1141,8 @@ Work make_work(char *b, const Layout &l, const Launch &launch, int cus) {
     const int64_t sh = (int64_t)cus * launch.shallow_wpc * WAVE;
     w.dstride = fd < l.threads ? fd : l.threads;
     w.sstride = sh < l.threads ? sh : l.threads;
+    const int64_t rt = (int64_t)cus * RETRIGGER_BPC * BLOCK;
+    w.rstride = rt < l.threads ? rt : l.threads;
     w.lmax = l.lmax;
     w.cus = cus;
     return w;
@@ -1151,17 +1181,23 @@ int launch_step(const Src &src, const Work &w, hipStream_t st, hipEvent_t *ev) {
     if (ev) (void)hipEventRecord(ev[1], st);
     hipLaunchKernelGGL((k_trigger<Src, DEEP, SHALLOW>), dim3(gt), dim3(BLOCK), 0, st, src, w);
     if (ev) (void)hipEventRecord(ev[2], st);
-    if (DEEP) hipLaunchKernelGGL((k_deep_plume<Src>), dim3(gd), dim3(WAVE), 0, st, src, w);
+    if (DEEP) {
+        if (deep_xl(w.lmax))
+            hipLaunchKernelGGL((k_deep_plume<Src, true>), dim3(gd), dim3(WAVE), deep_xl_bytes(w.lmax),
+                               st, src, w);
+        else
+            hipLaunchKernelGGL((k_deep_plume<Src, false>), dim3(gd), dim3(WAVE), 0, st, src, w);
+    }
     if (ev) (void)hipEventRecord(ev[3], st);
     if (DEEP && SHALLOW) {
-        const int64_t cap = (int64_t)w.cus * RETRIGGER_BPC;
-        const unsigned gr = (unsigned)(src.ntiles < cap ? src.ntiles : cap);
         // one-wavefront blocks, RETRIGGER_BPC x 256 threads per CU (78 -> 69 us against
-        // 256-thread blocks on the 884,736-column grid)
-        hipLaunchKernelGGL((k_shallow_retrigger<Src>), dim3(gr * NWAVES), dim3(WAVE), 0, st, src, w);
+        // 256-thread blocks on the 884,736-column grid); the shallow plumes run inside
+        const unsigned gr = (unsigned)(w.rstride / WAVE);
+        hipLaunchKernelGGL((k_shallow_retrigger<Src>), dim3(gr), dim3(WAVE), 0, st, src, w);
     }
     if (ev) (void)hipEventRecord(ev[4], st);
-    if (SHALLOW) hipLaunchKernelGGL((k_shallow_plume<Src>), dim3(gs), dim3(WAVE), 0, st, src, w);
+    if (SHALLOW && !DEEP)
+        hipLaunchKernelGGL((k_shallow_plume<Src>), dim3(gs), dim3(WAVE), 0, st, src, w);
     if (ev) (void)hipEventRecord(ev[5], st);
     return finish();
 }

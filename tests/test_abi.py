@@ -126,7 +126,7 @@ def test_mlp_training_batch_limit_sizes():
 def test_static_step_rejects_sizes_beyond_its_scratch_without_gpu():
     """conv_step_static checks its arguments and the size of the workspace its static device array
     must hold before any HIP call that launches or allocates: bad arguments give CONV_EINVAL,
-    sizes beyond the array CONV_ERANGE (on 256 compute units the bound for 72 levels is 98,272
+    sizes beyond the array CONV_ERANGE (on 256 compute units the bound for 72 levels is 385,344
     columns), nothing is enqueued."""
     if not os.path.exists(binding.LIB_PATH):
         pytest.skip("libconv.so not built")

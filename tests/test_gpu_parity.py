@@ -171,7 +171,10 @@ def test_other_level_counts(torch, nlev):
 @pytest.mark.parametrize("over", [dict(alpha_dd=0.0), dict(eps_deep=0.0), dict(eps_deep=5e-4),
                                   dict(cape_threshold=0.0), dict(tau=600.0),
                                   dict(eps_sh=2e-3, delta_sh=5e-4), dict(qlcrit_sh=0.0),
-                                  dict(cin_max=1e9, p_sh_top_min=20000.0)])
+                                  dict(cin_max=1e9, p_sh_top_min=20000.0),
+                                  # the evaporation cap on alpha (D6): every active column, and
+                                  # about one in eight (a wavefront's lanes on both branches)
+                                  dict(evap_max_frac=0.05), dict(evap_max_frac=0.15)])
 def test_parameter_variants(torch, over):
     st = S.subset(S.grid_1deg(), np.arange(288 * 70, 288 * 70 + 4000))
     B = _bind()
