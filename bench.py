@@ -35,11 +35,11 @@ NLON, NLAT = 1152, 768
 TRAFFIC_SOURCES = ("paper_1711_00289_amd/csrc/conv.hip", "paper_1711_00289_amd/csrc/conv_physics.hpp",
                    "paper_1711_00289_amd/csrc/conv_internal.hpp")
 MEASURED_TRAFFIC = {
-    "sources_sha256": "c0a29340a7d04f2b22a959e901f58a07b5216e1a4bb04a3c84e8f822984722e5",
+    "sources_sha256": "959cee15c998314cfb8664e67a8cb5b346847ea91d01919db07d30c7a0227604",
     "fetch_factor": 2.0, "write_factor": 1.0,
-    "k_trigger": (542374, 1530033),
-    "k_deep_plume": (146313, 195187),
-    "k_shallow_retrigger": (164343, 25923),
+    "k_trigger": (542323, 1530002),
+    "k_deep_plume": (145164, 197635),
+    "k_shallow_retrigger": (164802, 25929),
 }
 
 

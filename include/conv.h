@@ -309,8 +309,10 @@ int conv_ensemble_step(conv_ens_t *e, void *stream);
 int conv_ensemble_set_launch(conv_ens_t *e, int fused_waves_per_cu, int shallow_waves_per_cu);
 int conv_ensemble_get_launch(conv_ens_t *e, int *fused_waves_per_cu, int *shallow_waves_per_cu);
 
-/* Autotuner: times conv_ensemble_step (median of `reps` runs, 1..1000) for every candidate shape
- * in {4,5,6,8,12,16,24,32} x {4,8,16,32} wavefronts per CU and keeps the fastest.  Results are cached per process, keyed by
+/* Autotuner: times conv_ensemble_step (median of `reps` runs, 1..1000, the lower of two sweeps)
+ * for every deep-plume shape in {4,5,6,8} wavefronts per CU and keeps the fastest (the step runs the shallow
+ * plumes inside its re-trigger, so the shallow-plume shape keeps its default of 32; it serves
+ * conv_shallow alone).  Results are cached per process, keyed by
  * device and member shapes; `force` != 0 re-tunes.  Runs steps (the outputs are overwritten) and
  * waits on the host, so it may not be called during capture.  Outputs may be NULL. */
 int conv_ensemble_autotune(conv_ens_t *e, void *stream, int reps, int force,
@@ -329,8 +331,9 @@ int conv_autotune(conv_ctx_t *ctx, const conv_state_t *state, conv_deep_out_t *d
 
 /* Launch shape of the persistent kernels: wavefronts per compute unit for the deep-plume kernel
  * and for the shallow-plume kernel (each 1..32; default 5 and 32), launched as blocks of one
- * 64-thread wavefront each.  The workspace size does not depend on it.  Results do not depend on
- * it (bit-identical). */
+ * 64-thread wavefront each (the deep plume's LDS keeps at most 5 per CU resident; the others
+ * queue).  The workspace size does not depend on it.  Results do not depend on it
+ * (bit-identical). */
 int conv_set_launch(conv_ctx_t *ctx, int fused_waves_per_cu, int shallow_waves_per_cu);
 int conv_get_launch(conv_ctx_t *ctx, int *fused_waves_per_cu, int *shallow_waves_per_cu);
 

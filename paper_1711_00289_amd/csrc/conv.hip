@@ -87,12 +87,15 @@ struct Work {
 
 constexpr int RETRIGGER_BPC = 3;  // 256-thread units per compute unit of the shallow re-trigger
 
-// The deep plume keeps its unit tendencies (the last two of its DEEP_SCR profiles) in LDS when
-// they take at most a fifth of a CU's 160 KB, so that its default five wavefronts per CU stay
-// resident: up to 31 levels.  The workspace then holds only the other profiles.
-inline size_t deep_xl_bytes(int lmax) { return (size_t)2 * (lmax + 1) * WAVE * sizeof(double); }
-inline bool deep_xl(int lmax) { return deep_xl_bytes(lmax) <= 32768; }
-inline int deep_scr_global(int lmax) { return deep_xl(lmax) ? DEEP_SCR - 2 : DEEP_SCR; }
+// The deep plume keeps its unit tendencies (the last two of its DEEP_SCR profiles) of the XW
+// layers from the launch layer up in LDS: 31 KB per wavefront, so that its default five
+// wavefronts per CU stay resident (32 KB each left room for four).  Grids of at most XW levels
+// never need more, and the workspace then holds only the other profiles; deeper plumes keep
+// their upper layers' tendencies in the workspace.
+constexpr int XW = 31;
+constexpr size_t DEEP_X_LDS = (size_t)2 * XW * WAVE * sizeof(double);
+inline bool deep_xg(int lmax) { return lmax > XW; }
+inline int deep_scr_global(int lmax) { return deep_xg(lmax) ? DEEP_SCR : DEEP_SCR - 2; }
 
 
 // The inputs of one level of one column (pt = p_int at the level's top interface).
@@ -433,7 +436,7 @@ enum DeepScr : int {
     U_SU = 0, U_QU, U_C,   // updraft s, q_v and condensation at interfaces kd+1 .. kb
     D_ED,                  // downdraft eta_d (< 0) at interfaces kd+1 .. kb
     U_ETA,                 // updraft mass flux at interfaces kt+1 .. kb
-    X_DT1, X_DQ1,          // unit tendencies in layers kt .. kb (last: in LDS when they fit)
+    X_DT1, X_DQ1,          // unit tendencies in layers kt .. kb (last: in LDS up to XW layers)
 };
 
 // Deep plume pass, persistent over the deep list.  Per column: the entraining updraft (D5) from
@@ -446,11 +449,11 @@ enum DeepScr : int {
 // uncapped value; alpha is capped by the updraft's condensation only when the downdraft's total
 // evaporation, known at the end of the sweep, exceeds the allowed fraction of it, and then the
 // sweep runs again with the capped alpha (its contributions are accumulated apart for this).
-// With XL the unit tendencies live in the block's LDS (one wavefront per block, [array][level]
+// The unit tendencies live in the block's LDS (one wavefront per block, [array][kb - level]
 // [lane]) instead of the global scratch: they are written once per layer and read back by the
 // closure and the output stores, and in LDS they leave the caches to the inputs and the other
-// profiles.
-template <class Src, bool XL>
+// profiles.  With XG, layers more than XW above the launch layer use the global scratch.
+template <class Src, bool XG>
 __global__ __launch_bounds__(WAVE) void k_deep_plume(Src src, Work w) {
     const int n = w.cnt[CNT_DEEP];
     const int64_t gtid = (int64_t)blockIdx.x * WAVE + threadIdx.x;
@@ -458,8 +461,6 @@ __global__ __launch_bounds__(WAVE) void k_deep_plume(Src src, Work w) {
     double *scr = w.dscr;
 #define SCR(arr, lev) scr[((int64_t)(arr) * (w.lmax + 1) + (lev)) * w.dstride + gtid]
     extern __shared__ double xlds[];
-#define XS(arr, lev) \
-    (*(XL ? &xlds[(((arr) - X_DT1) * (w.lmax + 1) + (lev)) * WAVE + lane] : &SCR(arr, lev)))
 
     // Wavefront g takes slots 64g .. 64g+63 of the deep list, then claims the next 64 unclaimed
     // slots past the grid's first round until the list runs out (list order keeps a wavefront's
@@ -479,6 +480,18 @@ __global__ __launch_bounds__(WAVE) void k_deep_plume(Src src, Work w) {
         const double phis = M.phis[col];
         const double epsd = P.eps_deep;
         const double dt = M.dt;
+        // Unit tendency a (0: dT1, 1: dq1) of layer k (kt <= k <= kb).
+        auto xput = [&](int a, int k, double v) {
+            const int r = kb - k;
+            if (!XG || r < XW)
+                xlds[(a * XW + r) * WAVE + lane] = v;
+            else
+                SCR(X_DT1 + a, k) = v;
+        };
+        auto xget = [&](int a, int k) {
+            const int r = kb - k;
+            return (!XG || r < XW) ? xlds[(a * XW + r) * WAVE + lane] : SCR(X_DT1 + a, k);
+        };
 
         // Accumulations of D7-D9: the layers the updraft sweep completes, and the downdraft
         // region (kept apart, since it is recomputed when alpha is capped).
@@ -493,8 +506,8 @@ __global__ __launch_bounds__(WAVE) void k_deep_plume(Src src, Work w) {
             const double dp = p_bot - p_top;
             const double dT1 = (Fs_bot - Fs_top + LV * net) * GRAV / (CP * dp);
             const double dq1 = (Fq_bot - Fq_top - net) * GRAV / dp;
-            XS(X_DT1, k) = dT1;
-            XS(X_DQ1, k) = dq1;
+            xput(0, k, dT1);
+            xput(1, k, dq1);
             a.P1 += net;
             if (k <= kb - 1) {
                 a.Fenv += log(p_bot / p_top) * ((1.0 + CVIR * q) * dT1 + CVIR * T * dq1);
@@ -739,8 +752,8 @@ __global__ __launch_bounds__(WAVE) void k_deep_plume(Src src, Work w) {
                 v.q = AT(M.q, kk);
                 v.z = AT(M.z, kk);
                 v.pm = AT(M.pm, kk);
-                v.dT1 = XS(X_DT1, kk);
-                v.dq1 = XS(X_DQ1, kk);
+                v.dT1 = xget(0, kk);
+                v.dq1 = xget(1, kk);
                 v.pt = AT(M.pi, kk);
                 v.pb = AT(M.pi, kk + 1);
                 return v;
@@ -792,8 +805,8 @@ __global__ __launch_bounds__(WAVE) void k_deep_plume(Src src, Work w) {
 #pragma unroll
                 for (int j = 0; j < OUTC; ++j) {
                     const int k = min(k0 + j, kb);
-                    a[j] = XS(X_DT1, k);
-                    b[j] = XS(X_DQ1, k);
+                    a[j] = xget(0, k);
+                    b[j] = xget(1, k);
                     e[j] = SCR(U_ETA, max(k, kt + 1));
                     d[j] = SCR(D_ED, dd ? max(k, kd + 1) : k);
                 }
@@ -815,7 +828,6 @@ __global__ __launch_bounds__(WAVE) void k_deep_plume(Src src, Work w) {
         if (lane == 0) claim = atomicAdd(&w.cnt[CNT_DGRAB], WAVE);
         slot0 = first_round + __builtin_amdgcn_readfirstlane(claim);
     }
-#undef XS
 #undef SCR
 }
 
@@ -1182,11 +1194,11 @@ int launch_step(const Src &src, const Work &w, hipStream_t st, hipEvent_t *ev) {
     hipLaunchKernelGGL((k_trigger<Src, DEEP, SHALLOW>), dim3(gt), dim3(BLOCK), 0, st, src, w);
     if (ev) (void)hipEventRecord(ev[2], st);
     if (DEEP) {
-        if (deep_xl(w.lmax))
-            hipLaunchKernelGGL((k_deep_plume<Src, true>), dim3(gd), dim3(WAVE), deep_xl_bytes(w.lmax),
-                               st, src, w);
+        if (deep_xg(w.lmax))
+            hipLaunchKernelGGL((k_deep_plume<Src, true>), dim3(gd), dim3(WAVE), DEEP_X_LDS, st, src, w);
         else
-            hipLaunchKernelGGL((k_deep_plume<Src, false>), dim3(gd), dim3(WAVE), 0, st, src, w);
+            hipLaunchKernelGGL((k_deep_plume<Src, false>), dim3(gd), dim3(WAVE), DEEP_X_LDS, st, src,
+                               w);
     }
     if (ev) (void)hipEventRecord(ev[3], st);
     if (DEEP && SHALLOW) {
@@ -1220,8 +1232,11 @@ int run_one(conv_ctx *c, const conv_state_t *s, const conv_deep_out_t *d,
 // deep plume's candidates are fine around one and two wavefronts per SIMD: its end is set by how
 // many 64-column passes its busiest wavefronts take (on the 884,736-column grid, 5 per CU:
 // 0.255 -> 0.233 ms against 4).
-constexpr int TUNE_FUSED[] = {4, 5, 6, 8, 12, 16, 24, 32};
-constexpr int TUNE_SHALLOW[] = {4, 8, 16, 32};
+// Deep-plume shapes the autotuners try (its LDS leaves room for five resident wavefronts per CU;
+// a larger grid queues blocks, which helped the ensemble a little); the step does not launch the
+// shallow plume kernel (its re-trigger runs the shallow plumes), whose shape keeps its default.
+constexpr int TUNE_FUSED[] = {4, 5, 6, 8};
+constexpr int NTUNE = sizeof(TUNE_FUSED) / sizeof(TUNE_FUSED[0]);
 
 struct TuneResult {
     Launch launch;
@@ -1232,7 +1247,8 @@ std::mutex g_tune_mu;
 std::map<std::string, TuneResult> g_tune_cache;  // per process, keyed by device and shapes
 
 // Times `run(shape)` (which enqueues one step on `st`) for every candidate shape: one untimed
-// call, then `reps` calls each bracketed by events; the score is the median.  Waits on the host.
+// call, then `reps` calls each bracketed by events; the score is the median, the lower of two
+// sweeps (the first can run while the clocks still rise).  Waits on the host.
 template <class Run>
 int tune(hipStream_t st, int reps, Run run, TuneResult *best) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1242,11 +1258,12 @@ int tune(hipStream_t st, int reps, Run run, TuneResult *best) {
         return CONV_EHIP;
     }
     std::vector<float> t((size_t)reps);
-    TuneResult b{DEFAULT_LAUNCH, __builtin_inff()};
+    float score[NTUNE];
+    for (float &x : score) x = __builtin_inff();
     auto body = [&]() -> int {
-        for (int f : TUNE_FUSED) {
-            for (int sh : TUNE_SHALLOW) {
-                const Launch L{f, sh};
+        for (int sweep = 0; sweep < 2; ++sweep) {
+            for (int i = 0; i < NTUNE; ++i) {
+                const Launch L{TUNE_FUSED[i], DEFAULT_LAUNCH.shallow_wpc};
                 int rc = run(L);
                 if (rc != CONV_OK) return rc;
                 for (int r = 0; r < reps; ++r) {
@@ -1259,7 +1276,7 @@ int tune(hipStream_t st, int reps, Run run, TuneResult *best) {
                 }
                 std::sort(t.begin(), t.end());
                 const float med = t[(size_t)reps / 2];
-                if (med < b.ms) b = TuneResult{L, med};
+                if (med < score[i]) score[i] = med;
             }
         }
         return CONV_OK;
@@ -1268,7 +1285,13 @@ int tune(hipStream_t st, int reps, Run run, TuneResult *best) {
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc == CONV_EHIP) g_last_hip = (int)hipGetLastError();
-    if (rc == CONV_OK) *best = b;
+    if (rc == CONV_OK) {
+        TuneResult b{DEFAULT_LAUNCH, __builtin_inff()};
+        for (int i = 0; i < NTUNE; ++i)
+            if (score[i] < b.ms)
+                b = TuneResult{Launch{TUNE_FUSED[i], DEFAULT_LAUNCH.shallow_wpc}, score[i]};
+        *best = b;
+    }
     return rc;
 }
 
