@@ -981,11 +981,22 @@ __global__ __launch_bounds__(WAVE) void k_shallow_plume(Src src, Work w) {
 // (no deep convection there).  Persistent over the deep list.  Its own kernel (not the tail of
 // the deep plume pass) so that it runs at the occupancy its registers allow; the plumes run
 // inline because most of the columns that pass S1-S6 after deep convection stop at their first
-// level, which a separate pass would pay a list round trip and a launch for.  Held to three
-// wavefronts per SIMD (at most 168 registers; the inline plume wants more): the occupancy its
-// launch of 12 wavefronts per CU needs.
+// level, which a separate pass would pay a list round trip and a launch for.  On one grid it is
+// held to three wavefronts per SIMD (at most 168 registers, a few spilled; the inline plume wants
+// more), the occupancy its launch of 12 wavefronts per CU needs.  An ensemble's lanes also hold
+// their member's fields: there two wavefronts per SIMD without spills run faster (2.18 -> 2.13 ms
+// per ensemble step; the single grid's re-trigger 0.077 -> 0.081 ms).
 template <class Src>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3)))
+struct RetriggerOccupancy {
+    static constexpr int waves_per_simd = 3;
+};
+template <>
+struct RetriggerOccupancy<Many> {
+    static constexpr int waves_per_simd = 2;
+};
+template <class Src>
+__global__ __launch_bounds__(BLOCK)
+__attribute__((amdgpu_waves_per_eu(RetriggerOccupancy<Src>::waves_per_simd)))
 void k_shallow_retrigger(Src src, Work w) {
     const int n = w.cnt[CNT_DEEP];
     const int64_t gtid = (int64_t)blockIdx.x * WAVE + threadIdx.x;  // one wavefront per block
