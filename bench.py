@@ -35,7 +35,7 @@ NLON, NLAT = 1152, 768
 TRAFFIC_SOURCES = ("paper_1711_00289_amd/csrc/conv.hip", "paper_1711_00289_amd/csrc/conv_physics.hpp",
                    "paper_1711_00289_amd/csrc/conv_internal.hpp")
 MEASURED_TRAFFIC = {
-    "sources_sha256": "959cee15c998314cfb8664e67a8cb5b346847ea91d01919db07d30c7a0227604",
+    "sources_sha256": "38415483344beb6eb910f955476165b1d0ab81f46be4f4383d1400a7f5cbb369",
     "fetch_factor": 2.0, "write_factor": 1.0,
     "k_trigger": (542323, 1530002),
     "k_deep_plume": (145164, 197635),
