@@ -330,9 +330,9 @@ int conv_autotune(conv_ctx_t *ctx, const conv_state_t *state, conv_deep_out_t *d
                   int *fused_waves_per_cu, int *shallow_waves_per_cu, float *ms);
 
 /* Launch shape of the persistent kernels: wavefronts per compute unit for the deep-plume kernel
- * and for the shallow-plume kernel (each 1..32; default 5 and 32), launched as blocks of one
- * 64-thread wavefront each (the deep plume's LDS keeps at most 5 per CU resident; the others
- * queue).  The workspace size does not depend on it.  Results do not depend on it
+ * and for the shallow-plume kernel that conv_shallow launches (each 1..32; default 5 and 32),
+ * launched as blocks of one 64-thread wavefront each (the deep plume's LDS keeps at most 5 per CU
+ * resident; the others queue).  The workspace size does not depend on it.  Results do not depend on it
  * (bit-identical). */
 int conv_set_launch(conv_ctx_t *ctx, int fused_waves_per_cu, int shallow_waves_per_cu);
 int conv_get_launch(conv_ctx_t *ctx, int *fused_waves_per_cu, int *shallow_waves_per_cu);
@@ -340,9 +340,9 @@ int conv_get_launch(conv_ctx_t *ctx, int *fused_waves_per_cu, int *shallow_waves
 /* Instrumentation: record HIP events on the call's stream around each kernel of the next
  * `max_calls` calls (0 turns recording off).  conv_timing_read() waits for the recorded calls and
  * returns, per stage, the summed milliseconds over those calls in ms[0..4] (counter reset, trigger
- * pass, deep-plume pass, shallow re-trigger of the deep columns, shallow-plume pass; a stage a call
- * does not run reads as the time between its neighbours' events) and the number of recorded calls
- * in *ncalls.
+ * pass, deep-plume pass, shallow re-trigger of the deep columns with their shallow plumes,
+ * shallow-plume pass of the shallow scheme alone; a stage a call does not run reads as the time
+ * between its neighbours' events) and the number of recorded calls in *ncalls.
  * Events are host-side handles created here; no device memory is allocated. */
 int conv_timing_start(conv_ctx_t *ctx, int max_calls);
 int conv_timing_read(conv_ctx_t *ctx, double *ms, int *ncalls);
