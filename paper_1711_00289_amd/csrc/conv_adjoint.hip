@@ -67,7 +67,6 @@ __global__ __launch_bounds__(BLOCK) void k_adj_compact(Member M, AdjWork w) {
     const int slot = wave_append(act, &w.cnt[0]);
     if (slot >= 0) w.list[slot] = (int)col;
 }
-constexpr int COMPACT_SPLIT = 4;  // level groups of k_sadj_compact
 
 constexpr int AB = 4;  // levels per batch of loads in the reverse sweeps
 
@@ -1017,20 +1016,12 @@ struct SAdjWork {
     int upd;                     // the scheme saw T + dt*dTdt, q + dt*dqdt of M.dout (step)
 };
 
-// Shallow-active (status 0) columns into a list; every column gets zero gradients (whole lines,
-// blocks (x, y) writing levels y, y + gridDim.y, .. of their columns), the active ones overwritten
-// by the adjoint's last pass.
+// Shallow-active (status 0) columns into a list, and zero parameter-gradient rows; the other
+// columns' gradients are written by k_shallow_adjoint's blocks that hold no list entries.
 __global__ __launch_bounds__(BLOCK) void k_sadj_compact(Member M, SAdjWork w) {
     const int64_t col = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     const bool live = col < M.ncol;
     const int64_t ld = M.ld;
-    if (live) {
-        for (int k = blockIdx.y; k < M.nlev; k += gridDim.y) {
-            AT(w.gT, k) = 0.0;
-            AT(w.gq, k) = 0.0;
-        }
-    }
-    if (blockIdx.y != 0) return;
     const bool act = live && M.sout.status[col] == 0;
     if (live) {
         w.pgrad[col] = 0.0;
@@ -1401,6 +1392,23 @@ __global__ __launch_bounds__(WAVE) void k_shallow_adjoint(Member M, SAdjWork w) 
         w.pgrad[col] = geps;
         w.pgrad[ld + col] = gdel;
     }
+
+    // The columns without shallow convection get zero gradients, written by the blocks that hold
+    // no list entries while the others run their chains (if every block holds some, by all of
+    // them after their entries), as in k_deep_adjoint.
+    const int64_t nchunk = ((int64_t)n + WAVE - 1) / WAVE;
+    const int64_t nidle = (int64_t)gridDim.x - nchunk;
+    if (nidle > 0 && (int64_t)blockIdx.x < nchunk) return;
+    const int64_t fi = nidle > 0 ? (int64_t)blockIdx.x - nchunk : (int64_t)blockIdx.x;
+    const int64_t nf = nidle > 0 ? nidle : (int64_t)gridDim.x;
+    for (int64_t c0 = fi * WAVE; c0 < M.ncol; c0 += nf * WAVE) {
+        const int64_t col = c0 + threadIdx.x;
+        if (col >= M.ncol || M.sout.status[col] == 0) continue;
+        for (int k = 0; k < L; ++k) {
+            AT(w.gT, k) = 0.0;
+            AT(w.gq, k) = 0.0;
+        }
+    }
 #undef S
 }
 
@@ -1604,7 +1612,7 @@ int conv_shallow_backward(conv_ctx_t *ctx, const conv_state_t *state,
         shallow_work(b, l, ctx, cot, grad->g_T, grad->g_q, (double *)(b + l.total), 0);
     const unsigned gcols = (unsigned)((ctx->ncol + BLOCK - 1) / BLOCK);
     hipLaunchKernelGGL(k_adj_reset, dim3(1), dim3(NCOUNTERS), 0, st, w.cnt);
-    hipLaunchKernelGGL(k_sadj_compact, dim3(gcols, COMPACT_SPLIT), dim3(BLOCK), 0, st, M, w);
+    hipLaunchKernelGGL(k_sadj_compact, dim3(gcols), dim3(BLOCK), 0, st, M, w);
     hipLaunchKernelGGL(k_shallow_adjoint, dim3((unsigned)(l.threads / WAVE)), dim3(WAVE), 0, st,
                        M, w);
     param_sums(w.pgrad, ld, ctx->ncol, (double *)(b + l.part), grad->g_params, st);
@@ -1641,7 +1649,7 @@ int conv_step_backward(conv_ctx_t *ctx, const conv_state_t *state, const conv_de
     // Shallow adjoint at the updated state: dL/dT', dL/dq' into g_T, g_q.
     const SAdjWork sw = shallow_work(b, l, ctx, scot, grad->g_T, grad->g_q, pgrad + 2 * ld, 1);
     hipLaunchKernelGGL(k_adj_reset, dim3(1), dim3(NCOUNTERS), 0, st, sw.cnt);
-    hipLaunchKernelGGL(k_sadj_compact, dim3(gcols, COMPACT_SPLIT), dim3(BLOCK), 0, st, M, sw);
+    hipLaunchKernelGGL(k_sadj_compact, dim3(gcols), dim3(BLOCK), 0, st, M, sw);
     hipLaunchKernelGGL(k_shallow_adjoint, dim3(gpers), dim3(WAVE), 0, st, M, sw);
     // Deep adjoint with the update's chain rule, in place on g_T, g_q.
     AdjWork dw = deep_work(b, l, ctx, dcot, grad->g_T, grad->g_q, pgrad);
