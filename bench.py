@@ -453,7 +453,7 @@ def main():
                     help="time only the headline step (no adjoint, ensemble)")
     ap.add_argument("--surrogate-n", type=int, default=10_000_000,
                     help="training soundings for the surrogate (0 skips it)")
-    ap.add_argument("--surrogate-epochs", type=int, default=10)
+    ap.add_argument("--surrogate-epochs", type=int, default=30)
     ap.add_argument("--gemm-only", action="store_true",
                     help="time only the surrogate's GEMM kernel (mlp_gemm_nt, bias + GELU) on "
                          "131,072 and 884,736 x 512 x 512 and exit")
