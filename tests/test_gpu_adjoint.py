@@ -192,6 +192,44 @@ def test_parameter_gradients(torch, kw):
         assert np.abs(g["g_q"][:, c] - gq).max() <= TOL * np.abs(gq).max()
 
 
+@pytest.mark.parametrize("seed", range(3))
+def test_random_deep_parameter_sets(torch, seed):
+    """Seeded draws of all the deep scheme's parameters at once: the state gradient of every
+    active column through the per-column dot-product identity, and dL/dtau, dL/deps summed over
+    the columns, against the oracle's tangents."""
+    prng = np.random.default_rng(700 + seed)
+    lu = lambda lo, hi: float(np.exp(prng.uniform(np.log(lo), np.log(hi))))
+    kw = dict(cape_threshold=prng.uniform(0.0, 300.0), tau=lu(300.0, 14400.0),
+              eps_deep=lu(1e-5, 1e-3), alpha_dd=prng.uniform(0.0, 1.0),
+              evap_max_frac=prng.uniform(0.02, 1.0), p_launch_min=prng.uniform(5e4, 8e4),
+              p_top_min=prng.uniform(1e3, 2e4))
+    st = S.small_warm()
+    L, n = st["nlev"], st["ncol"]
+    rng = np.random.default_rng(30 + seed)
+    cT, cq, cP = _cotangents(rng, L, n)
+    op = oracle.make_params(**kw)
+    _, _, out, g = _run(torch, st, cT, cq, cP, _B().make_params(**kw))
+    act = np.nonzero(_np(out["status"]) == 0)[0]
+    assert len(act) > 10, kw
+    want = np.zeros(2)
+    scale = np.zeros(2)
+    for c in act:
+        col = oracle.column(st, int(c))
+        dT = rng.standard_normal(L)
+        dq = rng.standard_normal(L) * 1e-3 * col["q"]
+        j = oracle.deep_column_jvp(col, dT, dq, params=op)
+        rhs, rscale = _cot_dot(cT, cq, cP, c, j)
+        lterms = np.concatenate([g["g_T"][:, c] * dT, g["g_q"][:, c] * dq])
+        assert abs(lterms.sum() - rhs) <= TOL * max(rscale, np.abs(lterms).sum()), (int(c), kw)
+        for i, (dtau, deps) in enumerate(((1.0, 0.0), (0.0, 1.0))):
+            jp = oracle.deep_column_jvp(col, np.zeros(L), np.zeros(L), dtau, deps, params=op)
+            s, a = _cot_dot(cT, cq, cP, c, jp)
+            want[i] += s
+            scale[i] += a
+    assert abs(g["g_tau"] - want[0]) <= TOL * scale[0], kw
+    assert abs(g["g_eps"] - want[1]) <= TOL * scale[1], kw
+
+
 @pytest.fixture(scope="module")
 def grid(torch):
     """The 288 x 192 = 55,296-column x 30-level workload with the squared-tendency loss."""
