@@ -68,3 +68,20 @@ def exact_positive_zero(d: dict, fields, cols):
     for f in fields:
         a = d[f][..., cols]
         assert (a == 0).all() and not np.signbit(a).any(), f
+
+
+def random_params(seed):
+    """Every parameter drawn at once around its default (rates log-uniform, thresholds and
+    pressures uniform), odd seeds with a dilute CAPE: combinations that variants of one parameter
+    at a time do not reach."""
+    rng = np.random.default_rng(seed)
+    lu = lambda lo, hi: float(np.exp(rng.uniform(np.log(lo), np.log(hi))))
+    return dict(cape_threshold=rng.uniform(0.0, 300.0), tau=lu(600.0, 14400.0),
+                eps_deep=lu(1e-5, 1e-3), alpha_dd=rng.uniform(0.0, 0.5),
+                evap_max_frac=rng.uniform(0.02, 1.0), p_launch_min=rng.uniform(5e4, 8e4),
+                p_top_min=rng.uniform(1e3, 2e4), eps_sh=lu(2e-4, 3e-3), delta_sh=lu(2e-4, 3e-3),
+                qlcrit_sh=lu(1e-4, 3e-3), cin_max=rng.uniform(10.0, 400.0),
+                a_buoy=rng.uniform(0.0, 2.0), b_drag=rng.uniform(0.2, 3.0),
+                c_tke=rng.uniform(0.3, 3.0), p_lcl_min=rng.uniform(5e4, 8e4),
+                p_sh_top_min=rng.uniform(2e4, 6e4),
+                eps_cape=lu(1e-5, 3e-4) if seed % 2 else 0.0)

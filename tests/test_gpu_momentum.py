@@ -5,6 +5,7 @@ invariance, column momentum conservation, closed forms without entrainment).
 * element-wise parity (1e-9 of each column's largest tendency) at c_pgf = 0.7 (Gregory, Kershaw &
   Inness 1997) and 1.0 on columns of the 1-degree grid where both schemes act, only one, and
   neither, with padded arrays; the deep part alone too;
+* the same at c_pgf = 0.7 under two seeded draws of the whole parameter set;
 * c_pgf = 0 gives conv_tracer_transport's bits for the two components;
 * the whole 1-degree grid against the oracle, and at every column of the 884,736-column grid the
   properties that hold at any size (a uniform wind moves nothing, column momentum conserved, zeros
@@ -105,6 +106,28 @@ def test_parity_with_the_oracle(torch, mixed, cpgf):
     quiet = (ds != 0) & (ss != 0)
     assert (ds == 0).sum() > 500 and (ss == 0).sum() > 100 and quiet.sum() > 100
     assert np.all(_np(tend)[:, :, :n][:, :, quiet] == 0.0)
+
+
+@pytest.mark.parametrize("seed", [2, 3])
+def test_parity_under_random_parameters(torch, seed):
+    """A seeded draw of the whole parameter set, 4,000 columns of the 1-degree grid's convecting
+    band, c_pgf = 0.7: the step and the momentum transport on the GPU against the oracle's."""
+    from parity import random_params
+
+    B = _B()
+    over = random_params(seed)
+    st = S.subset(S.grid_1deg(), np.arange(288 * 70, 288 * 70 + 4000))
+    n, L = st["ncol"], st["nlev"]
+    print(f"momentum parity, seed {seed}, {over}", flush=True)
+    dev = B.to_device(st)
+    conv = B.Conv(n, L, B.make_params(**over))
+    d, s = conv.step(dev)
+    w = _wind(L, n, 50 + seed)
+    tend, dpart = conv.momentum_transport(dev, d, s, _dev(torch, w, n), c_pgf=0.7, deep_part=True)
+    torch.cuda.synchronize()
+    want, want_d = oracle.momentum(st, w, cpgf=0.7, params=oracle.make_params(**over))
+    _check(_np(tend), want)
+    _check(_np(dpart), want_d)
 
 
 def test_zero_coefficient_gives_the_tracer_bits(torch, mixed):

@@ -10,7 +10,7 @@ import pytest
 
 import oracle
 from paper_1711_00289_amd import soundings as S
-from parity import compare_deep, compare_shallow, exact_positive_zero, to_np
+from parity import compare_deep, compare_shallow, exact_positive_zero, random_params, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -185,23 +185,6 @@ def test_parameter_variants(torch, over):
     od, osh = oracle.step(st, oracle.make_params(**over))
     compare_deep(d, od, st["ncol"], label=f"deep {over}")
     compare_shallow(s, osh, st["ncol"], label=f"shallow {over}")
-
-
-def random_params(seed):
-    """Every parameter drawn at once around its default (rates log-uniform, thresholds and
-    pressures uniform), half of the sets with a dilute CAPE: combinations that the one-at-a-time
-    variants above do not reach."""
-    rng = np.random.default_rng(seed)
-    lu = lambda lo, hi: float(np.exp(rng.uniform(np.log(lo), np.log(hi))))
-    return dict(cape_threshold=rng.uniform(0.0, 300.0), tau=lu(600.0, 14400.0),
-                eps_deep=lu(1e-5, 1e-3), alpha_dd=rng.uniform(0.0, 0.5),
-                evap_max_frac=rng.uniform(0.02, 1.0), p_launch_min=rng.uniform(5e4, 8e4),
-                p_top_min=rng.uniform(1e3, 2e4), eps_sh=lu(2e-4, 3e-3), delta_sh=lu(2e-4, 3e-3),
-                qlcrit_sh=lu(1e-4, 3e-3), cin_max=rng.uniform(10.0, 400.0),
-                a_buoy=rng.uniform(0.0, 2.0), b_drag=rng.uniform(0.2, 3.0),
-                c_tke=rng.uniform(0.3, 3.0), p_lcl_min=rng.uniform(5e4, 8e4),
-                p_sh_top_min=rng.uniform(2e4, 6e4),
-                eps_cape=lu(1e-5, 3e-4) if seed % 2 else 0.0)
 
 
 @pytest.mark.parametrize("seed", range(6))

@@ -217,6 +217,57 @@ def test_step_parameter_gradients(grid1):
         assert abs(got[i] - want[i]) <= TOL * scale[i], i
 
 
+@pytest.mark.parametrize("seed", [2, 4])
+def test_step_adjoint_under_random_parameters(torch, seed):
+    """A seeded draw of the whole parameter set (undilute CAPE: the adjoints refuse a dilute one)
+    on 4,000 columns of the 1-degree grid's convecting band: the step's adjoint through the
+    dot-product identity on every column where a scheme acts, and the four parameter gradients
+    summed over the columns, against the oracle's tangents."""
+    from parity import random_params
+
+    B = _B()
+    over = random_params(seed)
+    assert over["eps_cape"] == 0.0
+    st = S.subset(S.grid_1deg(), np.arange(288 * 70, 288 * 70 + 4000))
+    n, L = st["ncol"], st["nlev"]
+    print(f"step adjoint, seed {seed}, {over}", flush=True)
+    dev = B.to_device(st)
+    conv = B.Conv(n, L, B.make_params(**over))
+    deep, shs = conv.step(dev)
+    rng = np.random.default_rng(60 + seed)
+    cot = [_cotangents(rng, L, n), _cotangents(rng, L, n)]
+    g = conv.step_backward(dev, deep, shs, tuple(_t(torch, a) for a in cot[0]),
+                           tuple(_t(torch, a) for a in cot[1]))
+    torch.cuda.synchronize()
+    g = {k: _np(v) for k, v in g.items()}
+    ds, ss = _np(deep["status"]), _np(shs["status"])
+    active = np.nonzero((ds == 0) | (ss == 0))[0]
+    assert (ds == 0).sum() > 100 and (ss == 0).sum() > 50
+    op = oracle.make_params(**over)
+    want, scale = np.zeros(4), np.zeros(4)
+    for c in active:
+        col = oracle.column(st, int(c))
+        dT = rng.standard_normal(L)
+        dq = rng.standard_normal(L) * 1e-3 * col["q"]
+        r = oracle.step_column_jvp(col, dT, dq, params=op)
+        assert r["status"] == (int(ds[c]), int(ss[c])), int(c)
+        parts = [_dot(ct, int(c), j) for ct, j in zip(cot, (r["deep"], r["shallow"]))]
+        rhs, rscale = sum(p[0] for p in parts), sum(p[1] for p in parts)
+        lterms = np.concatenate([g["g_T"][:, c] * dT, g["g_q"][:, c] * dq])
+        assert abs(lterms.sum() - rhs) <= TOL * max(rscale, np.abs(lterms).sum()), int(c)
+        for i in range(4):
+            e = np.zeros(4)
+            e[i] = 1.0
+            rp = oracle.step_column_jvp(col, np.zeros(L), np.zeros(L), e, params=op)
+            for ct, j in zip(cot, (rp["deep"], rp["shallow"])):
+                s, a = _dot(ct, int(c), j)
+                want[i] += s
+                scale[i] += a
+    got = [g["g_tau"], g["g_eps"], g["g_eps_sh"], g["g_delta_sh"]]
+    for i in range(4):
+        assert abs(got[i] - want[i]) <= TOL * scale[i], (i, got[i], want[i])
+
+
 def test_step_quiet_columns_pass_the_shallow_gradient_through(grid1):
     """Where the deep scheme is inactive the update is the identity: the step's gradient is the
     shallow adjoint's at the (unchanged) state; where neither is active it is zero."""

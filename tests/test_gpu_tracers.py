@@ -4,6 +4,7 @@ the CPU by the moist-static-energy identity, uniform tracers, burden conservatio
 
 * element-wise parity (1e-9 of each column's largest tendency) on columns of the 1-degree grid where
   both schemes act, only the deep one, only the shallow one, and neither, with padded arrays;
+* the same under two seeded draws of the whole parameter set (4,000 columns of the convecting band);
 * the moist-static-energy identity on the GPU's own step: the tracer h gives cp dTdt + Lv dqdt of
   each scheme;
 * the 884,736-column grid with the benchmark's tracers: sampled columns against the oracle, and at
@@ -112,6 +113,30 @@ def test_parity_with_the_oracle(torch, mixed):
     assert (ds == 0).sum() > 500 and (ss == 0).sum() > 100 and ((ds != 0) & (ss != 0)).sum() > 100
     quiet = (ds != 0) & (ss != 0)
     assert np.all(_np(tend)[:, :, :n][:, :, quiet] == 0.0)
+
+
+@pytest.mark.parametrize("seed", [2, 3])
+def test_parity_under_random_parameters(torch, seed):
+    """A seeded draw of the whole parameter set (the plumes' rates, thresholds and closures all
+    change the mass fluxes the tracers ride): 4,000 columns of the 1-degree grid's convecting band,
+    the step and the transport of 2 tracers on the GPU against the oracle's."""
+    from parity import random_params
+
+    B = _B()
+    over = random_params(seed)
+    st = S.subset(S.grid_1deg(), np.arange(288 * 70, 288 * 70 + 4000))
+    n, L = st["ncol"], st["nlev"]
+    print(f"tracer parity, seed {seed}, {over}", flush=True)
+    dev = B.to_device(st)
+    conv = B.Conv(n, L, B.make_params(**over))
+    d, s = conv.step(dev)
+    tr, trd = _tracers(torch, 2, L, n, n, 40 + seed)
+    tend, dpart = conv.tracer_transport(dev, d, s, trd, deep_part=True)
+    torch.cuda.synchronize()
+    want, want_d = oracle.tracers(st, tr, oracle.make_params(**over))
+    _check(_np(tend), want)
+    _check(_np(dpart), want_d)
+    assert (_np(d["status"]) == 0).sum() > 100 and (_np(s["status"]) == 0).sum() > 50
 
 
 def test_moist_static_energy_identity_on_the_gpu_step(torch, mixed):
