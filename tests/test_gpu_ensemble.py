@@ -1,7 +1,7 @@
 """The batched ensemble (conv_ensemble_*, through the C ABI): members with different column
 counts, level counts (30/46/72) and parameters stepped by the same launches give, column for
 column, bit-identical results to conv_step on each member alone, and the oracle's results on
-sampled columns; a captured HIP graph replays to the same bits with eager work between replays;
+sampled columns, also with a seeded draw of every parameter per member; a captured HIP graph replays to the same bits with eager work between replays;
 every persistent-grid shape and the autotuner's choice give the same bits; the 884,736-column grid
 plus 16 members of 55,296 columns runs as one ensemble."""
 import os
@@ -124,6 +124,40 @@ def test_ensemble_matches_oracle_on_sampled_columns(torch):
         gs = {k: v[..., idx] for k, v in to_np(m["shallow"]).items()}
         compare_deep(gd, od, len(idx))
         compare_shallow(gs, osh, len(idx))
+
+
+def test_members_with_their_own_random_parameter_sets(torch):
+    """Each member carries its own seeded draw of all seventeen parameters (dilute CAPE in some,
+    undilute in others): every kernel must read each lane's parameters from that lane's member.
+    Every column of every member against the oracle under that member's parameters, and bit for
+    bit against conv_step on the member alone."""
+    from parity import random_params
+
+    B = _B()
+    specs = small_members()
+    draws = [random_params(20 + i) for i in range(len(specs))]
+    ms = []
+    for (st, L, _), over in zip(specs, draws):
+        dev = B.to_device(st) if st["ncol"] > 0 else _empty_dev(torch, L, st)
+        ms.append(dict(state=dev, nlev=L, ncol=st["ncol"], params=B.make_params(**over)))
+    ens = B.Ensemble(ms)
+    ens.step()
+    torch.cuda.synchronize()
+    active = 0
+    for (st, L, _), over, m in zip(specs, draws, ens.members):
+        n = st["ncol"]
+        if n == 0:
+            continue
+        print(f"member {n} x {L}: {over}", flush=True)
+        od, osh = oracle.step(st, oracle.make_params(**over))
+        gd, gs = to_np(m["deep"]), to_np(m["shallow"])
+        compare_deep(gd, od, n, label=f"deep {n} x {L}")
+        compare_shallow(gs, osh, n, label=f"shallow {n} x {L}")
+        d, s = _separate(torch, m)
+        _equal({f: m["deep"][f] for f in DEEP_F}, {f: d[f] for f in DEEP_F})
+        _equal({f: m["shallow"][f] for f in SHALLOW_F}, {f: s[f] for f in SHALLOW_F})
+        active += int((gd["status"] == 0).sum()) + int((gs["status"] == 0).sum())
+    assert active > 500
 
 
 def test_graph_replays_reproduce_eager_step(torch):
