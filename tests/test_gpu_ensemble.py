@@ -1,9 +1,10 @@
 """The batched ensemble (conv_ensemble_*, through the C ABI): members with different column
 counts, level counts (30/46/72) and parameters stepped by the same launches give, column for
 column, bit-identical results to conv_step on each member alone, and the oracle's results on
-sampled columns, also with a seeded draw of every parameter per member; a captured HIP graph replays to the same bits with eager work between replays;
-every persistent-grid shape and the autotuner's choice give the same bits; the 884,736-column grid
-plus 16 members of 55,296 columns runs as one ensemble."""
+sampled columns, also with a seeded draw of every parameter per member; a captured HIP graph
+replays to the same bits with eager work between replays; every persistent-grid shape and the
+autotuner's choice give the same bits; the 884,736-column grid plus 16 members of 55,296 columns
+runs as one ensemble."""
 import os
 
 import numpy as np
