@@ -14,16 +14,18 @@
 // mixing rates), the status and index outputs; the plumes are not run again.  The shallow scheme
 // transports the tracer already updated by the deep transport (Algorithm 1 order).
 //
-// One wavefront per block, one lane per column; block b takes tracer b % ntr of column block
-// b / ntr, so the tracers of one column block are dispatched together (they share its mass fluxes
-// in L2, and the slow convecting blocks spread over the run instead of piling up at its end).
+// One wavefront per block, one lane per column, two tracers per wavefront (one where the LDS of two
+// would pass 64 KiB, nlev > 64): the plumes' mass fluxes, pressures and indices are then loaded
+// once for both, and each load batch carries both tracers' values (8 tracers on the
+// 884,736-column grid: 0.537 -> 0.495 ms; u and v: 0.120 -> 0.114 ms).  Block b takes tracer
+// pair b % npairs of column block b / npairs, so the tracers of one column block are dispatched
+// together, and the slow convecting blocks spread over the run instead of piling up at its end.
 // The tendencies are written once and not read again here: non-temporal stores (0.58 -> 0.52 ms
-// for 8 tracers on the 884,736-column grid).
-// A lane accumulates its
-// column's tendencies in LDS ([level][lane]); then the wavefront stores level by level with every
-// lane active, so each store covers whole 128-byte lines (stores that cover only part of a line,
-// as a wavefront mixing quiet and convecting columns would issue, run at a fraction of the
-// bandwidth on this part).  Quiet columns contribute zeros.
+// for 8 tracers on the 884,736-column grid).  A lane accumulates its column's tendencies in LDS
+// ([tracer][level][lane]); then the wavefront stores level by level with every lane active, so
+// each store covers whole 128-byte lines (stores that cover only part of a line, as a wavefront
+// mixing quiet and convecting columns would issue, run at a fraction of the bandwidth on this
+// part).  Quiet columns contribute zeros.
 #include <cmath>
 #include <mutex>
 #include <set>
@@ -46,25 +48,34 @@ struct TrArgs {
     double *dtend;     // deep tendency alone (may be NULL)
 };
 
+// TPW tracers per wavefront (tracers t0 .. t0 + nt - 1; with nt < TPW the missing ones repeat the
+// last, which is computed again but not stored).
+template <int TPW>
 __global__ __launch_bounds__(TW) void k_tracers(TrArgs a) {
-    extern __shared__ double sh[];  // [nlev][TW]
+    extern __shared__ double sh[];  // [TPW][nlev][TW]
     const Member &M = a.M;
     const int lane = threadIdx.x;
-    const int t = (int)(blockIdx.x % (unsigned)a.ntr);
-    const int64_t col = (int64_t)(blockIdx.x / (unsigned)a.ntr) * TW + lane;
+    const int ngr = (a.ntr + TPW - 1) / TPW;
+    const int t0 = (int)(blockIdx.x % (unsigned)ngr) * TPW;
+    const int nt = min(TPW, a.ntr - t0);  // tracers of this block (a missing one repeats the last)
+    const int64_t col = (int64_t)(blockIdx.x / (unsigned)ngr) * TW + lane;
     const bool live = col < M.ncol;
     const int64_t ld = M.ld;
     const int L = M.nlev;
     const int64_t plane = (int64_t)L * ld;
     const conv_params_t &P = M.P;
-    const double *C = a.C + (int64_t)t * plane;
-    double *out = a.tend + (int64_t)t * plane;
-    double *dout = a.dtend ? a.dtend + (int64_t)t * plane : nullptr;
-#define SH(k) sh[(k) * TW + lane]
+    const double *C[TPW];
+    double *out[TPW];
+    double *dout[TPW];
+#pragma unroll
+    for (int j = 0; j < TPW; ++j) {
+        const int tj = t0 + min(j, nt - 1);
+        C[j] = a.C + (int64_t)tj * plane;
+        out[j] = a.tend + (int64_t)tj * plane;
+        dout[j] = a.dtend ? a.dtend + (int64_t)tj * plane : nullptr;
+    }
+#define SH(j, k) sh[((j) * L + (k)) * TW + lane]
 
-    // Active columns: status 0 with indices a status-0 column has, and a nonzero base mass flux
-    // (the shallow closure's exp(-a CIN / sigma_w^2) can underflow to zero; such a plume moves
-    // nothing).  Anything else moves nothing.
     bool deep = false, shal = false;
     int kb = 0, kt = 0, ks = 0, kts = 0;
     if (live) {
@@ -79,172 +90,206 @@ __global__ __launch_bounds__(TW) void k_tracers(TrArgs a) {
     }
     auto dp = [&](int k) { return AT(M.pi, k + 1) - AT(M.pi, k); };
 
-    // A wavefront with nothing convecting stores its zeros directly.
     if (__ballot(deep || shal) == 0ull) {
         if (live) {
-            for (int k = 0; k < L; ++k) {
-                __builtin_nontemporal_store(0.0, &AT(out, k));
-                if (dout) __builtin_nontemporal_store(0.0, &AT(dout, k));
+#pragma unroll
+            for (int j = 0; j < TPW; ++j) {
+                if (j >= nt) break;
+                for (int k = 0; k < L; ++k) {
+                    __builtin_nontemporal_store(0.0, &AT(out[j], k));
+                    if (dout[j]) __builtin_nontemporal_store(0.0, &AT(dout[j], k));
+                }
             }
         }
         return;
     }
-    for (int k = 0; k < L; ++k) SH(k) = 0.0;
+#pragma unroll
+    for (int j = 0; j < TPW; ++j)
+        for (int k = 0; k < L; ++k) SH(j, k) = 0.0;
 
+    const bool pgf = a.pgf != 0.0;
     if (deep) {
-        // Updraft, bottom-up: C_u at interface i, its flux, and layer i's tendency from its
-        // bottom (Fb) and top fluxes.  The loads of TB interfaces are issued together, then those
-        // interfaces are computed (a level's arithmetic is far shorter than a load's latency);
-        // indices are clamped, so values loaded past the top are not used.  The downdraft's
-        // first interface (the highest one with md != 0) is noted on the way.
-        // With a pressure-gradient term, crossing layer i adds pgf * mu[i+1] * (C_i - C_{i+1}):
-        // `Cbel` holds C of the layer below the interface being computed.
-        double Cu = AT(C, kb), Fb = 0.0, mu1 = 0.0, Cbel = 0.0;
-        const bool pgf = a.pgf != 0.0;
+        double Cu[TPW], Fb[TPW], Cbel[TPW], mu1 = 0.0;
+#pragma unroll
+        for (int j = 0; j < TPW; ++j) {
+            Cu[j] = AT(C[j], kb);
+            Fb[j] = 0.0;
+            Cbel[j] = 0.0;
+        }
         int i0 = kb + 1;
         for (int b = kb; b >= kt + 1; b -= TB) {
-            double mu[TB], md[TB], Ci[TB + 1], pt[TB + 1];
+            double mu[TB], md[TB], Ci[TPW][TB + 1], pt[TB + 1];
 #pragma unroll
-            for (int j = 0; j <= TB; ++j) {
-                const int i = max(b - j, kt);
-                Ci[j] = AT(C, i);
-                pt[j] = AT(M.pi, i);
+            for (int jj = 0; jj <= TB; ++jj) {
+                const int i = max(b - jj, kt);
+#pragma unroll
+                for (int j = 0; j < TPW; ++j) Ci[j][jj] = AT(C[j], i);
+                pt[jj] = AT(M.pi, i);
             }
             const double pbot0 = AT(M.pi, b + 1);
 #pragma unroll
-            for (int j = 0; j < TB; ++j) {
-                const int i = max(b - j, kt + 1);
-                mu[j] = AT(M.dout.mu, i);
-                md[j] = AT(M.dout.md, i);
+            for (int jj = 0; jj < TB; ++jj) {
+                const int i = max(b - jj, kt + 1);
+                mu[jj] = AT(M.dout.mu, i);
+                md[jj] = AT(M.dout.md, i);
             }
 #pragma unroll
-            for (int j = 0; j < TB; ++j) {
-                const int i = b - j;
+            for (int jj = 0; jj < TB; ++jj) {
+                const int i = b - jj;
                 if (i < kt + 1) break;
-                // interface i: layer i below (C_i), layer i-1 above (C_{i-1}); layer i spans
-                // pressures pt[j] (top) .. its bottom interface (pt[j-1], or pbot0 for j = 0)
-                if (md[j] != 0.0) i0 = i;
-                if (i < kb) {
-                    double num = mu1 * Cu + (mu[j] - mu1) * Ci[j];
-                    if (pgf) num += a.pgf * mu1 * (Ci[j] - Cbel);
-                    Cu = num / mu[j];
+                if (md[jj] != 0.0) i0 = i;
+                const double pbot = jj == 0 ? pbot0 : pt[jj - 1];
+                const bool upw = mu[jj] + md[jj] >= 0.0;
+#pragma unroll
+                for (int j = 0; j < TPW; ++j) {
+                    if (i < kb) {
+                        double num = mu1 * Cu[j] + (mu[jj] - mu1) * Ci[j][jj];
+                        if (pgf) num += a.pgf * mu1 * (Ci[j][jj] - Cbel[j]);
+                        Cu[j] = num / mu[jj];
+                    }
+                    Cbel[j] = Ci[j][jj];
+                    const double F = mu[jj] * (Cu[j] - (upw ? Ci[j][jj + 1] : Ci[j][jj]));
+                    SH(j, i) = (Fb[j] - F) * GRAV / (pbot - pt[jj]);
+                    Fb[j] = F;
                 }
-                Cbel = Ci[j];
-                const double F = mu[j] * (Cu - (mu[j] + md[j] >= 0.0 ? Ci[j + 1] : Ci[j]));
-                const double pbot = j == 0 ? pbot0 : pt[j - 1];
-                SH(i) = (Fb - F) * GRAV / (pbot - pt[j]);
-                Fb = F;
-                mu1 = mu[j];
+                mu1 = mu[jj];
             }
         }
-        SH(kt) = Fb * GRAV / dp(kt);
-        // Downdraft, top-down from its first interface: C_d at interface i mixes layer i-1's air
-        // into C_d at i-1; its flux enters layer i-1 from below and leaves layer i at the top.
-        if (i0 <= kb) {
-            // Crossing layer i-1 downward adds pgf * |md[i-1]| * (C_{i-1} - C_{i-2}): `Cabv` holds
-            // C of the layer above the one crossed.
-            double Cd = AT(C, i0 - 1), ad1 = 0.0, Cabv = 0.0;
-            for (int b = i0; b <= kb; b += TB) {
-                // interfaces b .. b+TB-1: layers b-1 .. b+TB-1 and their interfaces b-1 .. b+TB
-                double mu[TB], md[TB], Cl[TB + 1], pl[TB + 2];
 #pragma unroll
-                for (int j = 0; j < TB; ++j) {
-                    const int i = min(b + j, kb);
-                    mu[j] = AT(M.dout.mu, i);
-                    md[j] = AT(M.dout.md, i);
+        for (int j = 0; j < TPW; ++j) SH(j, kt) = Fb[j] * GRAV / dp(kt);
+        if (i0 <= kb) {
+            double Cd[TPW], Cabv[TPW], ad1 = 0.0;
+#pragma unroll
+            for (int j = 0; j < TPW; ++j) {
+                Cd[j] = AT(C[j], i0 - 1);
+                Cabv[j] = 0.0;
+            }
+            for (int b = i0; b <= kb; b += TB) {
+                double mu[TB], md[TB], Cl[TPW][TB + 1], pl[TB + 2];
+#pragma unroll
+                for (int jj = 0; jj < TB; ++jj) {
+                    const int i = min(b + jj, kb);
+                    mu[jj] = AT(M.dout.mu, i);
+                    md[jj] = AT(M.dout.md, i);
                 }
 #pragma unroll
-                for (int j = 0; j <= TB; ++j) Cl[j] = AT(C, min(b - 1 + j, kb));
+                for (int jj = 0; jj <= TB; ++jj)
 #pragma unroll
-                for (int j = 0; j <= TB + 1; ++j) pl[j] = AT(M.pi, min(b - 1 + j, kb + 1));
+                    for (int j = 0; j < TPW; ++j) Cl[j][jj] = AT(C[j], min(b - 1 + jj, kb));
 #pragma unroll
-                for (int j = 0; j < TB; ++j) {
-                    const int i = b + j;
+                for (int jj = 0; jj <= TB + 1; ++jj) pl[jj] = AT(M.pi, min(b - 1 + jj, kb + 1));
+#pragma unroll
+                for (int jj = 0; jj < TB; ++jj) {
+                    const int i = b + jj;
                     if (i > kb) break;
-                    const double ad = -md[j];
-                    if (i > i0) {
-                        double num = ad1 * Cd + (ad - ad1) * Cl[j];
-                        if (pgf) num += a.pgf * ad1 * (Cl[j] - Cabv);
-                        Cd = num / ad;
+                    const double ad = -md[jj];
+                    const bool upw = mu[jj] + md[jj] >= 0.0;
+#pragma unroll
+                    for (int j = 0; j < TPW; ++j) {
+                        if (i > i0) {
+                            double num = ad1 * Cd[j] + (ad - ad1) * Cl[j][jj];
+                            if (pgf) num += a.pgf * ad1 * (Cl[j][jj] - Cabv[j]);
+                            Cd[j] = num / ad;
+                        }
+                        Cabv[j] = Cl[j][jj];
+                        const double F = md[jj] * (Cd[j] - (upw ? Cl[j][jj] : Cl[j][jj + 1]));
+                        SH(j, i - 1) += F * GRAV / (pl[jj + 1] - pl[jj]);
+                        SH(j, i) -= F * GRAV / (pl[jj + 2] - pl[jj + 1]);
                     }
-                    Cabv = Cl[j];
-                    const double F = md[j] * (Cd - (mu[j] + md[j] >= 0.0 ? Cl[j] : Cl[j + 1]));
-                    SH(i - 1) += F * GRAV / (pl[j + 1] - pl[j]);
-                    SH(i) -= F * GRAV / (pl[j + 2] - pl[j + 1]);
                     ad1 = ad;
                 }
             }
         }
     }
-    if (dout) {
+    if (dout[0]) {
         __builtin_amdgcn_wave_barrier();
         if (live)
-            for (int k = 0; k < L; ++k) __builtin_nontemporal_store(SH(k), &AT(dout, k));
+#pragma unroll
+            for (int j = 0; j < TPW; ++j) {
+                if (j >= nt) break;
+                for (int k = 0; k < L; ++k) __builtin_nontemporal_store(SH(j, k), &AT(dout[j], k));
+            }
     }
     if (shal) {
-        // The tracer the shallow scheme sees: updated by the deep transport (zero where the deep
-        // scheme left the column alone).
-        // C2(k) = C(k) + dt SH(k): the tracer after the deep transport.  The recursion below adds
-        // the shallow part to level i only after reading C2(i) and C2(i - 1), and level i is read
-        // by no later step, so SH holds the deep part wherever C2 is evaluated.
-        double csum = 0.0, wsum = 0.0;
-        for (int b = L - 1; b >= ks; b -= TB) {
-            double Ck[TB], pt[TB], pb[TB];
+        double csum[TPW], wsum = 0.0;
 #pragma unroll
-            for (int j = 0; j < TB; ++j) {
-                const int k = max(b - j, ks);
-                Ck[j] = AT(C, k);
-                pt[j] = AT(M.pi, k);
-                pb[j] = AT(M.pi, k + 1);
+        for (int j = 0; j < TPW; ++j) csum[j] = 0.0;
+        for (int b = L - 1; b >= ks; b -= TB) {
+            double Ck[TPW][TB], pt[TB], pb[TB];
+#pragma unroll
+            for (int jj = 0; jj < TB; ++jj) {
+                const int k = max(b - jj, ks);
+#pragma unroll
+                for (int j = 0; j < TPW; ++j) Ck[j][jj] = AT(C[j], k);
+                pt[jj] = AT(M.pi, k);
+                pb[jj] = AT(M.pi, k + 1);
             }
 #pragma unroll
-            for (int j = 0; j < TB; ++j) {
-                const int k = b - j;
+            for (int jj = 0; jj < TB; ++jj) {
+                const int k = b - jj;
                 if (k < ks) break;
-                const double dpk = pb[j] - pt[j];
-                csum += dpk * (Ck[j] + M.dt * SH(k));
+                const double dpk = pb[jj] - pt[jj];
+#pragma unroll
+                for (int j = 0; j < TPW; ++j) csum[j] += dpk * (Ck[j][jj] + M.dt * SH(j, k));
                 wsum += dpk;
             }
         }
-        double Cu = csum / wsum, Fb = 0.0, mu1 = 0.0, C2bel = 0.0;
-        const bool pgf = a.pgf != 0.0;
+        double Cu[TPW], Fb[TPW], C2bel[TPW], mu1 = 0.0;
+#pragma unroll
+        for (int j = 0; j < TPW; ++j) {
+            Cu[j] = csum[j] / wsum;
+            Fb[j] = 0.0;
+            C2bel[j] = 0.0;
+        }
         for (int b = ks; b >= kts + 1; b -= TB) {
-            // interfaces b .. b-TB+1: layers b .. b-TB, heights b+1 .. b-TB, pressures b+1 .. b-TB+1
-            double mu[TB], Cl[TB + 1], zl[TB + 2], pl[TB + 1];
+            double mu[TB], Cl[TPW][TB + 1], zl[TB + 2], pl[TB + 1];
 #pragma unroll
-            for (int j = 0; j < TB; ++j) mu[j] = AT(M.sout.mu, max(b - j, kts + 1));
+            for (int jj = 0; jj < TB; ++jj) mu[jj] = AT(M.sout.mu, max(b - jj, kts + 1));
 #pragma unroll
-            for (int j = 0; j <= TB; ++j) Cl[j] = AT(C, max(b - j, kts));
+            for (int jj = 0; jj <= TB; ++jj)
 #pragma unroll
-            for (int j = 0; j <= TB + 1; ++j) zl[j] = AT(M.z, min(max(b + 1 - j, 0), L - 1));
+                for (int j = 0; j < TPW; ++j) Cl[j][jj] = AT(C[j], max(b - jj, kts));
 #pragma unroll
-            for (int j = 0; j <= TB; ++j) pl[j] = AT(M.pi, max(b + 1 - j, 0));
+            for (int jj = 0; jj <= TB + 1; ++jj) zl[jj] = AT(M.z, min(max(b + 1 - jj, 0), L - 1));
 #pragma unroll
-            for (int j = 0; j < TB; ++j) {
-                const int i = b - j;
+            for (int jj = 0; jj <= TB; ++jj) pl[jj] = AT(M.pi, max(b + 1 - jj, 0));
+#pragma unroll
+            for (int jj = 0; jj < TB; ++jj) {
+                const int i = b - jj;
                 if (i < kts + 1) break;
-                const double Cim1 = Cl[j + 1] + M.dt * SH(i - 1);
-                const double C2i = Cl[j] + M.dt * SH(i);  // before SH(i) takes its shallow part
+                double E = 0.0, D = 0.0;
                 if (i < ks) {
-                    // zi(i) - zi(i + 1), the interface heights as means of the layers around them
-                    const double dz = 0.5 * (zl[j + 2] + zl[j + 1]) - 0.5 * (zl[j + 1] + zl[j]);
-                    const double E = P.eps_sh * mu1 * dz, D = P.delta_sh * mu1 * dz;
-                    double num = (mu1 - D) * Cu + E * C2i;
-                    if (pgf) num += a.pgf * mu1 * (C2i - C2bel);
-                    Cu = num / mu[j];
+                    const double dz = 0.5 * (zl[jj + 2] + zl[jj + 1]) - 0.5 * (zl[jj + 1] + zl[jj]);
+                    E = P.eps_sh * mu1 * dz;
+                    D = P.delta_sh * mu1 * dz;
                 }
-                C2bel = C2i;
-                const double F = mu[j] * (Cu - Cim1);
-                SH(i) += (Fb - F) * GRAV / (pl[j] - pl[j + 1]);
-                Fb = F;
-                mu1 = mu[j];
+#pragma unroll
+                for (int j = 0; j < TPW; ++j) {
+                    const double Cim1 = Cl[j][jj + 1] + M.dt * SH(j, i - 1);
+                    const double C2i = Cl[j][jj] + M.dt * SH(j, i);
+                    if (i < ks) {
+                        double num = (mu1 - D) * Cu[j] + E * C2i;
+                        if (pgf) num += a.pgf * mu1 * (C2i - C2bel[j]);
+                        Cu[j] = num / mu[jj];
+                    }
+                    C2bel[j] = C2i;
+                    const double F = mu[jj] * (Cu[j] - Cim1);
+                    SH(j, i) += (Fb[j] - F) * GRAV / (pl[jj] - pl[jj + 1]);
+                    Fb[j] = F;
+                }
+                mu1 = mu[jj];
             }
         }
-        SH(kts) += Fb * GRAV / dp(kts);
+#pragma unroll
+        for (int j = 0; j < TPW; ++j) SH(j, kts) += Fb[j] * GRAV / dp(kts);
     }
     __builtin_amdgcn_wave_barrier();
     if (live)
-        for (int k = 0; k < L; ++k) __builtin_nontemporal_store(SH(k), &AT(out, k));
+#pragma unroll
+        for (int j = 0; j < TPW; ++j) {
+            if (j >= nt) break;
+            for (int k = 0; k < L; ++k) __builtin_nontemporal_store(SH(j, k), &AT(out[j], k));
+        }
 #undef SH
 }
 
@@ -294,24 +339,31 @@ int transport(conv_ctx_t *ctx, const conv_state_t *state, const conv_deep_out_t 
     a.C = tracers;
     a.tend = tend;
     a.dtend = deep_tend;
-    const size_t lds = (size_t)ctx->nlev * TW * sizeof(double);  // at most 128 KiB (nlev <= 256)
+    // Two tracers per wavefront while their LDS stays within the default 64 KiB (nlev <= 64),
+    // else one (at most 128 KiB for nlev <= 256, with the kernel's limit raised).
+    const int tpw = (ntr >= 2 && 2 * (size_t)ctx->nlev * TW * sizeof(double) <= 65536) ? 2 : 1;
+    const size_t lds = (size_t)tpw * ctx->nlev * TW * sizeof(double);
     if (lds > 65536) {
         static std::mutex mu;
-        static std::set<int> done;  // devices with the LDS limit of k_tracers raised
+        static std::set<int> done;  // devices with the LDS limit of k_tracers<1> raised
         int dev = 0;
         if (hipGetDevice(&dev) != hipSuccess) return CONV_EHIP;
         std::lock_guard<std::mutex> g(mu);
         if (!done.count(dev)) {
-            if (hipFuncSetAttribute((const void *)k_tracers,
+            if (hipFuncSetAttribute((const void *)k_tracers<1>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
                 hipSuccess)
                 return CONV_EHIP;
             done.insert(dev);
         }
     }
-    const int64_t blocks = (ctx->ncol + TW - 1) / TW * ntr;
+    const int64_t blocks = (ctx->ncol + TW - 1) / TW * ((ntr + tpw - 1) / tpw);
     if (blocks > 0x7fffffff) return CONV_EINVAL;
-    hipLaunchKernelGGL(k_tracers, dim3((unsigned)blocks), dim3(TW), lds, (hipStream_t)stream, a);
+    const hipStream_t st = (hipStream_t)stream;
+    if (tpw == 2)
+        hipLaunchKernelGGL(k_tracers<2>, dim3((unsigned)blocks), dim3(TW), lds, st, a);
+    else
+        hipLaunchKernelGGL(k_tracers<1>, dim3((unsigned)blocks), dim3(TW), lds, st, a);
     return check_launch();
 }
 }  // namespace
