@@ -35,11 +35,11 @@ NLON, NLAT = 1152, 768
 TRAFFIC_SOURCES = ("paper_1711_00289_amd/csrc/conv.hip", "paper_1711_00289_amd/csrc/conv_physics.hpp",
                    "paper_1711_00289_amd/csrc/conv_internal.hpp")
 MEASURED_TRAFFIC = {
-    "sources_sha256": "38415483344beb6eb910f955476165b1d0ab81f46be4f4383d1400a7f5cbb369",
+    "sources_sha256": "1481265f74d2f85489f797ac30f13960c3ec85057cc002f60663154ff552dd3f",
     "fetch_factor": 2.0, "write_factor": 1.0,
-    "k_trigger": (542323, 1530002),
-    "k_deep_plume": (145164, 197635),
-    "k_shallow_retrigger": (164802, 25929),
+    "k_trigger": (542324, 1530011),
+    "k_deep_plume": (143573, 183520),
+    "k_shallow_retrigger": (164584, 25922),
 }
 
 

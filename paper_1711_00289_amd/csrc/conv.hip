@@ -798,7 +798,7 @@ __global__ __launch_bounds__(WAVE) void k_deep_plume(Src src, Work w) {
             // Layers kt..kb and interfaces kt+1..kb, OUTC levels at a time: the scratch loads of
             // a batch are issued together (levels clamped to kb, so every load is in range), then
             // the stores, instead of one load round trip per stored value.
-            constexpr int OUTC = 4;
+            constexpr int OUTC = 8;
             const bool dd = kd >= 0;
             for (int k0 = kt; k0 <= kb; k0 += OUTC) {
                 double a[OUTC], b[OUTC], e[OUTC], d[OUTC];
