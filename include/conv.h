@@ -145,8 +145,9 @@ int conv_step(conv_ctx_t *ctx, const conv_state_t *state, conv_deep_out_t *deep,
  * on the first call there.  The plume kernels get the widest persistent grids (5 wavefronts per
  * compute unit down to 1) whose workspace fits the array; sizes for which even one wavefront per
  * compute unit does not fit (on 256 compute units: more than 1,017,088 columns of 30 levels,
- * 726,112 of 46 or 385,344 of 72) return CONV_ERANGE with nothing enqueued.  The call allocates no memory, host or
- * device, and does not synchronise the host; `params` is a host pointer, read during the call.
+ * 726,112 of 46 or 385,344 of 72) return CONV_ERANGE with nothing enqueued.  The call allocates
+ * no memory, host or device, and does not synchronise the host; `params` is a host pointer, read
+ * during the call.
  * Every call on one GPU shares that GPU's array and leaves its contents behind (the counters are
  * cleared by the call's own first kernel): calls that overlap on one GPU (different streams or
  * threads) race, so the caller must order them. */
@@ -310,11 +311,11 @@ int conv_ensemble_set_launch(conv_ens_t *e, int fused_waves_per_cu, int shallow_
 int conv_ensemble_get_launch(conv_ens_t *e, int *fused_waves_per_cu, int *shallow_waves_per_cu);
 
 /* Autotuner: times conv_ensemble_step (median of `reps` runs, 1..1000, the lower of two sweeps)
- * for every deep-plume shape in {4,5,6,8} wavefronts per CU and keeps the fastest (the step runs the shallow
- * plumes inside its re-trigger, so the shallow-plume shape keeps its default of 32; it serves
- * conv_shallow alone).  Results are cached per process, keyed by
- * device and member shapes; `force` != 0 re-tunes.  Runs steps (the outputs are overwritten) and
- * waits on the host, so it may not be called during capture.  Outputs may be NULL. */
+ * for every deep-plume shape in {4,5,6,8} wavefronts per CU and keeps the fastest (the step runs
+ * the shallow plumes inside its re-trigger, so the shallow-plume shape keeps its default of 32;
+ * it serves conv_shallow alone).  Results are cached per process, keyed by device and member
+ * shapes; `force` != 0 re-tunes.  Runs steps (the outputs are overwritten) and waits on the host,
+ * so it may not be called during capture.  Outputs may be NULL. */
 int conv_ensemble_autotune(conv_ens_t *e, void *stream, int reps, int force,
                            int *fused_waves_per_cu, int *shallow_waves_per_cu, float *ms);
 
@@ -332,8 +333,8 @@ int conv_autotune(conv_ctx_t *ctx, const conv_state_t *state, conv_deep_out_t *d
 /* Launch shape of the persistent kernels: wavefronts per compute unit for the deep-plume kernel
  * and for the shallow-plume kernel that conv_shallow launches (each 1..32; default 5 and 32),
  * launched as blocks of one 64-thread wavefront each (the deep plume's LDS keeps at most 5 per CU
- * resident; the others queue).  The workspace size does not depend on it.  Results do not depend on it
- * (bit-identical). */
+ * resident; the others queue).  Neither the workspace size nor the results depend on it (the
+ * results are bit-identical). */
 int conv_set_launch(conv_ctx_t *ctx, int fused_waves_per_cu, int shallow_waves_per_cu);
 int conv_get_launch(conv_ctx_t *ctx, int *fused_waves_per_cu, int *shallow_waves_per_cu);
 
